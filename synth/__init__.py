@@ -1,0 +1,61 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle's callers.
+
+This module holds no arithmetic of the solver: it only draws numbers and names
+workloads.  Every random vector is a counter-based SplitMix64 stream (Steele,
+Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014):
+element ``i`` of a stream with seed ``s`` is ``mix64(s + (i + 1) * GOLDEN)``
+with the published SplitMix64 finaliser, mapped to a double in ``[-1, 1)`` from
+its top 53 bits.  Because element ``i`` depends only on ``(s, i)``, any slice of
+a vector can be regenerated without the rest of it.
+
+Workloads (grid ordering is row-major with x fastest; Dirichlet boundary values
+are eliminated, so an ``nx*ny`` grid has ``nx*ny`` unknowns):
+
+* ``poisson64_manufactured`` - 2D 5-point, 64x64, x* uniform[-1,1) from the seed,
+  b = A x* (b is formed by the caller with its own operator), x0 = 0.
+* ``poisson2048`` - 2D 5-point, 2048x2048, b uniform[-1,1) from the seed, x0 = 0.
+* ``poisson3d256`` - 3D 7-point, 256^3, b uniform[-1,1) from the seed, x0 = 0.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Raw 64-bit outputs ``start .. start+count-1`` of the SplitMix64 stream ``seed``."""
+    idx = np.arange(start + 1, start + 1 + count, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + idx * GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(n: int, seed: int, start: int = 0) -> np.ndarray:
+    """``n`` float64 values uniform on [-1, 1): top 53 bits of SplitMix64, scaled."""
+    z = splitmix64(seed, start, n)
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return 2.0 * u - 1.0
+
+
+# Named workloads: (operator kind, grid dims, right-hand side kind, Chebyshev interval).
+WORKLOADS = {
+    "poisson64_manufactured": dict(kind="2d5", dims=(64, 64), rhs="manufactured",
+                                   interval=(0.0, 8.0), tol=1e-8),
+    "poisson2048": dict(kind="2d5", dims=(2048, 2048), rhs="uniform",
+                        interval=(0.0, 8.0), tol=1e-8),
+    "poisson3d256": dict(kind="3d7", dims=(256, 256, 256), rhs="uniform",
+                         interval=(0.0, 12.0), tol=1e-10),
+}
+
+
+def grid_size(dims) -> int:
+    n = 1
+    for d in dims:
+        n *= int(d)
+    return n
