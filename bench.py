@@ -1,0 +1,212 @@
+"""Benchmark: p(l)-CG and classic CG on the 2D 5-point Poisson problem, 2048x2048.
+
+One step = one complete solve (setup residual, every iteration, the final true
+residual) of A x = b with b uniform[-1, 1) from seed 0, x0 = 0, stopped at
+relative residual 1e-8; b and x already live in GPU memory when the clock
+starts.  `value` is the iteration rate (x updates per second) of the headline
+method; the JSON line also carries every method's rate, the iteration kernel's
+duration against the HBM roofline, and the oracle's rate on the host CPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--methods cg,1,2,3,4,5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "iters/s + HBM GB/s, p(l)-CG vs CG at 1e-8 rel res; batched solves/s, p99 lat"
+HBM_PEAK_GBS = 8000.0
+
+
+def vector_passes(method: str, l: int) -> int:
+    """Algorithmic vector passes per iteration (each pass = N doubles read or written).
+
+    p(l)-CG fused sweep: reads z^{(l)}_i (stencil input, once), z^{(l)}_{i-1},
+    the current and previous vector of each basis k < l, max(0, l-3) older
+    z^{(l)} vectors for the dot products, p and x; writes z^{(l)}_{i+1}, l new
+    basis vectors, p and x: 3l + 7 + max(0, l - 3).
+    Classic CG: sweep A reads r, p_{k-1}, writes p_k, A p_k (4); sweep B reads
+    x, p, r, A p and writes x, r (6): 10 per iteration.
+    """
+    if method == "cg":
+        return 10
+    return 3 * l + 7 + max(0, l - 3)
+
+
+def cpu_baseline(workload: str, l: int, iters: int) -> dict:
+    """Time the oracle on a bounded sample of the same workload (single thread)."""
+    code = f"""
+import sys, time, json
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+import synth
+from oracle import operators, shifts, plcg
+wl = synth.WORKLOADS[{workload!r}]
+A = operators.laplacian(wl["dims"])
+b = synth.uniform(A.n, 0)
+x0 = np.zeros(A.n)
+sig = shifts.chebyshev_shifts({l}, *wl["interval"])
+plcg.plcg(A, b, x0, {l}, sig, 1e-30, 2)
+t0 = time.perf_counter()
+r = plcg.plcg(A, b, x0, {l}, sig, 1e-30, {iters})
+dt = time.perf_counter() - t0
+print(json.dumps(dict(iters=r.iters, seconds=dt)))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr)
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    name = "CG" if l == 0 else f"p({l})-CG"
+    return {"value": r["iters"] / r["seconds"], "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {r['iters']} iterations of {name} on {workload} "
+                      f"(numpy FP64 oracle, one thread), {r['seconds']:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="poisson2048")
+    ap.add_argument("--methods", default="cg,1,2,3,4,5")
+    ap.add_argument("--headline", type=int, default=1, help="l of the headline p(l)-CG")
+    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the solver has no multi-GPU "
+              "path (see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_06850_amd import plcg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = synth.WORKLOADS[args.workload]
+    dims = wl["dims"]
+    kind = wl["kind"]
+    n = synth.grid_size(dims)
+    lo, hi = wl["interval"]
+    tol = wl["tol"]
+    b = torch.from_numpy(synth.uniform(n, 0)).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream
+
+    methods = []
+    for m in args.methods.split(","):
+        methods.append(("cg", 0) if m == "cg" else ("plcg", int(m)))
+    if ("plcg", args.headline) not in methods:
+        methods.append(("plcg", args.headline))
+
+    rows = {}
+    for method, l in methods:
+        name = "cg" if method == "cg" else f"p{l}"
+        s = plcg.Solver(kind, dims, method=method, l=max(l, 1), lmin=lo, lmax=hi)
+        for _ in range(args.warmup):
+            x.zero_()
+            s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
+        torch.cuda.synchronize()
+        total_iters = 0
+        results = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x.zero_()
+            r = s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
+            total_iters += r.iters
+            results.append(r)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        # Per-kernel duration: one more solve with HIP events around every
+        # iteration kernel (outside the timed steps).
+        s.set_timing(True)
+        x.zero_()
+        rt = s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
+        s.set_timing(False)
+        torch.cuda.synchronize()
+        s.close()
+        r = results[-1]
+        its = total_iters / dt
+        passes = vector_passes(method, l)
+        bytes_iter = passes * 8 * n
+        kernel_us = 1e3 * rt.sweep_ms / max(rt.sweeps, 1)
+        kernels_per_iter = 2 if method == "cg" else 1
+        rows[name] = {
+            "iters": r.iters, "reason": plcg.REASONS[r.reason], "restarts": r.restarts,
+            "true_relres": r.true_relres, "rec_relres": r.rec_relres,
+            "ms_per_solve": 1e3 * dt / args.steps, "iters_per_s": its,
+            "us_per_iter": 1e6 / its, "vector_passes": passes,
+            "alg_GBps": bytes_iter * its / 1e9,
+            "kernel_us": kernel_us, "kernels_per_iter": kernels_per_iter,
+            "kernel_GBps": (bytes_iter / kernels_per_iter) / (kernel_us * 1e-6) / 1e9
+            if method != "cg" else None,
+            "spmvs": r.spmvs,
+        }
+        if not args.quiet:
+            print(f"# {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
+
+    head = f"p{args.headline}"
+    hr = rows[head]
+    ms_per_step = hr["ms_per_solve"]
+    bytes_launch = hr["vector_passes"] * 8 * n
+    achieved = bytes_launch / (hr["kernel_us"] * 1e-6) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": hr["iters_per_s"],
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: 2D 5-point Dirichlet Poisson {dims[0]}x{dims[1]} "
+                        f"({n} unknowns), b uniform[-1,1) seed 0, x0 = 0, stop at relative "
+                        f"residual {tol:g}; Chebyshev shifts on [{lo:g},{hi:g}]",
+            "method": f"p({args.headline})-CG", "l": args.headline,
+            "iters_per_solve": hr["iters"], "true_relres": hr["true_relres"],
+            "alg_GBps": hr["alg_GBps"],
+            "cg_iters_per_s": rows["cg"]["iters_per_s"] if "cg" in rows else None,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": f"plcg_sweep_kernel<{args.headline}, 2D>",
+            "kernel_us": hr["kernel_us"],
+            "bytes_per_launch": bytes_launch,
+        },
+        "methods": rows,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.headline, args.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

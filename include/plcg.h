@@ -1,0 +1,161 @@
+/*
+ * libplcg - deep pipelined Conjugate Gradients, p(l)-CG, and classic CG on one
+ * AMD Instinct MI355X (gfx950), behind a plain C ABI.
+ *
+ * Method: Cools, Cornelis, Ghysels, Vanroose, "Improving strong scaling of the
+ * Conjugate Gradient method for solving large linear systems using global
+ * reduction pipelining" (EuroMPI'19), Alg. 1 with the identity preconditioner.
+ * Each p(l)-CG iteration applies the operator once to the auxiliary basis
+ * vector z^{(l)}_i (shifted by sigma_i during the first l iterations), updates
+ * the l+1 bases Z^{(0..l)} with three-term recurrences (Eqs. all_z_rec2 and
+ * specific_z_rec), updates the search direction p and the iterate x
+ * (Eqs. pdir, x_a2), and starts the l+1 dot products that form column i+1 of
+ * the banded basis transformation G (Sec. 2.2, "Number of dot products").  The
+ * dot products of iteration i are consumed l iterations later.
+ *
+ * Conventions shared by every call:
+ *  - Vectors are contiguous float64 arrays in device memory, 16-byte aligned,
+ *    indexed row-major with x fastest (index = x + nx*(y + ny*z)).  Values
+ *    outside the grid are zero (homogeneous Dirichlet boundary eliminated).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work of a call is enqueued on that stream.
+ *  - The library allocates its own workspace at plcg_create and frees it at
+ *    plcg_destroy.  Caller buffers are never retained after a call returns
+ *    (plcg_submit: until plcg_poll reports completion).
+ *  - Errors are returned as negative plcg_status codes; plcg_last_error()
+ *    gives a message for the calling thread.  Nothing aborts the process.
+ */
+#ifndef PLCG_H
+#define PLCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct plcg_handle plcg_handle;
+typedef int32_t plcg_status;
+
+enum {
+  PLCG_OK = 0,
+  PLCG_NOT_READY = 1,      /* plcg_poll: the solve is still running */
+  PLCG_E_INVALID = -1,     /* bad argument: NULL pointer, size, l, alignment */
+  PLCG_E_NOMEM = -2,       /* device or pinned-host allocation failed */
+  PLCG_E_HIP = -3,         /* a HIP runtime call failed (message has the code) */
+  PLCG_E_BUSY = -4,        /* the handle already has a solve in flight */
+  PLCG_E_NONFINITE = -5    /* the initial residual is not finite (NaN/Inf in b or x0) */
+};
+
+/* Operator kinds: unscaled integer Dirichlet Laplacians (spectrum inside (0, 8)
+ * in 2D and (0, 12) in 3D). */
+enum {
+  PLCG_OP_STENCIL2D5 = 1,  /* (Au) = 4u - u(x-1) - u(x+1) - u(y-1) - u(y+1) */
+  PLCG_OP_STENCIL3D7 = 2   /* (Au) = 6u - sum of the six face neighbours    */
+};
+
+enum { PLCG_METHOD_CG = 0, PLCG_METHOD_PLCG = 1 };
+
+enum {
+  PLCG_REASON_NONE = 0,
+  PLCG_REASON_CONVERGED = 1,        /* recursive residual below tol            */
+  PLCG_REASON_MAXIT = 2,            /* maxit x-updates made                    */
+  PLCG_REASON_BREAKDOWN_LIMIT = 3,  /* more than max_restarts restarts needed  */
+  PLCG_REASON_NONFINITE = 4,        /* initial residual not finite             */
+  PLCG_REASON_BREAKDOWN = 5         /* CG only: (p, Ap) <= 0, operator not SPD */
+};
+
+typedef struct {
+  int32_t kind;           /* PLCG_OP_* */
+  int32_t nx, ny, nz;     /* grid extents, each >= 1; nz ignored for 2D (use 1) */
+} plcg_operator_desc;
+
+typedef struct {
+  int32_t method;         /* PLCG_METHOD_CG or PLCG_METHOD_PLCG */
+  int32_t l;              /* pipeline length, 1..8 (ignored for CG) */
+  double lambda_min;      /* Chebyshev interval of Eq. (chebyshev), Sec. 2.2 */
+  double lambda_max;
+  const double *shifts;   /* host array of l shifts, or NULL for Chebyshev shifts */
+  int32_t check_every;    /* iterations per host status check; <= 0: default 64 */
+  int32_t max_restarts;   /* restarts after square-root breakdown; < 0: default 100 */
+  int32_t history_cap;    /* keep gamma_t, delta_t, eta_t, zeta_t for t < cap (0: off) */
+} plcg_config;
+
+typedef struct {
+  int32_t iters;          /* x updates (t of Alg. 1, summed over restarts) */
+  int32_t spmvs;          /* operator applications, including residuals */
+  int32_t restarts;       /* explicit restarts after breakdown (Sec. 2.2) */
+  int32_t reason;         /* PLCG_REASON_* */
+  double rnorm0;          /* ||b - A x0|| of the caller's x0 */
+  double rec_relres;      /* |zeta_t| / rnorm0 (CG: recursive ||r|| / rnorm0) */
+  double true_relres;     /* ||b - A x|| / rnorm0, recomputed in FP64 at the end */
+  double seconds;         /* host wall time of the call */
+  double sweep_ms;        /* with timing enabled: summed duration of the per-iteration kernels */
+  int64_t sweeps;         /* with timing enabled: number of per-iteration kernels timed */
+} plcg_result;
+
+/* Create a solver for one operator and one configuration.
+ * Validates the descriptor (extents >= 1, nx*ny*nz < 2^31) and the config
+ * (l in 1..8, lambda_min < lambda_max unless explicit shifts are given),
+ * computes the shifts (Eq. chebyshev, i = 0..l-1, so sigma_0 is the largest)
+ * and allocates all device workspace on the current HIP device.
+ * Returns PLCG_E_INVALID / PLCG_E_NOMEM / PLCG_E_HIP on failure (*out = NULL). */
+plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg,
+                        plcg_handle **out);
+
+/* Solve A x = b.  d_b: n doubles (read only).  d_x: n doubles, holds x0 on entry
+ * and the final iterate on return.  Stops when the recursive residual norm
+ * |zeta_t| (Alg. 1) falls below tol * ||b - A x0||, after maxit x-updates, or
+ * after max_restarts explicit restarts (restart = Alg. 1 from the latest
+ * iterate).  Blocks the host until the result is known.  Iteration counts,
+ * residuals and the stop reason are written to *out (may be NULL). */
+plcg_status plcg_solve(plcg_handle *h, const double *d_b, double *d_x, double tol,
+                       int32_t maxit, void *stream, plcg_result *out);
+
+/* Same as plcg_solve, but returns at once: a host worker thread drives the
+ * solve.  The handle accepts one solve at a time (PLCG_E_BUSY otherwise);
+ * d_b and d_x must stay valid until plcg_poll returns PLCG_OK for *ticket. */
+plcg_status plcg_submit(plcg_handle *h, const double *d_b, double *d_x, double tol,
+                        int32_t maxit, void *stream, uint64_t *ticket);
+
+/* PLCG_NOT_READY while the solve of `ticket` runs; PLCG_OK (result in *out)
+ * or the solve's error status once it has finished; PLCG_E_INVALID for an
+ * unknown ticket. */
+plcg_status plcg_poll(plcg_handle *h, uint64_t ticket, plcg_result *out);
+
+/* Release the handle and its workspace (waits for a submitted solve). */
+plcg_status plcg_destroy(plcg_handle *h);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *plcg_last_error(void);
+
+/* y = A x with the handle's operator (d_x, d_y: n doubles, distinct). */
+plcg_status plcg_apply(plcg_handle *h, const double *d_x, double *d_y, void *stream);
+
+/* Number of unknowns n of the handle's operator. */
+int64_t plcg_size(const plcg_handle *h);
+
+/* The l shifts the handle uses (host array of >= l doubles). */
+plcg_status plcg_get_shifts(const plcg_handle *h, double *out);
+
+/* Diagnostics of the last solve's last restart segment: rows t = 0..count-1
+ * of (gamma_t, delta_t, eta_t, zeta_t), 4 doubles per row, as computed on the
+ * device (needs history_cap > 0 at create). */
+plcg_status plcg_get_history(const plcg_handle *h, double *out, int32_t cap, int32_t *count);
+
+/* Enable (1) or disable (0) per-kernel timing of the iteration kernels with
+ * HIP events; reported in plcg_result.sweep_ms / sweeps. */
+plcg_status plcg_set_timing(plcg_handle *h, int32_t enable);
+
+/* Measurement aid: dst[i] = src[i], i < n, with a plain streaming kernel
+ * (calibrates hardware byte counters against a known traffic volume). */
+plcg_status plcg_copy(const double *d_src, double *d_dst, int64_t n, void *stream);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t plcg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLCG_H */

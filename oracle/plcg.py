@@ -171,19 +171,19 @@ def basis_updates(z, gam, dlt, sigma, t, l, i):
     z[l][i + 1] = new / dlt[t]
 
 
-def start_dots(G, z, i, l, dots):
+def start_dots(G, z, i, l, dots, dot=np.dot):
     """Dot products that start column i+1 of G (Alg. 1, 'initiate dot-products')."""
     u = z[l][i + 1]
     c = i + 1
     if dots == "full":
         for j in range(max(0, i - 2 * l + 1), i - l + 2):
-            G[j, c] = np.dot(u, z[0][j])
+            G[j, c] = dot(u, z[0][j])
     else:
         j = i - l + 1
         if j >= 0:
-            G[j, c] = np.dot(u, z[0][j])
+            G[j, c] = dot(u, z[0][j])
     for j in range(max(0, i - l + 2), i + 2):
-        G[j, c] = np.dot(u, z[l][j])
+        G[j, c] = dot(u, z[l][j])
     return 2 * l + 1 if dots == "full" else l + 1
 
 
@@ -200,11 +200,15 @@ class Segment:
     diag: dict
 
 
-def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False):
+def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=np.dot):
     """One run of Alg. 1 (no restart) with M = I, from x0, at most m x-updates.
 
+    ``dot`` is the inner product (default numpy's); tests pass a correctly
+    rounded one to measure how much the results depend on summation order.
+
     Stops when |zeta_t| < abs_tol.  Returns a Segment; ``diag`` holds G, gamma,
-    delta, eta, zeta, the bases and the search directions when keep_all is set.
+    delta, eta, lambda, zeta, and also the bases and the search directions when
+    keep_all is set.
     """
     if dots not in ("full", "symmetric"):
         raise ValueError(dots)
@@ -214,7 +218,7 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False):
     x = x0.copy()
     u0 = b - A(x)                              # line 1: u_0 = b - A x_0, r_0 = u_0 (M = I)
     spmvs = 1
-    beta = _sqrt(np.dot(u0, u0))               # sqrt((u_0, r_0))
+    beta = _sqrt(dot(u0, u0))                  # sqrt((u_0, r_0))
     if beta == 0 or abs_tol >= beta:
         return Segment(x, 0, "converged", -1, beta, beta, spmvs, [], {})
     if not _finite(beta):
@@ -257,7 +261,7 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False):
                 bt = e.t
                 break
             basis_updates(z, gam, dlt, sigma, t, l, i)   # K4
-        dots_per_iter.append(start_dots(G, z, i, l, dots))   # K5
+        dots_per_iter.append(start_dots(G, z, i, l, dots, dot))   # K5
         # K6: search direction and iterate
         if i == l:
             p = z[0][0] / eta[0]
@@ -276,9 +280,9 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False):
             _forget(z, i, l, dots)
             P.clear()
     zeta_last = abs(zeta[t_done]) if t_done in zeta else beta
-    diag = {}
+    diag = dict(G=G, gam=gam, dlt=dlt, eta=eta, lam=lam, zeta=zeta)
     if keep_all:
-        diag = dict(G=G, gam=gam, dlt=dlt, eta=eta, lam=lam, zeta=zeta, z=z, P=P)
+        diag.update(z=z, P=P)
     return Segment(x, t_done, reason, bt, beta, zeta_last, spmvs, dots_per_iter, diag)
 
 

@@ -1,0 +1,640 @@
+// Host engine and C ABI of libplcg.
+//
+// The engine enqueues one fused sweep kernel per p(l)-CG iteration (two per CG
+// iteration) on the caller's stream, with the buffer roles of the ring of
+// basis vectors decided here on the host.  The device writes its progress
+// (status, last usable t, residual norms) into mapped pinned host memory; the
+// host looks at it after each group of `check_every` iterations, keeping at
+// most two groups in flight, and stops enqueueing once the device reports
+// convergence or breakdown.  Sweeps enqueued past the stop see the status and
+// return at once.  A breakdown (Sec. 2.2, "Square root breakdowns") restarts
+// Alg. 1 from the most recent iterate with a recomputed residual, keeping the
+// original reference norm of the stopping test.
+#include "plcg_internal.h"
+
+#include "../../include/plcg.h"
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+using namespace plcg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+plcg_status fail(plcg_status code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define PLCG_HIP(call)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(PLCG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr int kMaxBlocks = 2048;   // 8 per CU on 256 CUs; every grid is a multiple of 8
+constexpr int kDefaultCheck = 64;
+constexpr int kDefaultRestarts = 100;
+
+int grid_blocks(int nchunks) {
+  int b = ((nchunks + kXcds - 1) / kXcds) * kXcds;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  if (b < kXcds) b = kXcds;
+  return b;
+}
+
+}  // namespace
+
+struct plcg_handle {
+  plcg_operator_desc op{};
+  int method = PLCG_METHOD_PLCG;
+  int l = 1;
+  int R = 2;                      // ring slots of the basis Z^{(l)}
+  double sigma[kLMax] = {0};
+  int check_every = kDefaultCheck;
+  int max_restarts = kDefaultRestarts;
+  int hist_cap = 0;
+  int n = 0, nchunks = 0, blocks = 0;
+  bool d3 = false;
+  int device = 0;
+  // device buffers
+  std::vector<void *> allocs;
+  double *basis[kLMax][2] = {};   // basis k < l, slots by index parity
+  double *ring[kLMax] = {};       // basis l, slot of z^{(l)}_j is j % R
+  double *p = nullptr;
+  double *cg_r = nullptr, *cg_p[2] = {nullptr, nullptr}, *cg_q = nullptr;
+  double *partials = nullptr;
+  int32_t *ticket = nullptr;
+  DevState *st = nullptr;
+  double *hist = nullptr;
+  HostStatus *hs_host = nullptr;  // pinned, mapped
+  HostStatus *hs_dev = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+  // asynchronous solves
+  std::mutex mu;
+  std::thread worker;
+  std::atomic<bool> busy{false};
+  uint64_t next_ticket = 1, cur_ticket = 0;
+  plcg_status async_status = PLCG_OK;
+  plcg_result async_result{};
+  int last_hist_count = 0;
+};
+
+namespace {
+
+plcg_status dev_alloc(plcg_handle *h, void **ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(PLCG_E_NOMEM, std::string("hipMalloc(") + std::to_string(bytes) +
+                                  " bytes): " + hipGetErrorString(e));
+  }
+  h->allocs.push_back(*ptr);
+  return PLCG_OK;
+}
+
+void release(plcg_handle *h) {
+  for (void *p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  if (h->hs_host) (void)hipHostFree(h->hs_host);
+  h->hs_host = nullptr;
+  for (hipEvent_t e : h->tev) (void)hipEventDestroy(e);
+  h->tev.clear();
+  for (auto &e : h->chunk_ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+volatile HostStatus *hstat(plcg_handle *h) { return h->hs_host; }
+
+// Keep at most two groups of iterations in flight; returns the device status.
+plcg_status throttle(plcg_handle *h, hipStream_t s, int group, int *status) {
+  PLCG_HIP(hipEventRecord(h->chunk_ev[group & 1], s));
+  if (group >= 1) PLCG_HIP(hipEventSynchronize(h->chunk_ev[(group - 1) & 1]));
+  *status = hstat(h)->status;
+  return PLCG_OK;
+}
+
+struct TimedLaunch {
+  plcg_handle *h;
+  hipStream_t s;
+  size_t used = 0;
+  plcg_status begin() {
+    if (!h->timing) return PLCG_OK;
+    while (h->tev.size() < used + 2) {
+      hipEvent_t e;
+      PLCG_HIP(hipEventCreate(&e));
+      h->tev.push_back(e);
+    }
+    PLCG_HIP(hipEventRecord(h->tev[used], s));
+    return PLCG_OK;
+  }
+  plcg_status end() {
+    if (!h->timing) return PLCG_OK;
+    PLCG_HIP(hipEventRecord(h->tev[used + 1], s));
+    used += 2;
+    return PLCG_OK;
+  }
+  plcg_status total(double *ms) {
+    *ms = 0.0;
+    for (size_t k = 0; k < used; k += 2) {
+      float e = 0.f;
+      PLCG_HIP(hipEventElapsedTime(&e, h->tev[k], h->tev[k + 1]));
+      *ms += e;
+    }
+    return PLCG_OK;
+  }
+};
+
+// Pointers of iteration i: ring roles, basis roles, start-up copies.
+void sweep_args(plcg_handle *h, int i, double *x, SweepArgs &a) {
+  std::memset(&a, 0, sizeof(a));
+  const int l = h->l, R = h->R;
+  const int t = i - l;
+  for (int k = 0; k < R; ++k) {
+    const int j = i - k;
+    a.zl[k] = j >= 0 ? h->ring[j % R] : nullptr;
+  }
+  a.zl_out = h->ring[(i + 1) % R];
+  if (t >= 0) {
+    for (int k = 0; k < l; ++k) {
+      a.zk_cur[k] = h->basis[k][(t + k) & 1];
+      a.zk_prev[k] = h->basis[k][(t + k + 1) & 1];
+    }
+  }
+  a.copy_dst = (i < l - 1) ? h->basis[i + 1][(i + 1) & 1] : nullptr;
+  a.v0 = (i == l - 1) ? h->basis[0][0] : nullptr;
+  a.p = h->p;
+  a.x = x;
+  a.partials = h->partials;
+  a.ticket = h->ticket;
+  a.st = h->st;
+  a.hs = h->hs_dev;
+  a.hist = h->hist;
+  a.i = i;
+  a.l = l;
+  a.n = h->n;
+  a.nx = h->op.nx;
+  a.ny = h->op.ny;
+  a.nz = h->op.nz;
+  a.d3 = h->d3 ? 1 : 0;
+  a.nchunks = h->nchunks;
+  a.max_blocks = kMaxBlocks;
+}
+
+plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r, int mode,
+                     double tol, double rref_in, hipStream_t s) {
+  PLCG_HIP(launch_residual(b, x, r, h->partials, h->ticket, h->st, h->hs_dev, mode, tol, rref_in,
+                           h->n, h->op.nx, h->op.ny, h->op.nz, h->d3, h->nchunks, h->blocks,
+                           kMaxBlocks, s));
+  return PLCG_OK;
+}
+
+plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, int maxit,
+                       hipStream_t s, plcg_result *res, TimedLaunch &tl) {
+  const int l = h->l;
+  int total = 0, restarts = 0;
+  int64_t spmvs = 0;
+  double rref = -1.0;
+  int reason = PLCG_REASON_NONE;
+  double rec = 0.0;
+  h->last_hist_count = 0;
+  while (true) {
+    // Alg. 1, first line: u_0 = b - A x_0; z^{(k)}_0 = u_0 / ||u_0||; g_00 = 1.
+    plcg_status e = residual(h, b, x, h->ring[0], 0, tol, rref, s);
+    if (e != PLCG_OK) return e;
+    PLCG_HIP(launch_scale(h->ring[0], h->ring[0], h->basis[0][0], nullptr, h->st, h->n,
+                          h->blocks, s));
+    PLCG_HIP(hipStreamSynchronize(s));
+    spmvs += 1;
+    const int st0 = hstat(h)->status;
+    if (rref < 0) {
+      rref = hstat(h)->rref;
+      res->rnorm0 = rref;
+    }
+    if (st0 == kNonFinite) {
+      res->reason = PLCG_REASON_NONFINITE;
+      return fail(PLCG_E_NONFINITE, "initial residual is not finite");
+    }
+    if (st0 == kConverged) {
+      reason = PLCG_REASON_CONVERGED;
+      rec = hstat(h)->beta;
+      break;
+    }
+    const int m = maxit - total;          // x-updates allowed in this segment
+    const int imax = m + l;               // Alg. 1 loop: i = 0 .. m + l
+    int status = kRunning;
+    int group = 0;
+    for (int i0 = 0; i0 <= imax; i0 += h->check_every, ++group) {
+      const int i1 = std::min(imax + 1, i0 + h->check_every);
+      for (int i = i0; i < i1; ++i) {
+        SweepArgs a;
+        sweep_args(h, i, x, a);
+        if ((e = tl.begin()) != PLCG_OK) return e;
+        PLCG_HIP(launch_plcg_sweep(a, h->blocks, s));
+        if ((e = tl.end()) != PLCG_OK) return e;
+      }
+      if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
+      if (status != kRunning) break;
+    }
+    PLCG_HIP(hipStreamSynchronize(s));
+    status = hstat(h)->status;
+    const int last_t = hstat(h)->last_t;
+    // Iterations that ran: every sweep up to last_t + l (or the whole loop).
+    int t_done;
+    if (status == kRunning) {
+      t_done = m;
+    } else {
+      t_done = std::min(std::max(last_t, 0), m);
+    }
+    spmvs += std::min(imax, (status == kRunning ? imax : last_t + l)) + 1;
+    total += t_done;
+    {
+      DevState ds;
+      PLCG_HIP(hipMemcpy(&ds, h->st, sizeof(ds), hipMemcpyDeviceToHost));
+      rec = t_done == 0 ? ds.beta : std::fabs(ds.zeta[t_done % kTRing]);
+      h->last_hist_count = std::min(h->hist_cap, ds.cols);
+    }
+    if (status == kConverged && last_t <= m) {
+      reason = PLCG_REASON_CONVERGED;
+      break;
+    }
+    if (status == kBroken && last_t < m) {
+      ++restarts;
+      if (restarts > h->max_restarts) {
+        reason = PLCG_REASON_BREAKDOWN_LIMIT;
+        break;
+      }
+      if (total >= maxit) {
+        reason = PLCG_REASON_MAXIT;
+        break;
+      }
+      continue;
+    }
+    reason = PLCG_REASON_MAXIT;
+    break;
+  }
+  res->iters = total;
+  res->restarts = restarts;
+  res->reason = reason;
+  res->spmvs = (int32_t)spmvs;
+  res->rec_relres = rref > 0 ? rec / rref : 0.0;
+  return PLCG_OK;
+}
+
+plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int maxit,
+                     hipStream_t s, plcg_result *res, TimedLaunch &tl) {
+  plcg_status e = residual(h, b, x, h->cg_r, 1, tol, -1.0, s);
+  if (e != PLCG_OK) return e;
+  PLCG_HIP(hipStreamSynchronize(s));
+  const double rref = hstat(h)->rref;
+  res->rnorm0 = rref;
+  int status = hstat(h)->status;
+  if (status == kNonFinite) {
+    res->reason = PLCG_REASON_NONFINITE;
+    return fail(PLCG_E_NONFINITE, "initial residual is not finite");
+  }
+  int64_t spmvs = 1;
+  if (status == kConverged) {
+    res->iters = 0;
+    res->reason = PLCG_REASON_CONVERGED;
+    res->rec_relres = rref > 0 ? hstat(h)->beta / rref : 0.0;
+    res->spmvs = 1;
+    return PLCG_OK;
+  }
+  CgArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.b = b;
+  a.x = x;
+  a.r = h->cg_r;
+  a.q = h->cg_q;
+  a.partials = h->partials;
+  a.ticket = h->ticket;
+  a.st = h->st;
+  a.hs = h->hs_dev;
+  a.n = h->n;
+  a.nx = h->op.nx;
+  a.ny = h->op.ny;
+  a.nz = h->op.nz;
+  a.d3 = h->d3 ? 1 : 0;
+  a.nchunks = h->nchunks;
+  a.max_blocks = kMaxBlocks;
+  int group = 0;
+  for (int k0 = 0; k0 < maxit; k0 += h->check_every, ++group) {
+    const int k1 = std::min(maxit, k0 + h->check_every);
+    for (int k = k0; k < k1; ++k) {
+      a.k = k;
+      a.p_new = h->cg_p[k & 1];
+      a.p_old = h->cg_p[(k + 1) & 1];
+      if ((e = tl.begin()) != PLCG_OK) return e;
+      PLCG_HIP(launch_cg_sweep_a(a, h->blocks, s));
+      if ((e = tl.end()) != PLCG_OK) return e;
+      if ((e = tl.begin()) != PLCG_OK) return e;
+      PLCG_HIP(launch_cg_sweep_b(a, h->blocks, s));
+      if ((e = tl.end()) != PLCG_OK) return e;
+    }
+    if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
+    if (status != kRunning) break;
+  }
+  PLCG_HIP(hipStreamSynchronize(s));
+  status = hstat(h)->status;
+  const int iters = status == kRunning ? maxit : hstat(h)->last_t;
+  res->iters = iters;
+  res->spmvs = (int32_t)(spmvs + iters);
+  res->rec_relres = rref > 0 ? hstat(h)->zeta / rref : 0.0;
+  res->reason = status == kConverged  ? PLCG_REASON_CONVERGED
+                : status == kCgBreak ? PLCG_REASON_BREAKDOWN
+                                     : PLCG_REASON_MAXIT;
+  return PLCG_OK;
+}
+
+plcg_status check_vectors(const plcg_handle *h, const double *b, const double *x) {
+  if (b == nullptr || x == nullptr) return fail(PLCG_E_INVALID, "NULL vector");
+  if ((reinterpret_cast<uintptr_t>(b) & 15) || (reinterpret_cast<uintptr_t>(x) & 15))
+    return fail(PLCG_E_INVALID, "vectors must be 16-byte aligned");
+  if (b == x) return fail(PLCG_E_INVALID, "b and x must be distinct buffers");
+  (void)h;
+  return PLCG_OK;
+}
+
+plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int32_t maxit,
+                     void *stream, plcg_result *out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  plcg_result res{};
+  plcg_status e = check_vectors(h, b, x);
+  if (e != PLCG_OK) return e;
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(PLCG_E_INVALID, "tol must be > 0");
+  if (maxit < 0) return fail(PLCG_E_INVALID, "maxit must be >= 0");
+  PLCG_HIP(hipSetDevice(h->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TimedLaunch tl{h, s};
+  if (h->method == PLCG_METHOD_CG)
+    e = solve_cg(h, b, x, tol, maxit, s, &res, tl);
+  else
+    e = solve_plcg(h, b, x, tol, maxit, s, &res, tl);
+  if (e != PLCG_OK) {
+    if (out) *out = res;
+    return e;
+  }
+  // True residual ||b - A x|| in FP64 (one more operator application).
+  if ((e = residual(h, b, x, nullptr, 2, tol, -1.0, s)) != PLCG_OK) return e;
+  PLCG_HIP(hipStreamSynchronize(s));
+  res.spmvs += 1;
+  res.true_relres = res.rnorm0 > 0 ? std::sqrt(hstat(h)->sumsq) / res.rnorm0 : 0.0;
+  if (h->timing) {
+    double ms = 0;
+    if ((e = tl.total(&ms)) != PLCG_OK) return e;
+    res.sweep_ms = ms;
+    res.sweeps = (int64_t)(tl.used / 2);
+  }
+  res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (out) *out = res;
+  return PLCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *plcg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t plcg_version(void) { return 100; }
+
+plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, plcg_handle **out) {
+  if (out == nullptr) return fail(PLCG_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (op == nullptr || cfg == nullptr) return fail(PLCG_E_INVALID, "NULL descriptor or config");
+  if (op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7)
+    return fail(PLCG_E_INVALID, "unknown operator kind");
+  const int nz = op->kind == PLCG_OP_STENCIL2D5 ? 1 : op->nz;
+  if (op->nx < 1 || op->ny < 1 || nz < 1) return fail(PLCG_E_INVALID, "grid extents must be >= 1");
+  if (op->kind == PLCG_OP_STENCIL2D5 && op->nz > 1)
+    return fail(PLCG_E_INVALID, "2D operator needs nz = 1");
+  const long long n = (long long)op->nx * op->ny * nz;
+  if (n >= (1LL << 31) - 4 * kChunk) return fail(PLCG_E_INVALID, "grid too large (n >= 2^31)");
+  if (cfg->method != PLCG_METHOD_CG && cfg->method != PLCG_METHOD_PLCG)
+    return fail(PLCG_E_INVALID, "unknown method");
+  const bool pl = cfg->method == PLCG_METHOD_PLCG;
+  if (pl && (cfg->l < 1 || cfg->l > kLMax)) return fail(PLCG_E_INVALID, "l must be in 1..8");
+  if (pl && cfg->shifts == nullptr &&
+      !(cfg->lambda_max > cfg->lambda_min && std::isfinite(cfg->lambda_min) &&
+        std::isfinite(cfg->lambda_max)))
+    return fail(PLCG_E_INVALID, "need lambda_min < lambda_max (or explicit shifts)");
+  if (cfg->history_cap < 0) return fail(PLCG_E_INVALID, "history_cap must be >= 0");
+
+  hipError_t he;
+  int dev = 0;
+  if ((he = hipGetDevice(&dev)) != hipSuccess)
+    return fail(PLCG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+
+  plcg_handle *h = new plcg_handle();
+  h->op = *op;
+  h->op.nz = nz;
+  h->d3 = op->kind == PLCG_OP_STENCIL3D7;
+  h->device = dev;
+  h->method = cfg->method;
+  h->l = pl ? cfg->l : 1;
+  h->R = h->l - 1 > 2 ? h->l - 1 : 2;
+  h->check_every = cfg->check_every > 0 ? cfg->check_every : kDefaultCheck;
+  h->max_restarts = cfg->max_restarts >= 0 ? cfg->max_restarts : kDefaultRestarts;
+  h->hist_cap = cfg->history_cap;
+  h->n = (int)n;
+  h->nchunks = (int)((n + kChunk - 1) / kChunk);
+  h->blocks = grid_blocks(h->nchunks);
+  if (pl) {
+    // Eq. (chebyshev): sigma_i = (lmax + lmin)/2 + (lmax - lmin)/2 cos((2i+1) pi / (2l)).
+    for (int i = 0; i < h->l; ++i) {
+      if (cfg->shifts) {
+        h->sigma[i] = cfg->shifts[i];
+      } else {
+        const double mid = 0.5 * (cfg->lambda_max + cfg->lambda_min);
+        const double half = 0.5 * (cfg->lambda_max - cfg->lambda_min);
+        h->sigma[i] = mid + half * std::cos((2 * i + 1) * M_PI / (2 * h->l));
+      }
+      if (!std::isfinite(h->sigma[i])) {
+        delete h;
+        return fail(PLCG_E_INVALID, "shifts must be finite");
+      }
+    }
+  }
+
+  const size_t vb = (size_t)n * sizeof(double);
+  plcg_status e = PLCG_OK;
+  auto vec = [&](double **dst) {
+    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(dst), vb);
+  };
+  if (pl) {
+    for (int k = 0; k < h->l; ++k) {
+      vec(&h->basis[k][0]);
+      vec(&h->basis[k][1]);
+    }
+    for (int k = 0; k < h->R; ++k) vec(&h->ring[k]);
+    vec(&h->p);
+  } else {
+    vec(&h->cg_r);
+    vec(&h->cg_p[0]);
+    vec(&h->cg_p[1]);
+    vec(&h->cg_q);
+  }
+  if (e == PLCG_OK)
+    e = dev_alloc(h, reinterpret_cast<void **>(&h->partials),
+                  sizeof(double) * (kLMax + 1) * kMaxBlocks);
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->ticket), 256);
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->st), sizeof(DevState));
+  if (e == PLCG_OK && h->hist_cap > 0)
+    e = dev_alloc(h, reinterpret_cast<void **>(&h->hist), sizeof(double) * 4 * h->hist_cap);
+  if (e != PLCG_OK) {
+    release(h);
+    delete h;
+    return e;
+  }
+  if ((he = hipHostMalloc(reinterpret_cast<void **>(&h->hs_host), sizeof(HostStatus),
+                          hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess) {
+    release(h);
+    delete h;
+    return fail(PLCG_E_NOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(he));
+  }
+  std::memset(h->hs_host, 0, sizeof(HostStatus));
+  void *dptr = nullptr;
+  if ((he = hipHostGetDevicePointer(&dptr, h->hs_host, 0)) != hipSuccess) {
+    release(h);
+    delete h;
+    return fail(PLCG_E_HIP, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(he));
+  }
+  h->hs_dev = reinterpret_cast<HostStatus *>(dptr);
+  DevState init;
+  std::memset(&init, 0, sizeof(init));
+  init.l = h->l;
+  init.hist_cap = h->hist_cap;
+  for (int k = 0; k < kLMax; ++k) init.sigma[k] = h->sigma[k];
+  bool ok = hipMemcpy(h->st, &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemset(h->ticket, 0, 256) == hipSuccess &&
+            hipEventCreateWithFlags(&h->chunk_ev[0], hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&h->chunk_ev[1], hipEventDisableTiming) == hipSuccess &&
+            hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    release(h);
+    delete h;
+    return fail(PLCG_E_HIP, "initialising device state failed");
+  }
+  *out = h;
+  return PLCG_OK;
+}
+
+plcg_status plcg_solve(plcg_handle *h, const double *d_b, double *d_x, double tol, int32_t maxit,
+                       void *stream, plcg_result *out) {
+  if (h == nullptr) return fail(PLCG_E_INVALID, "NULL handle");
+  bool expected = false;
+  if (!h->busy.compare_exchange_strong(expected, true))
+    return fail(PLCG_E_BUSY, "a solve is already in flight on this handle");
+  plcg_status e = do_solve(h, d_b, d_x, tol, maxit, stream, out);
+  h->busy = false;
+  return e;
+}
+
+plcg_status plcg_submit(plcg_handle *h, const double *d_b, double *d_x, double tol,
+                        int32_t maxit, void *stream, uint64_t *ticket) {
+  if (h == nullptr || ticket == nullptr) return fail(PLCG_E_INVALID, "NULL handle or ticket");
+  bool expected = false;
+  if (!h->busy.compare_exchange_strong(expected, true))
+    return fail(PLCG_E_BUSY, "a solve is already in flight on this handle");
+  plcg_status e = check_vectors(h, d_b, d_x);
+  if (e != PLCG_OK) {
+    h->busy = false;
+    return e;
+  }
+  std::lock_guard<std::mutex> lk(h->mu);
+  if (h->worker.joinable()) h->worker.join();
+  h->cur_ticket = h->next_ticket++;
+  *ticket = h->cur_ticket;
+  h->worker = std::thread([h, d_b, d_x, tol, maxit, stream]() {
+    plcg_result r{};
+    plcg_status st = do_solve(h, d_b, d_x, tol, maxit, stream, &r);
+    h->async_result = r;
+    h->async_status = st;
+    h->busy = false;
+  });
+  return PLCG_OK;
+}
+
+plcg_status plcg_poll(plcg_handle *h, uint64_t ticket, plcg_result *out) {
+  if (h == nullptr) return fail(PLCG_E_INVALID, "NULL handle");
+  std::lock_guard<std::mutex> lk(h->mu);
+  if (ticket == 0 || ticket != h->cur_ticket) return fail(PLCG_E_INVALID, "unknown ticket");
+  if (h->busy) return PLCG_NOT_READY;
+  if (h->worker.joinable()) h->worker.join();
+  if (out) *out = h->async_result;
+  if (h->async_status != PLCG_OK) return fail(h->async_status, "submitted solve failed");
+  return PLCG_OK;
+}
+
+plcg_status plcg_destroy(plcg_handle *h) {
+  if (h == nullptr) return PLCG_OK;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->worker.joinable()) h->worker.join();
+  }
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  release(h);
+  delete h;
+  return PLCG_OK;
+}
+
+plcg_status plcg_apply(plcg_handle *h, const double *d_x, double *d_y, void *stream) {
+  if (h == nullptr || d_x == nullptr || d_y == nullptr)
+    return fail(PLCG_E_INVALID, "NULL argument");
+  if (d_x == d_y) return fail(PLCG_E_INVALID, "x and y must be distinct");
+  int blocks = (h->n + kThreads - 1) / kThreads;
+  if (blocks > 8192) blocks = 8192;
+  PLCG_HIP(launch_apply(d_x, d_y, h->n, h->op.nx, h->op.ny, h->op.nz, h->d3, blocks,
+                        reinterpret_cast<hipStream_t>(stream)));
+  return PLCG_OK;
+}
+
+int64_t plcg_size(const plcg_handle *h) { return h ? (int64_t)h->n : -1; }
+
+plcg_status plcg_get_shifts(const plcg_handle *h, double *out) {
+  if (h == nullptr || out == nullptr) return fail(PLCG_E_INVALID, "NULL argument");
+  for (int k = 0; k < h->l; ++k) out[k] = h->sigma[k];
+  return PLCG_OK;
+}
+
+plcg_status plcg_get_history(const plcg_handle *h, double *out, int32_t cap, int32_t *count) {
+  if (h == nullptr || out == nullptr || count == nullptr)
+    return fail(PLCG_E_INVALID, "NULL argument");
+  if (h->hist == nullptr) return fail(PLCG_E_INVALID, "history not enabled (history_cap = 0)");
+  const int c = std::min(cap, h->last_hist_count);
+  if (c > 0) PLCG_HIP(hipMemcpy(out, h->hist, sizeof(double) * 4 * c, hipMemcpyDeviceToHost));
+  *count = c;
+  return PLCG_OK;
+}
+
+plcg_status plcg_set_timing(plcg_handle *h, int32_t enable) {
+  if (h == nullptr) return fail(PLCG_E_INVALID, "NULL handle");
+  h->timing = enable != 0;
+  return PLCG_OK;
+}
+
+plcg_status plcg_copy(const double *d_src, double *d_dst, int64_t n, void *stream) {
+  if (d_src == nullptr || d_dst == nullptr || n < 0) return fail(PLCG_E_INVALID, "bad argument");
+  if ((reinterpret_cast<uintptr_t>(d_src) & 15) || (reinterpret_cast<uintptr_t>(d_dst) & 15))
+    return fail(PLCG_E_INVALID, "buffers must be 16-byte aligned");
+  if (n == 0) return PLCG_OK;
+  PLCG_HIP(launch_copy(d_src, d_dst, n, reinterpret_cast<hipStream_t>(stream)));
+  return PLCG_OK;
+}
+
+}  // extern "C"

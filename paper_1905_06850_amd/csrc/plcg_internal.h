@@ -1,0 +1,98 @@
+// Internal layout shared by the HIP kernels and the host engine of libplcg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace plcg {
+
+constexpr int kLMax = 8;            // largest pipeline length
+constexpr int kBand = 2 * kLMax + 1;  // stored rows per column of G (rows c-2l .. c)
+constexpr int kGRing = 16;          // columns of G kept (>= l+1 are read)
+constexpr int kTRing = 16;          // entries of gamma/delta/eta/zeta kept (>= l+1 are read)
+constexpr int kThreads = 256;       // threads per block of every streaming kernel
+constexpr int kVec = 2;             // consecutive unknowns per thread and chunk
+constexpr int kChunk = kThreads * kVec;
+constexpr int kXcds = 8;            // MI355X: workgroups are dealt round-robin to 8 XCDs
+
+enum Status : int32_t { kRunning = 0, kConverged = 1, kBroken = 2, kNonFinite = 3, kCgBreak = 4 };
+
+// Host-visible progress record, written by the device into pinned host memory
+// (mapped) whenever the scalar engine changes it.
+struct HostStatus {
+  int32_t status;     // Status
+  int32_t last_t;     // last index t whose x_t is (or will be) formed; -1: none
+  int32_t cols;       // columns of G finalised (p(l)) or CG iterations completed
+  int32_t pad;
+  double zeta;        // |zeta_t| of the last finalised t (CG: ||r||)
+  double beta;        // ||r_0|| of the current segment
+  double rref;        // reference norm of the stopping test (caller's ||b - A x0||)
+  double sumsq;       // result of the last plain reduction (residual norms)
+};
+
+// Device-resident scalar state of one solve segment.  Only the last block of a
+// kernel (after the atomic ticket) writes it.
+struct DevState {
+  double g[kGRing][kBand];   // column c of G at g[c % kGRing][r - c + 2*kLMax], r in [c-2l, c]
+  double gam[kTRing], dlt[kTRing], eta[kTRing], zeta[kTRing];
+  double sigma[kLMax];
+  double beta;               // ||r_0|| of this segment (Alg. 1: sqrt((u_0, r_0)))
+  double rref;               // reference norm for the stopping test
+  double abs_tol;            // tol * rref
+  double cg_rho, cg_alpha, cg_beta;
+  double sumsq;
+  int32_t l;
+  int32_t status;
+  int32_t last_t;
+  int32_t cols;
+  int32_t hist_cap;
+  int32_t pad[3];
+};
+
+// Arguments of one p(l)-CG sweep (iteration i of Alg. 1).
+struct SweepArgs {
+  const double *zl[kLMax];   // z^{(l)}_{i-h} for h = 0..R-1 (R ring slots; zl[0] = z^{(l)}_i)
+  double *zl_out;            // slot receiving z^{(l)}_{i+1} (the slot of z^{(l)}_{i+1-R})
+  double *zk_cur[kLMax];     // basis k < l: z^{(k)}_{t+k}
+  double *zk_prev[kLMax];    // basis k < l: z^{(k)}_{t+k-1}; overwritten with z^{(k)}_{t+k+1}
+  double *copy_dst;          // i < l-1: basis i+1 slot receiving z^{(l)}_{i+1}; else NULL
+  const double *v0;          // i == l-1: z^{(0)}_0 for the product (u_l, v_0)
+  double *p, *x;
+  double *partials;          // [kLMax+1][max_blocks]
+  int32_t *ticket;
+  DevState *st;
+  HostStatus *hs;            // mapped pinned host memory
+  double *hist;              // [hist_cap][4] or NULL
+  int32_t i, l, n, nx, ny, nz, d3;
+  int32_t nchunks, max_blocks;
+};
+
+struct CgArgs {
+  const double *b;
+  double *x, *r, *p_old, *p_new, *q;
+  double *partials;
+  int32_t *ticket;
+  DevState *st;
+  HostStatus *hs;
+  int32_t k, n, nx, ny, nz, d3, nchunks, max_blocks;
+};
+
+// Launchers (plcg_kernels.hip).
+hipError_t launch_plcg_sweep(const SweepArgs &a, int blocks, hipStream_t s);
+hipError_t launch_cg_sweep_a(const CgArgs &a, int blocks, hipStream_t s);
+hipError_t launch_cg_sweep_b(const CgArgs &a, int blocks, hipStream_t s);
+// r = b - A x; sum of squares finalised into st->sumsq by the last block, which
+// then starts a segment: mode 0 = p(l)-CG (sets G, beta, status), 1 = CG,
+// 2 = only report the sum (true residual).
+hipError_t launch_residual(const double *b, const double *x, double *r, double *partials,
+                           int32_t *ticket, DevState *st, HostStatus *hs, int mode,
+                           double tol, double rref_in, int n, int nx, int ny, int nz, bool d3,
+                           int nchunks, int blocks, int max_blocks, hipStream_t s);
+// z = r / beta written to up to three destinations (beta from st); no-op unless running.
+hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, DevState *st,
+                        int n, int blocks, hipStream_t s);
+hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
+                        int blocks, hipStream_t s);
+hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);
+
+}  // namespace plcg

@@ -1,0 +1,199 @@
+"""ctypes binding of libplcg (argument marshalling only).
+
+Each function has the name and arguments of the C entry point in include/plcg.h;
+device vectors are passed as integer addresses (for a torch tensor on the GPU,
+``t.data_ptr()``) and streams as integer hipStream_t handles (for torch,
+``torch.cuda.current_stream().cuda_stream``).  The ``Solver`` class is a small
+convenience wrapper over the same calls.  All computation happens in the HIP
+library; if it has not been built, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libplcg.so")
+
+PLCG_OK = 0
+PLCG_NOT_READY = 1
+PLCG_E_INVALID = -1
+PLCG_E_NOMEM = -2
+PLCG_E_HIP = -3
+PLCG_E_BUSY = -4
+PLCG_E_NONFINITE = -5
+
+PLCG_OP_STENCIL2D5 = 1
+PLCG_OP_STENCIL3D7 = 2
+PLCG_METHOD_CG = 0
+PLCG_METHOD_PLCG = 1
+
+REASONS = {0: "none", 1: "converged", 2: "maxit", 3: "breakdown_limit", 4: "nonfinite",
+           5: "breakdown"}
+
+
+class plcg_operator_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32)]
+
+
+class plcg_config(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("l", ctypes.c_int32),
+                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("shifts", ctypes.POINTER(ctypes.c_double)),
+                ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
+                ("history_cap", ctypes.c_int32)]
+
+
+class plcg_result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("spmvs", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("reason", ctypes.c_int32),
+                ("rnorm0", ctypes.c_double), ("rec_relres", ctypes.c_double),
+                ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double), ("sweeps", ctypes.c_int64)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["reason_name"] = REASONS.get(self.reason, str(self.reason))
+        return d
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libplcg.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_h = ctypes.c_void_p
+_dp = ctypes.c_void_p       # device pointer as an address
+_st = ctypes.c_int32
+
+SYMBOLS = {
+    "plcg_create": (_st, [ctypes.POINTER(plcg_operator_desc), ctypes.POINTER(plcg_config),
+                          ctypes.POINTER(_h)]),
+    "plcg_solve": (_st, [_h, _dp, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                         ctypes.POINTER(plcg_result)]),
+    "plcg_submit": (_st, [_h, _dp, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                          ctypes.POINTER(ctypes.c_uint64)]),
+    "plcg_poll": (_st, [_h, ctypes.c_uint64, ctypes.POINTER(plcg_result)]),
+    "plcg_destroy": (_st, [_h]),
+    "plcg_last_error": (ctypes.c_char_p, []),
+    "plcg_apply": (_st, [_h, _dp, _dp, ctypes.c_void_p]),
+    "plcg_size": (ctypes.c_int64, [_h]),
+    "plcg_get_shifts": (_st, [_h, ctypes.POINTER(ctypes.c_double)]),
+    "plcg_get_history": (_st, [_h, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32)]),
+    "plcg_set_timing": (_st, [_h, ctypes.c_int32]),
+    "plcg_copy": (_st, [_dp, _dp, ctypes.c_int64, ctypes.c_void_p]),
+    "plcg_version": (ctypes.c_int32, []),
+}
+for _name, (_res, _args) in SYMBOLS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+plcg_create = _lib.plcg_create
+plcg_solve = _lib.plcg_solve
+plcg_submit = _lib.plcg_submit
+plcg_poll = _lib.plcg_poll
+plcg_destroy = _lib.plcg_destroy
+plcg_last_error = _lib.plcg_last_error
+plcg_apply = _lib.plcg_apply
+plcg_size = _lib.plcg_size
+plcg_get_shifts = _lib.plcg_get_shifts
+plcg_get_history = _lib.plcg_get_history
+plcg_set_timing = _lib.plcg_set_timing
+plcg_copy = _lib.plcg_copy
+plcg_version = _lib.plcg_version
+
+
+class PlcgError(RuntimeError):
+    def __init__(self, status, where):
+        msg = plcg_last_error()
+        super().__init__(f"{where} failed with status {status}: "
+                         f"{msg.decode() if msg else ''}")
+        self.status = status
+
+
+def check(status, where):
+    if status < 0:
+        raise PlcgError(status, where)
+    return status
+
+
+def _dims_desc(kind, dims):
+    dims = tuple(int(d) for d in dims)
+    if kind in ("2d5", PLCG_OP_STENCIL2D5):
+        return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1)
+    if kind in ("3d7", PLCG_OP_STENCIL3D7):
+        return plcg_operator_desc(PLCG_OP_STENCIL3D7, dims[0], dims[1], dims[2])
+    raise ValueError(f"unknown operator kind {kind!r}")
+
+
+class Solver:
+    """Convenience owner of one plcg_handle."""
+
+    def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
+                 check_every=0, max_restarts=-1, history_cap=0):
+        self.desc = _dims_desc(kind, dims)
+        self._shifts = None
+        sp = None
+        if shifts is not None:
+            self._shifts = (ctypes.c_double * len(shifts))(*shifts)
+            sp = ctypes.cast(self._shifts, ctypes.POINTER(ctypes.c_double))
+        m = PLCG_METHOD_CG if method == "cg" else PLCG_METHOD_PLCG
+        self.cfg = plcg_config(m, int(l), float(lmin), float(lmax), sp, int(check_every),
+                               int(max_restarts), int(history_cap))
+        self.method = method
+        self.l = int(l)
+        self.handle = _h()
+        check(plcg_create(ctypes.byref(self.desc), ctypes.byref(self.cfg),
+                          ctypes.byref(self.handle)), "plcg_create")
+        self.n = plcg_size(self.handle)
+
+    def solve(self, b_ptr, x_ptr, tol, maxit, stream=0):
+        res = plcg_result()
+        st = plcg_solve(self.handle, b_ptr, x_ptr, float(tol), int(maxit), stream,
+                        ctypes.byref(res))
+        check(st, "plcg_solve")
+        return res
+
+    def submit(self, b_ptr, x_ptr, tol, maxit, stream=0):
+        t = ctypes.c_uint64(0)
+        check(plcg_submit(self.handle, b_ptr, x_ptr, float(tol), int(maxit), stream,
+                          ctypes.byref(t)), "plcg_submit")
+        return t.value
+
+    def poll(self, ticket):
+        res = plcg_result()
+        st = plcg_poll(self.handle, ticket, ctypes.byref(res))
+        if st == PLCG_NOT_READY:
+            return None
+        check(st, "plcg_poll")
+        return res
+
+    def apply(self, x_ptr, y_ptr, stream=0):
+        check(plcg_apply(self.handle, x_ptr, y_ptr, stream), "plcg_apply")
+
+    def shifts(self):
+        out = (ctypes.c_double * max(self.l, 1))()
+        check(plcg_get_shifts(self.handle, out), "plcg_get_shifts")
+        return list(out)[: self.l]
+
+    def history(self, cap):
+        out = (ctypes.c_double * (4 * cap))()
+        cnt = ctypes.c_int32(0)
+        check(plcg_get_history(self.handle, out, cap, ctypes.byref(cnt)), "plcg_get_history")
+        return [tuple(out[4 * k: 4 * k + 4]) for k in range(cnt.value)]
+
+    def set_timing(self, on):
+        check(plcg_set_timing(self.handle, 1 if on else 0), "plcg_set_timing")
+
+    def close(self):
+        if self.handle:
+            plcg_destroy(self.handle)
+            self.handle = _h()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

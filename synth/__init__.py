@@ -59,3 +59,13 @@ def grid_size(dims) -> int:
     for d in dims:
         n *= int(d)
     return n
+
+
+def sample_indices(n: int, count: int = 512, seed: int = 12345) -> np.ndarray:
+    """Sorted distinct indices for spot checks: the first and last 32, plus
+    SplitMix64 draws spread over [0, n)."""
+    edge = min(32, n)
+    head = np.arange(edge, dtype=np.int64)
+    tail = np.arange(max(0, n - edge), n, dtype=np.int64)
+    draws = (splitmix64(seed, 0, count) % np.uint64(max(n, 1))).astype(np.int64)
+    return np.unique(np.concatenate([head, tail, draws]))

@@ -1,0 +1,64 @@
+"""The C-ABI library loads, exports every declared entry point, and validates
+its arguments on the host (no device work: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "plcg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(plcg_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1905_06850_amd import plcg
+    lib = ctypes.CDLL(plcg.LIB_PATH)
+    names = _declared()
+    assert "plcg_solve" in names and "plcg_create" in names and "plcg_poll" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(plcg.SYMBOLS)
+
+
+def test_version():
+    from paper_1905_06850_amd import plcg
+    assert plcg.plcg_version() >= 100
+
+
+def _create(kind=1, nx=8, ny=8, nz=1, method=1, l=2, lmin=0.0, lmax=8.0):
+    from paper_1905_06850_amd import plcg
+    desc = plcg.plcg_operator_desc(kind, nx, ny, nz)
+    cfg = plcg.plcg_config(method, l, lmin, lmax, None, 0, -1, 0)
+    h = ctypes.c_void_p()
+    st = plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("kwargs", [
+    dict(kind=7), dict(nx=0), dict(ny=-3), dict(kind=2, nz=0), dict(kind=1, nz=4),
+    dict(l=0), dict(l=9), dict(method=5), dict(lmin=1.0, lmax=1.0), dict(lmin=3.0, lmax=2.0),
+    dict(nx=65536, ny=65536),
+])
+def test_create_rejects_bad_arguments(kwargs):
+    from paper_1905_06850_amd import plcg
+    st, h = _create(**kwargs)
+    assert st == plcg.PLCG_E_INVALID
+    assert not h.value
+    assert plcg.plcg_last_error()
+
+
+def test_null_arguments():
+    from paper_1905_06850_amd import plcg
+    assert plcg.plcg_create(None, None, None) == plcg.PLCG_E_INVALID
+    res = plcg.plcg_result()
+    assert plcg.plcg_solve(None, 0, 0, 1e-8, 10, None, ctypes.byref(res)) == plcg.PLCG_E_INVALID
+    assert plcg.plcg_poll(None, 1, ctypes.byref(res)) == plcg.PLCG_E_INVALID
+    assert plcg.plcg_apply(None, 0, 0, None) == plcg.PLCG_E_INVALID
+    assert plcg.plcg_copy(0, 0, 10, None) == plcg.PLCG_E_INVALID
+    assert plcg.plcg_destroy(None) == plcg.PLCG_OK
+    assert plcg.plcg_size(None) == -1

@@ -129,7 +129,7 @@ def _mut_basis_wrong_shift_index(z, gam, dlt, sigma, t, l, i):
     z[l][i + 1] = new / dlt[t]
 
 
-def _mut_dots_wrong_basis(G, z, i, l, dots):
+def _mut_dots_wrong_basis(G, z, i, l, dots, dot=np.dot):
     u = z[l][i + 1]
     c = i + 1
     j = i - l + 1
