@@ -42,13 +42,13 @@ plcg_status fail(plcg_status code, const std::string &msg) {
       return fail(PLCG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
   } while (0)
 
-constexpr int kMaxBlocks = 2048;   // 8 per CU on 256 CUs; every grid is a multiple of 8
 constexpr int kDefaultCheck = 64;
 constexpr int kDefaultRestarts = 100;
 
+// Streaming workgroups of a launch: one per chunk up to kMaxStream, a multiple of 8.
 int grid_blocks(int nchunks) {
   int b = ((nchunks + kXcds - 1) / kXcds) * kXcds;
-  if (b > kMaxBlocks) b = kMaxBlocks;
+  if (b > kMaxStream) b = kMaxStream;
   if (b < kXcds) b = kXcds;
   return b;
 }
@@ -73,9 +73,8 @@ struct plcg_handle {
   double *ring[kLMax] = {};       // basis l, slot of z^{(l)}_j is j % R
   double *p = nullptr;
   double *cg_r = nullptr, *cg_p[2] = {nullptr, nullptr}, *cg_q = nullptr;
-  double *partials = nullptr;
-  int32_t *ticket = nullptr;
-  DevState *st = nullptr;
+  double *part[2] = {nullptr, nullptr};   // partials of launches with even / odd index
+  DevState *st[2] = {nullptr, nullptr};   // scalar state read by odd / even launches
   double *hist = nullptr;
   HostStatus *hs_host = nullptr;  // pinned, mapped
   HostStatus *hs_dev = nullptr;
@@ -158,7 +157,8 @@ struct TimedLaunch {
   }
 };
 
-// Pointers of iteration i: ring roles, basis roles, start-up copies.
+// Pointers of iteration i: ring roles, basis roles, start-up copies, and the
+// alternating partials / state copies (launch i reads copy (i-1)&1, writes i&1).
 void sweep_args(plcg_handle *h, int i, double *x, SweepArgs &a) {
   std::memset(&a, 0, sizeof(a));
   const int l = h->l, R = h->R;
@@ -178,9 +178,10 @@ void sweep_args(plcg_handle *h, int i, double *x, SweepArgs &a) {
   a.v0 = (i == l - 1) ? h->basis[0][0] : nullptr;
   a.p = h->p;
   a.x = x;
-  a.partials = h->partials;
-  a.ticket = h->ticket;
-  a.st = h->st;
+  a.part_in = h->part[(i + 1) & 1];
+  a.part_out = h->part[i & 1];
+  a.st_in = h->st[(i + 1) & 1];
+  a.st_out = h->st[i & 1];
   a.hs = h->hs_dev;
   a.hist = h->hist;
   a.i = i;
@@ -191,19 +192,24 @@ void sweep_args(plcg_handle *h, int i, double *x, SweepArgs &a) {
   a.nz = h->op.nz;
   a.d3 = h->d3 ? 1 : 0;
   a.nchunks = h->nchunks;
-  a.max_blocks = kMaxBlocks;
+  a.nstream = h->blocks;
+  a.nparts_in = i >= 1 ? h->blocks : 0;
+  a.pstride = kMaxStream;
+  a.work = 1;
 }
 
-plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r, int mode,
-                     double tol, double rref_in, hipStream_t s) {
-  PLCG_HIP(launch_residual(b, x, r, h->partials, h->ticket, h->st, h->hs_dev, mode, tol, rref_in,
-                           h->n, h->op.nx, h->op.ny, h->op.nz, h->d3, h->nchunks, h->blocks,
-                           kMaxBlocks, s));
+// r = b - A x (r may be NULL) and ||r||^2 into state copy `slot`; mode as in
+// launch_start.
+plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r, int slot,
+                     int mode, double tol, double rref_in, hipStream_t s) {
+  PLCG_HIP(launch_residual(b, x, r, h->part[0], h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
+                           h->nchunks, h->blocks, s));
+  PLCG_HIP(launch_start(h->part[0], h->blocks, h->st[slot], h->hs_dev, mode, tol, rref_in, s));
   return PLCG_OK;
 }
 
 plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, int maxit,
-                       hipStream_t s, plcg_result *res, TimedLaunch &tl) {
+                       hipStream_t s, plcg_result *res, TimedLaunch &tl, int *final_slot) {
   const int l = h->l;
   int total = 0, restarts = 0;
   int64_t spmvs = 0;
@@ -211,14 +217,16 @@ plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, i
   int reason = PLCG_REASON_NONE;
   double rec = 0.0;
   h->last_hist_count = 0;
+  *final_slot = 1;
   while (true) {
     // Alg. 1, first line: u_0 = b - A x_0; z^{(k)}_0 = u_0 / ||u_0||; g_00 = 1.
-    plcg_status e = residual(h, b, x, h->ring[0], 0, tol, rref, s);
+    // Sweep 0 reads state copy 1.
+    plcg_status e = residual(h, b, x, h->ring[0], 1, 0, tol, rref, s);
     if (e != PLCG_OK) return e;
-    PLCG_HIP(launch_scale(h->ring[0], h->ring[0], h->basis[0][0], nullptr, h->st, h->n,
-                          h->blocks, s));
+    PLCG_HIP(launch_scale(h->ring[0], h->ring[0], h->basis[0][0], nullptr, h->st[1], h->n, s));
     PLCG_HIP(hipStreamSynchronize(s));
     spmvs += 1;
+    *final_slot = 1;
     const int st0 = hstat(h)->status;
     if (rref < 0) {
       rref = hstat(h)->rref;
@@ -237,21 +245,26 @@ plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, i
     const int imax = m + l;               // Alg. 1 loop: i = 0 .. m + l
     int status = kRunning;
     int group = 0;
+    int last_i = -1;
     for (int i0 = 0; i0 <= imax; i0 += h->check_every, ++group) {
       const int i1 = std::min(imax + 1, i0 + h->check_every);
       for (int i = i0; i < i1; ++i) {
         SweepArgs a;
         sweep_args(h, i, x, a);
         if ((e = tl.begin()) != PLCG_OK) return e;
-        PLCG_HIP(launch_plcg_sweep(a, h->blocks, s));
+        PLCG_HIP(launch_plcg_sweep(a, s));
         if ((e = tl.end()) != PLCG_OK) return e;
+        last_i = i;
       }
       if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
       if (status != kRunning) break;
     }
     PLCG_HIP(hipStreamSynchronize(s));
-    status = hstat(h)->status;
-    const int last_t = hstat(h)->last_t;
+    *final_slot = last_i & 1;
+    DevState ds;
+    PLCG_HIP(hipMemcpy(&ds, h->st[*final_slot], sizeof(ds), hipMemcpyDeviceToHost));
+    status = ds.status;
+    const int last_t = ds.last_t;
     // Iterations that ran: every sweep up to last_t + l (or the whole loop).
     int t_done;
     if (status == kRunning) {
@@ -261,12 +274,9 @@ plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, i
     }
     spmvs += std::min(imax, (status == kRunning ? imax : last_t + l)) + 1;
     total += t_done;
-    {
-      DevState ds;
-      PLCG_HIP(hipMemcpy(&ds, h->st, sizeof(ds), hipMemcpyDeviceToHost));
-      rec = t_done == 0 ? ds.beta : std::fabs(ds.zeta[t_done % kTRing]);
-      h->last_hist_count = std::min(h->hist_cap, ds.cols);
-    }
+    rec = t_done == 0 ? ds.beta : std::fabs(ds.zeta[t_done % kTRing]);
+    // t = 0 .. cols-1 were recorded unless the last column broke down.
+    h->last_hist_count = std::min(h->hist_cap, std::max(ds.cols - (status == kBroken ? 1 : 0), 0));
     if (status == kConverged && last_t <= m) {
       reason = PLCG_REASON_CONVERGED;
       break;
@@ -295,10 +305,13 @@ plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, i
 }
 
 plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int maxit,
-                     hipStream_t s, plcg_result *res, TimedLaunch &tl) {
-  plcg_status e = residual(h, b, x, h->cg_r, 1, tol, -1.0, s);
+                     hipStream_t s, plcg_result *res, TimedLaunch &tl, int *final_slot) {
+  // Sweep A reads state copy 1 and partials 1, writes copy 0 and partials 0;
+  // sweep B the other way round.  The segment start writes copy 1.
+  plcg_status e = residual(h, b, x, h->cg_r, 1, 1, tol, -1.0, s);
   if (e != PLCG_OK) return e;
   PLCG_HIP(hipStreamSynchronize(s));
+  *final_slot = 1;
   const double rref = hstat(h)->rref;
   res->rnorm0 = rref;
   int status = hstat(h)->status;
@@ -306,7 +319,6 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
     res->reason = PLCG_REASON_NONFINITE;
     return fail(PLCG_E_NONFINITE, "initial residual is not finite");
   }
-  int64_t spmvs = 1;
   if (status == kConverged) {
     res->iters = 0;
     res->reason = PLCG_REASON_CONVERGED;
@@ -320,9 +332,6 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   a.x = x;
   a.r = h->cg_r;
   a.q = h->cg_q;
-  a.partials = h->partials;
-  a.ticket = h->ticket;
-  a.st = h->st;
   a.hs = h->hs_dev;
   a.n = h->n;
   a.nx = h->op.nx;
@@ -330,30 +339,64 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   a.nz = h->op.nz;
   a.d3 = h->d3 ? 1 : 0;
   a.nchunks = h->nchunks;
-  a.max_blocks = kMaxBlocks;
+  a.nstream = h->blocks;
+  a.nparts_in = h->blocks;
+  a.pstride = kMaxStream;
+  auto set_a = [&](int k, int work) {
+    a.k = k;
+    a.work = work;
+    a.p_new = h->cg_p[k & 1];
+    a.p_old = h->cg_p[(k + 1) & 1];
+    a.part_in = h->part[1];
+    a.part_out = h->part[0];
+    a.st_in = h->st[1];
+    a.st_out = h->st[0];
+  };
+  auto set_b = [&](int k) {
+    a.k = k;
+    a.work = 1;
+    a.p_new = h->cg_p[k & 1];
+    a.p_old = h->cg_p[(k + 1) & 1];
+    a.part_in = h->part[0];
+    a.part_out = h->part[1];
+    a.st_in = h->st[0];
+    a.st_out = h->st[1];
+  };
   int group = 0;
+  bool stopped = false;
   for (int k0 = 0; k0 < maxit; k0 += h->check_every, ++group) {
     const int k1 = std::min(maxit, k0 + h->check_every);
     for (int k = k0; k < k1; ++k) {
-      a.k = k;
-      a.p_new = h->cg_p[k & 1];
-      a.p_old = h->cg_p[(k + 1) & 1];
+      set_a(k, 1);
       if ((e = tl.begin()) != PLCG_OK) return e;
-      PLCG_HIP(launch_cg_sweep_a(a, h->blocks, s));
+      PLCG_HIP(launch_cg_sweep_a(a, s));
       if ((e = tl.end()) != PLCG_OK) return e;
+      set_b(k);
       if ((e = tl.begin()) != PLCG_OK) return e;
-      PLCG_HIP(launch_cg_sweep_b(a, h->blocks, s));
+      PLCG_HIP(launch_cg_sweep_b(a, s));
       if ((e = tl.end()) != PLCG_OK) return e;
     }
     if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
-    if (status != kRunning) break;
+    if (status != kRunning) {
+      stopped = true;
+      break;
+    }
+  }
+  if (!stopped) {
+    // Form rho_maxit and the stopping test of the last iterate (no streaming).
+    set_a(maxit, 0);
+    PLCG_HIP(launch_cg_sweep_a(a, s));
+    *final_slot = 0;
   }
   PLCG_HIP(hipStreamSynchronize(s));
-  status = hstat(h)->status;
-  const int iters = status == kRunning ? maxit : hstat(h)->last_t;
+  if (stopped) *final_slot = 1;
+  DevState ds;
+  PLCG_HIP(hipMemcpy(&ds, h->st[*final_slot], sizeof(ds), hipMemcpyDeviceToHost));
+  status = ds.status;
+  const int iters = status == kRunning ? maxit : ds.last_t;
   res->iters = iters;
-  res->spmvs = (int32_t)(spmvs + iters);
-  res->rec_relres = rref > 0 ? hstat(h)->zeta / rref : 0.0;
+  res->spmvs = (int32_t)(1 + iters);
+  res->rec_relres = rref > 0 ? std::sqrt(ds.cg_rho) / rref : 0.0;
   res->reason = status == kConverged  ? PLCG_REASON_CONVERGED
                 : status == kCgBreak ? PLCG_REASON_BREAKDOWN
                                      : PLCG_REASON_MAXIT;
@@ -380,16 +423,17 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   PLCG_HIP(hipSetDevice(h->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   TimedLaunch tl{h, s};
+  int final_slot = 1;
   if (h->method == PLCG_METHOD_CG)
-    e = solve_cg(h, b, x, tol, maxit, s, &res, tl);
+    e = solve_cg(h, b, x, tol, maxit, s, &res, tl, &final_slot);
   else
-    e = solve_plcg(h, b, x, tol, maxit, s, &res, tl);
+    e = solve_plcg(h, b, x, tol, maxit, s, &res, tl, &final_slot);
   if (e != PLCG_OK) {
     if (out) *out = res;
     return e;
   }
   // True residual ||b - A x|| in FP64 (one more operator application).
-  if ((e = residual(h, b, x, nullptr, 2, tol, -1.0, s)) != PLCG_OK) return e;
+  if ((e = residual(h, b, x, nullptr, final_slot, 2, tol, -1.0, s)) != PLCG_OK) return e;
   PLCG_HIP(hipStreamSynchronize(s));
   res.spmvs += 1;
   res.true_relres = res.rnorm0 > 0 ? std::sqrt(hstat(h)->sumsq) / res.rnorm0 : 0.0;
@@ -488,11 +532,12 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     vec(&h->cg_p[1]);
     vec(&h->cg_q);
   }
-  if (e == PLCG_OK)
-    e = dev_alloc(h, reinterpret_cast<void **>(&h->partials),
-                  sizeof(double) * (kLMax + 1) * kMaxBlocks);
-  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->ticket), 256);
-  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->st), sizeof(DevState));
+  for (int k = 0; k < 2; ++k) {
+    if (e == PLCG_OK)
+      e = dev_alloc(h, reinterpret_cast<void **>(&h->part[k]),
+                    sizeof(double) * (kLMax + 1) * kMaxStream);
+    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->st[k]), sizeof(DevState));
+  }
   if (e == PLCG_OK && h->hist_cap > 0)
     e = dev_alloc(h, reinterpret_cast<void **>(&h->hist), sizeof(double) * 4 * h->hist_cap);
   if (e != PLCG_OK) {
@@ -519,8 +564,10 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   init.l = h->l;
   init.hist_cap = h->hist_cap;
   for (int k = 0; k < kLMax; ++k) init.sigma[k] = h->sigma[k];
-  bool ok = hipMemcpy(h->st, &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemset(h->ticket, 0, 256) == hipSuccess &&
+  bool ok = hipMemcpy(h->st[0], &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(h->st[1], &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemset(h->part[0], 0, sizeof(double) * (kLMax + 1) * kMaxStream) == hipSuccess &&
+            hipMemset(h->part[1], 0, sizeof(double) * (kLMax + 1) * kMaxStream) == hipSuccess &&
             hipEventCreateWithFlags(&h->chunk_ev[0], hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->chunk_ev[1], hipEventDisableTiming) == hipSuccess &&
             hipDeviceSynchronize() == hipSuccess;
@@ -597,9 +644,7 @@ plcg_status plcg_apply(plcg_handle *h, const double *d_x, double *d_y, void *str
   if (h == nullptr || d_x == nullptr || d_y == nullptr)
     return fail(PLCG_E_INVALID, "NULL argument");
   if (d_x == d_y) return fail(PLCG_E_INVALID, "x and y must be distinct");
-  int blocks = (h->n + kThreads - 1) / kThreads;
-  if (blocks > 8192) blocks = 8192;
-  PLCG_HIP(launch_apply(d_x, d_y, h->n, h->op.nx, h->op.ny, h->op.nz, h->d3, blocks,
+  PLCG_HIP(launch_apply(d_x, d_y, h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
                         reinterpret_cast<hipStream_t>(stream)));
   return PLCG_OK;
 }

@@ -6,32 +6,34 @@
 
 namespace plcg {
 
-constexpr int kLMax = 8;            // largest pipeline length
+constexpr int kLMax = 8;              // largest pipeline length
 constexpr int kBand = 2 * kLMax + 1;  // stored rows per column of G (rows c-2l .. c)
-constexpr int kGRing = 16;          // columns of G kept (>= l+1 are read)
-constexpr int kTRing = 16;          // entries of gamma/delta/eta/zeta kept (>= l+1 are read)
-constexpr int kThreads = 256;       // threads per block of every streaming kernel
-constexpr int kVec = 2;             // consecutive unknowns per thread and chunk
+constexpr int kGRing = 16;            // columns of G kept (>= l+1 are read)
+constexpr int kTRing = 16;            // entries of gamma/delta/eta/zeta kept (>= l+1 are read)
+constexpr int kThreads = 256;         // threads per block of every streaming kernel
+constexpr int kVec = 2;               // consecutive unknowns per thread and chunk
 constexpr int kChunk = kThreads * kVec;
-constexpr int kXcds = 8;            // MI355X: workgroups are dealt round-robin to 8 XCDs
+constexpr int kXcds = 8;              // MI355X: workgroups are dealt round-robin to 8 XCDs
+constexpr int kMaxStream = 1024;      // streaming blocks per launch (multiple of kXcds)
 
 enum Status : int32_t { kRunning = 0, kConverged = 1, kBroken = 2, kNonFinite = 3, kCgBreak = 4 };
 
 // Host-visible progress record, written by the device into pinned host memory
-// (mapped) whenever the scalar engine changes it.
+// (mapped) by the block that owns the scalar state.
 struct HostStatus {
   int32_t status;     // Status
   int32_t last_t;     // last index t whose x_t is (or will be) formed; -1: none
   int32_t cols;       // columns of G finalised (p(l)) or CG iterations completed
-  int32_t pad;
-  double zeta;        // |zeta_t| of the last finalised t (CG: ||r||)
+  int32_t seq;        // launch index of the kernel that wrote this record
+  double zeta;        // |zeta_t| of the last finalised t (CG: ||r_k||)
   double beta;        // ||r_0|| of the current segment
   double rref;        // reference norm of the stopping test (caller's ||b - A x0||)
   double sumsq;       // result of the last plain reduction (residual norms)
 };
 
-// Device-resident scalar state of one solve segment.  Only the last block of a
-// kernel (after the atomic ticket) writes it.
+// Scalar state of one solve segment.  Two copies alternate between launches:
+// launch s reads copy (s-1)&1 and its owning block writes copy s&1, so no
+// block ever reads a copy that is being written.
 struct DevState {
   double g[kGRing][kBand];   // column c of G at g[c % kGRing][r - c + 2*kLMax], r in [c-2l, c]
   double gam[kTRing], dlt[kTRing], eta[kTRing], zeta[kTRing];
@@ -58,41 +60,48 @@ struct SweepArgs {
   double *copy_dst;          // i < l-1: basis i+1 slot receiving z^{(l)}_{i+1}; else NULL
   const double *v0;          // i == l-1: z^{(0)}_0 for the product (u_l, v_0)
   double *p, *x;
-  double *partials;          // [kLMax+1][max_blocks]
-  int32_t *ticket;
-  DevState *st;
+  const double *part_in;     // partials of sweep i-1, [l+1][pstride]
+  double *part_out;          // partials of sweep i
+  const DevState *st_in;     // state after column i-1
+  DevState *st_out;          // state after column i (written by the owning block)
   HostStatus *hs;            // mapped pinned host memory
   double *hist;              // [hist_cap][4] or NULL
   int32_t i, l, n, nx, ny, nz, d3;
-  int32_t nchunks, max_blocks;
+  int32_t nchunks;           // ceil(n / kChunk)
+  int32_t nstream;           // streaming blocks (multiple of kXcds)
+  int32_t nparts_in;         // partials per product in part_in
+  int32_t pstride;
+  int32_t work;              // 0: only carry the scalar state forward
 };
 
 struct CgArgs {
   const double *b;
   double *x, *r, *p_old, *p_new, *q;
-  double *partials;
-  int32_t *ticket;
-  DevState *st;
+  const double *part_in;
+  double *part_out;
+  const DevState *st_in;
+  DevState *st_out;
   HostStatus *hs;
-  int32_t k, n, nx, ny, nz, d3, nchunks, max_blocks;
+  int32_t k, n, nx, ny, nz, d3, nchunks, nstream, nparts_in, pstride, work;
 };
 
 // Launchers (plcg_kernels.hip).
-hipError_t launch_plcg_sweep(const SweepArgs &a, int blocks, hipStream_t s);
-hipError_t launch_cg_sweep_a(const CgArgs &a, int blocks, hipStream_t s);
-hipError_t launch_cg_sweep_b(const CgArgs &a, int blocks, hipStream_t s);
-// r = b - A x; sum of squares finalised into st->sumsq by the last block, which
-// then starts a segment: mode 0 = p(l)-CG (sets G, beta, status), 1 = CG,
-// 2 = only report the sum (true residual).
-hipError_t launch_residual(const double *b, const double *x, double *r, double *partials,
-                           int32_t *ticket, DevState *st, HostStatus *hs, int mode,
-                           double tol, double rref_in, int n, int nx, int ny, int nz, bool d3,
-                           int nchunks, int blocks, int max_blocks, hipStream_t s);
+hipError_t launch_plcg_sweep(const SweepArgs &a, hipStream_t s);
+hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s);
+hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s);
+// r = b - A x (r may be NULL); per-block partial sums of r.r into part_out.
+hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out,
+                           int n, int nx, int ny, int nz, bool d3, int nchunks, int nstream,
+                           hipStream_t s);
+// One block: sum the residual partials and start a segment in *st:
+// mode 0 = p(l)-CG (G, beta, status), 1 = CG (rho), 2 = only report the sum.
+hipError_t launch_start(const double *part_in, int nparts, DevState *st, HostStatus *hs,
+                        int mode, double tol, double rref_in, hipStream_t s);
 // z = r / beta written to up to three destinations (beta from st); no-op unless running.
-hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, DevState *st,
-                        int n, int blocks, hipStream_t s);
+hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, const DevState *st,
+                        int n, hipStream_t s);
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
-                        int blocks, hipStream_t s);
+                        hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);
 
 }  // namespace plcg

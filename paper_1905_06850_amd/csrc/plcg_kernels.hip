@@ -1,17 +1,22 @@
 // Device code of libplcg for gfx950 (MI355X).
 //
-// Every kernel streams the unknowns in chunks of kChunk = 512 consecutive
-// indices (two per thread, 16-byte loads).  Chunks are dealt to workgroups so
-// that each of the 8 XCDs owns one contiguous band of the grid: the hardware
-// hands workgroup b to XCD b % 8, so workgroup b works on band b % 8, chunk
-// (b / 8) + k * (gridDim / 8).  Stencil neighbours in the next or previous row
-// or plane are then read by workgroups on the same XCD and hit its L2.
+// Streaming: every kernel walks the unknowns in chunks of kChunk = 512
+// consecutive indices (two per thread, 16-byte loads).  Chunks are dealt so that
+// each of the 8 XCDs owns one contiguous band of the grid: the hardware hands
+// workgroup b to XCD b % 8, so workgroup b works on band b % 8.  Stencil
+// neighbours in the next or previous row or plane are then read by workgroups on
+// the same XCD and hit its L2.
 //
-// Reductions are deterministic: each workgroup reduces its products in a fixed
-// order (per-thread sums, wave butterfly, waves in order) and stores one
-// partial per dot product; the last workgroup to take the atomic ticket adds
-// the partials in workgroup order and runs the O(l^2) scalar steps of the
-// method in one thread, from a copy of the scalar state in LDS.
+// Reductions: a kernel never waits for the other workgroups of the same launch.
+// Each workgroup reduces its products in a fixed order (per-thread sums, wave
+// butterfly, waves in order) and stores one partial per product.  The partials
+// are added up by the next launch, after the kernel boundary has made them
+// visible: for p(1)-CG and classic CG, whose next iteration needs the result at
+// once, every workgroup adds them itself (same order, so every workgroup gets
+// the same bits); for p(l)-CG with l >= 2 one extra workgroup does it while the
+// others stream, and the coefficients it produces are first used l-1 launches
+// later - the reduction of iteration i-1 runs during the SpMV of iteration i
+// (Sec. 3.1, Alg. 2).  No fences, atomics or host round trips per iteration.
 #include "plcg_internal.h"
 
 #include <math.h>
@@ -19,17 +24,20 @@
 namespace plcg {
 
 // ---------------------------------------------------------------------------
-// Chunk scheduling and stencil helpers
+// Chunk scheduling
 // ---------------------------------------------------------------------------
 
 struct ChunkIter {
   int c, end, step;
 };
 
-__device__ inline ChunkIter xcd_chunks(int nchunks) {
+// Streaming workgroups are blockIdx.x = first .. first + nstream - 1 (first is 0
+// or 1, nstream a multiple of 8); workgroup b sits on XCD b % 8 and takes band
+// b % 8 of the chunks.
+__device__ inline ChunkIter xcd_chunks(int nchunks, int nstream, int first) {
   const int band = blockIdx.x % kXcds;
-  const int lb = blockIdx.x / kXcds;
-  const int nlb = gridDim.x / kXcds;
+  const int lb = (blockIdx.x - first) / kXcds;
+  const int nlb = nstream / kXcds;
   const int lo = (int)(((long long)band * nchunks) / kXcds);
   const int hi = (int)(((long long)(band + 1) * nchunks) / kXcds);
   return ChunkIter{lo + lb, hi, nlb};
@@ -39,25 +47,9 @@ struct Grid {
   int n, nx, ny, nz;
 };
 
-// Sum of the face neighbours of unknown p (zero outside the grid).
-template <bool D3>
-__device__ inline double neighbour_sum(const double *z, int p, const Grid &g) {
-  const int x = p % g.nx;
-  const int rest = p / g.nx;
-  const int y = D3 ? rest % g.ny : rest;
-  double s = 0.0;
-  if (x > 0) s += z[p - 1];
-  if (x < g.nx - 1) s += z[p + 1];
-  if (y > 0) s += z[p - g.nx];
-  if (y < g.ny - 1) s += z[p + g.nx];
-  if (D3) {
-    const int zz = rest / g.ny;
-    const int plane = g.nx * g.ny;
-    if (zz > 0) s += z[p - plane];
-    if (zz < g.nz - 1) s += z[p + plane];
-  }
-  return s;
-}
+// ---------------------------------------------------------------------------
+// Stencil
+// ---------------------------------------------------------------------------
 
 template <int V>
 struct Vals {
@@ -84,8 +76,83 @@ struct Vals {
   }
 };
 
+// Sum of the face neighbours of unknown p (zero outside the grid), one load each.
+template <bool D3>
+__device__ inline double neighbour_sum(const double *z, int p, const Grid &g) {
+  const int x = p % g.nx;
+  const int rest = p / g.nx;
+  const int y = D3 ? rest % g.ny : rest;
+  double s = 0.0;
+  if (x > 0) s += z[p - 1];
+  if (x < g.nx - 1) s += z[p + 1];
+  if (y > 0) s += z[p - g.nx];
+  if (y < g.ny - 1) s += z[p + g.nx];
+  if (D3) {
+    const int zz = rest / g.ny;
+    const int plane = g.nx * g.ny;
+    if (zz > 0) s += z[p - plane];
+    if (zz < g.nz - 1) s += z[p + plane];
+  }
+  return s;
+}
+
+// w = A z at the V unknowns starting at idx, given their values zc.
+// FAST (a full chunk and an even nx): both unknowns of a thread share a row,
+// x-neighbours come from the adjacent lanes (consecutive pairs), the rows and
+// planes above and below are 16-byte loads.  Called by all 64 lanes together.
+template <int V, bool D3, bool FAST>
+__device__ inline void apply_stencil(const double *z, int idx, const Vals<V> &zc, const Grid &g,
+                                     double (&w)[V]) {
+  const double diag = D3 ? 6.0 : 4.0;
+  if constexpr (FAST && V == 2) {
+    const int x = idx % g.nx;
+    const int rest = idx / g.nx;
+    const int y = D3 ? rest % g.ny : rest;
+    const int lane = threadIdx.x & 63;
+    double left = __shfl_up(zc.v[1], 1, 64);     // z[idx-1] held by the previous lane
+    double right = __shfl_down(zc.v[0], 1, 64);  // z[idx+2] held by the next lane
+    if (lane == 0 && x > 0) left = z[idx - 1];
+    if (lane == 63 && x + 2 < g.nx) right = z[idx + 2];
+    double s0 = (x > 0 ? left : 0.0) + zc.v[1];
+    double s1 = zc.v[0] + (x + 2 < g.nx ? right : 0.0);
+    if (y > 0) {
+      Vals<2> u;
+      u.load(z + idx - g.nx);
+      s0 += u.v[0];
+      s1 += u.v[1];
+    }
+    if (y < g.ny - 1) {
+      Vals<2> d;
+      d.load(z + idx + g.nx);
+      s0 += d.v[0];
+      s1 += d.v[1];
+    }
+    if (D3) {
+      const int zz = rest / g.ny;
+      const int plane = g.nx * g.ny;
+      if (zz > 0) {
+        Vals<2> f;
+        f.load(z + idx - plane);
+        s0 += f.v[0];
+        s1 += f.v[1];
+      }
+      if (zz < g.nz - 1) {
+        Vals<2> k;
+        k.load(z + idx + plane);
+        s0 += k.v[0];
+        s1 += k.v[1];
+      }
+    }
+    w[0] = diag * zc.v[0] - s0;
+    w[1] = diag * zc.v[1] - s1;
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) w[v] = diag * zc.v[v] - neighbour_sum<D3>(z, idx + v, g);
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Deterministic block reduction and the last-block ticket
+// Deterministic block reductions
 // ---------------------------------------------------------------------------
 
 __device__ inline double wave_sum(double v) {
@@ -94,7 +161,7 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Reduce acc[0..ND-1] over the workgroup; result valid in out[] (LDS) after the call.
+// Sum acc[0..ND-1] over the workgroup; out[] (LDS) holds the result afterwards.
 template <int ND>
 __device__ inline void block_sum(const double (&acc)[ND], double *lds /* [4][ND] */,
                                  double *out /* [ND] */) {
@@ -113,33 +180,26 @@ __device__ inline void block_sum(const double (&acc)[ND], double *lds /* [4][ND]
   __syncthreads();
 }
 
-// Store this workgroup's partials, take a ticket; returns true in the last
-// workgroup, which then holds the grid-wide sums in tot[] (LDS).
+// Grid-wide sums of the previous launch's partials, in a fixed order.
 template <int ND>
-__device__ inline bool reduce_grid(const double (&acc)[ND], double *partials, int max_blocks,
-                                   int32_t *ticket, double *lds, double *blk, double *tot) {
-  __shared__ int s_last;
-  block_sum<ND>(acc, lds, blk);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int m = 0; m < ND; ++m) partials[m * max_blocks + blockIdx.x] = blk[m];
-    __threadfence();
-    const int tk = atomicAdd(ticket, 1);
-    s_last = (tk == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  double sums[ND];
+__device__ inline void sum_partials(const double *part, int nparts, int pstride, double *lds,
+                                    double *out) {
+  double s[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kThreads) s += partials[m * max_blocks + b];
-    sums[m] = s;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kThreads) acc += part[m * pstride + b];
+    s[m] = acc;
   }
-  block_sum<ND>(sums, lds, tot);
-  if (threadIdx.x == 0) *ticket = 0;
-  return true;
+  block_sum<ND>(s, lds, out);
+}
+
+// This workgroup's partials (index = streaming workgroup number).
+template <int ND>
+__device__ inline void store_partials(const double (&acc)[ND], double *part, int pstride,
+                                      int slot, double *lds, double *blk) {
+  block_sum<ND>(acc, lds, blk);
+  if (threadIdx.x < ND) part[threadIdx.x * pstride + slot] = blk[threadIdx.x];
 }
 
 // Copy the scalar state between global memory and LDS (all threads).
@@ -156,15 +216,16 @@ __device__ inline void state_store(const DevState *sh, DevState *st) {
   for (int k = threadIdx.x; k < (int)(sizeof(DevState) / 8); k += kThreads) dst[k] = src[k];
 }
 
-__device__ inline void publish(const DevState &s, HostStatus *hs, double zeta) {
+// Progress for the host (visible there at the latest when the kernel ends).
+__device__ inline void publish(const DevState &s, HostStatus *hs, double zeta, int seq) {
   hs->status = s.status;
   hs->last_t = s.last_t;
   hs->cols = s.cols;
+  hs->seq = seq;
   hs->zeta = zeta;
   hs->beta = s.beta;
   hs->rref = s.rref;
   hs->sumsq = s.sumsq;
-  __threadfence_system();
 }
 
 // ---------------------------------------------------------------------------
@@ -175,12 +236,13 @@ __device__ inline double &gref(DevState &s, int r, int c) {
   return s.g[c % kGRing][r - c + 2 * kLMax];
 }
 
-__device__ inline bool finite_d(double v) { return isfinite(v); }
-
 // Column c of G from the raw products raw[0] = (z_c, v_{c-l}) and
-// raw[m] = (z_c, z_{c-l+m}), m = 1..l (Sec. 2.1 corrections, Eq. symmetry_G),
-// then gamma_t, delta_t (Eqs. haa1, haa3), eta_t, zeta_t (Eq. LU) for t = c-1,
-// then the breakdown and convergence tests.  Runs in one thread.
+// raw[m] = (z_c, z_{c-l+m}), m = 1..l: the entries below the l-th upper
+// diagonal from Eq. (symmetry_G), the forward substitution for rows
+// c-l+1 .. c-1 and the square root for the diagonal (Alg. 1, update of G);
+// then gamma_t, delta_t (Eqs. haa1, haa3) and eta_t, zeta_t (Eq. LU and the
+// recursion for zeta) for t = c-1, and the breakdown / convergence tests.
+// Runs in one thread.
 __device__ void engine_column(DevState &s, const double *raw, int c, double *hist) {
   const int l = s.l;
   const int t = c - 1;
@@ -200,7 +262,7 @@ __device__ void engine_column(DevState &s, const double *raw, int c, double *his
   }
   double arg = gref(s, c, c);
   for (int k = lo; k < c; ++k) arg -= gref(s, k, c) * gref(s, k, c);
-  bool broken = !(finite_d(arg) && arg > 0.0);
+  bool broken = !(isfinite(arg) && arg > 0.0);
   double gam = 0.0, dlt = 0.0, eta = 0.0, zeta = 0.0;
   if (!broken) {
     gref(s, c, c) = sqrt(arg);
@@ -213,7 +275,7 @@ __device__ void engine_column(DevState &s, const double *raw, int c, double *his
       gam = (gtt * s.gam[(t - l) % kTRing] + gref(s, t, c) * s.dlt[(t - l) % kTRing] - corr) / gtt;
       dlt = (gref(s, c, c) * s.dlt[(t - l) % kTRing]) / gtt;
     }
-    broken = !(finite_d(gam) && finite_d(dlt) && dlt > 0.0);
+    broken = !(isfinite(gam) && isfinite(dlt) && dlt > 0.0);
     if (!broken) {
       if (t == 0) {
         eta = gam;
@@ -223,7 +285,7 @@ __device__ void engine_column(DevState &s, const double *raw, int c, double *his
         eta = gam - lam * s.dlt[(t - 1) % kTRing];
         zeta = -lam * s.zeta[(t - 1) % kTRing];
       }
-      broken = !(finite_d(eta) && eta > 0.0 && finite_d(zeta));
+      broken = !(isfinite(eta) && eta > 0.0 && isfinite(zeta));
     }
   }
   s.cols = c;
@@ -252,28 +314,32 @@ __device__ void engine_column(DevState &s, const double *raw, int c, double *his
 // p(l)-CG sweep: iteration i of Alg. 1
 // ---------------------------------------------------------------------------
 
+template <int L>
+struct Coef {
+  double gam, dm1, inv_del, inv_eta, zm1, sigma_i;
+  double sig[L];
+};
+
 template <int L, bool D3>
 struct Sweep {
   static constexpr int ND = L + 1;
 
-  // Steady state, i >= l: K1 (SpMV of z^{(l)}_i), K4 (all basis recurrences),
-  // K6 (p_t, x_t), K5 (l+1 products for column i+1).
-  template <int V>
+  // Steady state, i >= l: K1 (SpMV of z^{(l)}_i), K4 (all basis recurrences,
+  // Eqs. all_z_rec2 and specific_z_rec), K6 (p_t, x_t; Eqs. pdir, x_a2) and
+  // K5 (the l+1 products that start column i+1 of G).
+  template <int V, bool FAST>
   __device__ static inline void steady(const SweepArgs &a, const Grid &g, int idx, int t,
-                                       double gam, double dm1, double inv_del, double inv_eta,
-                                       double zm1, const double *sig, double (&acc)[ND]) {
+                                       const Coef<L> &cf, double (&acc)[ND]) {
     Vals<V> zc, zp;
     zc.load(a.zl[0] + idx);
     zp.load(a.zl[1] + idx);
-    const double diag = D3 ? 6.0 : 4.0;
+    double w[V];
+    apply_stencil<V, D3, FAST>(a.zl[0], idx, zc, g, w);
     double zn[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const double w = diag * zc.v[v] - neighbour_sum<D3>(a.zl[0], idx + v, g);
-      zn[v] = ((w - gam * zc.v[v]) - dm1 * zp.v[v]) * inv_del;
-    }
-    // Dot products against older z^{(l)} history, read before zl_out is written
-    // (zl_out is the slot of z^{(l)}_{i+1-R}).
+    for (int v = 0; v < V; ++v) zn[v] = ((w[v] - cf.gam * zc.v[v]) - cf.dm1 * zp.v[v]) * cf.inv_del;
+    // Products with older z^{(l)} vectors, read before zl_out (the slot of
+    // z^{(l)}_{i+1-R}) is overwritten below.
 #pragma unroll
     for (int m = 1; m <= L - 3; ++m) {
       Vals<V> zh;
@@ -290,9 +356,9 @@ struct Sweep {
       ck.load(a.zk_cur[k] + idx);
       if (t >= 1) pk.load(a.zk_prev[k] + idx); else pk.zero();
       Vals<V> nk;
-      const double sk = sig[k] - gam;
+      const double sk = cf.sig[k] - cf.gam;
 #pragma unroll
-      for (int v = 0; v < V; ++v) nk.v[v] = ((above[v] + sk * ck.v[v]) - dm1 * pk.v[v]) * inv_del;
+      for (int v = 0; v < V; ++v) nk.v[v] = ((above[v] + sk * ck.v[v]) - cf.dm1 * pk.v[v]) * cf.inv_del;
       nk.store(a.zk_prev[k] + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) above[v] = ck.v[v];
@@ -307,15 +373,15 @@ struct Sweep {
     Vals<V> pv;
     if (t == 0) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) pv.v[v] = vt[v] * inv_eta;
+      for (int v = 0; v < V; ++v) pv.v[v] = vt[v] * cf.inv_eta;
     } else {
       Vals<V> xv;
       pv.load(a.p + idx);
       xv.load(a.x + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        xv.v[v] += zm1 * pv.v[v];
-        pv.v[v] = (vt[v] - dm1 * pv.v[v]) * inv_eta;
+        xv.v[v] += cf.zm1 * pv.v[v];
+        pv.v[v] = (vt[v] - cf.dm1 * pv.v[v]) * cf.inv_eta;
       }
       xv.store(a.x + idx);
     }
@@ -326,27 +392,25 @@ struct Sweep {
     out.store(a.zl_out + idx);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      acc[0] += zn[v] * vnew[v];            // (z_{i+1}, v_{t+1})
-      acc[L] += zn[v] * zn[v];              // (z_{i+1}, z_{i+1})
-      if (L >= 2) acc[L - 1] += zn[v] * zc.v[v];   // (z_{i+1}, z_i)
-      if (L >= 3) acc[L - 2] += zn[v] * zp.v[v];   // (z_{i+1}, z_{i-1})
+      acc[0] += zn[v] * vnew[v];                    // (z_{i+1}, v_{t+1})
+      acc[L] += zn[v] * zn[v];                      // (z_{i+1}, z_{i+1})
+      if (L >= 2) acc[L - 1] += zn[v] * zc.v[v];    // (z_{i+1}, z_i)
+      if (L >= 3) acc[L - 2] += zn[v] * zp.v[v];    // (z_{i+1}, z_{i-1})
     }
   }
 
-  // Start-up, i < l: z^{(l)}_{i+1} = (A - sigma_i) z^{(l)}_i, copy into basis
-  // i+1, products (z_{i+1}, z_j), j >= 0, and (z_l, v_0) when i = l-1.
-  template <int V>
+  // Start-up, i < l: z^{(l)}_{i+1} = (A - sigma_i) z^{(l)}_i, copied into basis
+  // i+1; products (z_{i+1}, z_j), j >= 0, and (z_l, v_0) when i = l-1.
+  template <int V, bool FAST>
   __device__ static inline void startup(const SweepArgs &a, const Grid &g, int idx, int i,
                                         double sigma_i, double (&acc)[ND]) {
     Vals<V> zc;
     zc.load(a.zl[0] + idx);
-    const double diag = D3 ? 6.0 : 4.0;
+    double w[V];
+    apply_stencil<V, D3, FAST>(a.zl[0], idx, zc, g, w);
     Vals<V> zn;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const double w = diag * zc.v[v] - neighbour_sum<D3>(a.zl[0], idx + v, g);
-      zn.v[v] = w - sigma_i * zc.v[v];
-    }
+    for (int v = 0; v < V; ++v) zn.v[v] = w[v] - sigma_i * zc.v[v];
 #pragma unroll
     for (int m = 1; m <= L - 2; ++m) {
       const int h = L - 1 - m;
@@ -371,87 +435,144 @@ struct Sweep {
       if (L >= 2) acc[L - 1] += zn.v[v] * zc.v[v];
     }
   }
+
+  template <bool FAST>
+  __device__ static inline void chunk(const SweepArgs &a, const Grid &g, int idx, int t,
+                                      const Coef<L> &cf, double (&acc)[ND]) {
+    if (t >= 0) {
+      if (idx + 1 < a.n)
+        steady<2, FAST>(a, g, idx, t, cf, acc);
+      else if (idx < a.n)
+        steady<1, false>(a, g, idx, t, cf, acc);
+    } else {
+      if (idx + 1 < a.n)
+        startup<2, FAST>(a, g, idx, a.i, cf.sigma_i, acc);
+      else if (idx < a.n)
+        startup<1, false>(a, g, idx, a.i, cf.sigma_i, acc);
+    }
+  }
 };
+
+template <int L>
+__device__ inline void read_coef(const DevState &s, int i, int t, Coef<L> &cf) {
+  if (t >= 0) {
+    cf.gam = s.gam[t % kTRing];
+    cf.inv_del = 1.0 / s.dlt[t % kTRing];
+    cf.dm1 = t >= 1 ? s.dlt[(t - 1) % kTRing] : 0.0;
+    cf.inv_eta = 1.0 / s.eta[t % kTRing];
+    cf.zm1 = t >= 1 ? s.zeta[(t - 1) % kTRing] : 0.0;
+    cf.sigma_i = 0.0;
+  } else {
+    cf.gam = cf.inv_del = cf.dm1 = cf.inv_eta = cf.zm1 = 0.0;
+    cf.sigma_i = s.sigma[i];
+  }
+#pragma unroll
+  for (int k = 0; k < L; ++k) cf.sig[k] = s.sigma[k];
+}
 
 template <int L, bool D3>
 __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgs a) {
   using S = Sweep<L, D3>;
   constexpr int ND = S::ND;
   __shared__ double lds[4 * ND];
-  __shared__ double blk[ND];
-  __shared__ double tot[ND];
+  __shared__ double red[ND];
   __shared__ DevState sh;
 
-  const DevState *st = a.st;
+  // Workgroup 0 owns the scalar state and carries it from launch i-1 to launch
+  // i.  For l = 1 every workgroup finalises column i itself (this launch needs
+  // it); for l >= 2 only workgroup 0 does, and it streams nothing.
+  const bool owner = blockIdx.x == 0;
+  const bool engine = (L == 1) || owner;
+  if (engine) {
+    state_load(a.st_in, &sh);
+    if (a.i >= 1 && sh.status == kRunning && a.nparts_in > 0) {
+      sum_partials<ND>(a.part_in, a.nparts_in, a.pstride, lds, red);
+      if (threadIdx.x == 0) engine_column(sh, red, a.i, owner ? a.hist : nullptr);
+      __syncthreads();
+    }
+    if (owner) {
+      state_store(&sh, a.st_out);
+      if (threadIdx.x == 0) publish(sh, a.hs, fabs(sh.zeta[(a.i + kTRing - 1) % kTRing]), a.i);
+    }
+    if (L >= 2) return;
+  }
+  if (!a.work) return;
+
   const int i = a.i;
   const int t = i - L;
-  const int status = st->status;
-  // Sweeps past the stop no longer change anything (the solve's x is x_{last_t}).
-  if (status != kRunning && t > st->last_t) return;
+  int status, last_t;
+  Coef<L> cf;
+  if (L == 1) {
+    status = sh.status;
+    last_t = sh.last_t;
+    read_coef<L>(sh, i, t, cf);
+  } else {
+    status = a.st_in->status;
+    last_t = a.st_in->last_t;
+    read_coef<L>(*a.st_in, i, t, cf);
+  }
+  // Sweeps past the stop change nothing (the solve's x is x_{last_t}).
+  if (status != kRunning && t > last_t) return;
 
   const Grid g{a.n, a.nx, a.ny, a.nz};
   double acc[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) acc[m] = 0.0;
-
-  if (t >= 0) {
-    const double gam = st->gam[t % kTRing];
-    const double del = st->dlt[t % kTRing];
-    const double dm1 = t >= 1 ? st->dlt[(t - 1) % kTRing] : 0.0;
-    const double inv_del = 1.0 / del;
-    const double inv_eta = 1.0 / st->eta[t % kTRing];
-    const double zm1 = t >= 1 ? st->zeta[(t - 1) % kTRing] : 0.0;
-    double sig[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) sig[k] = st->sigma[k];
-    for (ChunkIter it = xcd_chunks(a.nchunks); it.c < it.end; it.c += it.step) {
-      const int idx = it.c * kChunk + threadIdx.x * kVec;
-      if (idx + 1 < a.n)
-        S::template steady<2>(a, g, idx, t, gam, dm1, inv_del, inv_eta, zm1, sig, acc);
-      else if (idx < a.n)
-        S::template steady<1>(a, g, idx, t, gam, dm1, inv_del, inv_eta, zm1, sig, acc);
-    }
-  } else {
-    const double sigma_i = st->sigma[i];
-    for (ChunkIter it = xcd_chunks(a.nchunks); it.c < it.end; it.c += it.step) {
-      const int idx = it.c * kChunk + threadIdx.x * kVec;
-      if (idx + 1 < a.n)
-        S::template startup<2>(a, g, idx, i, sigma_i, acc);
-      else if (idx < a.n)
-        S::template startup<1>(a, g, idx, i, sigma_i, acc);
-    }
+  const int first = L == 1 ? 0 : 1;
+  const bool fast_rows = (a.nx & 1) == 0;
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, first); it.c < it.end; it.c += it.step) {
+    const int base = it.c * kChunk;
+    const int idx = base + threadIdx.x * kVec;
+    if (fast_rows && base + kChunk <= a.n)
+      S::template chunk<true>(a, g, idx, t, cf, acc);
+    else
+      S::template chunk<false>(a, g, idx, t, cf, acc);
   }
-
-  if (!reduce_grid<ND>(acc, a.partials, a.max_blocks, a.ticket, lds, blk, tot)) return;
-
-  // Last workgroup: finalise column i+1 of G and the scalars for t' = i.
-  state_load(st, &sh);
-  if (threadIdx.x == 0 && sh.status == kRunning) {
-    engine_column(sh, tot, i + 1, a.hist);
-    publish(sh, a.hs, fabs(sh.zeta[i % kTRing]));
-  }
-  state_store(&sh, a.st);
+  store_partials<ND>(acc, a.part_out, a.pstride, blockIdx.x - first, lds, red);
 }
 
 // ---------------------------------------------------------------------------
 // Classic CG: two sweeps per iteration
 // ---------------------------------------------------------------------------
 
-// Sweep A of iteration k: p_k = r_k + beta_{k-1} p_{k-1} (p_0 = r_0), q = A p_k,
-// product (p_k, q); the last workgroup forms alpha_k = (r_k, r_k) / (p_k, q).
+// Sweep A of iteration k.  Prologue (every workgroup): rho_k = (r_k, r_k) from
+// sweep B of iteration k-1, beta_{k-1} = rho_k / rho_{k-1}, stopping test
+// ||r_k|| < tol ||r_0||.  Then p_k = r_k + beta_{k-1} p_{k-1} (p_0 = r_0),
+// q = A p_k and the product (p_k, q).
 template <bool D3>
 __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
   __shared__ double lds[4];
-  __shared__ double blk[1];
-  __shared__ double tot[1];
-  const DevState *st = a.st;
-  if (st->status != kRunning) return;
+  __shared__ double red[1];
+  __shared__ DevState sh;
+  state_load(a.st_in, &sh);
+  if (a.k >= 1 && sh.status == kRunning) {
+    sum_partials<1>(a.part_in, a.nparts_in, a.pstride, lds, red);
+    if (threadIdx.x == 0) {
+      const double rho = red[0];
+      sh.cols = a.k;
+      sh.last_t = a.k;
+      if (!isfinite(rho)) {
+        sh.status = kCgBreak;
+      } else {
+        sh.cg_beta = rho / sh.cg_rho;
+        sh.cg_rho = rho;
+        if (sqrt(rho) < sh.abs_tol) sh.status = kConverged;
+      }
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    state_store(&sh, a.st_out);
+    if (threadIdx.x == 0) publish(sh, a.hs, sqrt(sh.cg_rho), 2 * a.k);
+  }
+  if (sh.status != kRunning || !a.work) return;
+
   const bool first = a.k == 0;
-  const double beta = first ? 0.0 : st->cg_beta;
+  const double beta = first ? 0.0 : sh.cg_beta;
   const Grid g{a.n, a.nx, a.ny, a.nz};
   const double diag = D3 ? 6.0 : 4.0;
   double acc[1] = {0.0};
-  for (ChunkIter it = xcd_chunks(a.nchunks); it.c < it.end; it.c += it.step) {
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
     const int idx0 = it.c * kChunk + threadIdx.x * kVec;
 #pragma unroll
     for (int v = 0; v < kVec; ++v) {
@@ -480,33 +601,39 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       acc[0] += pc * q;
     }
   }
-  __shared__ DevState sh;
-  if (!reduce_grid<1>(acc, a.partials, a.max_blocks, a.ticket, lds, blk, tot)) return;
-  state_load(st, &sh);
-  if (threadIdx.x == 0) {
-    const double pq = tot[0];
-    if (!(isfinite(pq) && pq > 0.0)) {
-      sh.status = kCgBreak;
-      sh.last_t = a.k;
-    } else {
-      sh.cg_alpha = sh.cg_rho / pq;
-    }
-    publish(sh, a.hs, sqrt(sh.cg_rho));
-  }
-  state_store(&sh, a.st);
+  store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
 }
 
-// Sweep B of iteration k: x += alpha p_k, r -= alpha q, product (r, r);
-// the last workgroup forms beta_k and tests ||r_{k+1}|| < tol ||r_0||.
+// Sweep B of iteration k.  Prologue: alpha_k = rho_k / (p_k, q) from sweep A
+// (breakdown if (p_k, A p_k) <= 0).  Then x += alpha p_k, r -= alpha q and the
+// product (r_{k+1}, r_{k+1}).
 __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
   __shared__ double lds[4];
-  __shared__ double blk[1];
-  __shared__ double tot[1];
-  const DevState *st = a.st;
-  if (st->status != kRunning) return;
-  const double alpha = st->cg_alpha;
+  __shared__ double red[1];
+  __shared__ DevState sh;
+  state_load(a.st_in, &sh);
+  if (sh.status == kRunning) {
+    sum_partials<1>(a.part_in, a.nparts_in, a.pstride, lds, red);
+    if (threadIdx.x == 0) {
+      const double pq = red[0];
+      if (!(isfinite(pq) && pq > 0.0)) {
+        sh.status = kCgBreak;
+        sh.last_t = a.k;
+      } else {
+        sh.cg_alpha = sh.cg_rho / pq;
+      }
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    state_store(&sh, a.st_out);
+    if (threadIdx.x == 0) publish(sh, a.hs, sqrt(sh.cg_rho), 2 * a.k + 1);
+  }
+  if (sh.status != kRunning || !a.work) return;
+
+  const double alpha = sh.cg_alpha;
   double acc[1] = {0.0};
-  for (ChunkIter it = xcd_chunks(a.nchunks); it.c < it.end; it.c += it.step) {
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
     const int idx = it.c * kChunk + threadIdx.x * kVec;
     if (idx + 1 < a.n) {
       Vals<2> x, p, r, q;
@@ -529,55 +656,45 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
       acc[0] += rv * rv;
     }
   }
-  __shared__ DevState sh;
-  if (!reduce_grid<1>(acc, a.partials, a.max_blocks, a.ticket, lds, blk, tot)) return;
-  state_load(st, &sh);
-  if (threadIdx.x == 0) {
-    const double rho = tot[0];
-    const double rn = sqrt(rho);
-    sh.cols = a.k + 1;
-    sh.last_t = a.k + 1;
-    if (!isfinite(rho)) {
-      sh.status = kCgBreak;
-    } else {
-      sh.cg_beta = rho / sh.cg_rho;
-      sh.cg_rho = rho;
-      if (rn < sh.abs_tol) sh.status = kConverged;
-    }
-    publish(sh, a.hs, rn);
-  }
-  state_store(&sh, a.st);
+  store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
 }
 
 // ---------------------------------------------------------------------------
-// Residual, scaling, operator application, copy
+// Residual, segment start, scaling, operator application, copy
 // ---------------------------------------------------------------------------
 
 template <bool D3>
-__global__ __launch_bounds__(kThreads) void residual_kernel(
-    const double *b, const double *x, double *r, double *partials, int32_t *ticket, DevState *st,
-    HostStatus *hs, int mode, double tol, double rref_in, Grid g, int nchunks, int max_blocks) {
+__global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, const double *x,
+                                                            double *r, double *part_out, Grid g,
+                                                            int nchunks, int nstream) {
   __shared__ double lds[4];
-  __shared__ double blk[1];
-  __shared__ double tot[1];
-  const double diag = D3 ? 6.0 : 4.0;
+  __shared__ double red[1];
   double acc[1] = {0.0};
-  for (ChunkIter it = xcd_chunks(nchunks); it.c < it.end; it.c += it.step) {
+  for (ChunkIter it = xcd_chunks(nchunks, nstream, 0); it.c < it.end; it.c += it.step) {
     const int idx0 = it.c * kChunk + threadIdx.x * kVec;
 #pragma unroll
     for (int v = 0; v < kVec; ++v) {
       const int p = idx0 + v;
       if (p >= g.n) break;
-      const double rv = b[p] - (diag * x[p] - neighbour_sum<D3>(x, p, g));
+      const double rv = b[p] - ((D3 ? 6.0 : 4.0) * x[p] - neighbour_sum<D3>(x, p, g));
       if (r != nullptr) r[p] = rv;
       acc[0] += rv * rv;
     }
   }
+  store_partials<1>(acc, part_out, kMaxStream, blockIdx.x, lds, red);
+}
+
+// One workgroup: ||b - A x||^2 from the residual partials; starts a segment.
+__global__ __launch_bounds__(kThreads) void start_kernel(const double *part_in, int nparts,
+                                                         DevState *st, HostStatus *hs, int mode,
+                                                         double tol, double rref_in) {
+  __shared__ double lds[4];
+  __shared__ double red[1];
   __shared__ DevState sh;
-  if (!reduce_grid<1>(acc, partials, max_blocks, ticket, lds, blk, tot)) return;
   state_load(st, &sh);
+  sum_partials<1>(part_in, nparts, kMaxStream, lds, red);
   if (threadIdx.x == 0) {
-    const double ss = tot[0];
+    const double ss = red[0];
     sh.sumsq = ss;
     if (mode != 2) {
       const double beta = sqrt(ss);
@@ -594,18 +711,15 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(
         sh.status = kRunning;
         sh.last_t = -1;
       }
-      if (mode == 0) {
-        for (int c = 0; c < kGRing; ++c)
-          for (int r2 = 0; r2 < kBand; ++r2) sh.g[c][r2] = 0.0;
-        for (int k = 0; k < kTRing; ++k) sh.gam[k] = sh.dlt[k] = sh.eta[k] = sh.zeta[k] = 0.0;
-        gref(sh, 0, 0) = 1.0;
-      } else {
-        sh.cg_rho = ss;
-        sh.cg_alpha = 0.0;
-        sh.cg_beta = 0.0;
-      }
+      for (int c = 0; c < kGRing; ++c)
+        for (int r2 = 0; r2 < kBand; ++r2) sh.g[c][r2] = 0.0;
+      for (int k = 0; k < kTRing; ++k) sh.gam[k] = sh.dlt[k] = sh.eta[k] = sh.zeta[k] = 0.0;
+      gref(sh, 0, 0) = 1.0;                    // g_00 = 1 (Alg. 1, first line)
+      sh.cg_rho = ss;
+      sh.cg_alpha = 0.0;
+      sh.cg_beta = 0.0;
     }
-    publish(sh, hs, sqrt(ss));
+    publish(sh, hs, sqrt(ss), -1);
   }
   state_store(&sh, st);
 }
@@ -641,78 +755,90 @@ __global__ __launch_bounds__(kThreads) void copy_kernel(const double *src, doubl
 // Launchers
 // ---------------------------------------------------------------------------
 
+static int simple_blocks(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
 template <int L>
-static hipError_t launch_sweep_l(const SweepArgs &a, int blocks, hipStream_t s) {
+static hipError_t launch_sweep_l(const SweepArgs &a, hipStream_t s) {
+  const int grid = a.nstream + (L >= 2 ? 1 : 0);
   if (a.d3)
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, true>), dim3(blocks), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, true>), dim3(grid), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, false>), dim3(blocks), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, false>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_plcg_sweep(const SweepArgs &a, int blocks, hipStream_t s) {
+hipError_t launch_plcg_sweep(const SweepArgs &a, hipStream_t s) {
   switch (a.l) {
-    case 1: return launch_sweep_l<1>(a, blocks, s);
-    case 2: return launch_sweep_l<2>(a, blocks, s);
-    case 3: return launch_sweep_l<3>(a, blocks, s);
-    case 4: return launch_sweep_l<4>(a, blocks, s);
-    case 5: return launch_sweep_l<5>(a, blocks, s);
-    case 6: return launch_sweep_l<6>(a, blocks, s);
-    case 7: return launch_sweep_l<7>(a, blocks, s);
-    case 8: return launch_sweep_l<8>(a, blocks, s);
+    case 1: return launch_sweep_l<1>(a, s);
+    case 2: return launch_sweep_l<2>(a, s);
+    case 3: return launch_sweep_l<3>(a, s);
+    case 4: return launch_sweep_l<4>(a, s);
+    case 5: return launch_sweep_l<5>(a, s);
+    case 6: return launch_sweep_l<6>(a, s);
+    case 7: return launch_sweep_l<7>(a, s);
+    case 8: return launch_sweep_l<8>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_cg_sweep_a(const CgArgs &a, int blocks, hipStream_t s) {
+hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s) {
   if (a.d3)
-    hipLaunchKernelGGL((cg_sweep_a_kernel<true>), dim3(blocks), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((cg_sweep_a_kernel<true>), dim3(a.nstream), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((cg_sweep_a_kernel<false>), dim3(blocks), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((cg_sweep_a_kernel<false>), dim3(a.nstream), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_sweep_b(const CgArgs &a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(cg_sweep_b_kernel, dim3(blocks), dim3(kThreads), 0, s, a);
+hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(cg_sweep_b_kernel, dim3(a.nstream), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const double *b, const double *x, double *r, double *partials,
-                           int32_t *ticket, DevState *st, HostStatus *hs, int mode, double tol,
-                           double rref_in, int n, int nx, int ny, int nz, bool d3, int nchunks,
-                           int blocks, int max_blocks, hipStream_t s) {
+hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out, int n,
+                           int nx, int ny, int nz, bool d3, int nchunks, int nstream,
+                           hipStream_t s) {
   const Grid g{n, nx, ny, nz};
   if (d3)
-    hipLaunchKernelGGL((residual_kernel<true>), dim3(blocks), dim3(kThreads), 0, s, b, x, r,
-                       partials, ticket, st, hs, mode, tol, rref_in, g, nchunks, max_blocks);
+    hipLaunchKernelGGL((residual_kernel<true>), dim3(nstream), dim3(kThreads), 0, s, b, x, r,
+                       part_out, g, nchunks, nstream);
   else
-    hipLaunchKernelGGL((residual_kernel<false>), dim3(blocks), dim3(kThreads), 0, s, b, x, r,
-                       partials, ticket, st, hs, mode, tol, rref_in, g, nchunks, max_blocks);
+    hipLaunchKernelGGL((residual_kernel<false>), dim3(nstream), dim3(kThreads), 0, s, b, x, r,
+                       part_out, g, nchunks, nstream);
   return hipGetLastError();
 }
 
-hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, DevState *st, int n,
-                        int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(scale_kernel, dim3(blocks), dim3(kThreads), 0, s, r, d0, d1, d2, st, n);
+hipError_t launch_start(const double *part_in, int nparts, DevState *st, HostStatus *hs, int mode,
+                        double tol, double rref_in, hipStream_t s) {
+  hipLaunchKernelGGL(start_kernel, dim3(1), dim3(kThreads), 0, s, part_in, nparts, st, hs, mode,
+                     tol, rref_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, const DevState *st,
+                        int n, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel, dim3(simple_blocks(n)), dim3(kThreads), 0, s, r, d0, d1, d2,
+                     st, n);
   return hipGetLastError();
 }
 
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
-                        int blocks, hipStream_t s) {
+                        hipStream_t s) {
   const Grid g{n, nx, ny, nz};
   if (d3)
-    hipLaunchKernelGGL((apply_kernel<true>), dim3(blocks), dim3(kThreads), 0, s, x, y, g);
+    hipLaunchKernelGGL((apply_kernel<true>), dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, y, g);
   else
-    hipLaunchKernelGGL((apply_kernel<false>), dim3(blocks), dim3(kThreads), 0, s, x, y, g);
+    hipLaunchKernelGGL((apply_kernel<false>), dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, y, g);
   return hipGetLastError();
 }
 
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s) {
-  int64_t pairs = (n + 1) / 2;
-  int64_t blocks = (pairs + kThreads - 1) / kThreads;
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, src, dst, n);
+  hipLaunchKernelGGL(copy_kernel, dim3(simple_blocks((n + 1) / 2)), dim3(kThreads), 0, s, src, dst,
+                     n);
   return hipGetLastError();
 }
 
