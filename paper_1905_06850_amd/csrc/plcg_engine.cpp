@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -514,10 +515,20 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     }
   }
 
+  // All work vectors live in one allocation.  Consecutive vectors are spaced by
+  // their size rounded up to 64 KiB plus a stagger, so that the many streams
+  // of a sweep do not start on the same HBM channel when n*8 is a power of two.
   const size_t vb = (size_t)n * sizeof(double);
+  size_t stagger = 4096 + 256;
+  if (const char *env = std::getenv("PLCG_VECTOR_STAGGER")) stagger = (size_t)std::atoll(env) & ~size_t(255);
+  const size_t vstride = ((vb + 65535) / 65536) * 65536 + stagger;
+  const int nvec = pl ? 2 * h->l + h->R + 1 : 4;
   plcg_status e = PLCG_OK;
+  char *arena = nullptr;
+  e = dev_alloc(h, reinterpret_cast<void **>(&arena), vstride * nvec);
+  int used = 0;
   auto vec = [&](double **dst) {
-    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(dst), vb);
+    if (e == PLCG_OK) *dst = reinterpret_cast<double *>(arena + vstride * used++);
   };
   if (pl) {
     for (int k = 0; k < h->l; ++k) {

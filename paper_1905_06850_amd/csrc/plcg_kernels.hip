@@ -571,29 +571,93 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
   const double beta = first ? 0.0 : sh.cg_beta;
   const Grid g{a.n, a.nx, a.ny, a.nz};
   const double diag = D3 ? 6.0 : 4.0;
+  const bool fast_rows = (a.nx & 1) == 0;
   double acc[1] = {0.0};
+  // p_k at index q, formed on the fly from r and p_{k-1}
+  auto pk1 = [&](int q) { return first ? a.r[q] : a.r[q] + beta * a.p_old[q]; };
+  auto pk2 = [&](int q, double &v0, double &v1) {
+    Vals<2> rr;
+    rr.load(a.r + q);
+    v0 = rr.v[0];
+    v1 = rr.v[1];
+    if (!first) {
+      Vals<2> po;
+      po.load(a.p_old + q);
+      v0 += beta * po.v[0];
+      v1 += beta * po.v[1];
+    }
+  };
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
-    const int idx0 = it.c * kChunk + threadIdx.x * kVec;
+    const int base = it.c * kChunk;
+    const int idx0 = base + threadIdx.x * kVec;
+    if (fast_rows && base + kChunk <= a.n) {
+      // Same layout as the p(l)-CG fast path: pairs in one row, x-neighbours
+      // from the adjacent lanes, 16-byte loads for the other rows and planes.
+      double c0, c1;
+      pk2(idx0, c0, c1);
+      const int x = idx0 % g.nx;
+      const int rest = idx0 / g.nx;
+      const int y = D3 ? rest % g.ny : rest;
+      const int lane = threadIdx.x & 63;
+      double left = __shfl_up(c1, 1, 64);
+      double right = __shfl_down(c0, 1, 64);
+      if (lane == 0 && x > 0) left = pk1(idx0 - 1);
+      if (lane == 63 && x + 2 < g.nx) right = pk1(idx0 + 2);
+      double s0 = (x > 0 ? left : 0.0) + c1;
+      double s1 = c0 + (x + 2 < g.nx ? right : 0.0);
+      double u0, u1;
+      if (y > 0) {
+        pk2(idx0 - g.nx, u0, u1);
+        s0 += u0;
+        s1 += u1;
+      }
+      if (y < g.ny - 1) {
+        pk2(idx0 + g.nx, u0, u1);
+        s0 += u0;
+        s1 += u1;
+      }
+      if (D3) {
+        const int zz = rest / g.ny;
+        const int plane = g.nx * g.ny;
+        if (zz > 0) {
+          pk2(idx0 - plane, u0, u1);
+          s0 += u0;
+          s1 += u1;
+        }
+        if (zz < g.nz - 1) {
+          pk2(idx0 + plane, u0, u1);
+          s0 += u0;
+          s1 += u1;
+        }
+      }
+      Vals<2> pn, qv;
+      pn.v[0] = c0;
+      pn.v[1] = c1;
+      qv.v[0] = diag * c0 - s0;
+      qv.v[1] = diag * c1 - s1;
+      pn.store(a.p_new + idx0);
+      qv.store(a.q + idx0);
+      acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
+      continue;
+    }
 #pragma unroll
     for (int v = 0; v < kVec; ++v) {
       const int p = idx0 + v;
       if (p >= a.n) break;
-      // p_k at p and at its neighbours, formed on the fly from r and p_{k-1}
-      auto pk = [&](int q) { return first ? a.r[q] : a.r[q] + beta * a.p_old[q]; };
-      const double pc = pk(p);
+      const double pc = pk1(p);
       const int x = p % g.nx;
       const int rest = p / g.nx;
       const int y = D3 ? rest % g.ny : rest;
       double s = 0.0;
-      if (x > 0) s += pk(p - 1);
-      if (x < g.nx - 1) s += pk(p + 1);
-      if (y > 0) s += pk(p - g.nx);
-      if (y < g.ny - 1) s += pk(p + g.nx);
+      if (x > 0) s += pk1(p - 1);
+      if (x < g.nx - 1) s += pk1(p + 1);
+      if (y > 0) s += pk1(p - g.nx);
+      if (y < g.ny - 1) s += pk1(p + g.nx);
       if (D3) {
         const int zz = rest / g.ny;
         const int plane = g.nx * g.ny;
-        if (zz > 0) s += pk(p - plane);
-        if (zz < g.nz - 1) s += pk(p + plane);
+        if (zz > 0) s += pk1(p - plane);
+        if (zz < g.nz - 1) s += pk1(p + plane);
       }
       const double q = diag * pc - s;
       a.p_new[p] = pc;

@@ -293,3 +293,43 @@ def test_tiny_systems_krylov_exhaustion(dev, dims, l):
     if A.n == 1:
         assert ref.reason == "breakdown_limit" and res.reason == 3
     s.close()
+
+
+# ------------------------------------------------------------ full-size cases --
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result {name}")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["poisson2048_cg", "poisson2048_p1", "poisson2048_p2",
+                                  "poisson2048_p3", "poisson2048_p4", "poisson2048_p5",
+                                  "poisson3d256_p3"])
+def test_full_size_against_stored_oracle(dev, name):
+    """The benchmark workloads at full size, in the launch configuration the
+    benchmark times, against the oracle's stored result (tests/golden,
+    written by make_golden.py from the oracle only): same iteration count within
+    1, true residual within 10x, and ||x - x_oracle|| / ||x_oracle|| < 1e-8
+    estimated from the stored sample of x (plus ||x|| itself)."""
+    g = _golden(name)
+    dims = tuple(g["dims"])
+    n = int(np.prod(dims))
+    b = synth.uniform(n, g["seed"])
+    method = g["method"]
+    l = max(int(g["l"]), 1)
+    x, res, s = gpu_solve(dev, dims, method, l, b, np.zeros(n), g["tol"], 100000,
+                          interval=tuple(g["interval"]))
+    assert res.reason == 1
+    assert abs(res.iters - g["iters"]) <= 1
+    assert res.true_relres <= 10 * g["true_relres"] and g["true_relres"] <= 10 * res.true_relres
+    idx = np.array(g["sample_idx"])
+    ref = np.array(g["sample_x"])
+    est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
+    assert est < 1e-8
+    assert abs(np.linalg.norm(x) - g["xnorm"]) <= 1e-8 * g["xnorm"]
+    s.close()
