@@ -71,6 +71,53 @@ print(json.dumps(dict(iters=r.iters, seconds=dt)))
                       f"(numpy FP64 oracle, one thread), {r['seconds']:.1f} s"}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1905_06850_amd", "csrc", "plcg_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None.
+
+    profiles/traffic_poisson2048.txt holds lines `key value`: the kernel source
+    hash the counters were taken with, and `<kernel> <bytes>` per launch (FETCH_SIZE
+    plus WRITE_SIZE, each scaled by the copy-kernel calibration factor).  A
+    different source hash means the kernel changed since: None.
+    """
+    path = os.path.join(ROOT, "profiles", "traffic_poisson2048.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    v = vals.get(kernel)
+    return float(v) if v is not None else None
+
+
+def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods):
+    import torch
+    n = b.numel()
+    y = torch.empty_like(b)
+    for _ in range(10):
+        plcg.check(plcg.plcg_copy(b.data_ptr(), y.data_ptr(), n, sp), "plcg_copy")
+    torch.cuda.synchronize()
+    for m in methods.split(","):
+        method, l = ("cg", 1) if m == "cg" else ("plcg", int(m))
+        s = plcg.Solver(kind, dims, method=method, l=l, lmin=lo, lmax=hi)
+        x.zero_()
+        s.solve(b.data_ptr(), x.data_ptr(), 1e-30, 100, sp)
+        torch.cuda.synchronize()
+        s.close()
+    print("profile run done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +129,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short fixed run for hardware-counter passes: 10 copies of "
+                         "n doubles, then 100 iterations of each method")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -110,6 +160,10 @@ def main():
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     sp = stream.cuda_stream
+
+    if args.profile_run:
+        profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods)
+        return
 
     methods = []
     for m in args.methods.split(","):
@@ -196,7 +250,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(f"plcg_sweep_kernel<{args.headline},false>"),
             "kernel": f"plcg_sweep_kernel<{args.headline}, 2D>",
             "kernel_us": hr["kernel_us"],
             "bytes_per_launch": bytes_launch,
