@@ -26,6 +26,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 def vector_passes(method: str, l: int) -> int:
+    # (mixed methods run the same sweep on 4-byte values: see bytes_per_pass)
     """Algorithmic vector passes per iteration (each pass = N doubles read or written).
 
     p(l)-CG fused sweep: reads z^{(l)}_i (stencil input, once), z^{(l)}_{i-1},
@@ -125,7 +126,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson2048")
     ap.add_argument("--methods", default="cg,1,2,3,4,5")
-    ap.add_argument("--headline", type=int, default=1, help="l of the headline p(l)-CG")
+    ap.add_argument("--headline", default="1",
+                    help="headline method: l of p(l)-CG, or m<l> for FP32-refined p(l)-CG")
+    ap.add_argument("--inner-tol", type=float, default=1e-3,
+                    help="inner tolerance of the FP32-refined methods (m<l>)")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -165,16 +169,24 @@ def main():
         profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods)
         return
 
-    methods = []
-    for m in args.methods.split(","):
-        methods.append(("cg", 0) if m == "cg" else ("plcg", int(m)))
-    if ("plcg", args.headline) not in methods:
-        methods.append(("plcg", args.headline))
+    def parse(tok):
+        if tok == "cg":
+            return ("cg", 0)
+        if tok.startswith("m"):
+            return ("mixed", int(tok[1:]))
+        return ("plcg", int(tok))
+
+    methods = [parse(m) for m in args.methods.split(",")]
+    head_method = parse(args.headline)
+    if head_method not in methods:
+        methods.append(head_method)
 
     rows = {}
     for method, l in methods:
-        name = "cg" if method == "cg" else f"p{l}"
-        s = plcg.Solver(kind, dims, method=method, l=max(l, 1), lmin=lo, lmax=hi)
+        name = {"cg": "cg", "plcg": f"p{l}", "mixed": f"m{l}"}[method]
+        s = plcg.Solver(kind, dims, method="cg" if method == "cg" else "plcg", l=max(l, 1),
+                        lmin=lo, lmax=hi, precision="fp32" if method == "mixed" else "fp64",
+                        inner_tol=args.inner_tol)
         for _ in range(args.warmup):
             x.zero_()
             s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
@@ -199,8 +211,8 @@ def main():
         s.close()
         r = results[-1]
         its = total_iters / dt
-        passes = vector_passes(method, l)
-        bytes_iter = passes * 8 * n
+        passes = vector_passes("cg" if method == "cg" else "plcg", l)
+        bytes_iter = passes * (4 if method == "mixed" else 8) * n
         kernel_us = 1e3 * rt.sweep_ms / max(rt.sweeps, 1)
         kernels_per_iter = 2 if method == "cg" else 1
         rows[name] = {
@@ -213,14 +225,18 @@ def main():
             "kernel_GBps": (bytes_iter / kernels_per_iter) / (kernel_us * 1e-6) / 1e9
             if method != "cg" else None,
             "spmvs": r.spmvs,
+            "outer": r.outer,
+            "solves_per_s": args.steps / dt,
         }
         if not args.quiet:
             print(f"# {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
 
-    head = f"p{args.headline}"
+    head = {"plcg": "p", "mixed": "m"}[head_method[0]] + str(head_method[1])
+    hl = head_method[1]
     hr = rows[head]
     ms_per_step = hr["ms_per_solve"]
-    bytes_launch = hr["vector_passes"] * 8 * n
+    word = 4 if head_method[0] == "mixed" else 8
+    bytes_launch = hr["vector_passes"] * word * n
     achieved = bytes_launch / (hr["kernel_us"] * 1e-6) / 1e9
     line = {
         "metric": METRIC,
@@ -233,13 +249,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if word == 8 else "f32-storage/f64-dots",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: 2D 5-point Dirichlet Poisson {dims[0]}x{dims[1]} "
+            "workload": f"{args.workload}: {'2D 5-point' if kind == '2d5' else '3D 7-point'} "
+                        f"Dirichlet Poisson {'x'.join(str(d) for d in dims)} "
                         f"({n} unknowns), b uniform[-1,1) seed 0, x0 = 0, stop at relative "
                         f"residual {tol:g}; Chebyshev shifts on [{lo:g},{hi:g}]",
-            "method": f"p({args.headline})-CG", "l": args.headline,
+            "method": (f"p({hl})-CG" if head_method[0] == "plcg"
+                       else f"FP32-stored p({hl})-CG in FP64 refinement"), "l": hl,
             "iters_per_solve": hr["iters"], "true_relres": hr["true_relres"],
             "alg_GBps": hr["alg_GBps"],
             "cg_iters_per_s": rows["cg"]["iters_per_s"] if "cg" in rows else None,
@@ -250,15 +268,17 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(f"plcg_sweep_kernel<{args.headline},false>"),
-            "kernel": f"plcg_sweep_kernel<{args.headline}, 2D>",
+            "traffic": (measured_traffic(f"plcg_sweep_kernel<{hl},false>")
+                        if kind == "2d5" and word == 8 else None),
+            "kernel": f"plcg_sweep_kernel<{hl}, {'2D' if kind == '2d5' else '3D'}, "
+                      f"{'double' if word == 8 else 'float'}>",
             "kernel_us": hr["kernel_us"],
             "bytes_per_launch": bytes_launch,
         },
         "methods": rows,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.headline, args.cpu_iters)
+        line["cpu_baseline"] = cpu_baseline(args.workload, hl, args.cpu_iters)
     print(json.dumps(line), flush=True)
 
 

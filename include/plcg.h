@@ -56,6 +56,12 @@ enum {
 
 enum { PLCG_METHOD_CG = 0, PLCG_METHOD_PLCG = 1 };
 
+/* Arithmetic of p(l)-CG.  FP32_REFINED: iterative refinement in FP64 around an
+ * inner p(l)-CG whose vectors (bases, p, correction) are stored in FP32 and whose
+ * dot products, G, T and LU scalars are FP64; each refinement step recomputes
+ * r = b - A x in FP64, solves A d = r to inner_tol, and adds x += d in FP64. */
+enum { PLCG_PREC_FP64 = 0, PLCG_PREC_FP32_REFINED = 1 };
+
 enum {
   PLCG_REASON_NONE = 0,
   PLCG_REASON_CONVERGED = 1,        /* recursive residual below tol            */
@@ -79,6 +85,9 @@ typedef struct {
   int32_t check_every;    /* iterations per host status check; <= 0: default 64 */
   int32_t max_restarts;   /* restarts after square-root breakdown; < 0: default 100 */
   int32_t history_cap;    /* keep gamma_t, delta_t, eta_t, zeta_t for t < cap (0: off) */
+  int32_t precision;      /* PLCG_PREC_*; FP32_REFINED needs method PLCG */
+  double inner_tol;       /* FP32_REFINED: relative tolerance of each inner solve, in (0, 1);
+                             <= 0: default 1e-3 */
 } plcg_config;
 
 typedef struct {
@@ -92,6 +101,8 @@ typedef struct {
   double seconds;         /* host wall time of the call */
   double sweep_ms;        /* with timing enabled: summed duration of the per-iteration kernels */
   int64_t sweeps;         /* with timing enabled: number of per-iteration kernels timed */
+  int32_t outer;          /* FP32_REFINED: refinement steps (0 otherwise) */
+  int32_t pad;
 } plcg_result;
 
 /* Create a solver for one operator and one configuration.
@@ -107,8 +118,10 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg,
  * and the final iterate on return.  Stops when the recursive residual norm
  * |zeta_t| (Alg. 1) falls below tol * ||b - A x0||, after maxit x-updates, or
  * after max_restarts explicit restarts (restart = Alg. 1 from the latest
- * iterate).  Blocks the host until the result is known.  Iteration counts,
- * residuals and the stop reason are written to *out (may be NULL). */
+ * iterate).  In FP32_REFINED mode the test is on the FP64 residual recomputed
+ * at every refinement step, and maxit bounds the inner x-updates.  Blocks the
+ * host until the result is known.  Iteration counts, residuals and the stop
+ * reason are written to *out (may be NULL). */
 plcg_status plcg_solve(plcg_handle *h, const double *d_b, double *d_x, double tol,
                        int32_t maxit, void *stream, plcg_result *out);
 

@@ -16,5 +16,6 @@ Modules:
   cg        - classic Hestenes-Stiefel CG, the method p(l)-CG is compared with.
   plcg      - Alg. 1 (preconditioner M = I) with both dot-product forms,
               the explicit restart on square-root breakdown, diagnostics.
+  refine    - FP32-stored p(l)-CG inside FP64 iterative refinement.
 """
-from . import operators, shifts, cg, plcg  # noqa: F401
+from . import operators, shifts, cg, plcg, refine  # noqa: F401

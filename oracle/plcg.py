@@ -148,7 +148,7 @@ def update_LU(gam, dlt, eta, lam, zeta, t, beta):
 # Vector steps (K1, K4, K5 and the vector half of K6)
 # ---------------------------------------------------------------------------
 
-def basis_updates(z, gam, dlt, sigma, t, l, i):
+def basis_updates(z, gam, dlt, sigma, t, l, i, store=None):
     """Three-term recurrences of all l+1 bases (Eqs. all_z_rec2, specific_z_rec).
 
     For k = 0..l-1:
@@ -159,16 +159,17 @@ def basis_updates(z, gam, dlt, sigma, t, l, i):
     that this iteration does not overwrite (basis k writes index t+k+1 and
     basis k-1 reads index t+k of basis k).
     """
+    keep = store or (lambda v: v)
     dm1 = dlt[t - 1] if t >= 1 else 0.0
     for k in range(l):
         new = z[k + 1][t + k + 1] + (sigma[k] - gam[t]) * z[k][t + k]
         if t >= 1:
             new = new - dm1 * z[k][t + k - 1]
-        z[k][t + k + 1] = new / dlt[t]
+        z[k][t + k + 1] = keep(new / dlt[t])
     new = z[l][i + 1] - gam[t] * z[l][i]
     if t >= 1:
         new = new - dm1 * z[l][i - 1]
-    z[l][i + 1] = new / dlt[t]
+    z[l][i + 1] = keep(new / dlt[t])
 
 
 def start_dots(G, z, i, l, dots, dot=np.dot):
@@ -200,11 +201,16 @@ class Segment:
     diag: dict
 
 
-def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=np.dot):
+def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=np.dot,
+         store=None):
     """One run of Alg. 1 (no restart) with M = I, from x0, at most m x-updates.
 
     ``dot`` is the inner product (default numpy's); tests pass a correctly
     rounded one to measure how much the results depend on summation order.
+    ``store`` (default: none) is applied to every vector the algorithm keeps -
+    z^{(k)}_0, each new basis vector, p and x - and models storing them in a
+    narrower format (see oracle.refine); A z^{(l)}_i itself is not stored for
+    i >= l, it is consumed by the recurrence at once.
 
     Stops when |zeta_t| < abs_tol.  Returns a Segment; ``diag`` holds G, gamma,
     delta, eta, lambda, zeta, and also the bases and the search directions when
@@ -223,8 +229,9 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
         return Segment(x, 0, "converged", -1, beta, beta, spmvs, [], {})
     if not _finite(beta):
         return Segment(x, 0, "nonfinite", -1, beta, beta, spmvs, [], {})
+    keep = store or (lambda v: v)
     z = [dict() for _ in range(l + 1)]
-    v0 = u0 / beta
+    v0 = keep(u0 / beta)
     for k in range(l + 1):
         z[k][0] = v0                           # z^{(k)}_0 = r_0 / sqrt((u_0, r_0))
     G = {(0, 0): 1.0 if x0.dtype != object else type(beta)(1)}
@@ -240,7 +247,7 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
         w = A(z[l][i])
         spmvs += 1
         if i < l:
-            w = w - sigma[i] * z[l][i]
+            w = keep(w - sigma[i] * z[l][i])
         z[l][i + 1] = w
         # line 5-6: the first vectors of bases i+1 .. l-1 are copies
         if i < l - 1:
@@ -260,16 +267,16 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
                 reason = "breakdown"
                 bt = e.t
                 break
-            basis_updates(z, gam, dlt, sigma, t, l, i)   # K4
+            basis_updates(z, gam, dlt, sigma, t, l, i, store)   # K4
         dots_per_iter.append(start_dots(G, z, i, l, dots, dot))   # K5
         # K6: search direction and iterate
         if i == l:
-            p = z[0][0] / eta[0]
+            p = keep(z[0][0] / eta[0])
             P[0] = p
         elif i >= l + 1:
             t = i - l
-            p_new = (z[0][t] - dlt[t - 1] * p) / eta[t]
-            x = x + zeta[t - 1] * p
+            p_new = keep((z[0][t] - dlt[t - 1] * p) / eta[t])
+            x = keep(x + zeta[t - 1] * p)
             p = p_new
             P[t] = p
             t_done = t

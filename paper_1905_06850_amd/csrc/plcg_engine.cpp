@@ -74,6 +74,13 @@ struct plcg_handle {
   double *ring[kLMax] = {};       // basis l, slot of z^{(l)}_j is j % R
   double *p = nullptr;
   double *cg_r = nullptr, *cg_p[2] = {nullptr, nullptr}, *cg_q = nullptr;
+  // FP32_REFINED: FP32 storage of the inner solver and the FP64 outer residual
+  int precision = PLCG_PREC_FP64;
+  double inner_tol = 1e-3;
+  float *basis32[kLMax][2] = {};
+  float *ring32[kLMax] = {};
+  float *p32 = nullptr, *d32 = nullptr;
+  double *r64 = nullptr;
   double *part[2] = {nullptr, nullptr};   // partials of launches with even / odd index
   DevState *st[2] = {nullptr, nullptr};   // scalar state read by odd / even launches
   double *hist = nullptr;
@@ -160,24 +167,26 @@ struct TimedLaunch {
 
 // Pointers of iteration i: ring roles, basis roles, start-up copies, and the
 // alternating partials / state copies (launch i reads copy (i-1)&1, writes i&1).
-void sweep_args(plcg_handle *h, int i, double *x, SweepArgs &a) {
+template <typename S>
+void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring, S *p, S *x,
+                     SweepArgsT<S> &a) {
   std::memset(&a, 0, sizeof(a));
   const int l = h->l, R = h->R;
   const int t = i - l;
   for (int k = 0; k < R; ++k) {
     const int j = i - k;
-    a.zl[k] = j >= 0 ? h->ring[j % R] : nullptr;
+    a.zl[k] = j >= 0 ? ring[j % R] : nullptr;
   }
-  a.zl_out = h->ring[(i + 1) % R];
+  a.zl_out = ring[(i + 1) % R];
   if (t >= 0) {
     for (int k = 0; k < l; ++k) {
-      a.zk_cur[k] = h->basis[k][(t + k) & 1];
-      a.zk_prev[k] = h->basis[k][(t + k + 1) & 1];
+      a.zk_cur[k] = basis[k][(t + k) & 1];
+      a.zk_prev[k] = basis[k][(t + k + 1) & 1];
     }
   }
-  a.copy_dst = (i < l - 1) ? h->basis[i + 1][(i + 1) & 1] : nullptr;
-  a.v0 = (i == l - 1) ? h->basis[0][0] : nullptr;
-  a.p = h->p;
+  a.copy_dst = (i < l - 1) ? basis[i + 1][(i + 1) & 1] : nullptr;
+  a.v0 = (i == l - 1) ? basis[0][0] : nullptr;
+  a.p = p;
   a.x = x;
   a.part_in = h->part[(i + 1) & 1];
   a.part_out = h->part[i & 1];
@@ -206,6 +215,109 @@ plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r
   PLCG_HIP(launch_residual(b, x, r, h->part[0], h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
                            h->nchunks, h->blocks, s));
   PLCG_HIP(launch_start(h->part[0], h->blocks, h->st[slot], h->hs_dev, mode, tol, rref_in, s));
+  return PLCG_OK;
+}
+
+struct Segment {
+  int status, last_t, t_done, sweeps_run, final_slot;
+  double rec;
+};
+
+// Sweeps i = 0 .. m + l of one run of Alg. 1 (setup already done; sweep 0 reads
+// state copy 1), with lagged status checks; stops early once the device reports
+// a stop.  t_done = x-updates made; rec = |zeta_{t_done}|.
+template <typename S>
+plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S *p, S *x, int m,
+                        hipStream_t s, TimedLaunch &tl, Segment *out) {
+  const int l = h->l;
+  const int imax = m + l;               // Alg. 1 loop: i = 0 .. m + l
+  int status = kRunning;
+  int group = 0;
+  int last_i = -1;
+  plcg_status e;
+  for (int i0 = 0; i0 <= imax; i0 += h->check_every, ++group) {
+    const int i1 = std::min(imax + 1, i0 + h->check_every);
+    for (int i = i0; i < i1; ++i) {
+      SweepArgsT<S> a;
+      fill_sweep_args<S>(h, i, basis, ring, p, x, a);
+      if ((e = tl.begin()) != PLCG_OK) return e;
+      PLCG_HIP(launch_plcg_sweep(a, s));
+      if ((e = tl.end()) != PLCG_OK) return e;
+      last_i = i;
+    }
+    if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
+    if (status != kRunning) break;
+  }
+  PLCG_HIP(hipStreamSynchronize(s));
+  out->final_slot = last_i & 1;
+  DevState ds;
+  PLCG_HIP(hipMemcpy(&ds, h->st[out->final_slot], sizeof(ds), hipMemcpyDeviceToHost));
+  out->status = ds.status;
+  out->last_t = ds.last_t;
+  // Iterations that ran: every sweep up to last_t + l (or the whole loop).
+  out->t_done = ds.status == kRunning ? m : std::min(std::max(ds.last_t, 0), m);
+  out->sweeps_run = std::min(imax, (ds.status == kRunning ? imax : ds.last_t + l)) + 1;
+  out->rec = out->t_done == 0 ? ds.beta : std::fabs(ds.zeta[out->t_done % kTRing]);
+  // t = 0 .. cols-1 were recorded unless the last column broke down.
+  h->last_hist_count =
+      std::min(h->hist_cap, std::max(ds.cols - (ds.status == kBroken ? 1 : 0), 0));
+  return PLCG_OK;
+}
+
+// FP32_REFINED: FP64 iterative refinement around an FP32-stored p(l)-CG.
+plcg_status solve_mixed(plcg_handle *h, const double *b, double *x, double tol, int maxit,
+                        hipStream_t s, plcg_result *res, TimedLaunch &tl, int *final_slot) {
+  int total = 0, outer = 0, restarts = 0;
+  int64_t spmvs = 0;
+  double rref = -1.0, rn = 0.0;
+  int reason = PLCG_REASON_MAXIT;
+  const int max_outer = 1000;
+  plcg_status e;
+  *final_slot = 1;
+  while (true) {
+    // r = b - A x in FP64; the inner solve starts from z_0 = r / ||r|| (FP32).
+    if ((e = residual(h, b, x, h->r64, 1, 0, h->inner_tol, -1.0, s)) != PLCG_OK) return e;
+    PLCG_HIP(launch_scale(h->r64, h->ring32[0], h->basis32[0][0], (float *)nullptr, h->st[1], h->n,
+                          s));
+    PLCG_HIP(hipMemsetAsync(h->d32, 0, sizeof(float) * (size_t)h->n, s));
+    PLCG_HIP(hipStreamSynchronize(s));
+    spmvs += 1;
+    *final_slot = 1;
+    rn = std::sqrt(hstat(h)->sumsq);
+    if (rref < 0) {
+      rref = rn;
+      res->rnorm0 = rref;
+    }
+    if (!std::isfinite(rn)) {
+      res->reason = PLCG_REASON_NONFINITE;
+      return fail(PLCG_E_NONFINITE, "residual is not finite");
+    }
+    if (rn == 0.0 || rn < tol * rref) {
+      reason = PLCG_REASON_CONVERGED;
+      break;
+    }
+    if (total >= maxit || outer >= max_outer) break;
+    Segment sg;
+    if ((e = run_segment<float>(h, h->basis32, h->ring32, h->p32, h->d32, maxit - total, s, tl,
+                                &sg)) != PLCG_OK)
+      return e;
+    *final_slot = sg.final_slot;
+    spmvs += sg.sweeps_run;
+    total += sg.t_done;
+    if (sg.status == kBroken) ++restarts;
+    PLCG_HIP(launch_add_correction(x, h->d32, h->n, s));
+    ++outer;
+    if (sg.status == kBroken && restarts > h->max_restarts) {
+      reason = PLCG_REASON_BREAKDOWN_LIMIT;
+      break;
+    }
+  }
+  res->iters = total;
+  res->outer = outer;
+  res->restarts = restarts;
+  res->reason = reason;
+  res->spmvs = (int32_t)spmvs;
+  res->rec_relres = rref > 0 ? rn / rref : 0.0;
   return PLCG_OK;
 }
 
@@ -243,41 +355,16 @@ plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, i
       break;
     }
     const int m = maxit - total;          // x-updates allowed in this segment
-    const int imax = m + l;               // Alg. 1 loop: i = 0 .. m + l
-    int status = kRunning;
-    int group = 0;
-    int last_i = -1;
-    for (int i0 = 0; i0 <= imax; i0 += h->check_every, ++group) {
-      const int i1 = std::min(imax + 1, i0 + h->check_every);
-      for (int i = i0; i < i1; ++i) {
-        SweepArgs a;
-        sweep_args(h, i, x, a);
-        if ((e = tl.begin()) != PLCG_OK) return e;
-        PLCG_HIP(launch_plcg_sweep(a, s));
-        if ((e = tl.end()) != PLCG_OK) return e;
-        last_i = i;
-      }
-      if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
-      if (status != kRunning) break;
-    }
-    PLCG_HIP(hipStreamSynchronize(s));
-    *final_slot = last_i & 1;
-    DevState ds;
-    PLCG_HIP(hipMemcpy(&ds, h->st[*final_slot], sizeof(ds), hipMemcpyDeviceToHost));
-    status = ds.status;
-    const int last_t = ds.last_t;
-    // Iterations that ran: every sweep up to last_t + l (or the whole loop).
-    int t_done;
-    if (status == kRunning) {
-      t_done = m;
-    } else {
-      t_done = std::min(std::max(last_t, 0), m);
-    }
-    spmvs += std::min(imax, (status == kRunning ? imax : last_t + l)) + 1;
+    Segment sg;
+    if ((e = run_segment<double>(h, h->basis, h->ring, h->p, x, m, s, tl, &sg)) != PLCG_OK)
+      return e;
+    *final_slot = sg.final_slot;
+    const int status = sg.status;
+    const int last_t = sg.last_t;
+    const int t_done = sg.t_done;
+    spmvs += sg.sweeps_run;
     total += t_done;
-    rec = t_done == 0 ? ds.beta : std::fabs(ds.zeta[t_done % kTRing]);
-    // t = 0 .. cols-1 were recorded unless the last column broke down.
-    h->last_hist_count = std::min(h->hist_cap, std::max(ds.cols - (status == kBroken ? 1 : 0), 0));
+    rec = sg.rec;
     if (status == kConverged && last_t <= m) {
       reason = PLCG_REASON_CONVERGED;
       break;
@@ -427,6 +514,8 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   int final_slot = 1;
   if (h->method == PLCG_METHOD_CG)
     e = solve_cg(h, b, x, tol, maxit, s, &res, tl, &final_slot);
+  else if (h->precision == PLCG_PREC_FP32_REFINED)
+    e = solve_mixed(h, b, x, tol, maxit, s, &res, tl, &final_slot);
   else
     e = solve_plcg(h, b, x, tol, maxit, s, &res, tl, &final_slot);
   if (e != PLCG_OK) {
@@ -478,6 +567,12 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
         std::isfinite(cfg->lambda_max)))
     return fail(PLCG_E_INVALID, "need lambda_min < lambda_max (or explicit shifts)");
   if (cfg->history_cap < 0) return fail(PLCG_E_INVALID, "history_cap must be >= 0");
+  if (cfg->precision != PLCG_PREC_FP64 && cfg->precision != PLCG_PREC_FP32_REFINED)
+    return fail(PLCG_E_INVALID, "unknown precision");
+  if (cfg->precision == PLCG_PREC_FP32_REFINED && !pl)
+    return fail(PLCG_E_INVALID, "FP32_REFINED needs method PLCG");
+  if (cfg->precision == PLCG_PREC_FP32_REFINED && !(cfg->inner_tol < 1.0))
+    return fail(PLCG_E_INVALID, "inner_tol must be < 1");
 
   hipError_t he;
   int dev = 0;
@@ -495,6 +590,8 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   h->check_every = cfg->check_every > 0 ? cfg->check_every : kDefaultCheck;
   h->max_restarts = cfg->max_restarts >= 0 ? cfg->max_restarts : kDefaultRestarts;
   h->hist_cap = cfg->history_cap;
+  h->precision = cfg->precision;
+  h->inner_tol = cfg->inner_tol > 0.0 ? cfg->inner_tol : 1e-3;
   h->n = (int)n;
   h->nchunks = (int)((n + kChunk - 1) / kChunk);
   h->blocks = grid_blocks(h->nchunks);
@@ -522,15 +619,33 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   size_t stagger = 4096 + 256;
   if (const char *env = std::getenv("PLCG_VECTOR_STAGGER")) stagger = (size_t)std::atoll(env) & ~size_t(255);
   const size_t vstride = ((vb + 65535) / 65536) * 65536 + stagger;
-  const int nvec = pl ? 2 * h->l + h->R + 1 : 4;
+  const bool mixed = h->precision == PLCG_PREC_FP32_REFINED;
+  const size_t vb32 = (size_t)n * sizeof(float);
+  const size_t vstride32 = ((vb32 + 65535) / 65536) * 65536 + stagger;
+  // FP64 vectors: bases + ring + p (p(l)-CG), r (mixed), r, p, p, q (CG).
+  const int nvec = mixed ? 1 : (pl ? 2 * h->l + h->R + 1 : 4);
+  const int nvec32 = mixed ? 2 * h->l + h->R + 2 : 0;
   plcg_status e = PLCG_OK;
   char *arena = nullptr;
-  e = dev_alloc(h, reinterpret_cast<void **>(&arena), vstride * nvec);
-  int used = 0;
+  e = dev_alloc(h, reinterpret_cast<void **>(&arena), vstride * nvec + vstride32 * nvec32);
+  int used = 0, used32 = 0;
   auto vec = [&](double **dst) {
     if (e == PLCG_OK) *dst = reinterpret_cast<double *>(arena + vstride * used++);
   };
-  if (pl) {
+  auto vec32 = [&](float **dst) {
+    if (e == PLCG_OK)
+      *dst = reinterpret_cast<float *>(arena + vstride * nvec + vstride32 * used32++);
+  };
+  if (mixed) {
+    vec(&h->r64);
+    for (int k = 0; k < h->l; ++k) {
+      vec32(&h->basis32[k][0]);
+      vec32(&h->basis32[k][1]);
+    }
+    for (int k = 0; k < h->R; ++k) vec32(&h->ring32[k]);
+    vec32(&h->p32);
+    vec32(&h->d32);
+  } else if (pl) {
     for (int k = 0; k < h->l; ++k) {
       vec(&h->basis[k][0]);
       vec(&h->basis[k][1]);

@@ -51,15 +51,18 @@ struct DevState {
   int32_t pad[3];
 };
 
-// Arguments of one p(l)-CG sweep (iteration i of Alg. 1).
-struct SweepArgs {
-  const double *zl[kLMax];   // z^{(l)}_{i-h} for h = 0..R-1 (R ring slots; zl[0] = z^{(l)}_i)
-  double *zl_out;            // slot receiving z^{(l)}_{i+1} (the slot of z^{(l)}_{i+1-R})
-  double *zk_cur[kLMax];     // basis k < l: z^{(k)}_{t+k}
-  double *zk_prev[kLMax];    // basis k < l: z^{(k)}_{t+k-1}; overwritten with z^{(k)}_{t+k+1}
-  double *copy_dst;          // i < l-1: basis i+1 slot receiving z^{(l)}_{i+1}; else NULL
-  const double *v0;          // i == l-1: z^{(0)}_0 for the product (u_l, v_0)
-  double *p, *x;
+// Arguments of one p(l)-CG sweep (iteration i of Alg. 1).  S is the storage
+// type of the vectors (double; float for the FP32-stored inner solver of the
+// mixed-precision mode).  Partial sums and the scalar state are always FP64.
+template <typename S>
+struct SweepArgsT {
+  const S *zl[kLMax];        // z^{(l)}_{i-h} for h = 0..R-1 (R ring slots; zl[0] = z^{(l)}_i)
+  S *zl_out;                 // slot receiving z^{(l)}_{i+1} (the slot of z^{(l)}_{i+1-R})
+  S *zk_cur[kLMax];          // basis k < l: z^{(k)}_{t+k}
+  S *zk_prev[kLMax];         // basis k < l: z^{(k)}_{t+k-1}; overwritten with z^{(k)}_{t+k+1}
+  S *copy_dst;               // i < l-1: basis i+1 slot receiving z^{(l)}_{i+1}; else NULL
+  const S *v0;               // i == l-1: z^{(0)}_0 for the product (u_l, v_0)
+  S *p, *x;
   const double *part_in;     // partials of sweep i-1, [l+1][pstride]
   double *part_out;          // partials of sweep i
   const DevState *st_in;     // state after column i-1
@@ -73,6 +76,7 @@ struct SweepArgs {
   int32_t pstride;
   int32_t work;              // 0: only carry the scalar state forward
 };
+using SweepArgs = SweepArgsT<double>;
 
 struct CgArgs {
   const double *b;
@@ -86,7 +90,8 @@ struct CgArgs {
 };
 
 // Launchers (plcg_kernels.hip).
-hipError_t launch_plcg_sweep(const SweepArgs &a, hipStream_t s);
+hipError_t launch_plcg_sweep(const SweepArgsT<double> &a, hipStream_t s);
+hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s);
 hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s);
 hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s);
 // r = b - A x (r may be NULL); per-block partial sums of r.r into part_out.
@@ -100,6 +105,10 @@ hipError_t launch_start(const double *part_in, int nparts, DevState *st, HostSta
 // z = r / beta written to up to three destinations (beta from st); no-op unless running.
 hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, const DevState *st,
                         int n, hipStream_t s);
+hipError_t launch_scale(const double *r, float *d0, float *d1, float *d2, const DevState *st, int n,
+                        hipStream_t s);
+// x += d (FP64 += FP32).
+hipError_t launch_add_correction(double *x, const float *d, int n, hipStream_t s);
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
                         hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);

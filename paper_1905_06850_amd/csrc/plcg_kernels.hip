@@ -51,23 +51,31 @@ struct Grid {
 // Stencil
 // ---------------------------------------------------------------------------
 
-template <int V>
+// V consecutive values held in FP64 registers; S is the storage type in memory
+// (double, or float for the FP32-stored inner solver), converted on load/store.
+template <int V, typename S = double>
 struct Vals {
   double v[V];
-  __device__ inline void load(const double *p) {
-    if constexpr (V == 2) {
+  __device__ inline void load(const S *p) {
+    if constexpr (V == 2 && sizeof(S) == 8) {
       const double2 t = *reinterpret_cast<const double2 *>(p);
       v[0] = t.x;
       v[1] = t.y;
+    } else if constexpr (V == 2) {
+      const float2 t = *reinterpret_cast<const float2 *>(p);
+      v[0] = (double)t.x;
+      v[1] = (double)t.y;
     } else {
-      v[0] = *p;
+      v[0] = (double)*p;
     }
   }
-  __device__ inline void store(double *p) const {
-    if constexpr (V == 2) {
+  __device__ inline void store(S *p) const {
+    if constexpr (V == 2 && sizeof(S) == 8) {
       *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    } else if constexpr (V == 2) {
+      *reinterpret_cast<float2 *>(p) = make_float2((float)v[0], (float)v[1]);
     } else {
-      *p = v[0];
+      *p = (S)v[0];
     }
   }
   __device__ inline void zero() {
@@ -77,21 +85,21 @@ struct Vals {
 };
 
 // Sum of the face neighbours of unknown p (zero outside the grid), one load each.
-template <bool D3>
-__device__ inline double neighbour_sum(const double *z, int p, const Grid &g) {
+template <bool D3, typename S = double>
+__device__ inline double neighbour_sum(const S *z, int p, const Grid &g) {
   const int x = p % g.nx;
   const int rest = p / g.nx;
   const int y = D3 ? rest % g.ny : rest;
   double s = 0.0;
-  if (x > 0) s += z[p - 1];
-  if (x < g.nx - 1) s += z[p + 1];
-  if (y > 0) s += z[p - g.nx];
-  if (y < g.ny - 1) s += z[p + g.nx];
+  if (x > 0) s += (double)z[p - 1];
+  if (x < g.nx - 1) s += (double)z[p + 1];
+  if (y > 0) s += (double)z[p - g.nx];
+  if (y < g.ny - 1) s += (double)z[p + g.nx];
   if (D3) {
     const int zz = rest / g.ny;
     const int plane = g.nx * g.ny;
-    if (zz > 0) s += z[p - plane];
-    if (zz < g.nz - 1) s += z[p + plane];
+    if (zz > 0) s += (double)z[p - plane];
+    if (zz < g.nz - 1) s += (double)z[p + plane];
   }
   return s;
 }
@@ -100,8 +108,8 @@ __device__ inline double neighbour_sum(const double *z, int p, const Grid &g) {
 // FAST (a full chunk and an even nx): both unknowns of a thread share a row,
 // x-neighbours come from the adjacent lanes (consecutive pairs), the rows and
 // planes above and below are 16-byte loads.  Called by all 64 lanes together.
-template <int V, bool D3, bool FAST>
-__device__ inline void apply_stencil(const double *z, int idx, const Vals<V> &zc, const Grid &g,
+template <int V, bool D3, bool FAST, typename S>
+__device__ inline void apply_stencil(const S *z, int idx, const Vals<V, S> &zc, const Grid &g,
                                      double (&w)[V]) {
   const double diag = D3 ? 6.0 : 4.0;
   if constexpr (FAST && V == 2) {
@@ -111,18 +119,18 @@ __device__ inline void apply_stencil(const double *z, int idx, const Vals<V> &zc
     const int lane = threadIdx.x & 63;
     double left = __shfl_up(zc.v[1], 1, 64);     // z[idx-1] held by the previous lane
     double right = __shfl_down(zc.v[0], 1, 64);  // z[idx+2] held by the next lane
-    if (lane == 0 && x > 0) left = z[idx - 1];
-    if (lane == 63 && x + 2 < g.nx) right = z[idx + 2];
+    if (lane == 0 && x > 0) left = (double)z[idx - 1];
+    if (lane == 63 && x + 2 < g.nx) right = (double)z[idx + 2];
     double s0 = (x > 0 ? left : 0.0) + zc.v[1];
     double s1 = zc.v[0] + (x + 2 < g.nx ? right : 0.0);
     if (y > 0) {
-      Vals<2> u;
+      Vals<2, S> u;
       u.load(z + idx - g.nx);
       s0 += u.v[0];
       s1 += u.v[1];
     }
     if (y < g.ny - 1) {
-      Vals<2> d;
+      Vals<2, S> d;
       d.load(z + idx + g.nx);
       s0 += d.v[0];
       s1 += d.v[1];
@@ -131,13 +139,13 @@ __device__ inline void apply_stencil(const double *z, int idx, const Vals<V> &zc
       const int zz = rest / g.ny;
       const int plane = g.nx * g.ny;
       if (zz > 0) {
-        Vals<2> f;
+        Vals<2, S> f;
         f.load(z + idx - plane);
         s0 += f.v[0];
         s1 += f.v[1];
       }
       if (zz < g.nz - 1) {
-        Vals<2> k;
+        Vals<2, S> k;
         k.load(z + idx + plane);
         s0 += k.v[0];
         s1 += k.v[1];
@@ -147,7 +155,7 @@ __device__ inline void apply_stencil(const double *z, int idx, const Vals<V> &zc
     w[1] = diag * zc.v[1] - s1;
   } else {
 #pragma unroll
-    for (int v = 0; v < V; ++v) w[v] = diag * zc.v[v] - neighbour_sum<D3>(z, idx + v, g);
+    for (int v = 0; v < V; ++v) w[v] = diag * zc.v[v] - neighbour_sum<D3, S>(z, idx + v, g);
   }
 }
 
@@ -320,21 +328,22 @@ struct Coef {
   double sig[L];
 };
 
-template <int L, bool D3>
+template <int L, bool D3, typename S>
 struct Sweep {
+  using Args = SweepArgsT<S>;
   static constexpr int ND = L + 1;
 
   // Steady state, i >= l: K1 (SpMV of z^{(l)}_i), K4 (all basis recurrences,
   // Eqs. all_z_rec2 and specific_z_rec), K6 (p_t, x_t; Eqs. pdir, x_a2) and
   // K5 (the l+1 products that start column i+1 of G).
   template <int V, bool FAST>
-  __device__ static inline void steady(const SweepArgs &a, const Grid &g, int idx, int t,
+  __device__ static inline void steady(const Args &a, const Grid &g, int idx, int t,
                                        const Coef<L> &cf, double (&acc)[ND]) {
-    Vals<V> zc, zp;
+    Vals<V, S> zc, zp;
     zc.load(a.zl[0] + idx);
     zp.load(a.zl[1] + idx);
     double w[V];
-    apply_stencil<V, D3, FAST>(a.zl[0], idx, zc, g, w);
+    apply_stencil<V, D3, FAST, S>(a.zl[0], idx, zc, g, w);
     double zn[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) zn[v] = ((w[v] - cf.gam * zc.v[v]) - cf.dm1 * zp.v[v]) * cf.inv_del;
@@ -342,7 +351,7 @@ struct Sweep {
     // z^{(l)}_{i+1-R}) is overwritten below.
 #pragma unroll
     for (int m = 1; m <= L - 3; ++m) {
-      Vals<V> zh;
+      Vals<V, S> zh;
       zh.load(a.zl[L - 1 - m] + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[m] += zn[v] * zh.v[v];
@@ -352,10 +361,10 @@ struct Sweep {
     for (int v = 0; v < V; ++v) above[v] = zc.v[v];
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
-      Vals<V> ck, pk;
+      Vals<V, S> ck, pk;
       ck.load(a.zk_cur[k] + idx);
       if (t >= 1) pk.load(a.zk_prev[k] + idx); else pk.zero();
-      Vals<V> nk;
+      Vals<V, S> nk;
       const double sk = cf.sig[k] - cf.gam;
 #pragma unroll
       for (int v = 0; v < V; ++v) nk.v[v] = ((above[v] + sk * ck.v[v]) - cf.dm1 * pk.v[v]) * cf.inv_del;
@@ -370,12 +379,12 @@ struct Sweep {
         }
       }
     }
-    Vals<V> pv;
+    Vals<V, S> pv;
     if (t == 0) {
 #pragma unroll
       for (int v = 0; v < V; ++v) pv.v[v] = vt[v] * cf.inv_eta;
     } else {
-      Vals<V> xv;
+      Vals<V, S> xv;
       pv.load(a.p + idx);
       xv.load(a.x + idx);
 #pragma unroll
@@ -386,7 +395,7 @@ struct Sweep {
       xv.store(a.x + idx);
     }
     pv.store(a.p + idx);
-    Vals<V> out;
+    Vals<V, S> out;
 #pragma unroll
     for (int v = 0; v < V; ++v) out.v[v] = zn[v];
     out.store(a.zl_out + idx);
@@ -402,27 +411,27 @@ struct Sweep {
   // Start-up, i < l: z^{(l)}_{i+1} = (A - sigma_i) z^{(l)}_i, copied into basis
   // i+1; products (z_{i+1}, z_j), j >= 0, and (z_l, v_0) when i = l-1.
   template <int V, bool FAST>
-  __device__ static inline void startup(const SweepArgs &a, const Grid &g, int idx, int i,
+  __device__ static inline void startup(const Args &a, const Grid &g, int idx, int i,
                                         double sigma_i, double (&acc)[ND]) {
-    Vals<V> zc;
+    Vals<V, S> zc;
     zc.load(a.zl[0] + idx);
     double w[V];
-    apply_stencil<V, D3, FAST>(a.zl[0], idx, zc, g, w);
-    Vals<V> zn;
+    apply_stencil<V, D3, FAST, S>(a.zl[0], idx, zc, g, w);
+    Vals<V, S> zn;
 #pragma unroll
     for (int v = 0; v < V; ++v) zn.v[v] = w[v] - sigma_i * zc.v[v];
 #pragma unroll
     for (int m = 1; m <= L - 2; ++m) {
       const int h = L - 1 - m;
       if (h <= i) {
-        Vals<V> zh;
+        Vals<V, S> zh;
         zh.load(a.zl[h] + idx);
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[m] += zn.v[v] * zh.v[v];
       }
     }
     if (a.v0 != nullptr) {
-      Vals<V> vz;
+      Vals<V, S> vz;
       vz.load(a.v0 + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[0] += zn.v[v] * vz.v[v];
@@ -437,7 +446,7 @@ struct Sweep {
   }
 
   template <bool FAST>
-  __device__ static inline void chunk(const SweepArgs &a, const Grid &g, int idx, int t,
+  __device__ static inline void chunk(const Args &a, const Grid &g, int idx, int t,
                                       const Coef<L> &cf, double (&acc)[ND]) {
     if (t >= 0) {
       if (idx + 1 < a.n)
@@ -470,9 +479,9 @@ __device__ inline void read_coef(const DevState &s, int i, int t, Coef<L> &cf) {
   for (int k = 0; k < L; ++k) cf.sig[k] = s.sigma[k];
 }
 
-template <int L, bool D3>
-__global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgs a) {
-  using S = Sweep<L, D3>;
+template <int L, bool D3, typename ST>
+__global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) {
+  using S = Sweep<L, D3, ST>;
   constexpr int ND = S::ND;
   __shared__ double lds[4 * ND];
   __shared__ double red[ND];
@@ -788,16 +797,23 @@ __global__ __launch_bounds__(kThreads) void start_kernel(const double *part_in, 
   state_store(&sh, st);
 }
 
-__global__ __launch_bounds__(kThreads) void scale_kernel(const double *r, double *d0, double *d1,
-                                                          double *d2, const DevState *st, int n) {
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scale_kernel(const double *r, T *d0, T *d1, T *d2,
+                                                          const DevState *st, int n) {
   if (st->status != kRunning) return;
   const double inv = 1.0 / st->beta;
   for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads) {
-    const double v = r[p] * inv;
+    const T v = (T)(r[p] * inv);
     if (d0) d0[p] = v;
     if (d1) d1[p] = v;
     if (d2) d2[p] = v;
   }
+}
+
+// x += d: the FP32 correction of one refinement step added to the FP64 iterate.
+__global__ __launch_bounds__(kThreads) void add_correction_kernel(double *x, const float *d, int n) {
+  for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads)
+    x[p] += (double)d[p];
 }
 
 template <bool D3>
@@ -826,28 +842,37 @@ static int simple_blocks(int64_t n) {
   return (int)b;
 }
 
-template <int L>
-static hipError_t launch_sweep_l(const SweepArgs &a, hipStream_t s) {
+template <int L, typename S>
+static hipError_t launch_sweep_l(const SweepArgsT<S> &a, hipStream_t s) {
   const int grid = a.nstream + (L >= 2 ? 1 : 0);
   if (a.d3)
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S>), dim3(grid), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, false, S>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_plcg_sweep(const SweepArgs &a, hipStream_t s) {
+template <typename S>
+static hipError_t launch_sweep_any(const SweepArgsT<S> &a, hipStream_t s) {
   switch (a.l) {
-    case 1: return launch_sweep_l<1>(a, s);
-    case 2: return launch_sweep_l<2>(a, s);
-    case 3: return launch_sweep_l<3>(a, s);
-    case 4: return launch_sweep_l<4>(a, s);
-    case 5: return launch_sweep_l<5>(a, s);
-    case 6: return launch_sweep_l<6>(a, s);
-    case 7: return launch_sweep_l<7>(a, s);
-    case 8: return launch_sweep_l<8>(a, s);
+    case 1: return launch_sweep_l<1, S>(a, s);
+    case 2: return launch_sweep_l<2, S>(a, s);
+    case 3: return launch_sweep_l<3, S>(a, s);
+    case 4: return launch_sweep_l<4, S>(a, s);
+    case 5: return launch_sweep_l<5, S>(a, s);
+    case 6: return launch_sweep_l<6, S>(a, s);
+    case 7: return launch_sweep_l<7, S>(a, s);
+    case 8: return launch_sweep_l<8, S>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_plcg_sweep(const SweepArgsT<double> &a, hipStream_t s) {
+  return launch_sweep_any<double>(a, s);
+}
+
+hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s) {
+  return launch_sweep_any<float>(a, s);
 }
 
 hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s) {
@@ -885,8 +910,20 @@ hipError_t launch_start(const double *part_in, int nparts, DevState *st, HostSta
 
 hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, const DevState *st,
                         int n, hipStream_t s) {
-  hipLaunchKernelGGL(scale_kernel, dim3(simple_blocks(n)), dim3(kThreads), 0, s, r, d0, d1, d2,
-                     st, n);
+  hipLaunchKernelGGL(scale_kernel<double>, dim3(simple_blocks(n)), dim3(kThreads), 0, s, r, d0, d1,
+                     d2, st, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double *r, float *d0, float *d1, float *d2, const DevState *st, int n,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel<float>, dim3(simple_blocks(n)), dim3(kThreads), 0, s, r, d0, d1,
+                     d2, st, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_correction(double *x, const float *d, int n, hipStream_t s) {
+  hipLaunchKernelGGL(add_correction_kernel, dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, d, n);
   return hipGetLastError();
 }
 

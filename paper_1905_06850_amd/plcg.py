@@ -27,6 +27,8 @@ PLCG_OP_STENCIL2D5 = 1
 PLCG_OP_STENCIL3D7 = 2
 PLCG_METHOD_CG = 0
 PLCG_METHOD_PLCG = 1
+PLCG_PREC_FP64 = 0
+PLCG_PREC_FP32_REFINED = 1
 
 REASONS = {0: "none", 1: "converged", 2: "maxit", 3: "breakdown_limit", 4: "nonfinite",
            5: "breakdown"}
@@ -42,7 +44,8 @@ class plcg_config(ctypes.Structure):
                 ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
                 ("shifts", ctypes.POINTER(ctypes.c_double)),
                 ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
-                ("history_cap", ctypes.c_int32)]
+                ("history_cap", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double)]
 
 
 class plcg_result(ctypes.Structure):
@@ -50,7 +53,8 @@ class plcg_result(ctypes.Structure):
                 ("restarts", ctypes.c_int32), ("reason", ctypes.c_int32),
                 ("rnorm0", ctypes.c_double), ("rec_relres", ctypes.c_double),
                 ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("sweep_ms", ctypes.c_double), ("sweeps", ctypes.c_int64)]
+                ("sweep_ms", ctypes.c_double), ("sweeps", ctypes.c_int64),
+                ("outer", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -132,7 +136,8 @@ class Solver:
     """Convenience owner of one plcg_handle."""
 
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
-                 check_every=0, max_restarts=-1, history_cap=0):
+                 check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
+                 inner_tol=0.0):
         self.desc = _dims_desc(kind, dims)
         self._shifts = None
         sp = None
@@ -140,8 +145,9 @@ class Solver:
             self._shifts = (ctypes.c_double * len(shifts))(*shifts)
             sp = ctypes.cast(self._shifts, ctypes.POINTER(ctypes.c_double))
         m = PLCG_METHOD_CG if method == "cg" else PLCG_METHOD_PLCG
+        prec = PLCG_PREC_FP32_REFINED if precision == "fp32" else PLCG_PREC_FP64
         self.cfg = plcg_config(m, int(l), float(lmin), float(lmax), sp, int(check_every),
-                               int(max_restarts), int(history_cap))
+                               int(max_restarts), int(history_cap), prec, float(inner_tol))
         self.method = method
         self.l = int(l)
         self.handle = _h()

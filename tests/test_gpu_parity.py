@@ -333,3 +333,51 @@ def test_full_size_against_stored_oracle(dev, name):
     assert est < 1e-8
     assert abs(np.linalg.norm(x) - g["xnorm"]) <= 1e-8 * g["xnorm"]
     s.close()
+
+
+# ------------------------------------------------------------ mixed precision --
+
+def _mixed_oracle(dims, l, b, tol, inner_tol, maxit=20000, max_outer=50):
+    from oracle import refine
+    A = operators.laplacian(dims)
+    lo, hi = _interval(dims)
+    return refine.refine(A, b, np.zeros(A.n), l, shifts.chebyshev_shifts(l, lo, hi), tol,
+                         inner_tol, maxit, max_outer=max_outer)
+
+
+@pytest.mark.parametrize("dims,l,tol,inner_tol", [((48, 48, 48), 3, 1e-10, 1e-3),
+                                                  ((48, 48, 48), 3, 1e-10, 1e-5),
+                                                  ((64, 64), 1, 1e-10, 1e-3),
+                                                  ((100, 37), 2, 1e-10, 1e-4)])
+def test_mixed_precision_against_oracle(dev, dims, l, tol, inner_tol):
+    """FP32-stored inner p(l)-CG inside FP64 refinement against the oracle's
+    model of the same arithmetic (oracle.refine): both reach the FP64 tolerance,
+    with the same number of refinement steps (within 1) and inner iteration
+    counts within 10 %; the solutions agree within kappa times the tolerance."""
+    n = int(np.prod(dims))
+    b = synth.uniform(n, 0)
+    ref = _mixed_oracle(dims, l, b, tol, inner_tol)
+    x, res, s = gpu_solve(dev, dims, "plcg", l, b, np.zeros(n), tol, 20000, precision="fp32",
+                          inner_tol=inner_tol)
+    assert ref.reason == "converged" and res.reason == 1
+    assert res.true_relres < tol and ref.true_relres < tol
+    assert abs(res.outer - ref.outer) <= 1
+    assert abs(res.iters - ref.inner_iters) <= 0.1 * ref.inner_iters + 2
+    lmin, lmax = operators.laplacian_extremes(dims)
+    assert _rel(x, ref.x) <= (lmax / lmin) * 2 * tol
+    s.close()
+
+
+def test_mixed_precision_first_inner_steps(dev):
+    """After a few inner iterations the FP32-stored GPU iterate equals the oracle's
+    FP32-stored iterate to FP32 rounding."""
+    dims = (40, 30)
+    n = 1200
+    b = synth.uniform(n, 2)
+    for m in (1, 3, 8):
+        ref = _mixed_oracle(dims, 2, b, 1e-30, 1e-30, maxit=m, max_outer=1)
+        x, res, s = gpu_solve(dev, dims, "plcg", 2, b, np.zeros(n), 1e-30, m, precision="fp32",
+                              inner_tol=1e-30)
+        assert res.iters == m == ref.inner_iters and res.outer == 1 == ref.outer
+        assert _rel(x, ref.x) < 1e-6
+        s.close()

@@ -103,7 +103,7 @@ def _mut_LU_zeta_sign(gam, dlt, eta, lam, zeta, t, beta):
         zeta[t] = lam[t] * zeta[t - 1]
 
 
-def _mut_basis_sigma_sign(z, gam, dlt, sigma, t, l, i):
+def _mut_basis_sigma_sign(z, gam, dlt, sigma, t, l, i, store=None):
     dm1 = dlt[t - 1] if t >= 1 else 0.0
     for k in range(l):
         new = z[k + 1][t + k + 1] - (sigma[k] - gam[t]) * z[k][t + k]
@@ -116,7 +116,7 @@ def _mut_basis_sigma_sign(z, gam, dlt, sigma, t, l, i):
     z[l][i + 1] = new / dlt[t]
 
 
-def _mut_basis_wrong_shift_index(z, gam, dlt, sigma, t, l, i):
+def _mut_basis_wrong_shift_index(z, gam, dlt, sigma, t, l, i, store=None):
     dm1 = dlt[t - 1] if t >= 1 else 0.0
     for k in range(l):
         new = z[k + 1][t + k + 1] + (sigma[l - 1 - k] - gam[t]) * z[k][t + k]
