@@ -167,6 +167,86 @@ plcg_status plcg_copy(const double *d_src, double *d_dst, int64_t n, void *strea
 /* Library version, major*10000 + minor*100 + patch. */
 int32_t plcg_version(void);
 
+/* ------------------------------------------------------------------------
+ * Batched and served solves.
+ *
+ * A batch holds up to max_slots independent systems at once, each in a slot of
+ * HBM sized by its footprint.  One launch ("tick") advances every system by one
+ * step: setup, one p(l)-CG iteration, or the final residual and report.  A
+ * system's result does not depend on which other systems share the batch.
+ * The operator of a batched system is the variable-coefficient Laplacian
+ * (A u)_p = sum_q c_pq (u_p - u_q) over the grid edges incident to p (edges to
+ * the Dirichlet boundary included, u = 0 outside), solved in its symmetrically
+ * Jacobi-scaled form D^{-1/2} A D^{-1/2} (unit diagonal, spectrum in (0, 2)),
+ * with Chebyshev shifts on [lambda_min, lambda_max] (default [0, 2]).  The
+ * stopping test is on the scaled residual; the original-space residual is
+ * reported beside it.
+ * ------------------------------------------------------------------------ */
+
+typedef struct plcg_batch plcg_batch;
+
+typedef struct {
+  int32_t l;              /* pipeline length, 2..5 (coefficients are used one launch late) */
+  double lambda_min;      /* Chebyshev interval for the scaled operator; both 0: [0, 2] */
+  double lambda_max;
+  int32_t max_slots;      /* systems in flight, >= 1 */
+  int64_t arena_bytes;    /* device memory reserved for the systems' data */
+  int32_t chunks_per_block; /* unknowns per workgroup = 512 * this; <= 0: autotune */
+  int32_t max_restarts;   /* < 0: default 100 */
+  int32_t use_graph;      /* 1: replay groups of ticks from a captured hipGraph */
+  int32_t pad;
+} plcg_batch_config;
+
+typedef struct {
+  int32_t kind;           /* PLCG_OP_STENCIL2D5 or PLCG_OP_STENCIL3D7 */
+  int32_t nx, ny, nz;     /* grid extents (nz = 1 in 2D) */
+  const double *cx;       /* host, edge coefficients c > 0 between x-neighbours: per row (y, z)
+                             nx+1 values, the first and last being the boundary edges;
+                             NULL: all 1 */
+  const double *cy;       /* host, per (z, x) column ny+1 values stored as [z][y][x] with y in
+                             0..ny (edge between y-1 and y); NULL: all 1 */
+  const double *cz;       /* host, 3D only, [z][y][x] with z in 0..nz; NULL: all 1 */
+} plcg_system_desc;
+
+/* Create an empty batch on the current HIP device. */
+plcg_status plcg_batch_create(const plcg_batch_config *cfg, plcg_batch **out);
+
+/* Device bytes a system takes in the batch arena (work vectors + scaled operator). */
+int64_t plcg_batch_footprint(const plcg_batch *b, const plcg_system_desc *sys);
+
+/* Admit one system: d_b, d_x device vectors of n doubles (x0 on entry, solution
+ * once polled done), tol relative to the initial scaled residual, maxit x-updates.
+ * Copies and scales the coefficients (enqueued on `stream`).  PLCG_E_BUSY when
+ * no slot or not enough arena space is free (nothing is changed then). */
+plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const double *d_b,
+                           double *d_x, double tol, int32_t maxit, void *stream,
+                           uint64_t *ticket);
+
+/* Enqueue `ticks` launches on `stream` (returns without waiting). */
+plcg_status plcg_batch_step(plcg_batch *b, int32_t ticks, void *stream);
+
+/* PLCG_NOT_READY until the system of `ticket` is done; then PLCG_OK with the
+ * result (iters, restarts, reason; rnorm0 = original-space ||b - A x0||,
+ * rec_relres = scaled residual, true_relres = original-space residual) and the
+ * slot is freed.  PLCG_E_INVALID for an unknown ticket. */
+plcg_status plcg_batch_poll(plcg_batch *b, uint64_t ticket, plcg_result *out);
+
+/* Systems admitted and not yet polled done. */
+int32_t plcg_batch_active(const plcg_batch *b);
+
+/* Workgroups per launch in the current schedule (0 when nothing is admitted). */
+int32_t plcg_batch_grid(const plcg_batch *b);
+
+/* Chunks (512 unknowns) per workgroup in use (after autotuning: the choice made). */
+int32_t plcg_batch_chunks_per_block(const plcg_batch *b);
+
+/* Autotuner: time `ticks` launches for each candidate workgroup size on the
+ * systems currently admitted (the launches advance the solves) and keep the
+ * fastest per unknown.  Blocks the host. */
+plcg_status plcg_batch_autotune(plcg_batch *b, int32_t ticks, void *stream);
+
+plcg_status plcg_batch_destroy(plcg_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

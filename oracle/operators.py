@@ -98,3 +98,49 @@ def laplacian_extremes(dims):
     lmin = sum(4.0 * np.sin(np.pi / (2.0 * (n + 1))) ** 2 for n in dims)
     lmax = sum(4.0 * np.cos(np.pi / (2.0 * (n + 1))) ** 2 for n in dims)
     return lmin, lmax
+
+
+def variable_laplacian(dims, cx, cy, cz=None):
+    """Variable-coefficient Dirichlet Laplacian and its Jacobi scaling.
+
+    (A u)_p = sum over the grid edges (p, q) incident to p of c_pq (u_p - u_q),
+    with u = 0 outside the grid, so the diagonal d_p is the sum of all edges at
+    p (boundary edges included) and A is an SPD M-matrix.  Returns (A, As, dis)
+    where As = D^{-1/2} A D^{-1/2} and dis = D^{-1/2} (diagonal of As is 1).
+    Edge layouts as in synth.edge_coefficients.
+    """
+    dims = tuple(int(d) for d in dims)
+    d3 = len(dims) == 3
+    nx, ny = dims[0], dims[1]
+    nz = dims[2] if d3 else 1
+    CX = np.asarray(cx, dtype=float).reshape(nz, ny, nx + 1)
+    CY = np.asarray(cy, dtype=float).reshape(nz, ny + 1, nx)
+    CZ = np.asarray(cz, dtype=float).reshape(nz + 1, ny, nx) if d3 else None
+    diag = CX[:, :, :-1] + CX[:, :, 1:] + CY[:, :-1, :] + CY[:, 1:, :]
+    if d3:
+        diag = diag + CZ[:-1] + CZ[1:]
+    W = CX[:, :, 1:-1]          # interior x-edges between (x, x+1)
+    N = CY[:, 1:-1, :]          # interior y-edges
+    T = CZ[1:-1] if d3 else None
+
+    def apply(u):
+        U = u.reshape(nz, ny, nx)
+        out = diag * U
+        out[:, :, :-1] -= W * U[:, :, 1:]
+        out[:, :, 1:] -= W * U[:, :, :-1]
+        out[:, :-1, :] -= N * U[:, 1:, :]
+        out[:, 1:, :] -= N * U[:, :-1, :]
+        if d3:
+            out[:-1] -= T * U[1:]
+            out[1:] -= T * U[:-1]
+        return out.reshape(-1)
+
+    dis = (1.0 / np.sqrt(diag)).reshape(-1)
+
+    def apply_scaled(u):
+        return dis * apply(dis * u)
+
+    n = nx * ny * nz
+    apply.n = n
+    apply_scaled.n = n
+    return apply, apply_scaled, dis

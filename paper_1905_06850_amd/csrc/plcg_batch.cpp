@@ -1,0 +1,538 @@
+// Host side of batched and served solves: slots, HBM arena, schedule, ticks.
+//
+// Admission: a system needs (2l + R + 1) work vectors plus its scaled operator
+// (edge weights and D^{-1/2}); it is admitted when a slot and a first-fit block
+// of the arena are free.  The coefficients are scaled here, on the host, as part
+// of the operator setup: d_p = sum of the edges incident to p, s_pq = c_pq /
+// sqrt(d_p d_q).  The schedule lists, for every admitted slot, one owner
+// workgroup and the slot's streaming workgroups; it is rebuilt when slots come
+// or go and uploaded on the stream, so launches already enqueued keep theirs.
+#include "plcg_internal.h"
+
+#include "../../include/plcg.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace plcg;
+
+namespace {
+
+#define BHIP(call)                                                                    \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return set_last_error(PLCG_E_HIP, (std::string(#call) + ": " + hipGetErrorString(e_)).c_str()); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Block {
+  size_t off, size;
+};
+
+}  // namespace
+
+struct plcg_batch {
+  plcg_batch_config cfg{};
+  int l = 2, R = 2, device = 0;
+  double sigma[kLMax] = {0};
+  int cpb = 4;                          // chunks per streaming workgroup
+  // device
+  char *arena = nullptr;
+  size_t arena_size = 0;
+  SlotDesc *d_slots = nullptr;
+  BatchState *d_state = nullptr;
+  double *d_part = nullptr;
+  int2 *d_sched = nullptr;
+  uint64_t *d_tickets = nullptr;
+  SlotReport *reports = nullptr;        // mapped pinned host memory
+  SlotReport *d_reports = nullptr;
+  size_t sched_cap = 0;
+  // host mirrors
+  std::vector<SlotDesc> slots;
+  std::vector<int> in_use;              // 1 while a system occupies the slot
+  std::vector<uint64_t> tickets;
+  std::vector<Block> slot_mem;
+  std::vector<Block> free_list;         // sorted by offset
+  std::map<uint64_t, int> ticket_slot;
+  uint64_t next_ticket = 1;
+  std::vector<int2> sched;
+  bool dirty = true;
+  int64_t tick = 0;
+  // graph of a group of ticks for the current schedule
+  hipGraphExec_t gexec = nullptr;
+  int graph_ticks = 0;
+};
+
+namespace {
+
+void free_graph(plcg_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->graph_ticks = 0;
+}
+
+bool arena_alloc(plcg_batch *b, size_t size, size_t *off) {
+  for (size_t k = 0; k < b->free_list.size(); ++k) {
+    Block &f = b->free_list[k];
+    if (f.size >= size) {
+      *off = f.off;
+      f.off += size;
+      f.size -= size;
+      if (f.size == 0) b->free_list.erase(b->free_list.begin() + k);
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_free(plcg_batch *b, Block blk) {
+  auto it = std::lower_bound(b->free_list.begin(), b->free_list.end(), blk.off,
+                             [](const Block &x, size_t off) { return x.off < off; });
+  it = b->free_list.insert(it, blk);
+  // merge with neighbours
+  size_t k = it - b->free_list.begin();
+  if (k + 1 < b->free_list.size() && b->free_list[k].off + b->free_list[k].size == b->free_list[k + 1].off) {
+    b->free_list[k].size += b->free_list[k + 1].size;
+    b->free_list.erase(b->free_list.begin() + k + 1);
+  }
+  if (k > 0 && b->free_list[k - 1].off + b->free_list[k - 1].size == b->free_list[k].off) {
+    b->free_list[k - 1].size += b->free_list[k].size;
+    b->free_list.erase(b->free_list.begin() + k);
+  }
+}
+
+struct Layout {
+  int64_t n;
+  size_t vstride, nsx, nsy, nsz, bytes;
+};
+
+int32_t layout(const plcg_batch *b, const plcg_system_desc *sys, Layout *L) {
+  if (sys == nullptr) return PLCG_E_INVALID;
+  if (sys->kind != PLCG_OP_STENCIL2D5 && sys->kind != PLCG_OP_STENCIL3D7) return PLCG_E_INVALID;
+  const bool d3 = sys->kind == PLCG_OP_STENCIL3D7;
+  const int64_t nx = sys->nx, ny = sys->ny, nz = d3 ? sys->nz : 1;
+  if (nx < 1 || ny < 1 || nz < 1 || (!d3 && sys->nz > 1)) return PLCG_E_INVALID;
+  L->n = nx * ny * nz;
+  if (L->n >= (1LL << 31) - 4 * kChunk) return PLCG_E_INVALID;
+  L->vstride = round_up((size_t)L->n * 8, kAlign) / 8;
+  L->nsx = (size_t)(nx + 1) * ny * nz;
+  L->nsy = (size_t)nx * (ny + 1) * nz;
+  L->nsz = d3 ? (size_t)nx * ny * (nz + 1) : 0;
+  const int nvec = 2 * b->l + b->R + 1;
+  L->bytes = (size_t)nvec * L->vstride * 8 + round_up(L->nsx * 8, kAlign) +
+             round_up(L->nsy * 8, kAlign) + round_up(L->nsz * 8, kAlign) +
+             round_up((size_t)L->n * 8, kAlign);
+  return PLCG_OK;
+}
+
+int blocks_for(const plcg_batch *b, int nchunks) {
+  int nb = (nchunks + b->cpb - 1) / b->cpb;
+  return std::max(1, std::min(nb, kMaxStream));
+}
+
+void rebuild_schedule(plcg_batch *b) {
+  b->sched.clear();
+  for (size_t s = 0; s < b->slots.size(); ++s) {
+    if (!b->in_use[s]) continue;
+    b->sched.push_back(make_int2((int)s, -1));
+    for (int k = 0; k < b->slots[s].nblocks; ++k) b->sched.push_back(make_int2((int)s, k));
+  }
+}
+
+int32_t upload_schedule(plcg_batch *b, hipStream_t st) {
+  rebuild_schedule(b);
+  if (b->sched.size() > b->sched_cap) {
+    // enqueued launches may still read the old table: wait for them first
+    BHIP(hipStreamSynchronize(st));
+    if (b->d_sched) BHIP(hipFree(b->d_sched));
+    b->sched_cap = std::max<size_t>(b->sched.size() * 2, 1024);
+    BHIP(hipMalloc(reinterpret_cast<void **>(&b->d_sched), b->sched_cap * sizeof(int2)));
+  }
+  if (!b->sched.empty()) {
+    BHIP(hipMemcpyAsync(b->d_sched, b->sched.data(), b->sched.size() * sizeof(int2),
+                        hipMemcpyHostToDevice, st));
+    // the host vector is rebuilt on the next change: let the copy read it first
+    BHIP(hipStreamSynchronize(st));
+  }
+  free_graph(b);
+  b->dirty = false;
+  return PLCG_OK;
+}
+
+int32_t launch_ticks(plcg_batch *b, int ticks, hipStream_t st) {
+  BatchArgs a;
+  a.slots = b->d_slots;
+  a.state = b->d_state;
+  a.part = b->d_part;
+  a.sched = b->d_sched;
+  a.reports = b->d_reports;
+  a.tickets = b->d_tickets;
+  a.l = b->l;
+  const int grid = (int)b->sched.size();
+  for (int k = 0; k < ticks; ++k) {
+    a.tick = (int32_t)(b->tick & 1);
+    BHIP(launch_batch_tick(a, grid, st));
+    ++b->tick;
+  }
+  return PLCG_OK;
+}
+
+constexpr int kGraphTicks = 16;   // even, so a replay starts and ends on the same parity
+
+int32_t run_ticks(plcg_batch *b, int ticks, hipStream_t st) {
+  if (b->dirty) {
+    int32_t e = upload_schedule(b, st);
+    if (e != PLCG_OK) return e;
+  }
+  if (b->sched.empty()) return PLCG_OK;
+  if (!b->cfg.use_graph) return launch_ticks(b, ticks, st);
+  // Replay whole groups from the graph; the remainder and parity fix-ups directly.
+  if ((b->tick & 1) && ticks > 0) {
+    int32_t e = launch_ticks(b, 1, st);
+    if (e != PLCG_OK) return e;
+    --ticks;
+  }
+  if (ticks >= kGraphTicks && b->gexec == nullptr) {
+    hipStream_t cap;
+    BHIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g;
+    int64_t saved = b->tick;
+    hipError_t he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    int32_t e = he == hipSuccess ? launch_ticks(b, kGraphTicks, cap) : PLCG_E_HIP;
+    hipError_t he2 = hipStreamEndCapture(cap, &g);
+    b->tick = saved;
+    (void)hipStreamDestroy(cap);
+    if (e != PLCG_OK || he2 != hipSuccess) return set_last_error(PLCG_E_HIP, "graph capture failed");
+    BHIP(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    b->graph_ticks = kGraphTicks;
+  }
+  while (ticks >= kGraphTicks && b->gexec) {
+    BHIP(hipGraphLaunch(b->gexec, st));
+    b->tick += kGraphTicks;
+    ticks -= kGraphTicks;
+  }
+  return launch_ticks(b, ticks, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+plcg_status plcg_batch_create(const plcg_batch_config *cfg, plcg_batch **out) {
+  if (out == nullptr || cfg == nullptr) return set_last_error(PLCG_E_INVALID, "NULL argument");
+  *out = nullptr;
+  if (cfg->l < 2 || cfg->l > 5) return set_last_error(PLCG_E_INVALID, "batched l must be in 2..5");
+  if (cfg->max_slots < 1 || cfg->max_slots > 65536)
+    return set_last_error(PLCG_E_INVALID, "max_slots must be in 1..65536");
+  if (cfg->arena_bytes <= 0) return set_last_error(PLCG_E_INVALID, "arena_bytes must be > 0");
+  double lo = cfg->lambda_min, hi = cfg->lambda_max;
+  if (lo == 0.0 && hi == 0.0) hi = 2.0;
+  if (!(hi > lo)) return set_last_error(PLCG_E_INVALID, "need lambda_min < lambda_max");
+  plcg_batch *b = new plcg_batch();
+  b->cfg = *cfg;
+  b->cfg.lambda_min = lo;
+  b->cfg.lambda_max = hi;
+  if (b->cfg.max_restarts < 0) b->cfg.max_restarts = 100;
+  b->l = cfg->l;
+  b->R = b->l - 1 > 2 ? b->l - 1 : 2;
+  b->cpb = cfg->chunks_per_block > 0 ? cfg->chunks_per_block : 4;
+  // Eq. (chebyshev)
+  for (int i = 0; i < b->l; ++i)
+    b->sigma[i] = 0.5 * (hi + lo) + 0.5 * (hi - lo) * std::cos((2 * i + 1) * M_PI / (2 * b->l));
+  const int S = cfg->max_slots;
+  b->slots.assign(S, SlotDesc{});
+  b->in_use.assign(S, 0);
+  b->tickets.assign(S, 0);
+  b->slot_mem.assign(S, Block{0, 0});
+  b->arena_size = round_up((size_t)cfg->arena_bytes, kAlign);
+  auto bad = [&](const char *what, hipError_t e) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (b->arena) (void)hipFree(b->arena);
+    if (b->d_slots) (void)hipFree(b->d_slots);
+    if (b->d_state) (void)hipFree(b->d_state);
+    if (b->d_part) (void)hipFree(b->d_part);
+    if (b->d_tickets) (void)hipFree(b->d_tickets);
+    if (b->reports) (void)hipHostFree(b->reports);
+    delete b;
+    return set_last_error(PLCG_E_NOMEM, m.c_str());
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&b->device)) != hipSuccess) return bad("hipGetDevice", e);
+  if ((e = hipMalloc(reinterpret_cast<void **>(&b->arena), b->arena_size)) != hipSuccess)
+    return bad("hipMalloc(arena)", e);
+  if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_slots), sizeof(SlotDesc) * S)) != hipSuccess)
+    return bad("hipMalloc(slots)", e);
+  if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_state), sizeof(BatchState) * 2 * S)) !=
+      hipSuccess)
+    return bad("hipMalloc(state)", e);
+  const size_t part_bytes = sizeof(double) * (size_t)S * 2 * (b->l + 1) * kMaxStream;
+  if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_part), part_bytes)) != hipSuccess)
+    return bad("hipMalloc(partials)", e);
+  if ((e = hipMalloc(reinterpret_cast<void **>(&b->d_tickets), sizeof(uint64_t) * S)) != hipSuccess)
+    return bad("hipMalloc(tickets)", e);
+  if ((e = hipHostMalloc(reinterpret_cast<void **>(&b->reports), sizeof(SlotReport) * S,
+                         hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
+    return bad("hipHostMalloc(reports)", e);
+  std::memset(b->reports, 0, sizeof(SlotReport) * S);
+  void *dp = nullptr;
+  if ((e = hipHostGetDevicePointer(&dp, b->reports, 0)) != hipSuccess)
+    return bad("hipHostGetDevicePointer", e);
+  b->d_reports = reinterpret_cast<SlotReport *>(dp);
+  if ((e = hipMemset(b->d_state, 0, sizeof(BatchState) * 2 * S)) != hipSuccess)
+    return bad("hipMemset", e);
+  if ((e = hipMemset(b->d_part, 0, part_bytes)) != hipSuccess) return bad("hipMemset", e);
+  b->free_list.push_back(Block{0, b->arena_size});
+  *out = b;
+  return PLCG_OK;
+}
+
+int64_t plcg_batch_footprint(const plcg_batch *b, const plcg_system_desc *sys) {
+  if (b == nullptr) return -1;
+  Layout L;
+  if (layout(b, sys, &L) != PLCG_OK) return -1;
+  return (int64_t)L.bytes;
+}
+
+plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const double *d_b,
+                           double *d_x, double tol, int32_t maxit, void *stream,
+                           uint64_t *ticket) {
+  if (b == nullptr || ticket == nullptr || d_b == nullptr || d_x == nullptr)
+    return set_last_error(PLCG_E_INVALID, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(d_b) & 15) || (reinterpret_cast<uintptr_t>(d_x) & 15))
+    return set_last_error(PLCG_E_INVALID, "vectors must be 16-byte aligned");
+  if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0)
+    return set_last_error(PLCG_E_INVALID, "need tol > 0 and maxit >= 0");
+  Layout L;
+  if (layout(b, sys, &L) != PLCG_OK) return set_last_error(PLCG_E_INVALID, "bad system descriptor");
+  int slot = -1;
+  for (size_t s = 0; s < b->slots.size(); ++s)
+    if (!b->in_use[s]) {
+      slot = (int)s;
+      break;
+    }
+  if (slot < 0) return set_last_error(PLCG_E_BUSY, "no free slot");
+  size_t off = 0;
+  if (!arena_alloc(b, L.bytes, &off)) return set_last_error(PLCG_E_BUSY, "not enough arena space");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool d3 = sys->kind == PLCG_OP_STENCIL3D7;
+  const int nx = sys->nx, ny = sys->ny, nz = d3 ? sys->nz : 1;
+  const int64_t n = L.n;
+  // Jacobi scaling of the operator (host).
+  std::vector<double> cx(L.nsx, 1.0), cy(L.nsy, 1.0), cz(L.nsz, 1.0);
+  if (sys->cx) std::memcpy(cx.data(), sys->cx, L.nsx * 8);
+  if (sys->cy) std::memcpy(cy.data(), sys->cy, L.nsy * 8);
+  if (d3 && sys->cz) std::memcpy(cz.data(), sys->cz, L.nsz * 8);
+  std::vector<double> dis(n);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+        const int64_t row = y + (int64_t)ny * z;
+        double d = cx[row * (nx + 1) + x] + cx[row * (nx + 1) + x + 1] +
+                   cy[((int64_t)z * (ny + 1) + y) * nx + x] +
+                   cy[((int64_t)z * (ny + 1) + y + 1) * nx + x];
+        if (d3) d += cz[p] + cz[p + (int64_t)nx * ny];
+        if (!(d > 0.0) || !std::isfinite(d)) {
+          arena_free(b, Block{off, L.bytes});
+          return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
+        }
+        dis[p] = 1.0 / std::sqrt(d);
+      }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x <= nx; ++x) {
+        const int64_t row = y + (int64_t)ny * z;
+        const int64_t p = x + (int64_t)nx * row;
+        double &c = cx[row * (nx + 1) + x];
+        c = (x > 0 && x < nx) ? c * dis[p - 1] * dis[p] : 0.0;
+      }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y <= ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        double &c = cy[((int64_t)z * (ny + 1) + y) * nx + x];
+        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+        c = (y > 0 && y < ny) ? c * dis[p - nx] * dis[p] : 0.0;
+      }
+  if (d3)
+    for (int z = 0; z <= nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          double &c = cz[((int64_t)z * ny + y) * nx + x];
+          const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+          const int64_t plane = (int64_t)nx * ny;
+          c = (z > 0 && z < nz) ? c * dis[p - plane] * dis[p] : 0.0;
+        }
+  char *base = b->arena + off;
+  const int nvec = 2 * b->l + b->R + 1;
+  SlotDesc sd{};
+  sd.vec = reinterpret_cast<double *>(base);
+  sd.vstride = (int64_t)L.vstride;
+  char *q = base + (size_t)nvec * L.vstride * 8;
+  sd.sx = reinterpret_cast<double *>(q);
+  q += round_up(L.nsx * 8, kAlign);
+  sd.sy = reinterpret_cast<double *>(q);
+  q += round_up(L.nsy * 8, kAlign);
+  sd.sz = reinterpret_cast<double *>(q);
+  q += round_up(L.nsz * 8, kAlign);
+  sd.dis = reinterpret_cast<double *>(q);
+  sd.b = d_b;
+  sd.x = d_x;
+  sd.nx = nx;
+  sd.ny = ny;
+  sd.nz = nz;
+  sd.d3 = d3 ? 1 : 0;
+  sd.n = (int32_t)n;
+  sd.nchunks = (int32_t)((n + kChunk - 1) / kChunk);
+  sd.nblocks = blocks_for(b, sd.nchunks);
+  sd.maxit = maxit;
+  sd.max_restarts = b->cfg.max_restarts;
+  sd.tol = tol;
+  BatchState bs;
+  std::memset(&bs, 0, sizeof(bs));
+  bs.d.l = b->l;
+  for (int k = 0; k < kLMax; ++k) bs.d.sigma[k] = b->sigma[k];
+  bs.phase = kInit;
+  bs.first = 1;
+  BatchState pair[2] = {bs, bs};
+  const uint64_t tk = b->next_ticket++;
+  // Stream-ordered uploads: launches already enqueued see the slot as it was.
+  BHIP(hipMemcpyAsync(const_cast<double *>(sd.sx), cx.data(), L.nsx * 8, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(const_cast<double *>(sd.sy), cy.data(), L.nsy * 8, hipMemcpyHostToDevice, st));
+  if (d3)
+    BHIP(hipMemcpyAsync(const_cast<double *>(sd.sz), cz.data(), L.nsz * 8, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(const_cast<double *>(sd.dis), dis.data(), n * 8, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(b->d_slots + slot, &sd, sizeof(sd), hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(b->d_state + 2 * slot, pair, sizeof(pair), hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(b->d_tickets + slot, &tk, sizeof(tk), hipMemcpyHostToDevice, st));
+  // host copies are temporaries: make sure the copies have read them
+  BHIP(hipStreamSynchronize(st));
+  b->reports[slot].phase = kInit;
+  b->reports[slot].ticket = tk;
+  b->slots[slot] = sd;
+  b->in_use[slot] = 1;
+  b->tickets[slot] = tk;
+  b->slot_mem[slot] = Block{off, L.bytes};
+  b->ticket_slot[tk] = slot;
+  b->dirty = true;
+  *ticket = tk;
+  return PLCG_OK;
+}
+
+plcg_status plcg_batch_step(plcg_batch *b, int32_t ticks, void *stream) {
+  if (b == nullptr || ticks < 0) return set_last_error(PLCG_E_INVALID, "bad argument");
+  BHIP(hipSetDevice(b->device));
+  return run_ticks(b, ticks, reinterpret_cast<hipStream_t>(stream));
+}
+
+plcg_status plcg_batch_poll(plcg_batch *b, uint64_t ticket, plcg_result *out) {
+  if (b == nullptr) return set_last_error(PLCG_E_INVALID, "NULL batch");
+  auto it = b->ticket_slot.find(ticket);
+  if (it == b->ticket_slot.end()) return set_last_error(PLCG_E_INVALID, "unknown ticket");
+  const int slot = it->second;
+  volatile SlotReport *rp = b->reports + slot;
+  if (rp->phase != kDone || rp->ticket != ticket) return PLCG_NOT_READY;
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->iters = rp->iters;
+    out->restarts = rp->restarts;
+    out->reason = rp->reason;
+    out->rnorm0 = rp->rnorm0;
+    out->rec_relres = rp->res_scaled;
+    out->true_relres = rp->res_orig;
+  }
+  b->in_use[slot] = 0;
+  arena_free(b, b->slot_mem[slot]);
+  b->slot_mem[slot] = Block{0, 0};
+  b->ticket_slot.erase(it);
+  b->dirty = true;
+  return PLCG_OK;
+}
+
+int32_t plcg_batch_active(const plcg_batch *b) {
+  if (b == nullptr) return -1;
+  return (int32_t)b->ticket_slot.size();
+}
+
+int32_t plcg_batch_grid(const plcg_batch *b) {
+  if (b == nullptr) return -1;
+  if (b->dirty) {
+    int g = 0;
+    for (size_t s = 0; s < b->slots.size(); ++s)
+      if (b->in_use[s]) g += 1 + b->slots[s].nblocks;
+    return g;
+  }
+  return (int32_t)b->sched.size();
+}
+
+int32_t plcg_batch_chunks_per_block(const plcg_batch *b) { return b ? b->cpb : -1; }
+
+plcg_status plcg_batch_autotune(plcg_batch *b, int32_t ticks, void *stream) {
+  if (b == nullptr || ticks < 1) return set_last_error(PLCG_E_INVALID, "bad argument");
+  BHIP(hipSetDevice(b->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int cands[] = {1, 2, 4, 8, 16};
+  double best = 1e300;
+  int best_c = b->cpb;
+  hipEvent_t e0, e1;
+  BHIP(hipEventCreate(&e0));
+  BHIP(hipEventCreate(&e1));
+  for (int c : cands) {
+    b->cpb = c;
+    for (size_t s = 0; s < b->slots.size(); ++s)
+      if (b->in_use[s]) {
+        b->slots[s].nblocks = blocks_for(b, b->slots[s].nchunks);
+        BHIP(hipMemcpyAsync(b->d_slots + s, &b->slots[s], sizeof(SlotDesc), hipMemcpyHostToDevice, st));
+      }
+    b->dirty = true;
+    int32_t e = run_ticks(b, 2, st);  // settle: the new partial count reaches the owners
+    if (e != PLCG_OK) return e;
+    BHIP(hipEventRecord(e0, st));
+    if ((e = run_ticks(b, ticks, st)) != PLCG_OK) return e;
+    BHIP(hipEventRecord(e1, st));
+    BHIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BHIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_c = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->cpb = best_c;
+  for (size_t s = 0; s < b->slots.size(); ++s)
+    if (b->in_use[s]) {
+      b->slots[s].nblocks = blocks_for(b, b->slots[s].nchunks);
+      BHIP(hipMemcpyAsync(b->d_slots + s, &b->slots[s], sizeof(SlotDesc), hipMemcpyHostToDevice, st));
+    }
+  b->dirty = true;
+  return PLCG_OK;
+}
+
+plcg_status plcg_batch_destroy(plcg_batch *b) {
+  if (b == nullptr) return PLCG_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  free_graph(b);
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->d_slots) (void)hipFree(b->d_slots);
+  if (b->d_state) (void)hipFree(b->d_state);
+  if (b->d_part) (void)hipFree(b->d_part);
+  if (b->d_sched) (void)hipFree(b->d_sched);
+  if (b->d_tickets) (void)hipFree(b->d_tickets);
+  if (b->reports) (void)hipHostFree(b->reports);
+  delete b;
+  return PLCG_OK;
+}
+
+}  // extern "C"

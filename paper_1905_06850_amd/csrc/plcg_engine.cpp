@@ -56,6 +56,11 @@ int grid_blocks(int nchunks) {
 
 }  // namespace
 
+int32_t plcg::set_last_error(int32_t code, const char *msg) {
+  g_last_error = msg;
+  return code;
+}
+
 struct plcg_handle {
   plcg_operator_desc op{};
   int method = PLCG_METHOD_PLCG;
@@ -323,7 +328,6 @@ plcg_status solve_mixed(plcg_handle *h, const double *b, double *x, double tol, 
 
 plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, int maxit,
                        hipStream_t s, plcg_result *res, TimedLaunch &tl, int *final_slot) {
-  const int l = h->l;
   int total = 0, restarts = 0;
   int64_t spmvs = 0;
   double rref = -1.0;

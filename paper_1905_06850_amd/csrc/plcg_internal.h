@@ -114,3 +114,76 @@ hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int n
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);
 
 }  // namespace plcg
+
+namespace plcg {
+
+// ---------------------------------------------------------------------------
+// Batched solves: many independent systems, each in a slot with its own
+// vectors, scalar state and phase; one launch (a "tick") advances every slot
+// by one step.
+// ---------------------------------------------------------------------------
+
+enum Phase : int32_t {
+  kEmpty = 0,    // no system
+  kInit = 1,     // y = D^{1/2} x0 (the solver works on the Jacobi-scaled system)
+  kResid = 2,    // r = D^{-1/2} b - A~ y into ring slot 0, partial sums of r.r and r.r/dis^2
+  kStart = 3,    // owner: ||r||, start of Alg. 1 (G, status); or stop
+  kScale = 4,    // z_0 = r / ||r|| into ring slot 0 and basis 0
+  kSweep = 5,    // iteration i of Alg. 1
+  kFinal = 6,    // true residual partial sums
+  kFinal2 = 7,   // owner: residual norms; others: x = D^{-1/2} y
+  kReport = 8,   // owner: result to the host (x is final: written by the previous launch)
+  kDone = 9
+};
+
+// Per slot; two copies alternate by tick parity (tick s reads copy (s-1)&1).
+struct BatchState {
+  DevState d;
+  int32_t phase;
+  int32_t i;          // sweep index within the current segment
+  int32_t m;          // x-updates allowed in the current segment
+  int32_t restarts;
+  int32_t total;      // x-updates over all segments
+  int32_t reason;     // PLCG_REASON_* once done
+  int32_t first;      // 1 until the first segment has started
+  int32_t nparts;     // streaming blocks of the previous tick (partials written)
+  double rref_orig;   // ||b - A x0|| in the original (unscaled) norm
+  double res_scaled;  // final ||r~|| / ||r~_0||
+  double res_orig;    // final ||b - A x|| / ||b - A x0||
+};
+
+// Per slot, written by the host at admission.
+struct SlotDesc {
+  double *vec;                          // bases 2l, ring R, p: consecutive, vstride apart
+  const double *sx, *sy, *sz, *dis;     // scaled edge weights, D^{-1/2}
+  const double *b;                      // caller's right-hand side
+  double *x;                            // caller's x0 on entry, solution at the end
+  int64_t vstride;
+  int32_t nx, ny, nz, d3, n, nchunks, nblocks, maxit;
+  int32_t max_restarts, pad;
+  double tol;
+};
+
+// Per slot, in mapped pinned host memory: the result once phase == kDone.
+struct SlotReport {
+  int32_t phase, reason, iters, restarts;
+  double res_scaled, res_orig, rnorm0;
+  uint64_t ticket;
+};
+
+struct BatchArgs {
+  const SlotDesc *slots;
+  BatchState *state;       // [slots][2]
+  double *part;            // [slots][2][l+1][kMaxStream]
+  const int2 *sched;       // per block: (slot, streaming block index or -1 for the owner)
+  SlotReport *reports;     // mapped host memory
+  const uint64_t *tickets; // per slot
+  int32_t tick, l;
+};
+
+hipError_t launch_batch_tick(const BatchArgs &a, int blocks, hipStream_t s);
+
+// Records msg as the calling thread's last error (plcg_last_error) and returns code.
+int32_t set_last_error(int32_t code, const char *msg);
+
+}  // namespace plcg

@@ -62,6 +62,20 @@ class plcg_result(ctypes.Structure):
         return d
 
 
+class plcg_batch_config(ctypes.Structure):
+    _fields_ = [("l", ctypes.c_int32), ("lambda_min", ctypes.c_double),
+                ("lambda_max", ctypes.c_double), ("max_slots", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_int64), ("chunks_per_block", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class plcg_system_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("cx", ctypes.POINTER(ctypes.c_double)),
+                ("cy", ctypes.POINTER(ctypes.c_double)), ("cz", ctypes.POINTER(ctypes.c_double))]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libplcg.so is not built ({LIB_PATH}); run __graft_entry__.build()")
 _lib = ctypes.CDLL(LIB_PATH)
@@ -88,6 +102,17 @@ SYMBOLS = {
     "plcg_set_timing": (_st, [_h, ctypes.c_int32]),
     "plcg_copy": (_st, [_dp, _dp, ctypes.c_int64, ctypes.c_void_p]),
     "plcg_version": (ctypes.c_int32, []),
+    "plcg_batch_create": (_st, [ctypes.POINTER(plcg_batch_config), ctypes.POINTER(_h)]),
+    "plcg_batch_footprint": (ctypes.c_int64, [_h, ctypes.POINTER(plcg_system_desc)]),
+    "plcg_batch_add": (_st, [_h, ctypes.POINTER(plcg_system_desc), _dp, _dp, ctypes.c_double,
+                             ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "plcg_batch_step": (_st, [_h, ctypes.c_int32, ctypes.c_void_p]),
+    "plcg_batch_poll": (_st, [_h, ctypes.c_uint64, ctypes.POINTER(plcg_result)]),
+    "plcg_batch_active": (ctypes.c_int32, [_h]),
+    "plcg_batch_grid": (ctypes.c_int32, [_h]),
+    "plcg_batch_chunks_per_block": (ctypes.c_int32, [_h]),
+    "plcg_batch_autotune": (_st, [_h, ctypes.c_int32, ctypes.c_void_p]),
+    "plcg_batch_destroy": (_st, [_h]),
 }
 for _name, (_res, _args) in SYMBOLS.items():
     _fn = getattr(_lib, _name)
@@ -107,6 +132,16 @@ plcg_get_history = _lib.plcg_get_history
 plcg_set_timing = _lib.plcg_set_timing
 plcg_copy = _lib.plcg_copy
 plcg_version = _lib.plcg_version
+plcg_batch_create = _lib.plcg_batch_create
+plcg_batch_footprint = _lib.plcg_batch_footprint
+plcg_batch_add = _lib.plcg_batch_add
+plcg_batch_step = _lib.plcg_batch_step
+plcg_batch_poll = _lib.plcg_batch_poll
+plcg_batch_active = _lib.plcg_batch_active
+plcg_batch_grid = _lib.plcg_batch_grid
+plcg_batch_chunks_per_block = _lib.plcg_batch_chunks_per_block
+plcg_batch_autotune = _lib.plcg_batch_autotune
+plcg_batch_destroy = _lib.plcg_batch_destroy
 
 
 class PlcgError(RuntimeError):
@@ -196,6 +231,82 @@ class Solver:
     def close(self):
         if self.handle:
             plcg_destroy(self.handle)
+            self.handle = _h()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def system_desc(dims, cx=None, cy=None, cz=None):
+    """plcg_system_desc for host numpy coefficient arrays (kept alive by the caller)."""
+    dims = tuple(int(d) for d in dims)
+    kind = PLCG_OP_STENCIL2D5 if len(dims) == 2 else PLCG_OP_STENCIL3D7
+    nz = dims[2] if len(dims) == 3 else 1
+    return plcg_system_desc(kind, dims[0], dims[1], nz, _dptr(cx), _dptr(cy), _dptr(cz))
+
+
+class Batch:
+    """Convenience owner of one plcg_batch."""
+
+    def __init__(self, l=2, max_slots=64, arena_bytes=1 << 30, chunks_per_block=0,
+                 lmin=0.0, lmax=0.0, max_restarts=-1, use_graph=False):
+        cfg = plcg_batch_config(int(l), float(lmin), float(lmax), int(max_slots),
+                                int(arena_bytes), int(chunks_per_block), int(max_restarts),
+                                1 if use_graph else 0, 0)
+        self.handle = _h()
+        check(plcg_batch_create(ctypes.byref(cfg), ctypes.byref(self.handle)), "plcg_batch_create")
+        self._keep = {}
+
+    def footprint(self, dims, cx=None, cy=None, cz=None):
+        d = system_desc(dims, cx, cy, cz)
+        return plcg_batch_footprint(self.handle, ctypes.byref(d))
+
+    def add(self, dims, b_ptr, x_ptr, tol, maxit, stream=0, cx=None, cy=None, cz=None):
+        """Ticket, or None when the batch has no room (PLCG_E_BUSY)."""
+        d = system_desc(dims, cx, cy, cz)
+        t = ctypes.c_uint64(0)
+        st = plcg_batch_add(self.handle, ctypes.byref(d), b_ptr, x_ptr, float(tol), int(maxit),
+                            stream, ctypes.byref(t))
+        if st == PLCG_E_BUSY:
+            return None
+        check(st, "plcg_batch_add")
+        return t.value
+
+    def step(self, ticks, stream=0):
+        check(plcg_batch_step(self.handle, int(ticks), stream), "plcg_batch_step")
+
+    def poll(self, ticket):
+        res = plcg_result()
+        st = plcg_batch_poll(self.handle, ticket, ctypes.byref(res))
+        if st == PLCG_NOT_READY:
+            return None
+        check(st, "plcg_batch_poll")
+        return res
+
+    def active(self):
+        return plcg_batch_active(self.handle)
+
+    def grid(self):
+        return plcg_batch_grid(self.handle)
+
+    def chunks_per_block(self):
+        return plcg_batch_chunks_per_block(self.handle)
+
+    def autotune(self, ticks, stream=0):
+        check(plcg_batch_autotune(self.handle, int(ticks), stream), "plcg_batch_autotune")
+
+    def close(self):
+        if self.handle:
+            plcg_batch_destroy(self.handle)
             self.handle = _h()
 
     def __del__(self):

@@ -69,3 +69,39 @@ def sample_indices(n: int, count: int = 512, seed: int = 12345) -> np.ndarray:
     tail = np.arange(max(0, n - edge), n, dtype=np.int64)
     draws = (splitmix64(seed, 0, count) % np.uint64(max(n, 1))).astype(np.int64)
     return np.unique(np.concatenate([head, tail, draws]))
+
+
+def lognormal(n: int, seed: int, start: int = 0) -> np.ndarray:
+    """``n`` lognormal(0, 1) values: exp of a standard normal from the Box-Muller
+    transform of two SplitMix64 uniforms (u1 in (0, 1], u2 in [0, 1))."""
+    z = splitmix64(seed, 2 * start, 2 * n)
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    u1 = 1.0 - u[0::2]
+    u2 = u[1::2]
+    g = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return np.exp(g)
+
+
+def edge_coefficients(dims, seed: int):
+    """Edge coefficients of a variable-coefficient grid operator, lognormal(0, 1).
+
+    2D dims (nx, ny): cx has ny rows of nx+1 edges (x-edges, the first and last
+    of a row touch the boundary), cy has ny+1 rows of nx (y-edges).  3D adds cz
+    with nz+1 planes of ny*nx.  Flat arrays, x fastest; three independent
+    streams derived from ``seed``.
+    """
+    dims = tuple(int(d) for d in dims)
+    nx, ny = dims[0], dims[1]
+    nz = dims[2] if len(dims) == 3 else 1
+    cx = lognormal((nx + 1) * ny * nz, seed * 3 + 1)
+    cy = lognormal(nx * (ny + 1) * nz, seed * 3 + 2)
+    cz = lognormal(nx * ny * (nz + 1), seed * 3 + 3) if len(dims) == 3 else None
+    return cx, cy, cz
+
+
+def batch_recipe(count: int = 512, seed: int = 0, lo: int = 32, hi: int = 512):
+    """The batched workload: `count` 2D systems with side uniform on [lo, hi]
+    (square grids), edge coefficients lognormal(0, 1), b uniform[-1, 1).
+    Returns a list of (dims, coefficient seed, rhs seed)."""
+    sides = lo + (splitmix64(seed * 7 + 5, 0, count) % np.uint64(hi - lo + 1)).astype(np.int64)
+    return [((int(s), int(s)), 1000 + 2 * k, 1001 + 2 * k) for k, s in enumerate(sides)]

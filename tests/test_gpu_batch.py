@@ -1,0 +1,162 @@
+"""Batched solves through the C ABI against the oracle, system by system.
+
+Each system of a batch (mixed sizes, 2D and 3D, lognormal edge coefficients) is
+compared with the oracle solving the same Jacobi-scaled system alone: iteration
+count within 2, scaled residual within 10x, x within 1e-8 relative.  A system's
+result is bit for bit the same alone and in the mix, with and without graph
+replay, and whatever else is admitted or retired around it.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators, shifts
+from oracle import plcg as oplcg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _plcg():
+    from paper_1905_06850_amd import plcg
+    return plcg
+
+
+def _system(dims, cseed, bseed):
+    cx, cy, cz = synth.edge_coefficients(dims, cseed)
+    n = int(np.prod(dims))
+    return dict(dims=dims, cx=cx, cy=cy, cz=cz, b=synth.uniform(n, bseed), n=n)
+
+
+def _oracle(sys_, l, tol, maxit=20000):
+    A, As, dis = operators.variable_laplacian(sys_["dims"], sys_["cx"], sys_["cy"], sys_["cz"])
+    bs = dis * sys_["b"]
+    r = oplcg.plcg(As, bs, np.zeros(sys_["n"]), l, shifts.chebyshev_shifts(l, 0.0, 2.0), tol, maxit)
+    x = dis * r.x
+    orig = np.linalg.norm(sys_["b"] - A(x)) / np.linalg.norm(sys_["b"])
+    return r, x, orig
+
+
+def run_batch(dev, systems, l, tol, maxit=20000, use_graph=False, cpb=0, max_slots=None,
+              ticks=32, autotune=False):
+    plcg = _plcg()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    batch = plcg.Batch(l=l, max_slots=max_slots or len(systems), arena_bytes=1 << 31,
+                       chunks_per_block=cpb, use_graph=use_graph)
+    bufs = []
+    pending = list(range(len(systems)))
+    tickets = {}
+    results = {}
+    guard = 0
+    print(f"[gpu] batch of {len(systems)} l={l} graph={use_graph} cpb={cpb}", flush=True)
+    while pending or tickets:
+        while pending:
+            k = pending[0]
+            s = systems[k]
+            bt = torch.from_numpy(s["b"]).to(dev)
+            xt = torch.zeros(s["n"], dtype=torch.float64, device=dev)
+            t = batch.add(s["dims"], bt.data_ptr(), xt.data_ptr(), tol, maxit, stream,
+                          s["cx"], s["cy"], s["cz"])
+            if t is None:
+                break
+            bufs.append((bt, xt))
+            tickets[t] = (k, xt)
+            pending.pop(0)
+        if autotune:
+            batch.autotune(4, stream)
+            autotune = False
+        batch.step(ticks, stream)
+        torch.cuda.synchronize()
+        for t in list(tickets):
+            r = batch.poll(t)
+            if r is not None:
+                k, xt = tickets.pop(t)
+                results[k] = (r, xt.cpu().numpy())
+        guard += 1
+        assert guard < 100000
+    batch.close()
+    return results
+
+
+SYSTEMS = [((40, 40), 1, 2), ((57, 33), 3, 4), ((96, 96), 5, 6), ((12, 10, 9), 7, 8),
+           ((130, 70), 9, 10), ((20, 20, 20), 11, 12), ((6, 11), 13, 14), ((1, 200), 15, 16)]
+
+
+@pytest.mark.parametrize("l", [2, 3])
+def test_batch_against_oracle(dev, l):
+    systems = [_system(*s) for s in SYSTEMS]
+    res = run_batch(dev, systems, l, 1e-8)
+    for k, s in enumerate(systems):
+        ref, xref, orig = _oracle(s, l, 1e-8)
+        r, x = res[k]
+        assert r.reason == 1, (k, r.as_dict())
+        assert abs(r.iters - ref.iters) <= 2, (k, r.iters, ref.iters)
+        assert r.rec_relres <= 10 * max(ref.true_relres, 1e-15)
+        assert np.linalg.norm(x - xref) <= 1e-8 * np.linalg.norm(xref)
+        assert abs(r.true_relres - orig) <= 0.1 * orig + 1e-15
+
+
+def test_alone_equals_in_the_mix(dev):
+    systems = [_system(*s) for s in SYSTEMS]
+    mix = run_batch(dev, systems, 2, 1e-9)
+    for k in (0, 3, 4):
+        alone = run_batch(dev, [systems[k]], 2, 1e-9)
+        assert alone[0][0].iters == mix[k][0].iters
+        assert np.array_equal(alone[0][1], mix[k][1])
+    # admission in waves (two slots at a time) and graph replay change nothing
+    waves = run_batch(dev, systems, 2, 1e-9, max_slots=2, ticks=20)
+    graph = run_batch(dev, systems, 2, 1e-9, use_graph=True, ticks=48)
+    for k in range(len(systems)):
+        assert np.array_equal(waves[k][1], mix[k][1])
+        assert np.array_equal(graph[k][1], mix[k][1])
+
+
+def test_autotune_keeps_results(dev):
+    systems = [_system(*s) for s in SYSTEMS[:5]]
+    ref = run_batch(dev, systems, 2, 1e-8, cpb=4)
+    tuned = run_batch(dev, systems, 2, 1e-8, autotune=True)
+    for k in range(len(systems)):
+        assert ref[k][0].reason == tuned[k][0].reason == 1
+        assert abs(ref[k][0].iters - tuned[k][0].iters) <= 1
+        assert np.linalg.norm(ref[k][1] - tuned[k][1]) <= 1e-8 * np.linalg.norm(ref[k][1])
+
+
+def test_batch_admission_limits(dev):
+    plcg = _plcg()
+    s = _system((64, 64), 1, 2)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    batch = plcg.Batch(l=2, max_slots=4, arena_bytes=3 * batch_footprint(plcg, s) // 2)
+    bt = torch.from_numpy(s["b"]).to(dev)
+    xs = [torch.zeros(s["n"], dtype=torch.float64, device=dev) for _ in range(3)]
+    t1 = batch.add(s["dims"], bt.data_ptr(), xs[0].data_ptr(), 1e-8, 5000, stream, s["cx"], s["cy"])
+    assert t1 is not None
+    # the arena holds one system and a half: the second waits
+    assert batch.add(s["dims"], bt.data_ptr(), xs[1].data_ptr(), 1e-8, 5000, stream,
+                     s["cx"], s["cy"]) is None
+    while batch.poll(t1) is None:
+        batch.step(64, stream)
+        torch.cuda.synchronize()
+    t2 = batch.add(s["dims"], bt.data_ptr(), xs[1].data_ptr(), 1e-8, 5000, stream, s["cx"], s["cy"])
+    assert t2 is not None
+    while batch.poll(t2) is None:
+        batch.step(64, stream)
+        torch.cuda.synchronize()
+    assert torch.equal(xs[0], xs[1])
+    with pytest.raises(plcg.PlcgError):
+        batch.poll(t2 + 100)
+    batch.close()
+
+
+def batch_footprint(plcg, s):
+    b = plcg.Batch(l=2, max_slots=1, arena_bytes=1 << 20)
+    f = b.footprint(s["dims"], s["cx"], s["cy"], s["cz"])
+    b.close()
+    return f
