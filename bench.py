@@ -119,6 +119,81 @@ def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods):
     print("profile run done", flush=True)
 
 
+def batch_bench(args, plcg, torch, dev, sp):
+    """512 variable-coefficient systems (sides uniform on [32, 512], lognormal(0,1)
+    edges, Jacobi-scaled, shifts on [0, 2]) solved together by the batch engine."""
+    import numpy as np
+    import synth
+    recipe = synth.batch_recipe(args.batch_count)
+    systems = []
+    for dims, cseed, bseed in recipe:
+        cx, cy, cz = synth.edge_coefficients(dims, cseed)
+        n = dims[0] * dims[1]
+        systems.append(dict(dims=dims, cx=cx, cy=cy, n=n,
+                            b=torch.from_numpy(synth.uniform(n, bseed)).to(dev)))
+    total_n = sum(s["n"] for s in systems)
+    xs = [torch.zeros(s["n"], dtype=torch.float64, device=dev) for s in systems]
+    l = args.batch_l
+
+    def run(cpb, autotune, timed):
+        probe = plcg.Batch(l=l, max_slots=1, arena_bytes=1 << 20)
+        need = sum(probe.footprint(s["dims"], s["cx"], s["cy"]) for s in systems)
+        probe.close()
+        batch = plcg.Batch(l=l, max_slots=len(systems), arena_bytes=need + (64 << 20),
+                           chunks_per_block=cpb, use_graph=True)
+        for x in xs:
+            x.zero_()
+        tickets = {}
+        for k, s in enumerate(systems):
+            t = batch.add(s["dims"], s["b"].data_ptr(), xs[k].data_ptr(), 1e-8, 100000, sp,
+                          s["cx"], s["cy"])
+            tickets[t] = k
+        if autotune:
+            batch.autotune(8, sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = {}
+        ticks = 0
+        while tickets:
+            batch.step(args.batch_ticks, sp)
+            ticks += args.batch_ticks
+            torch.cuda.synchronize()
+            now = time.perf_counter() - t0
+            for t in list(tickets):
+                r = batch.poll(t)
+                if r is not None:
+                    done[tickets.pop(t)] = (r, now)
+        dt = time.perf_counter() - t0
+        chosen = batch.chunks_per_block()
+        batch.close()
+        return dt, done, ticks, chosen
+
+    _, _, _, cpb = run(0, True, False)           # untimed: autotune the workgroup size
+    dt, done, ticks, _ = run(cpb, False, True)
+    lat = np.array([v[1] for v in done.values()]) * 1e3
+    iters = {k: v[0].iters for k, v in done.items()}
+    ok = sum(1 for v in done.values() if v[0].reason == 1)
+    passes = 3 * l + 7 + max(0, l - 3) + 2      # sweep passes + 2 coefficient arrays
+    sweep_bytes = sum(systems[k]["n"] * iters[k] * passes * 8 for k in iters)
+    line = {
+        "metric": "batched solves/s (" + METRIC + ")",
+        "value": len(done) / dt, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch{len(systems)}: 2D variable-coefficient 5-point systems, "
+                               f"side uniform on [32, 512] ({total_n} unknowns in all), "
+                               "lognormal(0,1) edge coefficients, Jacobi-scaled, b uniform[-1,1), "
+                               "tol 1e-8 on the scaled residual",
+                   "method": f"p({l})-CG, shifts on [0, 2]", "converged": ok,
+                   "chunks_per_block": cpb, "ticks": ticks,
+                   "iters_min": min(iters.values()), "iters_max": max(iters.values()),
+                   "latency_ms_p50": float(np.percentile(lat, 50)),
+                   "latency_ms_p99": float(np.percentile(lat, 99)),
+                   "alg_GBps": sweep_bytes / dt / 1e9},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +208,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-l", type=int, default=2)
+    ap.add_argument("--batch-ticks", type=int, default=64)
     ap.add_argument("--profile-run", action="store_true",
                     help="short fixed run for hardware-counter passes: 10 copies of "
                          "n doubles, then 100 iterations of each method")
@@ -154,6 +232,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.workload == "batch512":
+        batch_bench(args, plcg, torch, dev, torch.cuda.current_stream(dev).cuda_stream)
+        return
     wl = synth.WORKLOADS[args.workload]
     dims = wl["dims"]
     kind = wl["kind"]

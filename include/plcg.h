@@ -247,6 +247,46 @@ plcg_status plcg_batch_autotune(plcg_batch *b, int32_t ticks, void *stream);
 
 plcg_status plcg_batch_destroy(plcg_batch *b);
 
+/* Register an operator once (scaled and copied to the device, enqueued on
+ * `stream`); requests that name it (plcg_batch_add_op) share it.  The operator
+ * lives until the batch is destroyed. */
+plcg_status plcg_batch_register(plcg_batch *b, const plcg_system_desc *sys, void *stream,
+                                int32_t *op_id);
+
+/* Arena bytes one request on a registered operator takes (internal_x: the
+ * solution is kept in the slot instead of a caller buffer). */
+int64_t plcg_batch_request_footprint(const plcg_batch *b, int32_t op_id, int32_t internal_x);
+
+/* Admit one request on a registered operator; d_x may be NULL (the solution is
+ * then kept inside the slot, x0 = 0, and released with it).  PLCG_E_BUSY when no
+ * slot or arena space is free. */
+plcg_status plcg_batch_add_op(plcg_batch *b, int32_t op_id, const double *d_b, double *d_x,
+                              double tol, int32_t maxit, void *stream, uint64_t *ticket);
+
+typedef struct {
+  double arrival_s;       /* seconds after the start of plcg_serve; sorted */
+  int32_t system;         /* index into the op_ids / d_b arrays */
+  int32_t maxit;
+  double tol;
+} plcg_request;
+
+typedef struct {
+  double admit_s;         /* admitted into the batch (-1: never) */
+  double finish_s;        /* result available (-1: not finished within the time limit) */
+  plcg_result result;
+} plcg_request_outcome;
+
+/* Continuous-batching serving loop on an (empty) batch: admits arrived requests
+ * in FIFO order while a slot and arena space are free (admission by HBM
+ * footprint), enqueues ticks_per_round launches, retires finished solves, and
+ * repeats until every request is done or time_limit_s has passed.  Request k
+ * solves with operator op_ids[system] and right-hand side d_b[system] (device,
+ * shared, read only), x0 = 0.  Timings and results go to out[k]. */
+plcg_status plcg_serve(plcg_batch *b, const int32_t *op_ids, const double *const *d_b,
+                       int32_t nops, const plcg_request *reqs, int32_t nreq,
+                       int32_t ticks_per_round, double time_limit_s, void *stream,
+                       plcg_request_outcome *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,8 @@ LIB = os.path.join(HERE, "libplcg.so")
 SOURCES = [os.path.join(HERE, "csrc", "plcg_kernels.hip"),
            os.path.join(HERE, "csrc", "plcg_batch_kernels.hip"),
            os.path.join(HERE, "csrc", "plcg_engine.cpp"),
-           os.path.join(HERE, "csrc", "plcg_batch.cpp")]
+           os.path.join(HERE, "csrc", "plcg_batch.cpp"),
+           os.path.join(HERE, "csrc", "plcg_serve.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for every HIP translation unit.

@@ -66,13 +66,26 @@ struct plcg_batch {
   uint64_t next_ticket = 1;
   std::vector<int2> sched;
   bool dirty = true;
+  std::vector<int> pending_desc;        // admitted slots whose descriptors are not uploaded yet
+  std::vector<BatchState> pending_state;
+  std::vector<uint64_t> pending_ticket;
   int64_t tick = 0;
   // graph of a group of ticks for the current schedule
   hipGraphExec_t gexec = nullptr;
   int graph_ticks = 0;
+  // registered operators (scaled once, shared by the requests that name them)
+  struct Op {
+    int kind, nx, ny, nz;
+    int64_t n;
+    double *mem;
+    const double *sx, *sy, *sz, *dis;
+  };
+  std::vector<Op> ops;
 };
 
 namespace {
+
+int32_t flush_admissions(plcg_batch *b, hipStream_t st);
 
 void free_graph(plcg_batch *b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -112,7 +125,7 @@ void arena_free(plcg_batch *b, Block blk) {
 
 struct Layout {
   int64_t n;
-  size_t vstride, nsx, nsy, nsz, bytes;
+  size_t vstride, nsx, nsy, nsz, bytes, op_bytes;
 };
 
 int32_t layout(const plcg_batch *b, const plcg_system_desc *sys, Layout *L) {
@@ -128,9 +141,80 @@ int32_t layout(const plcg_batch *b, const plcg_system_desc *sys, Layout *L) {
   L->nsy = (size_t)nx * (ny + 1) * nz;
   L->nsz = d3 ? (size_t)nx * ny * (nz + 1) : 0;
   const int nvec = 2 * b->l + b->R + 1;
-  L->bytes = (size_t)nvec * L->vstride * 8 + round_up(L->nsx * 8, kAlign) +
-             round_up(L->nsy * 8, kAlign) + round_up(L->nsz * 8, kAlign) +
-             round_up((size_t)L->n * 8, kAlign);
+  L->op_bytes = round_up(L->nsx * 8, kAlign) + round_up(L->nsy * 8, kAlign) +
+                round_up(L->nsz * 8, kAlign) + round_up((size_t)L->n * 8, kAlign);
+  L->bytes = (size_t)nvec * L->vstride * 8 + L->op_bytes;
+  return PLCG_OK;
+}
+
+// Scale the edge coefficients of `sys` (Jacobi: s_pq = c_pq / sqrt(d_p d_q), d_p = sum
+// of the edges at p) and copy sx, sy, sz, D^{-1/2} to `dst` (device, L.op_bytes).
+int32_t upload_operator(const plcg_system_desc *sys, const Layout &L, char *dst, hipStream_t st,
+                        const double **psx, const double **psy, const double **psz,
+                        const double **pdis) {
+  const bool d3 = sys->kind == PLCG_OP_STENCIL3D7;
+  const int nx = sys->nx, ny = sys->ny, nz = d3 ? sys->nz : 1;
+  const int64_t n = L.n;
+  std::vector<double> cx(L.nsx, 1.0), cy(L.nsy, 1.0), cz(L.nsz, 1.0);
+  if (sys->cx) std::memcpy(cx.data(), sys->cx, L.nsx * 8);
+  if (sys->cy) std::memcpy(cy.data(), sys->cy, L.nsy * 8);
+  if (d3 && sys->cz) std::memcpy(cz.data(), sys->cz, L.nsz * 8);
+  std::vector<double> dis(n);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+        const int64_t row = y + (int64_t)ny * z;
+        double d = cx[row * (nx + 1) + x] + cx[row * (nx + 1) + x + 1] +
+                   cy[((int64_t)z * (ny + 1) + y) * nx + x] +
+                   cy[((int64_t)z * (ny + 1) + y + 1) * nx + x];
+        if (d3) d += cz[p] + cz[p + (int64_t)nx * ny];
+        if (!(d > 0.0) || !std::isfinite(d))
+          return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
+        dis[p] = 1.0 / std::sqrt(d);
+      }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x <= nx; ++x) {
+        const int64_t row = y + (int64_t)ny * z;
+        const int64_t p = x + (int64_t)nx * row;
+        double &c = cx[row * (nx + 1) + x];
+        c = (x > 0 && x < nx) ? c * dis[p - 1] * dis[p] : 0.0;
+      }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y <= ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        double &c = cy[((int64_t)z * (ny + 1) + y) * nx + x];
+        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+        c = (y > 0 && y < ny) ? c * dis[p - nx] * dis[p] : 0.0;
+      }
+  if (d3)
+    for (int z = 0; z <= nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          double &c = cz[((int64_t)z * ny + y) * nx + x];
+          const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+          const int64_t plane = (int64_t)nx * ny;
+          c = (z > 0 && z < nz) ? c * dis[p - plane] * dis[p] : 0.0;
+        }
+  char *q = dst;
+  double *sx = reinterpret_cast<double *>(q);
+  q += round_up(L.nsx * 8, kAlign);
+  double *sy = reinterpret_cast<double *>(q);
+  q += round_up(L.nsy * 8, kAlign);
+  double *sz = reinterpret_cast<double *>(q);
+  q += round_up(L.nsz * 8, kAlign);
+  double *ds = reinterpret_cast<double *>(q);
+  BHIP(hipMemcpyAsync(sx, cx.data(), L.nsx * 8, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(sy, cy.data(), L.nsy * 8, hipMemcpyHostToDevice, st));
+  if (d3) BHIP(hipMemcpyAsync(sz, cz.data(), L.nsz * 8, hipMemcpyHostToDevice, st));
+  BHIP(hipMemcpyAsync(ds, dis.data(), n * 8, hipMemcpyHostToDevice, st));
+  // the host vectors are temporaries: wait until the copies have read them
+  BHIP(hipStreamSynchronize(st));
+  *psx = sx;
+  *psy = sy;
+  *psz = sz;
+  *pdis = ds;
   return PLCG_OK;
 }
 
@@ -189,6 +273,10 @@ int32_t launch_ticks(plcg_batch *b, int ticks, hipStream_t st) {
 constexpr int kGraphTicks = 16;   // even, so a replay starts and ends on the same parity
 
 int32_t run_ticks(plcg_batch *b, int ticks, hipStream_t st) {
+  {
+    int32_t e = flush_admissions(b, st);
+    if (e != PLCG_OK) return e;
+  }
   if (b->dirty) {
     int32_t e = upload_schedule(b, st);
     if (e != PLCG_OK) return e;
@@ -303,17 +391,16 @@ int64_t plcg_batch_footprint(const plcg_batch *b, const plcg_system_desc *sys) {
   return (int64_t)L.bytes;
 }
 
-plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const double *d_b,
-                           double *d_x, double tol, int32_t maxit, void *stream,
-                           uint64_t *ticket) {
-  if (b == nullptr || ticket == nullptr || d_b == nullptr || d_x == nullptr)
-    return set_last_error(PLCG_E_INVALID, "NULL argument");
-  if ((reinterpret_cast<uintptr_t>(d_b) & 15) || (reinterpret_cast<uintptr_t>(d_x) & 15))
-    return set_last_error(PLCG_E_INVALID, "vectors must be 16-byte aligned");
-  if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0)
-    return set_last_error(PLCG_E_INVALID, "need tol > 0 and maxit >= 0");
-  Layout L;
-  if (layout(b, sys, &L) != PLCG_OK) return set_last_error(PLCG_E_INVALID, "bad system descriptor");
+}  // extern "C"
+
+namespace {
+
+// Admit a system whose scaled operator is at (sx, sy, sz, dis); `own_op` extra
+// bytes of the slot's arena block hold a private copy (plcg_batch_add).
+int32_t admit(plcg_batch *b, const plcg_system_desc *sys, const Layout &L, bool private_op,
+              const plcg_system_desc *op_src, const double *sx, const double *sy,
+              const double *sz, const double *dis, const double *d_b, double *d_x, double tol,
+              int32_t maxit, hipStream_t st, uint64_t *ticket) {
   int slot = -1;
   for (size_t s = 0; s < b->slots.size(); ++s)
     if (!b->in_use[s]) {
@@ -321,78 +408,35 @@ plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const dou
       break;
     }
   if (slot < 0) return set_last_error(PLCG_E_BUSY, "no free slot");
+  const int nvec = 2 * b->l + b->R + 1 + (d_x == nullptr ? 1 : 0);
+  const size_t vec_bytes = (size_t)nvec * L.vstride * 8;
+  const size_t bytes = vec_bytes + (private_op ? L.op_bytes : 0);
   size_t off = 0;
-  if (!arena_alloc(b, L.bytes, &off)) return set_last_error(PLCG_E_BUSY, "not enough arena space");
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const bool d3 = sys->kind == PLCG_OP_STENCIL3D7;
-  const int nx = sys->nx, ny = sys->ny, nz = d3 ? sys->nz : 1;
-  const int64_t n = L.n;
-  // Jacobi scaling of the operator (host).
-  std::vector<double> cx(L.nsx, 1.0), cy(L.nsy, 1.0), cz(L.nsz, 1.0);
-  if (sys->cx) std::memcpy(cx.data(), sys->cx, L.nsx * 8);
-  if (sys->cy) std::memcpy(cy.data(), sys->cy, L.nsy * 8);
-  if (d3 && sys->cz) std::memcpy(cz.data(), sys->cz, L.nsz * 8);
-  std::vector<double> dis(n);
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y < ny; ++y)
-      for (int x = 0; x < nx; ++x) {
-        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
-        const int64_t row = y + (int64_t)ny * z;
-        double d = cx[row * (nx + 1) + x] + cx[row * (nx + 1) + x + 1] +
-                   cy[((int64_t)z * (ny + 1) + y) * nx + x] +
-                   cy[((int64_t)z * (ny + 1) + y + 1) * nx + x];
-        if (d3) d += cz[p] + cz[p + (int64_t)nx * ny];
-        if (!(d > 0.0) || !std::isfinite(d)) {
-          arena_free(b, Block{off, L.bytes});
-          return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
-        }
-        dis[p] = 1.0 / std::sqrt(d);
-      }
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y < ny; ++y)
-      for (int x = 0; x <= nx; ++x) {
-        const int64_t row = y + (int64_t)ny * z;
-        const int64_t p = x + (int64_t)nx * row;
-        double &c = cx[row * (nx + 1) + x];
-        c = (x > 0 && x < nx) ? c * dis[p - 1] * dis[p] : 0.0;
-      }
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y <= ny; ++y)
-      for (int x = 0; x < nx; ++x) {
-        double &c = cy[((int64_t)z * (ny + 1) + y) * nx + x];
-        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
-        c = (y > 0 && y < ny) ? c * dis[p - nx] * dis[p] : 0.0;
-      }
-  if (d3)
-    for (int z = 0; z <= nz; ++z)
-      for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) {
-          double &c = cz[((int64_t)z * ny + y) * nx + x];
-          const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
-          const int64_t plane = (int64_t)nx * ny;
-          c = (z > 0 && z < nz) ? c * dis[p - plane] * dis[p] : 0.0;
-        }
+  if (!arena_alloc(b, bytes, &off)) return set_last_error(PLCG_E_BUSY, "not enough arena space");
   char *base = b->arena + off;
-  const int nvec = 2 * b->l + b->R + 1;
+  if (private_op) {
+    int32_t e = upload_operator(op_src, L, base + vec_bytes, st, &sx, &sy, &sz, &dis);
+    if (e != PLCG_OK) {
+      arena_free(b, Block{off, bytes});
+      return e;
+    }
+  }
+  const bool d3 = sys->kind == PLCG_OP_STENCIL3D7;
   SlotDesc sd{};
   sd.vec = reinterpret_cast<double *>(base);
   sd.vstride = (int64_t)L.vstride;
-  char *q = base + (size_t)nvec * L.vstride * 8;
-  sd.sx = reinterpret_cast<double *>(q);
-  q += round_up(L.nsx * 8, kAlign);
-  sd.sy = reinterpret_cast<double *>(q);
-  q += round_up(L.nsy * 8, kAlign);
-  sd.sz = reinterpret_cast<double *>(q);
-  q += round_up(L.nsz * 8, kAlign);
-  sd.dis = reinterpret_cast<double *>(q);
+  sd.sx = sx;
+  sd.sy = sy;
+  sd.sz = sz;
+  sd.dis = dis;
   sd.b = d_b;
-  sd.x = d_x;
-  sd.nx = nx;
-  sd.ny = ny;
-  sd.nz = nz;
+  sd.x = d_x != nullptr ? d_x : sd.vec + (size_t)(nvec - 1) * L.vstride;
+  sd.nx = sys->nx;
+  sd.ny = sys->ny;
+  sd.nz = d3 ? sys->nz : 1;
   sd.d3 = d3 ? 1 : 0;
-  sd.n = (int32_t)n;
-  sd.nchunks = (int32_t)((n + kChunk - 1) / kChunk);
+  sd.n = (int32_t)L.n;
+  sd.nchunks = (int32_t)((L.n + kChunk - 1) / kChunk);
   sd.nblocks = blocks_for(b, sd.nchunks);
   sd.maxit = maxit;
   sd.max_restarts = b->cfg.max_restarts;
@@ -406,26 +450,109 @@ plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const dou
   BatchState pair[2] = {bs, bs};
   const uint64_t tk = b->next_ticket++;
   // Stream-ordered uploads: launches already enqueued see the slot as it was.
-  BHIP(hipMemcpyAsync(const_cast<double *>(sd.sx), cx.data(), L.nsx * 8, hipMemcpyHostToDevice, st));
-  BHIP(hipMemcpyAsync(const_cast<double *>(sd.sy), cy.data(), L.nsy * 8, hipMemcpyHostToDevice, st));
-  if (d3)
-    BHIP(hipMemcpyAsync(const_cast<double *>(sd.sz), cz.data(), L.nsz * 8, hipMemcpyHostToDevice, st));
-  BHIP(hipMemcpyAsync(const_cast<double *>(sd.dis), dis.data(), n * 8, hipMemcpyHostToDevice, st));
-  BHIP(hipMemcpyAsync(b->d_slots + slot, &sd, sizeof(sd), hipMemcpyHostToDevice, st));
-  BHIP(hipMemcpyAsync(b->d_state + 2 * slot, pair, sizeof(pair), hipMemcpyHostToDevice, st));
-  BHIP(hipMemcpyAsync(b->d_tickets + slot, &tk, sizeof(tk), hipMemcpyHostToDevice, st));
-  // host copies are temporaries: make sure the copies have read them
-  BHIP(hipStreamSynchronize(st));
+  if (d_x == nullptr) BHIP(hipMemsetAsync(sd.x, 0, (size_t)L.n * 8, st));
+  b->slots[slot] = sd;
+  b->pending_desc.push_back(slot);
+  b->pending_state.push_back(pair[0]);
+  b->pending_ticket.push_back(tk);
   b->reports[slot].phase = kInit;
   b->reports[slot].ticket = tk;
-  b->slots[slot] = sd;
   b->in_use[slot] = 1;
   b->tickets[slot] = tk;
-  b->slot_mem[slot] = Block{off, L.bytes};
+  b->slot_mem[slot] = Block{off, bytes};
   b->ticket_slot[tk] = slot;
   b->dirty = true;
   *ticket = tk;
   return PLCG_OK;
+}
+
+// Upload the descriptors and initial states of newly admitted slots (one copy
+// each for all of them), ahead of the next launch.
+int32_t flush_admissions(plcg_batch *b, hipStream_t st) {
+  if (b->pending_desc.empty()) return PLCG_OK;
+  for (size_t k = 0; k < b->pending_desc.size(); ++k) {
+    const int slot = b->pending_desc[k];
+    BatchState pair[2] = {b->pending_state[k], b->pending_state[k]};
+    BHIP(hipMemcpyAsync(b->d_slots + slot, &b->slots[slot], sizeof(SlotDesc), hipMemcpyHostToDevice, st));
+    BHIP(hipMemcpyAsync(b->d_state + 2 * slot, pair, sizeof(pair), hipMemcpyHostToDevice, st));
+    BHIP(hipMemcpyAsync(b->d_tickets + slot, &b->pending_ticket[k], sizeof(uint64_t),
+                        hipMemcpyHostToDevice, st));
+  }
+  BHIP(hipStreamSynchronize(st));
+  b->pending_desc.clear();
+  b->pending_state.clear();
+  b->pending_ticket.clear();
+  return PLCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const double *d_b,
+                           double *d_x, double tol, int32_t maxit, void *stream,
+                           uint64_t *ticket) {
+  if (b == nullptr || ticket == nullptr || d_b == nullptr)
+    return set_last_error(PLCG_E_INVALID, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(d_b) & 15) || (reinterpret_cast<uintptr_t>(d_x) & 15))
+    return set_last_error(PLCG_E_INVALID, "vectors must be 16-byte aligned");
+  if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0)
+    return set_last_error(PLCG_E_INVALID, "need tol > 0 and maxit >= 0");
+  Layout L;
+  if (layout(b, sys, &L) != PLCG_OK) return set_last_error(PLCG_E_INVALID, "bad system descriptor");
+  return admit(b, sys, L, true, sys, nullptr, nullptr, nullptr, nullptr, d_b, d_x, tol, maxit,
+               reinterpret_cast<hipStream_t>(stream), ticket);
+}
+
+plcg_status plcg_batch_register(plcg_batch *b, const plcg_system_desc *sys, void *stream,
+                                int32_t *op_id) {
+  if (b == nullptr || sys == nullptr || op_id == nullptr)
+    return set_last_error(PLCG_E_INVALID, "NULL argument");
+  Layout L;
+  if (layout(b, sys, &L) != PLCG_OK) return set_last_error(PLCG_E_INVALID, "bad system descriptor");
+  BHIP(hipSetDevice(b->device));
+  plcg_batch::Op op{};
+  op.kind = sys->kind;
+  op.nx = sys->nx;
+  op.ny = sys->ny;
+  op.nz = sys->kind == PLCG_OP_STENCIL3D7 ? sys->nz : 1;
+  op.n = L.n;
+  hipError_t he = hipMalloc(reinterpret_cast<void **>(&op.mem), L.op_bytes);
+  if (he != hipSuccess)
+    return set_last_error(PLCG_E_NOMEM, (std::string("hipMalloc(operator): ") + hipGetErrorString(he)).c_str());
+  int32_t e = upload_operator(sys, L, reinterpret_cast<char *>(op.mem),
+                              reinterpret_cast<hipStream_t>(stream), &op.sx, &op.sy, &op.sz, &op.dis);
+  if (e != PLCG_OK) {
+    (void)hipFree(op.mem);
+    return e;
+  }
+  b->ops.push_back(op);
+  *op_id = (int32_t)b->ops.size() - 1;
+  return PLCG_OK;
+}
+
+int64_t plcg_batch_request_footprint(const plcg_batch *b, int32_t op_id, int32_t internal_x) {
+  if (b == nullptr || op_id < 0 || op_id >= (int32_t)b->ops.size()) return -1;
+  const int64_t vstride = (int64_t)(round_up((size_t)b->ops[op_id].n * 8, kAlign) / 8);
+  return (int64_t)(2 * b->l + b->R + 1 + (internal_x ? 1 : 0)) * vstride * 8;
+}
+
+plcg_status plcg_batch_add_op(plcg_batch *b, int32_t op_id, const double *d_b, double *d_x,
+                              double tol, int32_t maxit, void *stream, uint64_t *ticket) {
+  if (b == nullptr || ticket == nullptr || d_b == nullptr)
+    return set_last_error(PLCG_E_INVALID, "NULL argument");
+  if (op_id < 0 || op_id >= (int32_t)b->ops.size())
+    return set_last_error(PLCG_E_INVALID, "unknown operator");
+  if ((reinterpret_cast<uintptr_t>(d_b) & 15) || (reinterpret_cast<uintptr_t>(d_x) & 15))
+    return set_last_error(PLCG_E_INVALID, "vectors must be 16-byte aligned");
+  if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0)
+    return set_last_error(PLCG_E_INVALID, "need tol > 0 and maxit >= 0");
+  const plcg_batch::Op &op = b->ops[op_id];
+  plcg_system_desc sys{op.kind, op.nx, op.ny, op.nz, nullptr, nullptr, nullptr};
+  Layout L;
+  if (layout(b, &sys, &L) != PLCG_OK) return set_last_error(PLCG_E_INVALID, "bad operator");
+  return admit(b, &sys, L, false, nullptr, op.sx, op.sy, op.sz, op.dis, d_b, d_x, tol, maxit,
+               reinterpret_cast<hipStream_t>(stream), ticket);
 }
 
 plcg_status plcg_batch_step(plcg_batch *b, int32_t ticks, void *stream) {
@@ -480,6 +607,10 @@ plcg_status plcg_batch_autotune(plcg_batch *b, int32_t ticks, void *stream) {
   if (b == nullptr || ticks < 1) return set_last_error(PLCG_E_INVALID, "bad argument");
   BHIP(hipSetDevice(b->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  {
+    int32_t e = flush_admissions(b, st);
+    if (e != PLCG_OK) return e;
+  }
   const int cands[] = {1, 2, 4, 8, 16};
   double best = 1e300;
   int best_c = b->cpb;
@@ -524,6 +655,7 @@ plcg_status plcg_batch_destroy(plcg_batch *b) {
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   free_graph(b);
+  for (auto &op : b->ops) (void)hipFree(op.mem);
   if (b->arena) (void)hipFree(b->arena);
   if (b->d_slots) (void)hipFree(b->d_slots);
   if (b->d_state) (void)hipFree(b->d_state);

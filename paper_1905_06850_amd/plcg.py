@@ -76,6 +76,16 @@ class plcg_system_desc(ctypes.Structure):
                 ("cy", ctypes.POINTER(ctypes.c_double)), ("cz", ctypes.POINTER(ctypes.c_double))]
 
 
+class plcg_request(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("system", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class plcg_request_outcome(ctypes.Structure):
+    _fields_ = [("admit_s", ctypes.c_double), ("finish_s", ctypes.c_double),
+                ("result", plcg_result)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libplcg.so is not built ({LIB_PATH}); run __graft_entry__.build()")
 _lib = ctypes.CDLL(LIB_PATH)
@@ -113,6 +123,15 @@ SYMBOLS = {
     "plcg_batch_chunks_per_block": (ctypes.c_int32, [_h]),
     "plcg_batch_autotune": (_st, [_h, ctypes.c_int32, ctypes.c_void_p]),
     "plcg_batch_destroy": (_st, [_h]),
+    "plcg_batch_register": (_st, [_h, ctypes.POINTER(plcg_system_desc), ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_int32)]),
+    "plcg_batch_request_footprint": (ctypes.c_int64, [_h, ctypes.c_int32, ctypes.c_int32]),
+    "plcg_batch_add_op": (_st, [_h, ctypes.c_int32, _dp, _dp, ctypes.c_double, ctypes.c_int32,
+                                ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "plcg_serve": (_st, [_h, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
+                         ctypes.c_int32, ctypes.POINTER(plcg_request), ctypes.c_int32,
+                         ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                         ctypes.POINTER(plcg_request_outcome)]),
 }
 for _name, (_res, _args) in SYMBOLS.items():
     _fn = getattr(_lib, _name)
@@ -142,6 +161,10 @@ plcg_batch_grid = _lib.plcg_batch_grid
 plcg_batch_chunks_per_block = _lib.plcg_batch_chunks_per_block
 plcg_batch_autotune = _lib.plcg_batch_autotune
 plcg_batch_destroy = _lib.plcg_batch_destroy
+plcg_batch_register = _lib.plcg_batch_register
+plcg_batch_request_footprint = _lib.plcg_batch_request_footprint
+plcg_batch_add_op = _lib.plcg_batch_add_op
+plcg_serve = _lib.plcg_serve
 
 
 class PlcgError(RuntimeError):
@@ -280,6 +303,38 @@ class Batch:
             return None
         check(st, "plcg_batch_add")
         return t.value
+
+    def register(self, dims, cx=None, cy=None, cz=None, stream=0):
+        d = system_desc(dims, cx, cy, cz)
+        op = ctypes.c_int32(-1)
+        check(plcg_batch_register(self.handle, ctypes.byref(d), stream, ctypes.byref(op)),
+              "plcg_batch_register")
+        return op.value
+
+    def request_footprint(self, op_id, internal_x=True):
+        return plcg_batch_request_footprint(self.handle, int(op_id), 1 if internal_x else 0)
+
+    def add_op(self, op_id, b_ptr, x_ptr, tol, maxit, stream=0):
+        t = ctypes.c_uint64(0)
+        st = plcg_batch_add_op(self.handle, int(op_id), b_ptr, x_ptr, float(tol), int(maxit),
+                               stream, ctypes.byref(t))
+        if st == PLCG_E_BUSY:
+            return None
+        check(st, "plcg_batch_add_op")
+        return t.value
+
+    def serve(self, op_ids, b_ptrs, requests, ticks_per_round=16, time_limit_s=60.0, stream=0):
+        """requests: list of (arrival_s, system, maxit, tol), sorted by arrival.
+        Returns the list of plcg_request_outcome."""
+        n = len(op_ids)
+        ops = (ctypes.c_int32 * n)(*op_ids)
+        bp = (ctypes.c_void_p * n)(*b_ptrs)
+        rq = (plcg_request * len(requests))(*[plcg_request(float(a), int(s), int(m), float(t))
+                                              for a, s, m, t in requests])
+        out = (plcg_request_outcome * len(requests))()
+        check(plcg_serve(self.handle, ops, bp, n, rq, len(requests), int(ticks_per_round),
+                         float(time_limit_s), stream, out), "plcg_serve")
+        return list(out)
 
     def step(self, ticks, stream=0):
         check(plcg_batch_step(self.handle, int(ticks), stream), "plcg_batch_step")

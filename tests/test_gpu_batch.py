@@ -160,3 +160,83 @@ def batch_footprint(plcg, s):
     f = b.footprint(s["dims"], s["cx"], s["cy"], s["cz"])
     b.close()
     return f
+
+
+def test_registered_operator_equals_private_copy(dev):
+    plcg = _plcg()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    s = _system((77, 45), 21, 22)
+    bt = torch.from_numpy(s["b"]).to(dev)
+    batch = plcg.Batch(l=2, max_slots=4, arena_bytes=1 << 28)
+    op = batch.register(s["dims"], s["cx"], s["cy"], None, stream)
+    x1 = torch.zeros(s["n"], dtype=torch.float64, device=dev)
+    x2 = torch.zeros(s["n"], dtype=torch.float64, device=dev)
+    t1 = batch.add(s["dims"], bt.data_ptr(), x1.data_ptr(), 1e-9, 5000, stream, s["cx"], s["cy"])
+    t2 = batch.add_op(op, bt.data_ptr(), x2.data_ptr(), 1e-9, 5000, stream)
+    t3 = batch.add_op(op, bt.data_ptr(), None, 1e-9, 5000, stream)   # solution kept inside
+    res = {}
+    while len(res) < 3:
+        batch.step(32, stream)
+        torch.cuda.synchronize()
+        for t in (t1, t2, t3):
+            if t not in res:
+                r = batch.poll(t)
+                if r is not None:
+                    res[t] = r
+    assert torch.equal(x1, x2)
+    for t in (t2, t3):
+        assert res[t].iters == res[t1].iters
+        assert res[t].true_relres == res[t1].true_relres
+        assert res[t].rec_relres == res[t1].rec_relres
+    batch.close()
+
+
+def test_served_stream_equals_alone(dev):
+    """Requests arriving while others are in flight join the running batch
+    (continuous batching, admission by footprint); each request's iteration
+    count and residual norms are bit for bit those of the same solve alone."""
+    plcg = _plcg()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    pool = [_system(*s) for s in SYSTEMS[:6]]
+    tols = [1e-6, 1e-8, 1e-10]
+
+    def make_batch(slots, arena):
+        batch = plcg.Batch(l=2, max_slots=slots, arena_bytes=arena, use_graph=True)
+        ops = [batch.register(s["dims"], s["cx"], s["cy"], s["cz"], stream) for s in pool]
+        return batch, ops
+
+    bts = [torch.from_numpy(s["b"]).to(dev) for s in pool]
+    reqs = []
+    for k in range(18):
+        reqs.append((0.002 * k, k % len(pool), 20000, tols[k % 3]))
+    # alone: one request at a time
+    alone = {}
+    for k, (a, sidx, m, tol) in enumerate(reqs):
+        if (sidx, tol) in alone:
+            continue
+        batch, ops = make_batch(1, 1 << 28)
+        out = batch.serve(ops, [bt.data_ptr() for bt in bts], [(0.0, sidx, m, tol)], 16, 60.0, stream)
+        alone[(sidx, tol)] = out[0].result
+        batch.close()
+    # served: an arena for about three requests, so admission waits for space
+    probe, pops = make_batch(1, 1 << 20)
+    fps = [probe.request_footprint(o) for o in pops]
+    probe.close()
+    arena = 3 * max(fps)
+    batch, ops = make_batch(8, arena)
+    out = batch.serve(ops, [bt.data_ptr() for bt in bts], reqs, 8, 120.0, stream)
+    # footprint in flight at each admission: never more than the arena, and more
+    # than one solve at a time (new requests join solves in flight)
+    spans = [(o.admit_s, o.finish_s, fps[reqs[k][1]]) for k, o in enumerate(out)]
+    load = [sum(fp for a2, f2, fp in spans if a2 <= a < f2) for a, f, _ in spans]
+    count = [sum(1 for a2, f2, _ in spans if a2 <= a < f2) for a, f, _ in spans]
+    batch.close()
+    for k, (a, sidx, m, tol) in enumerate(reqs):
+        o = out[k]
+        assert o.finish_s >= o.admit_s >= a - 1e-9, (k, o.admit_s, o.finish_s)
+        r = o.result
+        ref = alone[(sidx, tol)]
+        assert r.reason == ref.reason == 1
+        assert r.iters == ref.iters and r.true_relres == ref.true_relres
+        assert r.rec_relres == ref.rec_relres < tol
+    assert max(load) <= arena and max(count) >= 2
