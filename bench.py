@@ -73,10 +73,13 @@ print(json.dumps(dict(iters=r.iters, seconds=dt)))
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources of the iteration kernels (device code of the single-system path)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1905_06850_amd", "csrc", "plcg_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("plcg_kernels.hip", "plcg_device.h", "plcg_internal.h"):
+        with open(os.path.join(ROOT, "paper_1905_06850_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
@@ -194,6 +197,81 @@ def batch_bench(args, plcg, torch, dev, sp):
     print(json.dumps(line), flush=True)
 
 
+def serve_bench(args, plcg, torch, dev, sp):
+    """Serving stream: Poisson arrivals of solve requests, 70 % 2D 5-point (side
+    uniform on 64..2048) and 30 % 3D 7-point (side 32..256), lognormal(0,1) edge
+    coefficients, tol uniform in {1e-6, 1e-8, 1e-10}; requests draw their
+    operator from a pool of registered operators."""
+    import numpy as np
+    import synth
+    rng_u = synth.uniform(4 * args.serve_pool, 900)        # in [-1, 1)
+    pool = []
+    for k in range(args.serve_pool):
+        u0, u1 = (rng_u[4 * k] + 1) / 2, (rng_u[4 * k + 1] + 1) / 2
+        if u0 < 0.7:
+            side = 64 + int(u1 * (2048 - 64 + 1))
+            dims = (side, side)
+        else:
+            side = 32 + int(u1 * (256 - 32 + 1))
+            dims = (side, side, side)
+        pool.append(dims)
+    batch = plcg.Batch(l=args.batch_l, max_slots=args.serve_slots,
+                       arena_bytes=int(args.serve_arena_gb * (1 << 30)), use_graph=True)
+    ops, bs = [], []
+    for k, dims in enumerate(pool):
+        cx, cy, cz = synth.edge_coefficients(dims, 5000 + k)
+        ops.append(batch.register(dims, cx, cy, cz, sp))
+        bs.append(torch.from_numpy(synth.uniform(int(np.prod(dims)), 6000 + k)).to(dev))
+        del cx, cy, cz
+    torch.cuda.synchronize()
+    tols = (1e-6, 1e-8, 1e-10)
+    results = {}
+    for rate, window in ((args.serve_rate, args.serve_window),
+                         (args.serve_sustain_rate, args.serve_sustain_window)):
+        n = max(1, int(rate * window))
+        gaps = -np.log(1.0 - (synth.uniform(n, 901 + int(rate)) + 1) / 2 * 0.999999) / rate
+        arrivals = np.cumsum(gaps) - gaps[0]
+        pick = ((synth.uniform(n, 902 + int(rate)) + 1) / 2 * len(pool)).astype(int) % len(pool)
+        ptol = ((synth.uniform(n, 903 + int(rate)) + 1) / 2 * 3).astype(int) % 3
+        reqs = [(float(arrivals[k]), int(pick[k]), 200000, tols[ptol[k]]) for k in range(n)]
+        t0 = time.perf_counter()
+        out = batch.serve(ops, [b.data_ptr() for b in bs], reqs, args.serve_ticks,
+                          args.serve_time_limit, sp)
+        wall = time.perf_counter() - t0
+        done = [k for k, o in enumerate(out) if o.finish_s >= 0]
+        lat = np.array([out[k].finish_s - reqs[k][0] for k in done]) * 1e3
+        wait = np.array([out[k].admit_s - reqs[k][0] for k in done]) * 1e3
+        ok = sum(1 for k in done if out[k].result.reason == 1)
+        last = max(out[k].finish_s for k in done) if done else wall
+        results[f"{rate:g}/s"] = {
+            "requests": n, "completed": len(done), "converged": ok,
+            "solves_per_s": len(done) / last if last > 0 else 0.0,
+            "latency_ms_p50": float(np.percentile(lat, 50)) if done else None,
+            "latency_ms_p99": float(np.percentile(lat, 99)) if done else None,
+            "queue_wait_ms_p50": float(np.percentile(wait, 50)) if done else None,
+            "queue_wait_ms_p99": float(np.percentile(wait, 99)) if done else None,
+            "makespan_s": last, "offered_window_s": window,
+        }
+        if not args.quiet:
+            print(f"# serve {rate:g}/s: {json.dumps(results[f'{rate:g}/s'])}", file=sys.stderr,
+                  flush=True)
+    batch.close()
+    head = results[f"{args.serve_rate:g}/s"]
+    line = {
+        "metric": "served solves/s and p99 latency (" + METRIC + ")",
+        "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": head["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serving stream: Poisson arrivals, 70 % 2D 5-point side 64..2048, "
+                               "30 % 3D 7-point side 32..256, lognormal(0,1) edge coefficients "
+                               "(Jacobi-scaled), tol uniform in {1e-6, 1e-8, 1e-10}",
+                   "method": f"p({args.batch_l})-CG, continuous batching, admission by HBM footprint",
+                   "pool": [list(d) for d in pool], "slots": args.serve_slots,
+                   "arena_gb": args.serve_arena_gb, "runs": results},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +289,15 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-l", type=int, default=2)
     ap.add_argument("--batch-ticks", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-window", type=float, default=1.0)
+    ap.add_argument("--serve-sustain-rate", type=float, default=6.0)
+    ap.add_argument("--serve-sustain-window", type=float, default=4.0)
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-arena-gb", type=float, default=48.0)
+    ap.add_argument("--serve-ticks", type=int, default=16)
+    ap.add_argument("--serve-time-limit", type=float, default=120.0)
     ap.add_argument("--profile-run", action="store_true",
                     help="short fixed run for hardware-counter passes: 10 copies of "
                          "n doubles, then 100 iterations of each method")
@@ -234,6 +321,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "batch512":
         batch_bench(args, plcg, torch, dev, torch.cuda.current_stream(dev).cuda_stream)
+        return
+    if args.workload == "serve":
+        serve_bench(args, plcg, torch, dev, torch.cuda.current_stream(dev).cuda_stream)
         return
     wl = synth.WORKLOADS[args.workload]
     dims = wl["dims"]
