@@ -14,8 +14,9 @@ Modules:
               closed-form spectra (textbook facts used by the pins).
   shifts    - Chebyshev shifts, Eq. (chebyshev) of Sec. 2.2.
   cg        - classic Hestenes-Stiefel CG, the method p(l)-CG is compared with.
-  plcg      - Alg. 1 (preconditioner M = I) with both dot-product forms,
-              the explicit restart on square-root breakdown, diagnostics.
+  plcg      - Alg. 1 with both dot-product forms, M = I by default or a
+              given M^{-1}, the explicit restart on square-root breakdown,
+              diagnostics.
   refine    - FP32-stored p(l)-CG inside FP64 iterative refinement.
 """
 from . import operators, shifts, cg, plcg, refine  # noqa: F401

@@ -172,9 +172,11 @@ def basis_updates(z, gam, dlt, sigma, t, l, i, store=None):
     z[l][i + 1] = keep(new / dlt[t])
 
 
-def start_dots(G, z, i, l, dots, dot=np.dot):
-    """Dot products that start column i+1 of G (Alg. 1, 'initiate dot-products')."""
-    u = z[l][i + 1]
+def start_dots(G, z, i, l, dots, dot=np.dot, u=None):
+    """Dot products that start column i+1 of G (Alg. 1, 'initiate dot-products'),
+    with u = u_{i+1} (z^{(l)}_{i+1} when M = I)."""
+    if u is None:
+        u = z[l][i + 1]
     c = i + 1
     if dots == "full":
         for j in range(max(0, i - 2 * l + 1), i - l + 2):
@@ -202,7 +204,7 @@ class Segment:
 
 
 def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=np.dot,
-         store=None):
+         store=None, Minv=None):
     """One run of Alg. 1 (no restart) with M = I, from x0, at most m x-updates.
 
     ``dot`` is the inner product (default numpy's); tests pass a correctly
@@ -211,6 +213,11 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
     z^{(k)}_0, each new basis vector, p and x - and models storing them in a
     narrower format (see oracle.refine); A z^{(l)}_i itself is not stored for
     i >= l, it is consumed by the recurrence at once.
+    ``Minv`` (default: M = I) applies the preconditioner: Alg. 1 then keeps the
+    unpreconditioned u_i = M z^{(l)}_i beside the bases (the u-lines of the
+    algorithm, Sec. 2.2 'Preconditioned p(l)-CG'), the dot products are
+    (u_{i+1}, z_j) - M-inner products of the z's - and the residual norm is the
+    natural one, sqrt((u_0, r_0)).  u_0 is normalised with the z's.
 
     Stops when |zeta_t| < abs_tol.  Returns a Segment; ``diag`` holds G, gamma,
     delta, eta, lambda, zeta, and also the bases and the search directions when
@@ -222,16 +229,18 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
     if len(sigma) != l:
         raise ValueError("need l shifts")
     x = x0.copy()
-    u0 = b - A(x)                              # line 1: u_0 = b - A x_0, r_0 = u_0 (M = I)
+    u0 = b - A(x)                              # u_0 = b - A x_0, r_0 = M^{-1} u_0
+    r0 = Minv(u0) if Minv is not None else u0
     spmvs = 1
-    beta = _sqrt(dot(u0, u0))                  # sqrt((u_0, r_0))
+    beta = _sqrt(dot(u0, r0))                  # sqrt((u_0, r_0))
     if beta == 0 or abs_tol >= beta:
         return Segment(x, 0, "converged", -1, beta, beta, spmvs, [], {})
     if not _finite(beta):
         return Segment(x, 0, "nonfinite", -1, beta, beta, spmvs, [], {})
     keep = store or (lambda v: v)
     z = [dict() for _ in range(l + 1)]
-    v0 = keep(u0 / beta)
+    v0 = keep(r0 / beta)
+    U = {0: u0 / beta} if Minv is not None else None
     for k in range(l + 1):
         z[k][0] = v0                           # z^{(k)}_0 = r_0 / sqrt((u_0, r_0))
     G = {(0, 0): 1.0 if x0.dtype != object else type(beta)(1)}
@@ -246,7 +255,15 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
         # line 3-4: u_{i+1} = A z^{(l)}_i - sigma_i u_i (i < l), z^{(l)}_{i+1} = u_{i+1}
         w = A(z[l][i])
         spmvs += 1
-        if i < l:
+        if Minv is not None:
+            # u_{i+1} = A z_i - sigma_i u_i (i < l), z^{(l)}_{i+1} = M^{-1} u_{i+1}
+            if i < l:
+                w = w - sigma[i] * U[i]
+            U[i + 1] = w
+            w = Minv(w)
+            if i < l:
+                w = keep(w)
+        elif i < l:
             w = keep(w - sigma[i] * z[l][i])
         z[l][i + 1] = w
         # line 5-6: the first vectors of bases i+1 .. l-1 are copies
@@ -268,7 +285,14 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
                 bt = e.t
                 break
             basis_updates(z, gam, dlt, sigma, t, l, i, store)   # K4
-        dots_per_iter.append(start_dots(G, z, i, l, dots, dot))   # K5
+            if Minv is not None:
+                # u_{i+1} = (u_{i+1} - gamma_t u_i - delta_{t-1} u_{i-1}) / delta_t
+                un = U[i + 1] - gam[t] * U[i]
+                if t >= 1:
+                    un = un - dlt[t - 1] * U[i - 1]
+                U[i + 1] = un / dlt[t]
+        extra = {} if Minv is None else {"u": U[i + 1]}
+        dots_per_iter.append(start_dots(G, z, i, l, dots, dot, **extra))   # K5
         # K6: search direction and iterate
         if i == l:
             p = keep(z[0][0] / eta[0])
@@ -286,6 +310,9 @@ def alg1(A, b, x0, l, sigma, abs_tol, m, dots="symmetric", keep_all=False, dot=n
         if not keep_all:
             _forget(z, i, l, dots)
             P.clear()
+            if U is not None:
+                for j in [j for j in U if j < i - 1]:
+                    del U[j]
     zeta_last = abs(zeta[t_done]) if t_done in zeta else beta
     diag = dict(G=G, gam=gam, dlt=dlt, eta=eta, lam=lam, zeta=zeta)
     if keep_all:

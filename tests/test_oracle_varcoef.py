@@ -68,3 +68,30 @@ def test_batch_recipe_sizes():
     sides = np.array([d[0] for d, _, _ in rec])
     assert len(rec) == 512 and sides.min() >= 32 and sides.max() <= 512
     assert 4.0e7 < np.sum(sides.astype(float) ** 2) < 6.5e7
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_preconditioned_alg1_equals_scaled_system(l):
+    """Alg. 1 with M = diag(A) (u != z, M-inner products, Sec. 2.2) on A x = b has
+    the same iterates as Alg. 1 with M = I on D^{-1/2} A D^{-1/2} y = D^{-1/2} b,
+    mapped back by x = D^{-1/2} y - the symmetric scaling the batched solver uses
+    - and both equal Jacobi-preconditioned CG (here: CG on the scaled system)."""
+    dims = (24, 20)
+    cx, cy, cz = synth.edge_coefficients(dims, 4)
+    A, As, dis = operators.variable_laplacian(dims, cx, cy, cz)
+    n = A.n
+    b = synth.uniform(n, 5)
+    dinv = dis * dis                            # M^{-1} = D^{-1}
+    sig = shifts.chebyshev_shifts(l, 0.0, 2.0)
+    ref = ocg.cg(As, dis * b, np.zeros(n), 1e-30, 12, record_iterates=True)
+    for t in (1, 4, 12):
+        pre = oplcg.alg1(A, b, np.zeros(n), l, sig, 0.0, t, Minv=lambda u: dinv * u)
+        sca = oplcg.alg1(As, dis * b, np.zeros(n), l, sig, 0.0, t)
+        xs = dis * sca.x
+        xc = dis * ref.iterates[t - 1]
+        assert pre.t_done == sca.t_done == t
+        assert np.linalg.norm(pre.x - xs) <= 1e-12 * np.linalg.norm(xs)
+        assert np.linalg.norm(pre.x - xc) <= 1e-12 * np.linalg.norm(xc)
+    # the natural residual norm sqrt((u_0, r_0)) is the scaled residual norm
+    pre = oplcg.alg1(A, b, np.zeros(n), l, sig, 0.0, 3, Minv=lambda u: dinv * u)
+    assert abs(pre.beta - np.linalg.norm(dis * b)) <= 1e-12 * pre.beta
