@@ -50,7 +50,8 @@ import numpy as np
 import synth
 from oracle import operators, shifts, plcg
 wl = synth.WORKLOADS[{workload!r}]
-A = operators.laplacian(wl["dims"])
+A = (operators.diagonal(synth.spectrum_diagonal(wl["dims"])) if wl["kind"] == "diag"
+     else operators.laplacian(wl["dims"]))
 b = synth.uniform(A.n, 0)
 x0 = np.zeros(A.n)
 sig = shifts.chebyshev_shifts({l}, *wl["interval"])
@@ -82,15 +83,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None.
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summary, or None.
 
-    profiles/traffic_poisson2048.txt holds lines `key value`: the kernel source
+    profiles/traffic_<workload>.txt holds lines `key value`: the kernel source
     hash the counters were taken with, and `<kernel> <bytes>` per launch (FETCH_SIZE
-    plus WRITE_SIZE, each scaled by the copy-kernel calibration factor).  A
-    different source hash means the kernel changed since: None.
+    plus WRITE_SIZE, each scaled by the copy-kernel calibration factor), the kernel
+    named without namespace, argument list or spaces, e.g.
+    `plcg_sweep_kernel<1,false,double>`.  A different source hash means the kernel
+    changed since: None.
     """
-    path = os.path.join(ROOT, "profiles", "traffic_poisson2048.txt")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -105,7 +109,7 @@ def measured_traffic(kernel: str):
     return float(v) if v is not None else None
 
 
-def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods):
+def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None):
     import torch
     n = b.numel()
     y = torch.empty_like(b)
@@ -113,8 +117,9 @@ def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods):
         plcg.check(plcg.plcg_copy(b.data_ptr(), y.data_ptr(), n, sp), "plcg_copy")
     torch.cuda.synchronize()
     for m in methods.split(","):
-        method, l = ("cg", 1) if m == "cg" else ("plcg", int(m))
-        s = plcg.Solver(kind, dims, method=method, l=l, lmin=lo, lmax=hi)
+        method, l = ("cg", 1) if m == "cg" else ("plcg", int(m.lstrip("m")))
+        s = plcg.Solver(kind, dims, method=method, l=l, lmin=lo, lmax=hi,
+                        precision="fp32" if m.startswith("m") else "fp64", diag=diag)
         x.zero_()
         s.solve(b.data_ptr(), x.data_ptr(), 1e-30, 100, sp)
         torch.cuda.synchronize()
@@ -335,9 +340,12 @@ def main():
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     sp = stream.cuda_stream
+    # the one-point-stencil toy: diagonal operator holding the Laplacian's spectrum
+    dg = (torch.from_numpy(synth.spectrum_diagonal(dims)).to(dev) if kind == "diag" else None)
+    dptr = dg.data_ptr() if dg is not None else None
 
     if args.profile_run:
-        profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods)
+        profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods, dptr)
         return
 
     def parse(tok):
@@ -357,7 +365,7 @@ def main():
         name = {"cg": "cg", "plcg": f"p{l}", "mixed": f"m{l}"}[method]
         s = plcg.Solver(kind, dims, method="cg" if method == "cg" else "plcg", l=max(l, 1),
                         lmin=lo, lmax=hi, precision="fp32" if method == "mixed" else "fp64",
-                        inner_tol=args.inner_tol)
+                        inner_tol=args.inner_tol, diag=dptr)
         for _ in range(args.warmup):
             x.zero_()
             s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
@@ -382,14 +390,18 @@ def main():
         s.close()
         r = results[-1]
         its = total_iters / dt
-        passes = vector_passes("cg" if method == "cg" else "plcg", l)
-        bytes_iter = passes * (4 if method == "mixed" else 8) * n
+        # the diagonal operator reads d once more per SpMV
+        passes = vector_passes("cg" if method == "cg" else "plcg", l) + (kind == "diag")
+        # (d stays FP64 when the vectors are stored in FP32)
+        bytes_iter = ((passes - (kind == "diag")) * (4 if method == "mixed" else 8)
+                      + 8 * (kind == "diag")) * n
         kernel_us = 1e3 * rt.sweep_ms / max(rt.sweeps, 1)
         kernels_per_iter = 2 if method == "cg" else 1
         rows[name] = {
             "iters": r.iters, "reason": plcg.REASONS[r.reason], "restarts": r.restarts,
             "true_relres": r.true_relres, "rec_relres": r.rec_relres,
             "ms_per_solve": 1e3 * dt / args.steps, "iters_per_s": its,
+            "bytes_per_iter": bytes_iter,
             "us_per_iter": 1e6 / its, "vector_passes": passes,
             "alg_GBps": bytes_iter * its / 1e9,
             "kernel_us": kernel_us, "kernels_per_iter": kernels_per_iter,
@@ -402,12 +414,17 @@ def main():
         if not args.quiet:
             print(f"# {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
 
+    opname = {"2d5": "2D 5-point Dirichlet Poisson", "3d7": "3D 7-point Dirichlet Poisson",
+              "diag": "diagonal one-point-stencil toy with the 2D Laplacian's spectrum on"}[kind]
+    kname = (f"plcg_diag_sweep_kernel<{head_method[1]},"
+             if kind == "diag" else
+             f"plcg_sweep_kernel<{head_method[1]},{'true' if kind == '3d7' else 'false'},")
     head = {"plcg": "p", "mixed": "m"}[head_method[0]] + str(head_method[1])
     hl = head_method[1]
     hr = rows[head]
     ms_per_step = hr["ms_per_solve"]
     word = 4 if head_method[0] == "mixed" else 8
-    bytes_launch = hr["vector_passes"] * word * n
+    bytes_launch = hr["bytes_per_iter"]
     achieved = bytes_launch / (hr["kernel_us"] * 1e-6) / 1e9
     line = {
         "metric": METRIC,
@@ -423,8 +440,7 @@ def main():
         "dtype": "f64" if word == 8 else "f32-storage/f64-dots",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {'2D 5-point' if kind == '2d5' else '3D 7-point'} "
-                        f"Dirichlet Poisson {'x'.join(str(d) for d in dims)} "
+            "workload": f"{args.workload}: {opname} {'x'.join(str(d) for d in dims)} "
                         f"({n} unknowns), b uniform[-1,1) seed 0, x0 = 0, stop at relative "
                         f"residual {tol:g}; Chebyshev shifts on [{lo:g},{hi:g}]",
             "method": (f"p({hl})-CG" if head_method[0] == "plcg"
@@ -439,10 +455,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (measured_traffic(f"plcg_sweep_kernel<{hl},false>")
-                        if kind == "2d5" and word == 8 else None),
-            "kernel": f"plcg_sweep_kernel<{hl}, {'2D' if kind == '2d5' else '3D'}, "
-                      f"{'double' if word == 8 else 'float'}>",
+            "traffic": measured_traffic(args.workload,
+                                        kname + ("double>" if word == 8 else "float>")),
+            "kernel": kname + ("double>" if word == 8 else "float>"),
             "kernel_us": hr["kernel_us"],
             "bytes_per_launch": bytes_launch,
         },

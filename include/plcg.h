@@ -48,10 +48,14 @@ enum {
 };
 
 /* Operator kinds: unscaled integer Dirichlet Laplacians (spectrum inside (0, 8)
- * in 2D and (0, 12) in 3D). */
+ * in 2D and (0, 12) in 3D), and a diagonal matrix - the "one-point stencil" of
+ * the paper's communication-bound toy problem (Sec. 4.2), whose diagonal holds
+ * the 2D Laplacian's eigenvalues so that CG sees the same spectrum with an SpMV
+ * that costs no more than a vector update. */
 enum {
   PLCG_OP_STENCIL2D5 = 1,  /* (Au) = 4u - u(x-1) - u(x+1) - u(y-1) - u(y+1) */
-  PLCG_OP_STENCIL3D7 = 2   /* (Au) = 6u - sum of the six face neighbours    */
+  PLCG_OP_STENCIL3D7 = 2,  /* (Au) = 6u - sum of the six face neighbours    */
+  PLCG_OP_DIAG = 3         /* (Au)_p = d_p u_p, d given in plcg_operator_desc.diag */
 };
 
 enum { PLCG_METHOD_CG = 0, PLCG_METHOD_PLCG = 1 };
@@ -73,7 +77,12 @@ enum {
 
 typedef struct {
   int32_t kind;           /* PLCG_OP_* */
-  int32_t nx, ny, nz;     /* grid extents, each >= 1; nz ignored for 2D (use 1) */
+  int32_t nx, ny, nz;     /* grid extents, each >= 1; nz ignored for 2D (use 1);
+                             PLCG_OP_DIAG: n = nx * ny * nz unknowns */
+  const double *diag;     /* PLCG_OP_DIAG only (else ignored): device array of n
+                             FP64 entries, each finite and > 0 (else
+                             PLCG_E_INVALID).  Copied at plcg_create; the caller
+                             keeps ownership and may free it afterwards. */
 } plcg_operator_desc;
 
 typedef struct {
@@ -99,8 +108,10 @@ typedef struct {
   double rec_relres;      /* |zeta_t| / rnorm0 (CG: recursive ||r|| / rnorm0) */
   double true_relres;     /* ||b - A x|| / rnorm0, recomputed in FP64 at the end */
   double seconds;         /* host wall time of the call */
-  double sweep_ms;        /* with timing enabled: summed duration of the per-iteration kernels */
-  int64_t sweeps;         /* with timing enabled: number of per-iteration kernels timed */
+  double sweep_ms;        /* with timing enabled: duration of the iteration kernels that did
+                             work, see plcg_set_timing (launches enqueued after the stop
+                             return at once and are left out) */
+  int64_t sweeps;         /* with timing enabled: number of launches in sweep_ms */
   int32_t outer;          /* FP32_REFINED: refinement steps (0 otherwise) */
   int32_t pad;
 } plcg_result;
@@ -156,8 +167,10 @@ plcg_status plcg_get_shifts(const plcg_handle *h, double *out);
  * device (needs history_cap > 0 at create). */
 plcg_status plcg_get_history(const plcg_handle *h, double *out, int32_t cap, int32_t *count);
 
-/* Enable (1) or disable (0) per-kernel timing of the iteration kernels with
- * HIP events; reported in plcg_result.sweep_ms / sweeps. */
+/* Enable (1) or disable (0) timing of the iteration kernels with HIP events
+ * around each group of check_every back-to-back launches; reported in
+ * plcg_result.sweep_ms / sweeps, summed over the groups in which every launch
+ * did work (over every group with work when a solve is shorter than a group). */
 plcg_status plcg_set_timing(plcg_handle *h, int32_t enable);
 
 /* Measurement aid: dst[i] = src[i], i < n, with a plain streaming kernel

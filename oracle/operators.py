@@ -56,6 +56,16 @@ def dense(M: np.ndarray):
     return apply
 
 
+def diagonal(d):
+    """The diagonal operator (A u)_p = d_p u_p (the one-point stencil, Sec. 4.2)."""
+    d = np.asarray(d, dtype=float)
+
+    def apply(u):
+        return d * u
+    apply.n = d.shape[0]
+    return apply
+
+
 def assemble(apply) -> np.ndarray:
     """Dense matrix of a (small) operator, column by column."""
     n = apply.n

@@ -339,6 +339,21 @@ struct ConstOp {
   }
 };
 
+// Diagonal operator, (A z)_p = d_p z_p with d in FP64: the one-point stencil of
+// the paper's communication-bound toy problem (Sec. 4.2), a diagonal matrix
+// holding the spectrum of the 2D Laplacian.  One extra FP64 read per unknown.
+template <typename S>
+struct DiagOp {
+  const double *d;
+  template <int V, bool FAST>
+  __device__ inline void apply(const S *, int idx, const Vals<V, S> &zc, double (&w)[V]) const {
+    Vals<V, double> dv;
+    dv.load(d + idx);
+#pragma unroll
+    for (int v = 0; v < V; ++v) w[v] = dv.v[v] * zc.v[v];
+  }
+};
+
 // ---------------------------------------------------------------------------
 // p(l)-CG sweep: iteration i of Alg. 1
 // ---------------------------------------------------------------------------

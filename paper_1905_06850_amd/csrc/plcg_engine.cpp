@@ -72,6 +72,7 @@ struct plcg_handle {
   int hist_cap = 0;
   int n = 0, nchunks = 0, blocks = 0;
   bool d3 = false;
+  double *dg = nullptr;           // diagonal operator: library copy of d; NULL for stencils
   int device = 0;
   // device buffers
   std::vector<void *> allocs;
@@ -139,32 +140,65 @@ plcg_status throttle(plcg_handle *h, hipStream_t s, int group, int *status) {
   return PLCG_OK;
 }
 
+// Timing mode: HIP events around each group of back-to-back iteration
+// launches (an event pair around every single launch would add its own gap to
+// each).  A group counts only if every launch in it streamed; launches
+// enqueued after the stop return at once and would bias the average down.
 struct TimedLaunch {
   plcg_handle *h;
   hipStream_t s;
-  size_t used = 0;
-  plcg_status begin() {
+  struct Group {
+    size_t ev;      // events ev (start) and ev + 1 (end)
+    size_t first;   // index of the group's first launch
+    size_t count;   // launches in the group
+  };
+  std::vector<Group> groups;
+  std::vector<uint8_t> counted;  // per launch: 1 if it streamed (did work)
+  plcg_status begin_group() {
     if (!h->timing) return PLCG_OK;
-    while (h->tev.size() < used + 2) {
+    const size_t ev = 2 * groups.size();
+    while (h->tev.size() < ev + 2) {
       hipEvent_t e;
       PLCG_HIP(hipEventCreate(&e));
       h->tev.push_back(e);
     }
-    PLCG_HIP(hipEventRecord(h->tev[used], s));
+    PLCG_HIP(hipEventRecord(h->tev[ev], s));
+    groups.push_back(Group{ev, counted.size(), 0});
     return PLCG_OK;
   }
-  plcg_status end() {
+  void launched() {
+    if (!h->timing) return;
+    counted.push_back(1);
+    ++groups.back().count;
+  }
+  plcg_status end_group() {
     if (!h->timing) return PLCG_OK;
-    PLCG_HIP(hipEventRecord(h->tev[used + 1], s));
-    used += 2;
+    PLCG_HIP(hipEventRecord(h->tev[groups.back().ev + 1], s));
     return PLCG_OK;
   }
-  plcg_status total(double *ms) {
-    *ms = 0.0;
-    for (size_t k = 0; k < used; k += 2) {
-      float e = 0.f;
-      PLCG_HIP(hipEventElapsedTime(&e, h->tev[k], h->tev[k + 1]));
-      *ms += e;
+  size_t launches() const { return counted.size(); }
+  // Launches [first + working, launches()) were enqueued after the stop and
+  // returned without streaming.
+  void keep(size_t first, size_t working) {
+    for (size_t k = first + working; k < counted.size(); ++k) counted[k] = 0;
+  }
+  // Summed duration and launch count of the groups in which every launch
+  // streamed; if there is none (a solve shorter than one group), of every
+  // group that holds a streaming launch.
+  plcg_status total(double *ms, int64_t *count) {
+    for (int pass = 0; pass < 2; ++pass) {
+      *ms = 0.0;
+      *count = 0;
+      for (const Group &g : groups) {
+        size_t work = 0;
+        for (size_t k = g.first; k < g.first + g.count; ++k) work += counted[k];
+        if (work == 0 || (pass == 0 && work != g.count)) continue;
+        float e = 0.f;
+        PLCG_HIP(hipEventElapsedTime(&e, h->tev[g.ev], h->tev[g.ev + 1]));
+        *ms += e;
+        *count += (int64_t)work;
+      }
+      if (*count > 0) break;
     }
     return PLCG_OK;
   }
@@ -193,6 +227,7 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
   a.v0 = (i == l - 1) ? basis[0][0] : nullptr;
   a.p = p;
   a.x = x;
+  a.dg = h->dg;
   a.part_in = h->part[(i + 1) & 1];
   a.part_out = h->part[i & 1];
   a.st_in = h->st[(i + 1) & 1];
@@ -218,7 +253,7 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
 plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r, int slot,
                      int mode, double tol, double rref_in, hipStream_t s) {
   PLCG_HIP(launch_residual(b, x, r, h->part[0], h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
-                           h->nchunks, h->blocks, s));
+                           h->dg, h->nchunks, h->blocks, s));
   PLCG_HIP(launch_start(h->part[0], h->blocks, h->st[slot], h->hs_dev, mode, tol, rref_in, s));
   return PLCG_OK;
 }
@@ -239,17 +274,19 @@ plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S 
   int status = kRunning;
   int group = 0;
   int last_i = -1;
+  const size_t first_launch = tl.launches();
   plcg_status e;
   for (int i0 = 0; i0 <= imax; i0 += h->check_every, ++group) {
     const int i1 = std::min(imax + 1, i0 + h->check_every);
+    if ((e = tl.begin_group()) != PLCG_OK) return e;
     for (int i = i0; i < i1; ++i) {
       SweepArgsT<S> a;
       fill_sweep_args<S>(h, i, basis, ring, p, x, a);
-      if ((e = tl.begin()) != PLCG_OK) return e;
       PLCG_HIP(launch_plcg_sweep(a, s));
-      if ((e = tl.end()) != PLCG_OK) return e;
+      tl.launched();
       last_i = i;
     }
+    if ((e = tl.end_group()) != PLCG_OK) return e;
     if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
     if (status != kRunning) break;
   }
@@ -262,6 +299,7 @@ plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S 
   // Iterations that ran: every sweep up to last_t + l (or the whole loop).
   out->t_done = ds.status == kRunning ? m : std::min(std::max(ds.last_t, 0), m);
   out->sweeps_run = std::min(imax, (ds.status == kRunning ? imax : ds.last_t + l)) + 1;
+  tl.keep(first_launch, (size_t)out->sweeps_run);
   out->rec = out->t_done == 0 ? ds.beta : std::fabs(ds.zeta[out->t_done % kTRing]);
   // t = 0 .. cols-1 were recorded unless the last column broke down.
   h->last_hist_count =
@@ -424,6 +462,7 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   a.x = x;
   a.r = h->cg_r;
   a.q = h->cg_q;
+  a.dg = h->dg;
   a.hs = h->hs_dev;
   a.n = h->n;
   a.nx = h->op.nx;
@@ -456,18 +495,19 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   };
   int group = 0;
   bool stopped = false;
+  const size_t first_launch = tl.launches();
   for (int k0 = 0; k0 < maxit; k0 += h->check_every, ++group) {
     const int k1 = std::min(maxit, k0 + h->check_every);
+    if ((e = tl.begin_group()) != PLCG_OK) return e;
     for (int k = k0; k < k1; ++k) {
       set_a(k, 1);
-      if ((e = tl.begin()) != PLCG_OK) return e;
       PLCG_HIP(launch_cg_sweep_a(a, s));
-      if ((e = tl.end()) != PLCG_OK) return e;
+      tl.launched();
       set_b(k);
-      if ((e = tl.begin()) != PLCG_OK) return e;
       PLCG_HIP(launch_cg_sweep_b(a, s));
-      if ((e = tl.end()) != PLCG_OK) return e;
+      tl.launched();
     }
+    if ((e = tl.end_group()) != PLCG_OK) return e;
     if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
     if (status != kRunning) {
       stopped = true;
@@ -486,6 +526,7 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   PLCG_HIP(hipMemcpy(&ds, h->st[*final_slot], sizeof(ds), hipMemcpyDeviceToHost));
   status = ds.status;
   const int iters = status == kRunning ? maxit : ds.last_t;
+  tl.keep(first_launch, 2 * (size_t)iters);   // sweeps A and B of iterations 0 .. iters-1
   res->iters = iters;
   res->spmvs = (int32_t)(1 + iters);
   res->rec_relres = rref > 0 ? std::sqrt(ds.cg_rho) / rref : 0.0;
@@ -533,9 +574,10 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   res.true_relres = res.rnorm0 > 0 ? std::sqrt(hstat(h)->sumsq) / res.rnorm0 : 0.0;
   if (h->timing) {
     double ms = 0;
-    if ((e = tl.total(&ms)) != PLCG_OK) return e;
+    int64_t count = 0;
+    if ((e = tl.total(&ms, &count)) != PLCG_OK) return e;
     res.sweep_ms = ms;
-    res.sweeps = (int64_t)(tl.used / 2);
+    res.sweeps = count;
   }
   res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = res;
@@ -554,8 +596,11 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   if (out == nullptr) return fail(PLCG_E_INVALID, "out is NULL");
   *out = nullptr;
   if (op == nullptr || cfg == nullptr) return fail(PLCG_E_INVALID, "NULL descriptor or config");
-  if (op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7)
+  if (op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7 &&
+      op->kind != PLCG_OP_DIAG)
     return fail(PLCG_E_INVALID, "unknown operator kind");
+  if (op->kind == PLCG_OP_DIAG && op->diag == nullptr)
+    return fail(PLCG_E_INVALID, "diagonal operator needs diag");
   const int nz = op->kind == PLCG_OP_STENCIL2D5 ? 1 : op->nz;
   if (op->nx < 1 || op->ny < 1 || nz < 1) return fail(PLCG_E_INVALID, "grid extents must be >= 1");
   if (op->kind == PLCG_OP_STENCIL2D5 && op->nz > 1)
@@ -670,6 +715,26 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   }
   if (e == PLCG_OK && h->hist_cap > 0)
     e = dev_alloc(h, reinterpret_cast<void **>(&h->hist), sizeof(double) * 4 * h->hist_cap);
+  if (e == PLCG_OK && op->kind == PLCG_OP_DIAG) {
+    // The library keeps its own copy of d; every entry must be finite and > 0
+    // (an SPD diagonal), checked once here on the host.
+    std::vector<double> d((size_t)n);
+    if ((he = hipMemcpy(d.data(), op->diag, sizeof(double) * (size_t)n,
+                        hipMemcpyDeviceToHost)) != hipSuccess) {
+      e = fail(PLCG_E_HIP, std::string("hipMemcpy(diag): ") + hipGetErrorString(he));
+    } else {
+      for (double v : d)
+        if (!(std::isfinite(v) && v > 0.0)) {
+          e = fail(PLCG_E_INVALID, "diagonal entries must be finite and > 0");
+          break;
+        }
+    }
+    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->dg), sizeof(double) * (size_t)n);
+    if (e == PLCG_OK &&
+        (he = hipMemcpy(h->dg, d.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice)) !=
+            hipSuccess)
+      e = fail(PLCG_E_HIP, std::string("hipMemcpy(diag): ") + hipGetErrorString(he));
+  }
   if (e != PLCG_OK) {
     release(h);
     delete h;
@@ -774,7 +839,7 @@ plcg_status plcg_apply(plcg_handle *h, const double *d_x, double *d_y, void *str
   if (h == nullptr || d_x == nullptr || d_y == nullptr)
     return fail(PLCG_E_INVALID, "NULL argument");
   if (d_x == d_y) return fail(PLCG_E_INVALID, "x and y must be distinct");
-  PLCG_HIP(launch_apply(d_x, d_y, h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
+  PLCG_HIP(launch_apply(d_x, d_y, h->n, h->op.nx, h->op.ny, h->op.nz, h->d3, h->dg,
                         reinterpret_cast<hipStream_t>(stream)));
   return PLCG_OK;
 }

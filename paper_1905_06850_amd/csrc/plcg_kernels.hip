@@ -25,9 +25,11 @@ namespace plcg {
 // p(l)-CG sweep: iteration i of Alg. 1
 // ---------------------------------------------------------------------------
 
-template <int L, bool D3, typename ST>
-__global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) {
-  using S = Sweep<L, ST, ConstOp<D3, ST>>;
+// Body shared by the stencil and the diagonal operators.  fast_rows: full
+// chunks may take the operator's FAST form.
+template <int L, typename ST, typename Op>
+__device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fast_rows) {
+  using S = Sweep<L, ST, Op>;
   constexpr int ND = S::ND;
   __shared__ double lds[4 * ND];
   __shared__ double red[ND];
@@ -69,12 +71,10 @@ __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) 
   // Sweeps past the stop change nothing (the solve's x is x_{last_t}).
   if (status != kRunning && t > last_t) return;
 
-  const ConstOp<D3, ST> op{Grid{a.n, a.nx, a.ny, a.nz}};
   double acc[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) acc[m] = 0.0;
   const int first = L == 1 ? 0 : 1;
-  const bool fast_rows = (a.nx & 1) == 0;
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, first); it.c < it.end; it.c += it.step) {
     const int base = it.c * kChunk;
     const int idx = base + threadIdx.x * kVec;
@@ -86,6 +86,16 @@ __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) 
   store_partials<ND>(acc, a.part_out, a.pstride, blockIdx.x - first, lds, red);
 }
 
+template <int L, bool D3, typename ST>
+__global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) {
+  plcg_sweep<L, ST>(a, ConstOp<D3, ST>{Grid{a.n, a.nx, a.ny, a.nz}}, (a.nx & 1) == 0);
+}
+
+template <int L, typename ST>
+__global__ __launch_bounds__(kThreads) void plcg_diag_sweep_kernel(SweepArgsT<ST> a) {
+  plcg_sweep<L, ST>(a, DiagOp<ST>{a.dg}, true);
+}
+
 // ---------------------------------------------------------------------------
 // Classic CG: two sweeps per iteration
 // ---------------------------------------------------------------------------
@@ -94,11 +104,9 @@ __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) 
 // sweep B of iteration k-1, beta_{k-1} = rho_k / rho_{k-1}, stopping test
 // ||r_k|| < tol ||r_0||.  Then p_k = r_k + beta_{k-1} p_{k-1} (p_0 = r_0),
 // q = A p_k and the product (p_k, q).
-template <bool D3>
-__global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
-  __shared__ double lds[4];
-  __shared__ double red[1];
-  __shared__ DevState sh;
+//
+// Prologue of sweep A, every workgroup; returns false when nothing is streamed.
+__device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds, double *red) {
   state_load(a.st_in, &sh);
   if (a.k >= 1 && sh.status == kRunning) {
     sum_partials<1>(a.part_in, a.nparts_in, a.pstride, lds, red);
@@ -120,7 +128,15 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
     state_store(&sh, a.st_out);
     if (threadIdx.x == 0) publish(sh, a.hs, sqrt(sh.cg_rho), 2 * a.k);
   }
-  if (sh.status != kRunning || !a.work) return;
+  return sh.status == kRunning && a.work;
+}
+
+template <bool D3>
+__global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
+  __shared__ double lds[4];
+  __shared__ double red[1];
+  __shared__ DevState sh;
+  if (!cg_a_prologue(a, sh, lds, red)) return;
 
   const bool first = a.k == 0;
   const double beta = first ? 0.0 : sh.cg_beta;
@@ -223,6 +239,48 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
   store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
 }
 
+// Sweep A for the diagonal operator: q = d * p_k.
+__global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
+  __shared__ double lds[4];
+  __shared__ double red[1];
+  __shared__ DevState sh;
+  if (!cg_a_prologue(a, sh, lds, red)) return;
+
+  const bool first = a.k == 0;
+  const double beta = first ? 0.0 : sh.cg_beta;
+  double acc[1] = {0.0};
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
+    const int idx = it.c * kChunk + threadIdx.x * kVec;
+    if (idx + 1 < a.n) {
+      Vals<2> r, d, pn, q;
+      r.load(a.r + idx);
+      d.load(a.dg + idx);
+      if (first) {
+        pn = r;
+      } else {
+        Vals<2> po;
+        po.load(a.p_old + idx);
+#pragma unroll
+        for (int v = 0; v < 2; ++v) pn.v[v] = r.v[v] + beta * po.v[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        q.v[v] = d.v[v] * pn.v[v];
+        acc[0] += pn.v[v] * q.v[v];
+      }
+      pn.store(a.p_new + idx);
+      q.store(a.q + idx);
+    } else if (idx < a.n) {
+      const double pc = first ? a.r[idx] : a.r[idx] + beta * a.p_old[idx];
+      const double q = a.dg[idx] * pc;
+      a.p_new[idx] = pc;
+      a.q[idx] = q;
+      acc[0] += pc * q;
+    }
+  }
+  store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
+}
+
 // Sweep B of iteration k.  Prologue: alpha_k = rho_k / (p_k, q) from sweep A
 // (breakdown if (p_k, A p_k) <= 0).  Then x += alpha p_k, r -= alpha q and the
 // product (r_{k+1}, r_{k+1}).
@@ -282,10 +340,12 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
 // Residual, segment start, scaling, operator application, copy
 // ---------------------------------------------------------------------------
 
-template <bool D3>
+// DG: the diagonal operator diag(dg) instead of the stencil.
+template <bool D3, bool DG>
 __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, const double *x,
                                                             double *r, double *part_out, Grid g,
-                                                            int nchunks, int nstream) {
+                                                            const double *dg, int nchunks,
+                                                            int nstream) {
   __shared__ double lds[4];
   __shared__ double red[1];
   double acc[1] = {0.0};
@@ -295,7 +355,8 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, con
     for (int v = 0; v < kVec; ++v) {
       const int p = idx0 + v;
       if (p >= g.n) break;
-      const double rv = b[p] - ((D3 ? 6.0 : 4.0) * x[p] - neighbour_sum<D3>(x, p, g));
+      const double ax = DG ? dg[p] * x[p] : (D3 ? 6.0 : 4.0) * x[p] - neighbour_sum<D3>(x, p, g);
+      const double rv = b[p] - ax;
       if (r != nullptr) r[p] = rv;
       acc[0] += rv * rv;
     }
@@ -362,11 +423,12 @@ __global__ __launch_bounds__(kThreads) void add_correction_kernel(double *x, con
     x[p] += (double)d[p];
 }
 
-template <bool D3>
-__global__ __launch_bounds__(kThreads) void apply_kernel(const double *x, double *y, Grid g) {
+template <bool D3, bool DG>
+__global__ __launch_bounds__(kThreads) void apply_kernel(const double *x, double *y, Grid g,
+                                                         const double *dg) {
   const double diag = D3 ? 6.0 : 4.0;
   for (int p = blockIdx.x * kThreads + threadIdx.x; p < g.n; p += gridDim.x * kThreads)
-    y[p] = diag * x[p] - neighbour_sum<D3>(x, p, g);
+    y[p] = DG ? dg[p] * x[p] : diag * x[p] - neighbour_sum<D3>(x, p, g);
 }
 
 __global__ __launch_bounds__(kThreads) void copy_kernel(const double *src, double *dst, int64_t n) {
@@ -391,7 +453,9 @@ static int simple_blocks(int64_t n) {
 template <int L, typename S>
 static hipError_t launch_sweep_l(const SweepArgsT<S> &a, hipStream_t s) {
   const int grid = a.nstream + (L >= 2 ? 1 : 0);
-  if (a.d3)
+  if (a.dg != nullptr)
+    hipLaunchKernelGGL((plcg_diag_sweep_kernel<L, S>), dim3(grid), dim3(kThreads), 0, s, a);
+  else if (a.d3)
     hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S>), dim3(grid), dim3(kThreads), 0, s, a);
   else
     hipLaunchKernelGGL((plcg_sweep_kernel<L, false, S>), dim3(grid), dim3(kThreads), 0, s, a);
@@ -422,7 +486,9 @@ hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s) {
 }
 
 hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s) {
-  if (a.d3)
+  if (a.dg != nullptr)
+    hipLaunchKernelGGL(cg_diag_sweep_a_kernel, dim3(a.nstream), dim3(kThreads), 0, s, a);
+  else if (a.d3)
     hipLaunchKernelGGL((cg_sweep_a_kernel<true>), dim3(a.nstream), dim3(kThreads), 0, s, a);
   else
     hipLaunchKernelGGL((cg_sweep_a_kernel<false>), dim3(a.nstream), dim3(kThreads), 0, s, a);
@@ -435,15 +501,18 @@ hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out, int n,
-                           int nx, int ny, int nz, bool d3, int nchunks, int nstream,
-                           hipStream_t s) {
+                           int nx, int ny, int nz, bool d3, const double *dg, int nchunks,
+                           int nstream, hipStream_t s) {
   const Grid g{n, nx, ny, nz};
-  if (d3)
-    hipLaunchKernelGGL((residual_kernel<true>), dim3(nstream), dim3(kThreads), 0, s, b, x, r,
-                       part_out, g, nchunks, nstream);
+  if (dg != nullptr)
+    hipLaunchKernelGGL((residual_kernel<false, true>), dim3(nstream), dim3(kThreads), 0, s, b, x,
+                       r, part_out, g, dg, nchunks, nstream);
+  else if (d3)
+    hipLaunchKernelGGL((residual_kernel<true, false>), dim3(nstream), dim3(kThreads), 0, s, b, x,
+                       r, part_out, g, dg, nchunks, nstream);
   else
-    hipLaunchKernelGGL((residual_kernel<false>), dim3(nstream), dim3(kThreads), 0, s, b, x, r,
-                       part_out, g, nchunks, nstream);
+    hipLaunchKernelGGL((residual_kernel<false, false>), dim3(nstream), dim3(kThreads), 0, s, b, x,
+                       r, part_out, g, dg, nchunks, nstream);
   return hipGetLastError();
 }
 
@@ -474,12 +543,15 @@ hipError_t launch_add_correction(double *x, const float *d, int n, hipStream_t s
 }
 
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
-                        hipStream_t s) {
+                        const double *dg, hipStream_t s) {
   const Grid g{n, nx, ny, nz};
-  if (d3)
-    hipLaunchKernelGGL((apply_kernel<true>), dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, y, g);
+  const dim3 grid(simple_blocks(n));
+  if (dg != nullptr)
+    hipLaunchKernelGGL((apply_kernel<false, true>), grid, dim3(kThreads), 0, s, x, y, g, dg);
+  else if (d3)
+    hipLaunchKernelGGL((apply_kernel<true, false>), grid, dim3(kThreads), 0, s, x, y, g, dg);
   else
-    hipLaunchKernelGGL((apply_kernel<false>), dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, y, g);
+    hipLaunchKernelGGL((apply_kernel<false, false>), grid, dim3(kThreads), 0, s, x, y, g, dg);
   return hipGetLastError();
 }
 

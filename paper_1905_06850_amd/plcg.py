@@ -25,6 +25,7 @@ PLCG_E_NONFINITE = -5
 
 PLCG_OP_STENCIL2D5 = 1
 PLCG_OP_STENCIL3D7 = 2
+PLCG_OP_DIAG = 3
 PLCG_METHOD_CG = 0
 PLCG_METHOD_PLCG = 1
 PLCG_PREC_FP64 = 0
@@ -36,7 +37,7 @@ REASONS = {0: "none", 1: "converged", 2: "maxit", 3: "breakdown_limit", 4: "nonf
 
 class plcg_operator_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nz", ctypes.c_int32)]
+                ("nz", ctypes.c_int32), ("diag", ctypes.c_void_p)]
 
 
 class plcg_config(ctypes.Structure):
@@ -181,12 +182,15 @@ def check(status, where):
     return status
 
 
-def _dims_desc(kind, dims):
+def _dims_desc(kind, dims, diag=None):
     dims = tuple(int(d) for d in dims)
     if kind in ("2d5", PLCG_OP_STENCIL2D5):
-        return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1)
+        return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1, None)
     if kind in ("3d7", PLCG_OP_STENCIL3D7):
-        return plcg_operator_desc(PLCG_OP_STENCIL3D7, dims[0], dims[1], dims[2])
+        return plcg_operator_desc(PLCG_OP_STENCIL3D7, dims[0], dims[1], dims[2], None)
+    if kind in ("diag", PLCG_OP_DIAG):
+        dims = dims + (1,) * (3 - len(dims))
+        return plcg_operator_desc(PLCG_OP_DIAG, dims[0], dims[1], dims[2], diag)
     raise ValueError(f"unknown operator kind {kind!r}")
 
 
@@ -195,8 +199,10 @@ class Solver:
 
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
                  check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
-                 inner_tol=0.0):
-        self.desc = _dims_desc(kind, dims)
+                 inner_tol=0.0, diag=None):
+        """kind "2d5", "3d7" or "diag"; for "diag", `diag` is the device address
+        of the n FP64 diagonal entries (copied by plcg_create)."""
+        self.desc = _dims_desc(kind, dims, diag)
         self._shifts = None
         sp = None
         if shifts is not None:

@@ -51,6 +51,12 @@ WORKLOADS = {
                         interval=(0.0, 8.0), tol=1e-8),
     "poisson3d256": dict(kind="3d7", dims=(256, 256, 256), rhs="uniform",
                          interval=(0.0, 12.0), tol=1e-10),
+    # the one-point-stencil toy: diagonal with the 2048^2 Laplacian's spectrum,
+    # the same right-hand side as poisson2048
+    "diag2048": dict(kind="diag", dims=(2048, 2048), rhs="uniform",
+                     interval=(0.0, 8.0), tol=1e-8),
+    "diag64": dict(kind="diag", dims=(64, 64), rhs="uniform",
+                   interval=(0.0, 8.0), tol=1e-8),
 }
 
 
@@ -59,6 +65,20 @@ def grid_size(dims) -> int:
     for d in dims:
         n *= int(d)
     return n
+
+
+def spectrum_diagonal(dims) -> np.ndarray:
+    """Diagonal of the one-point-stencil toy problem on the grid ``dims``: entry
+    p = x + nx*(y + ny*z) is the eigenvalue of the Dirichlet Laplacian's sine mode
+    with wave numbers (x+1, y+1, z+1), i.e. the sum over the axes of
+    4 sin^2(k pi / (2 (n + 1))).  An operator definition (input data), in the
+    order of the grid's unknowns."""
+    d = np.zeros(1)
+    for n in dims:          # x varies fastest: later axes are the slower index
+        k = np.arange(1, int(n) + 1)
+        f = 4.0 * np.sin(k * np.pi / (2.0 * (int(n) + 1))) ** 2
+        d = (f[:, None] + d[None, :]).reshape(-1)
+    return d
 
 
 def sample_indices(n: int, count: int = 512, seed: int = 12345) -> np.ndarray:

@@ -1,0 +1,106 @@
+"""The one-point-stencil toy (Sec. 4.2) through the C ABI against the oracle:
+diagonal operator d = the 2D Laplacian's spectrum (input generator), oracle
+applying it as a plain diagonal."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cg as ocg
+from oracle import operators, shifts
+from oracle import plcg as oplcg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _plcg():
+    from paper_1905_06850_amd import plcg
+    return plcg
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def gpu_solve(dev, d, method, l, b, x0, tol, maxit):
+    plcg = _plcg()
+    print(f"[gpu] diag {method} l={l} n={d.size} tol={tol} maxit={maxit}", flush=True)
+    dt = torch.from_numpy(d).to(dev)
+    s = plcg.Solver("diag", (d.size,), method=method, l=l, lmin=0.0, lmax=8.0,
+                    diag=dt.data_ptr())
+    del dt                                       # copied by plcg_create
+    bt = torch.from_numpy(b).to(dev)
+    xt = torch.from_numpy(x0.copy()).to(dev)
+    res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit,
+                  torch.cuda.current_stream(dev).cuda_stream)
+    x = xt.cpu().numpy()
+    s.close()
+    return x, res
+
+
+def oracle_solve(d, method, l, b, x0, tol, maxit):
+    D = operators.diagonal(d)
+    if method == "cg":
+        return ocg.cg(D, b, x0, tol, maxit)
+    return oplcg.plcg(D, b, x0, l, shifts.chebyshev_shifts(l, 0.0, 8.0), tol, maxit)
+
+
+@pytest.mark.parametrize("n", [1, 2, 511, 512, 513, 4096, 70001])
+def test_diag_apply_is_exact(dev, n):
+    plcg = _plcg()
+    d = 0.5 + (synth.uniform(n, 50) + 1.0) * 3.0
+    x = synth.uniform(n, 51)
+    dt = torch.from_numpy(d).to(dev)
+    s = plcg.Solver("diag", (n,), method="cg", diag=dt.data_ptr())
+    xt = torch.from_numpy(x).to(dev)
+    yt = torch.empty_like(xt)
+    s.apply(xt.data_ptr(), yt.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    assert np.array_equal(yt.cpu().numpy(), d * x)      # one correctly rounded product
+    s.close()
+
+
+@pytest.mark.parametrize("dims", [(64, 64), (37, 29), (130, 7)])
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3),
+                                      ("plcg", 5)])
+def test_diag_solve_parity(dev, dims, method, l):
+    d = synth.spectrum_diagonal(dims)
+    b = synth.uniform(d.size, 0)
+    x0 = np.zeros(d.size)
+    ref = oracle_solve(d, method, l, b, x0, 1e-8, 20000)
+    x, res = gpu_solve(dev, d, method, l, b, x0, 1e-8, 20000)
+    assert res.reason == 1 and ref.reason == "converged", res.as_dict()
+    assert abs(res.iters - ref.iters) <= 1
+    assert res.true_relres <= 10 * ref.true_relres and ref.true_relres <= 10 * res.true_relres
+    assert _rel(x, ref.x) < 1e-8
+
+
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 4)])
+def test_diag_early_iterates(dev, method, l):
+    d = synth.spectrum_diagonal((48, 40))
+    b = synth.uniform(d.size, 8)
+    x0 = 0.1 * synth.uniform(d.size, 9)
+    for m in (1, 2, 5, 20):
+        ref = oracle_solve(d, method, l, b, x0, 1e-30, m)
+        x, res = gpu_solve(dev, d, method, l, b, x0, 1e-30, m)
+        assert res.iters == m == ref.iters
+        assert _rel(x, ref.x) < 1e-13
+
+
+def test_diag_rejects_nonpositive_entries(dev):
+    plcg = _plcg()
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        d = np.ones(1000)
+        d[777] = bad
+        dt = torch.from_numpy(d).to(dev)
+        with pytest.raises(plcg.PlcgError) as ei:
+            plcg.Solver("diag", (1000,), method="plcg", l=2, diag=dt.data_ptr())
+        assert ei.value.status == plcg.PLCG_E_INVALID

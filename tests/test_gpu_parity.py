@@ -266,7 +266,15 @@ def test_timing_counts_sweeps(dev):
         xt = torch.zeros(4096, dtype=torch.float64, device=dev)
         r = s.solve(bt.data_ptr(), xt.data_ptr(), 1e-8, 5000,
                     torch.cuda.current_stream(dev).cuda_stream)
-        assert r.sweeps >= per * r.iters and r.sweep_ms > 0
+        # Launches that did work: for p(l)-CG every sweep of the segment
+        # (iters + l + 1; spmvs also counts the two residuals), for CG sweeps A
+        # and B of each iteration.  Timed in groups of 64 iterations; only the
+        # groups in which every launch did work are summed.
+        assert r.restarts == 0 and r.sweep_ms > 0
+        work = r.spmvs - 2 if method == "plcg" else per * r.iters
+        group = 64 * per
+        assert work >= group
+        assert r.sweeps == group * (work // group)
         s.close()
 
 
