@@ -142,13 +142,15 @@ def batch_bench(args, plcg, torch, dev, sp):
     total_n = sum(s["n"] for s in systems)
     xs = [torch.zeros(s["n"], dtype=torch.float64, device=dev) for s in systems]
     l = args.batch_l
+    prec = args.batch_precision
 
     def run(cpb, autotune, timed):
-        probe = plcg.Batch(l=l, max_slots=1, arena_bytes=1 << 20)
+        probe = plcg.Batch(l=l, max_slots=1, arena_bytes=1 << 20, precision=prec)
         need = sum(probe.footprint(s["dims"], s["cx"], s["cy"]) for s in systems)
         probe.close()
         batch = plcg.Batch(l=l, max_slots=len(systems), arena_bytes=need + (64 << 20),
-                           chunks_per_block=cpb, use_graph=True)
+                           chunks_per_block=cpb, use_graph=True, precision=prec,
+                           inner_tol=args.inner_tol)
         for x in xs:
             x.zero_()
         tickets = {}
@@ -180,19 +182,27 @@ def batch_bench(args, plcg, torch, dev, sp):
     dt, done, ticks, _ = run(cpb, False, True)
     lat = np.array([v[1] for v in done.values()]) * 1e3
     iters = {k: v[0].iters for k, v in done.items()}
+    outer = [v[0].outer for v in done.values()]
     ok = sum(1 for v in done.values() if v[0].reason == 1)
-    passes = 3 * l + 7 + max(0, l - 3) + 2      # sweep passes + 2 coefficient arrays
-    sweep_bytes = sum(systems[k]["n"] * iters[k] * passes * 8 for k in iters)
+    # per unknown and (inner) iteration: the sweep's vector passes in the storage
+    # precision plus the 2 FP64 edge-weight arrays of the 2D operator
+    word = 4 if prec == "fp32" else 8
+    per_unknown = (3 * l + 7 + max(0, l - 3)) * word + 2 * 8
+    sweep_bytes = sum(systems[k]["n"] * iters[k] * per_unknown for k in iters)
     line = {
         "metric": "batched solves/s (" + METRIC + ")",
         "value": len(done) / dt, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32-storage/f64-dots",
+        "data": "synthetic",
         "config": {"workload": f"batch{len(systems)}: 2D variable-coefficient 5-point systems, "
                                f"side uniform on [32, 512] ({total_n} unknowns in all), "
                                "lognormal(0,1) edge coefficients, Jacobi-scaled, b uniform[-1,1), "
                                "tol 1e-8 on the scaled residual",
-                   "method": f"p({l})-CG, shifts on [0, 2]", "converged": ok,
+                   "method": (f"p({l})-CG, shifts on [0, 2]" if prec == "fp64" else
+                              f"FP32-stored p({l})-CG in FP64 refinement (inner tol "
+                              f"{args.inner_tol:g}), shifts on [0, 2]"),
+                   "converged": ok, "outer_max": max(outer),
                    "chunks_per_block": cpb, "ticks": ticks,
                    "iters_min": min(iters.values()), "iters_max": max(iters.values()),
                    "latency_ms_p50": float(np.percentile(lat, 50)),
@@ -294,6 +304,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-l", type=int, default=2)
     ap.add_argument("--batch-ticks", type=int, default=64)
+    ap.add_argument("--batch-precision", choices=("fp64", "fp32"), default="fp64",
+                    help="batch512: FP64, or FP32-stored inner solves in FP64 refinement")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-window", type=float, default=1.0)
     ap.add_argument("--serve-sustain-rate", type=float, default=6.0)

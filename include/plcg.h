@@ -204,10 +204,16 @@ typedef struct {
   double lambda_max;
   int32_t max_slots;      /* systems in flight, >= 1 */
   int64_t arena_bytes;    /* device memory reserved for the systems' data */
-  int32_t chunks_per_block; /* unknowns per workgroup = 512 * this; <= 0: autotune */
+  int32_t chunks_per_block; /* unknowns per workgroup = 512 * this; <= 0: 4 (see
+                               plcg_batch_autotune) */
   int32_t max_restarts;   /* < 0: default 100 */
   int32_t use_graph;      /* 1: replay groups of ticks from a captured hipGraph */
-  int32_t pad;
+  int32_t precision;      /* PLCG_PREC_FP64, or PLCG_PREC_FP32_REFINED: every system runs
+                             FP64 iterative refinement (x, residual, operator in FP64)
+                             around an inner p(l)-CG whose vectors are stored in FP32
+                             (dot products, G, T, LU in FP64), as for plcg_create */
+  double inner_tol;       /* FP32_REFINED: inner stop |zeta_t| < inner_tol ||r_k||
+                             (0 < inner_tol < 1; <= 0: 1e-3) */
 } plcg_batch_config;
 
 typedef struct {
@@ -228,7 +234,8 @@ plcg_status plcg_batch_create(const plcg_batch_config *cfg, plcg_batch **out);
 int64_t plcg_batch_footprint(const plcg_batch *b, const plcg_system_desc *sys);
 
 /* Admit one system: d_b, d_x device vectors of n doubles (x0 on entry, solution
- * once polled done), tol relative to the initial scaled residual, maxit x-updates.
+ * once polled done), tol relative to the initial scaled residual, maxit x-updates
+ * (FP32_REFINED: inner iterations over all refinement steps).
  * Copies and scales the coefficients (enqueued on `stream`).  PLCG_E_BUSY when
  * no slot or not enough arena space is free (nothing is changed then). */
 plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const double *d_b,
@@ -239,9 +246,10 @@ plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const dou
 plcg_status plcg_batch_step(plcg_batch *b, int32_t ticks, void *stream);
 
 /* PLCG_NOT_READY until the system of `ticket` is done; then PLCG_OK with the
- * result (iters, restarts, reason; rnorm0 = original-space ||b - A x0||,
- * rec_relres = scaled residual, true_relres = original-space residual) and the
- * slot is freed.  PLCG_E_INVALID for an unknown ticket. */
+ * result (iters, restarts, reason, outer = refinement steps for FP32_REFINED;
+ * rnorm0 = original-space ||b - A x0||, rec_relres = scaled residual (FP32_REFINED:
+ * recomputed in FP64 after the last correction), true_relres = original-space
+ * residual) and the slot is freed.  PLCG_E_INVALID for an unknown ticket. */
 plcg_status plcg_batch_poll(plcg_batch *b, uint64_t ticket, plcg_result *out);
 
 /* Systems admitted and not yet polled done. */

@@ -1,6 +1,7 @@
 // Host side of batched and served solves: slots, HBM arena, schedule, ticks.
 //
-// Admission: a system needs (2l + R + 1) work vectors plus its scaled operator
+// Admission: a system needs (2l + R + 1) work vectors (FP32-refined: 2l + R + 2
+// FP32 vectors, the last one the correction) plus its scaled operator
 // (edge weights and D^{-1/2}); it is admitted when a slot and a first-fit block
 // of the arena are free.  The coefficients are scaled here, on the host, as part
 // of the operator setup: d_p = sum of the edges incident to p, s_pq = c_pq /
@@ -43,6 +44,8 @@ struct Block {
 struct plcg_batch {
   plcg_batch_config cfg{};
   int l = 2, R = 2, device = 0;
+  bool mixed = false;                   // FP32-refined: work vectors stored in FP32
+  double inner_tol = 1e-3;
   double sigma[kLMax] = {0};
   int cpb = 4;                          // chunks per streaming workgroup
   // device
@@ -125,8 +128,15 @@ void arena_free(plcg_batch *b, Block blk) {
 
 struct Layout {
   int64_t n;
-  size_t vstride, nsx, nsy, nsz, bytes, op_bytes;
+  size_t vstride;      // elements of the storage type between work vectors
+  size_t vec_bytes;    // all work vectors
+  size_t x_bytes;      // an internal FP64 iterate (requests without a caller x)
+  size_t nsx, nsy, nsz, bytes, op_bytes;
 };
+
+// Work vectors per system: bases 2l, ring R, p (and the FP32 correction).
+int work_vectors(const plcg_batch *b) { return 2 * b->l + b->R + 1 + (b->mixed ? 1 : 0); }
+size_t word_bytes(const plcg_batch *b) { return b->mixed ? 4 : 8; }
 
 int32_t layout(const plcg_batch *b, const plcg_system_desc *sys, Layout *L) {
   if (sys == nullptr) return PLCG_E_INVALID;
@@ -136,14 +146,16 @@ int32_t layout(const plcg_batch *b, const plcg_system_desc *sys, Layout *L) {
   if (nx < 1 || ny < 1 || nz < 1 || (!d3 && sys->nz > 1)) return PLCG_E_INVALID;
   L->n = nx * ny * nz;
   if (L->n >= (1LL << 31) - 4 * kChunk) return PLCG_E_INVALID;
-  L->vstride = round_up((size_t)L->n * 8, kAlign) / 8;
+  const size_t w = word_bytes(b);
+  L->vstride = round_up((size_t)L->n * w, kAlign) / w;
+  L->vec_bytes = (size_t)work_vectors(b) * L->vstride * w;
+  L->x_bytes = round_up((size_t)L->n * 8, kAlign);
   L->nsx = (size_t)(nx + 1) * ny * nz;
   L->nsy = (size_t)nx * (ny + 1) * nz;
   L->nsz = d3 ? (size_t)nx * ny * (nz + 1) : 0;
-  const int nvec = 2 * b->l + b->R + 1;
   L->op_bytes = round_up(L->nsx * 8, kAlign) + round_up(L->nsy * 8, kAlign) +
                 round_up(L->nsz * 8, kAlign) + round_up((size_t)L->n * 8, kAlign);
-  L->bytes = (size_t)nvec * L->vstride * 8 + L->op_bytes;
+  L->bytes = L->vec_bytes + L->op_bytes;
   return PLCG_OK;
 }
 
@@ -261,6 +273,8 @@ int32_t launch_ticks(plcg_batch *b, int ticks, hipStream_t st) {
   a.reports = b->d_reports;
   a.tickets = b->d_tickets;
   a.l = b->l;
+  a.mixed = b->mixed ? 1 : 0;
+  a.pad = 0;
   const int grid = (int)b->sched.size();
   for (int k = 0; k < ticks; ++k) {
     a.tick = (int32_t)(b->tick & 1);
@@ -326,7 +340,13 @@ plcg_status plcg_batch_create(const plcg_batch_config *cfg, plcg_batch **out) {
   double lo = cfg->lambda_min, hi = cfg->lambda_max;
   if (lo == 0.0 && hi == 0.0) hi = 2.0;
   if (!(hi > lo)) return set_last_error(PLCG_E_INVALID, "need lambda_min < lambda_max");
+  if (cfg->precision != PLCG_PREC_FP64 && cfg->precision != PLCG_PREC_FP32_REFINED)
+    return set_last_error(PLCG_E_INVALID, "unknown precision");
+  if (cfg->precision == PLCG_PREC_FP32_REFINED && !(cfg->inner_tol < 1.0))
+    return set_last_error(PLCG_E_INVALID, "inner_tol must be < 1");
   plcg_batch *b = new plcg_batch();
+  b->mixed = cfg->precision == PLCG_PREC_FP32_REFINED;
+  b->inner_tol = cfg->inner_tol > 0.0 ? cfg->inner_tol : 1e-3;
   b->cfg = *cfg;
   b->cfg.lambda_min = lo;
   b->cfg.lambda_max = hi;
@@ -408,8 +428,9 @@ int32_t admit(plcg_batch *b, const plcg_system_desc *sys, const Layout &L, bool 
       break;
     }
   if (slot < 0) return set_last_error(PLCG_E_BUSY, "no free slot");
-  const int nvec = 2 * b->l + b->R + 1 + (d_x == nullptr ? 1 : 0);
-  const size_t vec_bytes = (size_t)nvec * L.vstride * 8;
+  // work vectors, then an internal FP64 x if the caller gives none, then a
+  // private operator copy
+  const size_t vec_bytes = L.vec_bytes + (d_x == nullptr ? L.x_bytes : 0);
   const size_t bytes = vec_bytes + (private_op ? L.op_bytes : 0);
   size_t off = 0;
   if (!arena_alloc(b, bytes, &off)) return set_last_error(PLCG_E_BUSY, "not enough arena space");
@@ -430,7 +451,7 @@ int32_t admit(plcg_batch *b, const plcg_system_desc *sys, const Layout &L, bool 
   sd.sz = sz;
   sd.dis = dis;
   sd.b = d_b;
-  sd.x = d_x != nullptr ? d_x : sd.vec + (size_t)(nvec - 1) * L.vstride;
+  sd.x = d_x != nullptr ? d_x : reinterpret_cast<double *>(base + L.vec_bytes);
   sd.nx = sys->nx;
   sd.ny = sys->ny;
   sd.nz = d3 ? sys->nz : 1;
@@ -440,7 +461,9 @@ int32_t admit(plcg_batch *b, const plcg_system_desc *sys, const Layout &L, bool 
   sd.nblocks = blocks_for(b, sd.nchunks);
   sd.maxit = maxit;
   sd.max_restarts = b->cfg.max_restarts;
+  sd.mixed = b->mixed ? 1 : 0;
   sd.tol = tol;
+  sd.inner_tol = b->inner_tol;
   BatchState bs;
   std::memset(&bs, 0, sizeof(bs));
   bs.d.l = b->l;
@@ -533,8 +556,10 @@ plcg_status plcg_batch_register(plcg_batch *b, const plcg_system_desc *sys, void
 
 int64_t plcg_batch_request_footprint(const plcg_batch *b, int32_t op_id, int32_t internal_x) {
   if (b == nullptr || op_id < 0 || op_id >= (int32_t)b->ops.size()) return -1;
-  const int64_t vstride = (int64_t)(round_up((size_t)b->ops[op_id].n * 8, kAlign) / 8);
-  return (int64_t)(2 * b->l + b->R + 1 + (internal_x ? 1 : 0)) * vstride * 8;
+  const size_t n = (size_t)b->ops[op_id].n;
+  const size_t w = word_bytes(b);
+  return (int64_t)((size_t)work_vectors(b) * (round_up(n * w, kAlign) / w) * w +
+                   (internal_x ? round_up(n * 8, kAlign) : 0));
 }
 
 plcg_status plcg_batch_add_op(plcg_batch *b, int32_t op_id, const double *d_b, double *d_x,
@@ -576,6 +601,7 @@ plcg_status plcg_batch_poll(plcg_batch *b, uint64_t ticket, plcg_result *out) {
     out->rnorm0 = rp->rnorm0;
     out->rec_relres = rp->res_scaled;
     out->true_relres = rp->res_orig;
+    out->outer = rp->outer;
   }
   b->in_use[slot] = 0;
   arena_free(b, b->slot_mem[slot]);

@@ -14,35 +14,44 @@
 // A~ = D^{-1/2} A D^{-1/2} (unit diagonal), with (A u)_p = sum_q c_pq (u_p - u_q)
 // over the grid edges incident to p (u = 0 outside), stored as scaled edge
 // weights; the solver works on y = D^{1/2} x.
+//
+// FP32-refined batches store the inner solver's vectors (bases, p and the
+// correction c) in FP32 and keep y, the residual, the operator and every scalar
+// in FP64: each refinement step recomputes r = D^{-1/2} b - A~ y, solves
+// A~ c = r with the FP32-stored p(l)-CG to inner_tol ||r||, and adds y += c.
 #include "plcg_device.h"
+
+#include <type_traits>
 
 namespace plcg {
 
-// A~ at unknown p: u_p - sum of scaled edge weight * neighbour.
+// A~ at unknown p: u_p - sum of scaled edge weight * neighbour (u stored as T,
+// weights and arithmetic FP64).
 struct VarOp {
   const double *sx, *sy, *sz;
   int n, nx, ny, nz, d3;
-  __device__ inline double at(const double *u, int p) const {
+  template <typename T>
+  __device__ inline double at(const T *u, int p) const {
     const int x = p % nx;
     const int rest = p / nx;
     const int y = d3 ? rest % ny : rest;
     double s = 0.0;
     const int xe = rest * (nx + 1) + x;          // edge left of p in its row
-    if (x > 0) s += sx[xe] * u[p - 1];
-    if (x < nx - 1) s += sx[xe + 1] * u[p + 1];
+    if (x > 0) s += sx[xe] * (double)u[p - 1];
+    if (x < nx - 1) s += sx[xe + 1] * (double)u[p + 1];
     const int z = d3 ? rest / ny : 0;
     const int ye = p + z * nx;                   // edge below p in its column
-    if (y > 0) s += sy[ye] * u[p - nx];
-    if (y < ny - 1) s += sy[ye + nx] * u[p + nx];
+    if (y > 0) s += sy[ye] * (double)u[p - nx];
+    if (y < ny - 1) s += sy[ye + nx] * (double)u[p + nx];
     if (d3) {
       const int plane = nx * ny;
-      if (z > 0) s += sz[p] * u[p - plane];
-      if (z < nz - 1) s += sz[p + plane] * u[p + plane];
+      if (z > 0) s += sz[p] * (double)u[p - plane];
+      if (z < nz - 1) s += sz[p + plane] * (double)u[p + plane];
     }
-    return u[p] - s;
+    return (double)u[p] - s;
   }
-  template <int V, bool FAST>
-  __device__ inline void apply(const double *z, int idx, const Vals<V, double> &zc,
+  template <int V, bool FAST, typename S>
+  __device__ inline void apply(const S *z, int idx, const Vals<V, S> &zc,
                                double (&w)[V]) const {
 #pragma unroll
     for (int v = 0; v < V; ++v) w[v] = at(z, idx + v);
@@ -62,28 +71,38 @@ __device__ inline void bstate_store(const BatchState *sh, BatchState *st) {
   for (int k = threadIdx.x; k < (int)(sizeof(BatchState) / 8); k += kThreads) dst[k] = src[k];
 }
 
-// Vector k of the slot's storage.
-__device__ inline double *svec(const SlotDesc &S, int k) { return S.vec + (size_t)k * S.vstride; }
+// Vector k of the slot's storage (elements of type T, vstride apart).
+template <typename T>
+__device__ inline T *svec(const SlotDesc &S, int k) {
+  return reinterpret_cast<T *>(S.vec) + (size_t)k * S.vstride;
+}
 
-template <int L>
-__device__ inline void slot_sweep_args(const SlotDesc &S, int i, SweepArgsT<double> &a) {
+// Vector roles of sweep i: ring slot of z^{(l)}_j = 2l + j % R, basis k slots
+// 2k and 2k+1 by index parity, p after the ring; the iterate is y (FP64) or,
+// for an FP32-stored inner solve, the correction c after p.
+template <int L, typename T>
+__device__ inline void slot_sweep_args(const SlotDesc &S, int i, SweepArgsT<T> &a) {
   constexpr int R = L - 1 > 2 ? L - 1 : 2;
   const int t = i - L;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int j = i - k;
-    a.zl[k] = j >= 0 ? svec(S, 2 * L + j % R) : nullptr;
+    a.zl[k] = j >= 0 ? svec<T>(S, 2 * L + j % R) : nullptr;
   }
-  a.zl_out = svec(S, 2 * L + (i + 1) % R);
+  a.zl_out = svec<T>(S, 2 * L + (i + 1) % R);
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    a.zk_cur[k] = t >= 0 ? svec(S, 2 * k + ((t + k) & 1)) : nullptr;
-    a.zk_prev[k] = t >= 0 ? svec(S, 2 * k + ((t + k + 1) & 1)) : nullptr;
+    a.zk_cur[k] = t >= 0 ? svec<T>(S, 2 * k + ((t + k) & 1)) : nullptr;
+    a.zk_prev[k] = t >= 0 ? svec<T>(S, 2 * k + ((t + k + 1) & 1)) : nullptr;
   }
-  a.copy_dst = (i < L - 1) ? svec(S, 2 * (i + 1) + ((i + 1) & 1)) : nullptr;
-  a.v0 = (i == L - 1) ? svec(S, 0) : nullptr;
-  a.p = svec(S, 2 * L + R);
-  a.x = S.x;
+  a.copy_dst = (i < L - 1) ? svec<T>(S, 2 * (i + 1) + ((i + 1) & 1)) : nullptr;
+  a.v0 = (i == L - 1) ? svec<T>(S, 0) : nullptr;
+  a.p = svec<T>(S, 2 * L + R);
+  if constexpr (std::is_same<T, double>::value)
+    a.x = S.x;
+  else
+    a.x = svec<T>(S, 2 * L + R + 1);
+  a.dg = nullptr;
   a.i = i;
   a.l = L;
   a.n = S.n;
@@ -119,7 +138,10 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
           b.first = 0;
         }
         d.beta = beta;
-        d.abs_tol = S.tol * d.rref;
+        // FP64: Alg. 1 stops at tol ||r~_0||.  FP32-refined: the inner solve
+        // stops at inner_tol ||r_k||; the refinement at tol ||r~_0||.
+        const double outer_tol = S.tol * d.rref;
+        d.abs_tol = S.mixed ? S.inner_tol * beta : outer_tol;
         d.cols = 0;
         d.last_t = -1;
         for (int c = 0; c < kGRing; ++c)
@@ -132,9 +154,11 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
           d.status = kNonFinite;
           b.reason = 4;
           b.phase = kFinal;
-        } else if (beta == 0.0 || beta < d.abs_tol) {
+        } else if (beta == 0.0 || beta < outer_tol) {
           d.status = kConverged;
           b.reason = 1;
+          b.phase = kFinal;
+        } else if (b.reason == 3) {   // FP32-refined: restart limit hit in the last inner solve
           b.phase = kFinal;
         } else if (b.m <= 0) {
           d.status = kRunning;
@@ -155,31 +179,34 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
         const int i = b.i;
         if (i >= 1 && d.status == kRunning) engine_column(d, red, i, nullptr);
         // The next sweep has t' = i + 1 - l; stop once nothing is left to do.
+        // FP32-refined: every end of the inner solve adds its correction
+        // (kCorrect) and returns to the FP64 residual, where kStart decides.
         const int tn = i + 1 - L;
+        const int done = S.mixed ? kCorrect : kFinal;
         int next = kSweep;
         if (d.status == kRunning) {
           if (tn > b.m) {
             b.total += b.m;
             b.reason = 2;
-            next = kFinal;
+            next = done;
           }
         } else if (tn > d.last_t) {
           if (d.status == kConverged) {
             const int td = d.last_t < b.m ? d.last_t : b.m;
             b.total += td;
             b.reason = d.last_t <= b.m ? 1 : 2;
-            next = kFinal;
+            next = done;
           } else {  // breakdown: restart from x_{t-1} (Sec. 2.2), keeping the reference norm
             b.total += d.last_t > 0 ? (d.last_t < b.m ? d.last_t : b.m) : 0;
             b.restarts += 1;
             if (b.restarts > S.max_restarts) {
               b.reason = 3;
-              next = kFinal;
+              next = done;
             } else if (b.total >= S.maxit) {
               b.reason = 2;
-              next = kFinal;
+              next = done;
             } else {
-              next = kResid;
+              next = S.mixed ? kCorrect : kResid;
             }
           }
         }
@@ -187,6 +214,10 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
         b.i = i + 1;
         break;
       }
+      case kCorrect:
+        b.outer += 1;
+        b.phase = kResid;
+        break;
       case kFinal:
         b.phase = kFinal2;
         break;
@@ -204,6 +235,7 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
         rp.res_scaled = b.res_scaled;
         rp.res_orig = b.res_orig;
         rp.rnorm0 = b.rref_orig;
+        rp.outer = b.outer;
         rp.ticket = a.tickets[slot];
         rp.phase = kDone;
         break;
@@ -216,9 +248,13 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
   bstate_store(sh, out);
 }
 
-template <int L>
+// ST: storage type of the inner solver's vectors (double, or float for an
+// FP32-refined batch).  y, b, D^{-1/2} and the edge weights are FP64 either way.
+template <int L, typename ST>
 __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
   constexpr int ND = L + 1;
+  constexpr bool kMixed = std::is_same<ST, float>::value;
+  constexpr int R = L - 1 > 2 ? L - 1 : 2;
   __shared__ double lds[4 * ND];
   __shared__ double red[ND];
   __shared__ BatchState sh;
@@ -250,16 +286,17 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
     if (in->d.status != kRunning && t > in->d.last_t) return;
     Coef<L> cf;
     read_coef<L>(in->d, i, t, cf);
-    SweepArgsT<double> sa;
-    slot_sweep_args<L>(S, i, sa);
-    using SW = Sweep<L, double, VarOp>;
+    SweepArgsT<ST> sa;
+    slot_sweep_args<L, ST>(S, i, sa);
+    using SW = Sweep<L, ST, VarOp>;
     for (int idx = start; idx < S.n; idx += step) SW::template chunk<false>(sa, op, idx, t, cf, acc);
     store_partials<ND>(acc, part_out, kMaxStream, lb, lds, red);
     return;
   }
-  // Setup and final phases, one unknown at a time.
-  double *r0 = svec(S, 2 * L);                 // ring slot 0
-  double *v0 = svec(S, 0);                     // basis 0, slot 0
+  // Setup, correction and final phases, one unknown at a time.
+  ST *r0 = svec<ST>(S, 2 * L);                 // ring slot 0
+  ST *v0 = svec<ST>(S, 0);                     // basis 0, slot 0
+  ST *cc = kMixed ? svec<ST>(S, 2 * L + R + 1) : nullptr;   // FP32 correction
   const double inv_beta = phase == kScale ? 1.0 / in->d.beta : 0.0;
   for (int base = start; base < S.n; base += step) {
 #pragma unroll
@@ -270,14 +307,20 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
         S.x[p] = S.x[p] / S.dis[p];
       } else if (phase == kResid || phase == kFinal) {
         const double r = S.dis[p] * S.b[p] - op.at(S.x, p);
-        if (phase == kResid) r0[p] = r;
+        if (!kMixed && phase == kResid) r0[p] = (ST)r;
         acc[0] += r * r;
         const double ro = r / S.dis[p];       // D^{1/2} r~ = b - A x
         acc[1] += ro * ro;
       } else if (phase == kScale) {
-        const double z = r0[p] * inv_beta;
+        // z_0 = r / ||r||; the FP32 path recomputes r in FP64 (same bits as
+        // kResid) instead of keeping an FP64 copy, and clears the correction.
+        const double r = kMixed ? S.dis[p] * S.b[p] - op.at(S.x, p) : (double)r0[p];
+        const ST z = (ST)(r * inv_beta);
         r0[p] = z;
         v0[p] = z;
+        if (kMixed) cc[p] = (ST)0;
+      } else if (phase == kCorrect) {
+        if (kMixed) S.x[p] += (double)cc[p];
       } else if (phase == kFinal2) {
         S.x[p] = S.x[p] * S.dis[p];
       }
@@ -288,7 +331,10 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
 
 template <int L>
 static hipError_t launch_tick_l(const BatchArgs &a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((batch_tick_kernel<L>), dim3(blocks), dim3(kThreads), 0, s, a);
+  if (a.mixed)
+    hipLaunchKernelGGL((batch_tick_kernel<L, float>), dim3(blocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((batch_tick_kernel<L, double>), dim3(blocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -131,12 +131,13 @@ enum Phase : int32_t {
   kInit = 1,     // y = D^{1/2} x0 (the solver works on the Jacobi-scaled system)
   kResid = 2,    // r = D^{-1/2} b - A~ y into ring slot 0, partial sums of r.r and r.r/dis^2
   kStart = 3,    // owner: ||r||, start of Alg. 1 (G, status); or stop
-  kScale = 4,    // z_0 = r / ||r|| into ring slot 0 and basis 0
+  kScale = 4,    // z_0 = r / ||r|| into ring slot 0 and basis 0 (FP32: r recomputed; c = 0)
   kSweep = 5,    // iteration i of Alg. 1
   kFinal = 6,    // true residual partial sums
   kFinal2 = 7,   // owner: residual norms; others: x = D^{-1/2} y
   kReport = 8,   // owner: result to the host (x is final: written by the previous launch)
-  kDone = 9
+  kDone = 9,
+  kCorrect = 10  // FP32-refined: y += c (the inner solve's FP32 correction), then kResid
 };
 
 // Per slot; two copies alternate by tick parity (tick s reads copy (s-1)&1).
@@ -150,6 +151,8 @@ struct BatchState {
   int32_t reason;     // PLCG_REASON_* once done
   int32_t first;      // 1 until the first segment has started
   int32_t nparts;     // streaming blocks of the previous tick (partials written)
+  int32_t outer;      // FP32-refined: refinement steps (corrections added)
+  int32_t pad2;
   double rref_orig;   // ||b - A x0|| in the original (unscaled) norm
   double res_scaled;  // final ||r~|| / ||r~_0||
   double res_orig;    // final ||b - A x|| / ||b - A x0||
@@ -157,14 +160,16 @@ struct BatchState {
 
 // Per slot, written by the host at admission.
 struct SlotDesc {
-  double *vec;                          // bases 2l, ring R, p: consecutive, vstride apart
+  double *vec;                          // bases 2l, ring R, p (FP32-refined: then the correction
+                                        // c), consecutive, vstride elements of the storage type apart
   const double *sx, *sy, *sz, *dis;     // scaled edge weights, D^{-1/2}
   const double *b;                      // caller's right-hand side
   double *x;                            // caller's x0 on entry, solution at the end
   int64_t vstride;
   int32_t nx, ny, nz, d3, n, nchunks, nblocks, maxit;
-  int32_t max_restarts, pad;
+  int32_t max_restarts, mixed;         // mixed: FP32-refined
   double tol;
+  double inner_tol;                     // FP32-refined inner stop, relative to ||r_k||
 };
 
 // Per slot, in mapped pinned host memory: the result once phase == kDone.
@@ -172,6 +177,7 @@ struct SlotReport {
   int32_t phase, reason, iters, restarts;
   double res_scaled, res_orig, rnorm0;
   uint64_t ticket;
+  int32_t outer, pad;
 };
 
 struct BatchArgs {
@@ -182,6 +188,7 @@ struct BatchArgs {
   SlotReport *reports;     // mapped host memory
   const uint64_t *tickets; // per slot
   int32_t tick, l;
+  int32_t mixed, pad;      // FP32-refined batch: vectors stored in FP32
 };
 
 hipError_t launch_batch_tick(const BatchArgs &a, int blocks, hipStream_t s);

@@ -68,7 +68,7 @@ class plcg_batch_config(ctypes.Structure):
                 ("lambda_max", ctypes.c_double), ("max_slots", ctypes.c_int32),
                 ("arena_bytes", ctypes.c_int64), ("chunks_per_block", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
 
 
 class plcg_system_desc(ctypes.Structure):
@@ -287,10 +287,14 @@ class Batch:
     """Convenience owner of one plcg_batch."""
 
     def __init__(self, l=2, max_slots=64, arena_bytes=1 << 30, chunks_per_block=0,
-                 lmin=0.0, lmax=0.0, max_restarts=-1, use_graph=False):
+                 lmin=0.0, lmax=0.0, max_restarts=-1, use_graph=False, precision="fp64",
+                 inner_tol=0.0):
+        """precision "fp64", or "fp32" for FP32-stored inner solves inside FP64
+        iterative refinement (inner_tol: the inner solves' relative tolerance)."""
+        prec = PLCG_PREC_FP32_REFINED if precision == "fp32" else PLCG_PREC_FP64
         cfg = plcg_batch_config(int(l), float(lmin), float(lmax), int(max_slots),
                                 int(arena_bytes), int(chunks_per_block), int(max_restarts),
-                                1 if use_graph else 0, 0)
+                                1 if use_graph else 0, prec, float(inner_tol))
         self.handle = _h()
         check(plcg_batch_create(ctypes.byref(cfg), ctypes.byref(self.handle)), "plcg_batch_create")
         self._keep = {}

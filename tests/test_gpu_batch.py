@@ -46,17 +46,19 @@ def _oracle(sys_, l, tol, maxit=20000):
 
 
 def run_batch(dev, systems, l, tol, maxit=20000, use_graph=False, cpb=0, max_slots=None,
-              ticks=32, autotune=False):
+              ticks=32, autotune=False, precision="fp64", inner_tol=0.0):
     plcg = _plcg()
     stream = torch.cuda.current_stream(dev).cuda_stream
     batch = plcg.Batch(l=l, max_slots=max_slots or len(systems), arena_bytes=1 << 31,
-                       chunks_per_block=cpb, use_graph=use_graph)
+                       chunks_per_block=cpb, use_graph=use_graph, precision=precision,
+                       inner_tol=inner_tol)
     bufs = []
     pending = list(range(len(systems)))
     tickets = {}
     results = {}
     guard = 0
-    print(f"[gpu] batch of {len(systems)} l={l} graph={use_graph} cpb={cpb}", flush=True)
+    print(f"[gpu] batch of {len(systems)} l={l} graph={use_graph} cpb={cpb} {precision}",
+          flush=True)
     while pending or tickets:
         while pending:
             k = pending[0]
@@ -240,3 +242,67 @@ def test_served_stream_equals_alone(dev):
         assert r.iters == ref.iters and r.true_relres == ref.true_relres
         assert r.rec_relres == ref.rec_relres < tol
     assert max(load) <= arena and max(count) >= 2
+
+
+# ------------------------------------------------------- FP32-refined batches --
+
+MIXED_SYSTEMS = [((40, 40), 1, 2), ((57, 33), 3, 4), ((12, 10, 9), 7, 8), ((6, 11), 13, 14),
+                 ((1, 200), 15, 16), ((31, 29), 17, 18)]
+
+
+def _oracle_refined(sys_, l, tol, inner_tol, maxit=20000, max_outer=50):
+    from oracle import refine
+    A, As, dis = operators.variable_laplacian(sys_["dims"], sys_["cx"], sys_["cy"], sys_["cz"])
+    r = refine.refine(As, dis * sys_["b"], np.zeros(sys_["n"]), l,
+                      shifts.chebyshev_shifts(l, 0.0, 2.0), tol, inner_tol, maxit, max_outer)
+    return r, As, dis
+
+
+@pytest.mark.parametrize("l", [2, 3])
+def test_mixed_batch_against_oracle(dev, l):
+    """FP32-stored inner p(l)-CG inside FP64 refinement, per system of a mixed
+    batch, against the oracle's model of the same arithmetic (oracle.refine on
+    the Jacobi-scaled system): both converge with the same number of refinement
+    steps (within 1) and inner iteration counts within 10 %, the FP64 residual
+    below tol, and x within ||A~^{-1}|| times the two residuals of each other."""
+    tol, inner_tol = 1e-10, 1e-3
+    systems = [_system(*s) for s in MIXED_SYSTEMS]
+    res = run_batch(dev, systems, l, tol, precision="fp32", inner_tol=inner_tol)
+    for k, s in enumerate(systems):
+        ref, As, dis = _oracle_refined(s, l, tol, inner_tol)
+        r, x = res[k]
+        assert ref.reason == "converged" and r.reason == 1, (k, r.as_dict())
+        assert r.rec_relres < tol and ref.true_relres < tol
+        assert abs(r.outer - ref.outer) <= 1, (k, r.outer, ref.outer)
+        assert abs(r.iters - ref.inner_iters) <= 0.1 * ref.inner_iters + 2
+        lam_min = np.linalg.eigvalsh(operators.assemble(As))[0]
+        y, yref = x / dis, ref.x
+        bound = (r.rec_relres + ref.true_relres) * ref.rnorm0 / lam_min
+        assert np.linalg.norm(y - yref) <= 2 * bound + 1e-14 * np.linalg.norm(yref)
+
+
+def test_mixed_batch_first_inner_steps(dev):
+    """After m inner iterations of the first refinement step the batch's y
+    equals the oracle's FP32-stored iterate to FP32 rounding."""
+    s = _system((40, 30), 21, 22)
+    for m in (1, 3, 8):
+        res = run_batch(dev, [s], 2, 1e-30, maxit=m, precision="fp32", inner_tol=1e-30)
+        r, x = res[0]
+        ref, As, dis = _oracle_refined(s, 2, 1e-30, 1e-30, maxit=m, max_outer=1)
+        assert r.iters == m == ref.inner_iters and r.outer == 1 == ref.outer
+        assert r.reason == 2
+        y = x / dis
+        assert np.linalg.norm(y - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_mixed_batch_alone_equals_in_the_mix(dev):
+    systems = [_system(*s) for s in MIXED_SYSTEMS]
+    mix = run_batch(dev, systems, 2, 1e-9, precision="fp32", inner_tol=1e-4)
+    graph = run_batch(dev, systems, 2, 1e-9, precision="fp32", inner_tol=1e-4, use_graph=True,
+                      ticks=48)
+    for k in (0, 2):
+        alone = run_batch(dev, [systems[k]], 2, 1e-9, precision="fp32", inner_tol=1e-4)
+        assert alone[0][0].iters == mix[k][0].iters and alone[0][0].outer == mix[k][0].outer
+        assert np.array_equal(alone[0][1], mix[k][1])
+    for k in range(len(systems)):
+        assert np.array_equal(graph[k][1], mix[k][1])
