@@ -127,6 +127,36 @@ def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None):
     print("profile run done", flush=True)
 
 
+def copy_probe(plcg, torch, dev, sp):
+    """Streaming reference: a plain copy (the library's plcg_copy and torch's
+    copy_) of 32 MiB .. 4 GiB, to place the sweeps against what one read and one
+    write stream reach on this GPU below and above the 256 MB Infinity Cache."""
+    out = []
+    for mb in (32, 128, 256, 512, 1024, 4096):
+        n = mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        row = {"MiB": mb}
+        for name, fn in (("plcg_copy", lambda: plcg.check(
+                plcg.plcg_copy(a.data_ptr(), b.data_ptr(), n, sp), "plcg_copy")),
+                         ("torch_copy", lambda: b.copy_(a))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 20
+            row[name + "_GBps"] = 2 * n * 8 / ms / 1e6
+        out.append(row)
+        print(json.dumps(row), flush=True)
+        del a, b
+
+
 def batch_bench(args, plcg, torch, dev, sp):
     """512 variable-coefficient systems (sides uniform on [32, 512], lognormal(0,1)
     edges, Jacobi-scaled, shifts on [0, 2]) solved together by the batch engine."""
@@ -315,6 +345,8 @@ def main():
     ap.add_argument("--serve-arena-gb", type=float, default=48.0)
     ap.add_argument("--serve-ticks", type=int, default=16)
     ap.add_argument("--serve-time-limit", type=float, default=120.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="plain copy bandwidth at 32 MiB .. 4 GiB (streaming reference)")
     ap.add_argument("--profile-run", action="store_true",
                     help="short fixed run for hardware-counter passes: 10 copies of "
                          "n doubles, then 100 iterations of each method")
@@ -336,6 +368,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        copy_probe(plcg, torch, dev, torch.cuda.current_stream(dev).cuda_stream)
+        return
     if args.workload == "batch512":
         batch_bench(args, plcg, torch, dev, torch.cuda.current_stream(dev).cuda_stream)
         return

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
     SweepArgsT<ST> sa;
     slot_sweep_args<L, ST>(S, i, sa);
     using SW = Sweep<L, ST, VarOp>;
-    for (int idx = start; idx < S.n; idx += step) SW::template chunk<false>(sa, op, idx, t, cf, acc);
+    for (int idx = start; idx < S.n; idx += step) SW::template chunk<kVec, false>(sa, op, idx, t, cf, acc);
     store_partials<ND>(acc, part_out, kMaxStream, lb, lds, red);
     return;
   }

@@ -31,35 +31,84 @@ struct Grid {
   int n, nx, ny, nz;
 };
 
+// Order in which the chunks of a 3D grid are visited.  In plain index order the
+// z-neighbours of a chunk are a whole plane of chunks away, and by the time a
+// plane is read again as the neighbour of the next one the XCD's L2 has long
+// evicted it.  When a plane is a whole number of chunks, the chunks are visited
+// by column tiles of `tile` chunks: (tile, z, chunk in tile), so the workgroups
+// of an XCD, which run consecutive positions of this order side by side, read a
+// tile's planes a few chunks apart.  Visiting order is all that changes.
+struct ChunkOrder {
+  int cpp, tile, per_tile;   // chunks per plane, chunks per tile, nz * tile; cpp == 0: identity
+  __device__ inline int phys(int c) const {
+    if (cpp == 0) return c;
+    const int t = c / per_tile;
+    const int r = c - t * per_tile;
+    const int z = r / tile;
+    return z * cpp + t * tile + (r - z * tile);
+  }
+};
+
+__device__ inline ChunkOrder chunk_order(const Grid &g, bool d3, int chunk) {
+  const int plane = g.nx * g.ny;
+  if (!d3 || g.nz < 2 || plane % chunk != 0) return ChunkOrder{0, 0, 0};
+  const int cpp = plane / chunk;
+  int tile = 8;
+  while (cpp % tile != 0) tile >>= 1;
+  if (tile == cpp) return ChunkOrder{0, 0, 0};   // a tile would be the whole plane
+  return ChunkOrder{cpp, tile, g.nz * tile};
+}
+
+// Unknowns per thread and chunk for storage type S: one 16-byte access.
+template <typename S>
+constexpr int vec_of() { return 16 / (int)sizeof(S); }
+
 // ---------------------------------------------------------------------------
 // Stencil
 // ---------------------------------------------------------------------------
 
 // V consecutive values held in FP64 registers; S is the storage type in memory
 // (double, or float for the FP32-stored inner solver), converted on load/store.
+// V is 1, 2 or 4; p is aligned to V elements.
 template <int V, typename S = double>
 struct Vals {
   double v[V];
   __device__ inline void load(const S *p) {
-    if constexpr (V == 2 && sizeof(S) == 8) {
-      const double2 t = *reinterpret_cast<const double2 *>(p);
-      v[0] = t.x;
-      v[1] = t.y;
-    } else if constexpr (V == 2) {
+    if constexpr (sizeof(S) == 8 && V % 2 == 0) {
+#pragma unroll
+      for (int k = 0; k < V / 2; ++k) {
+        const double2 t = reinterpret_cast<const double2 *>(p)[k];
+        v[2 * k] = t.x;
+        v[2 * k + 1] = t.y;
+      }
+    } else if constexpr (sizeof(S) == 4 && V == 4) {
+      const float4 t = *reinterpret_cast<const float4 *>(p);
+      v[0] = (double)t.x;
+      v[1] = (double)t.y;
+      v[2] = (double)t.z;
+      v[3] = (double)t.w;
+    } else if constexpr (sizeof(S) == 4 && V == 2) {
       const float2 t = *reinterpret_cast<const float2 *>(p);
       v[0] = (double)t.x;
       v[1] = (double)t.y;
     } else {
-      v[0] = (double)*p;
+#pragma unroll
+      for (int k = 0; k < V; ++k) v[k] = (double)p[k];
     }
   }
   __device__ inline void store(S *p) const {
-    if constexpr (V == 2 && sizeof(S) == 8) {
-      *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
-    } else if constexpr (V == 2) {
+    if constexpr (sizeof(S) == 8 && V % 2 == 0) {
+#pragma unroll
+      for (int k = 0; k < V / 2; ++k)
+        reinterpret_cast<double2 *>(p)[k] = make_double2(v[2 * k], v[2 * k + 1]);
+    } else if constexpr (sizeof(S) == 4 && V == 4) {
+      *reinterpret_cast<float4 *>(p) =
+          make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    } else if constexpr (sizeof(S) == 4 && V == 2) {
       *reinterpret_cast<float2 *>(p) = make_float2((float)v[0], (float)v[1]);
     } else {
-      *p = (S)v[0];
+#pragma unroll
+      for (int k = 0; k < V; ++k) p[k] = (S)v[k];
     }
   }
   __device__ inline void zero() {
@@ -89,54 +138,58 @@ __device__ inline double neighbour_sum(const S *z, int p, const Grid &g) {
 }
 
 // w = A z at the V unknowns starting at idx, given their values zc.
-// FAST (a full chunk and an even nx): both unknowns of a thread share a row,
-// x-neighbours come from the adjacent lanes (consecutive pairs), the rows and
-// planes above and below are 16-byte loads.  Called by all 64 lanes together.
+// FAST (a full chunk, nx a multiple of V): the V unknowns of a thread share a
+// row, x-neighbours come from the thread's own values and the adjacent lanes
+// (consecutive groups of V), the rows and planes above and below are 16-byte
+// loads.  Called by all 64 lanes together.
 template <int V, bool D3, bool FAST, typename S>
 __device__ inline void apply_stencil(const S *z, int idx, const Vals<V, S> &zc, const Grid &g,
                                      double (&w)[V]) {
   const double diag = D3 ? 6.0 : 4.0;
-  if constexpr (FAST && V == 2) {
+  if constexpr (FAST && V >= 2) {
     const int x = idx % g.nx;
     const int rest = idx / g.nx;
     const int y = D3 ? rest % g.ny : rest;
     const int lane = threadIdx.x & 63;
-    double left = __shfl_up(zc.v[1], 1, 64);     // z[idx-1] held by the previous lane
-    double right = __shfl_down(zc.v[0], 1, 64);  // z[idx+2] held by the next lane
+    double left = __shfl_up(zc.v[V - 1], 1, 64);   // z[idx-1] held by the previous lane
+    double right = __shfl_down(zc.v[0], 1, 64);    // z[idx+V] held by the next lane
     if (lane == 0 && x > 0) left = (double)z[idx - 1];
-    if (lane == 63 && x + 2 < g.nx) right = (double)z[idx + 2];
-    double s0 = (x > 0 ? left : 0.0) + zc.v[1];
-    double s1 = zc.v[0] + (x + 2 < g.nx ? right : 0.0);
+    if (lane == 63 && x + V < g.nx) right = (double)z[idx + V];
+    double s[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      s[k] = (k > 0 ? zc.v[k - 1] : (x > 0 ? left : 0.0)) +
+             (k < V - 1 ? zc.v[k + 1] : (x + V < g.nx ? right : 0.0));
     if (y > 0) {
-      Vals<2, S> u;
+      Vals<V, S> u;
       u.load(z + idx - g.nx);
-      s0 += u.v[0];
-      s1 += u.v[1];
+#pragma unroll
+      for (int k = 0; k < V; ++k) s[k] += u.v[k];
     }
     if (y < g.ny - 1) {
-      Vals<2, S> d;
+      Vals<V, S> d;
       d.load(z + idx + g.nx);
-      s0 += d.v[0];
-      s1 += d.v[1];
+#pragma unroll
+      for (int k = 0; k < V; ++k) s[k] += d.v[k];
     }
     if (D3) {
       const int zz = rest / g.ny;
       const int plane = g.nx * g.ny;
       if (zz > 0) {
-        Vals<2, S> f;
+        Vals<V, S> f;
         f.load(z + idx - plane);
-        s0 += f.v[0];
-        s1 += f.v[1];
+#pragma unroll
+        for (int k = 0; k < V; ++k) s[k] += f.v[k];
       }
       if (zz < g.nz - 1) {
-        Vals<2, S> k;
-        k.load(z + idx + plane);
-        s0 += k.v[0];
-        s1 += k.v[1];
+        Vals<V, S> b;
+        b.load(z + idx + plane);
+#pragma unroll
+        for (int k = 0; k < V; ++k) s[k] += b.v[k];
       }
     }
-    w[0] = diag * zc.v[0] - s0;
-    w[1] = diag * zc.v[1] - s1;
+#pragma unroll
+    for (int k = 0; k < V; ++k) w[k] = diag * zc.v[k] - s[k];
   } else {
 #pragma unroll
     for (int v = 0; v < V; ++v) w[v] = diag * zc.v[v] - neighbour_sum<D3, S>(z, idx + v, g);
@@ -477,19 +530,23 @@ struct Sweep {
     }
   }
 
-  template <bool FAST>
+  // The V unknowns idx .. idx+V-1 of a thread (one at a time past the end of
+  // a ragged last chunk).
+  template <int V, bool FAST>
   __device__ static inline void chunk(const Args &a, const Op &op, int idx, int t,
                                       const Coef<L> &cf, double (&acc)[ND]) {
-    if (t >= 0) {
-      if (idx + 1 < a.n)
-        steady<2, FAST>(a, op, idx, t, cf, acc);
-      else if (idx < a.n)
-        steady<1, false>(a, op, idx, t, cf, acc);
+    if (idx + V <= a.n) {
+      if (t >= 0)
+        steady<V, FAST>(a, op, idx, t, cf, acc);
+      else
+        startup<V, FAST>(a, op, idx, a.i, cf.sigma_i, acc);
     } else {
-      if (idx + 1 < a.n)
-        startup<2, FAST>(a, op, idx, a.i, cf.sigma_i, acc);
-      else if (idx < a.n)
-        startup<1, false>(a, op, idx, a.i, cf.sigma_i, acc);
+      for (int k = idx; k < a.n; ++k) {
+        if (t >= 0)
+          steady<1, false>(a, op, k, t, cf, acc);
+        else
+          startup<1, false>(a, op, k, a.i, cf.sigma_i, acc);
+      }
     }
   }
 };

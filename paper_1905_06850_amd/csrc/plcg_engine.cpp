@@ -241,7 +241,9 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
   a.ny = h->op.ny;
   a.nz = h->op.nz;
   a.d3 = h->d3 ? 1 : 0;
-  a.nchunks = h->nchunks;
+  // chunks of kThreads * (16 / sizeof(S)) unknowns: 512 doubles or 1024 floats
+  const int chunk = kThreads * (16 / (int)sizeof(S));
+  a.nchunks = (h->n + chunk - 1) / chunk;
   a.nstream = h->blocks;
   a.nparts_in = i >= 1 ? h->blocks : 0;
   a.pstride = kMaxStream;

@@ -71,7 +71,7 @@ struct SweepArgsT {
   HostStatus *hs;            // mapped pinned host memory
   double *hist;              // [hist_cap][4] or NULL
   int32_t i, l, n, nx, ny, nz, d3;
-  int32_t nchunks;           // ceil(n / kChunk)
+  int32_t nchunks;           // ceil(n / (kThreads * 16 / sizeof(S))): chunks of one 16-byte access per thread
   int32_t nstream;           // streaming blocks (multiple of kXcds)
   int32_t nparts_in;         // partials per product in part_in
   int32_t pstride;

@@ -25,10 +25,16 @@ namespace plcg {
 // p(l)-CG sweep: iteration i of Alg. 1
 // ---------------------------------------------------------------------------
 
-// Body shared by the stencil and the diagonal operators.  fast_rows: full
-// chunks may take the operator's FAST form.
+// Body shared by the stencil and the diagonal operators.  Each thread takes V =
+// 16 / sizeof(ST) consecutive unknowns of a chunk (one 16-byte access per
+// vector: 2 doubles, or 4 floats for the FP32-stored inner solver).
+// fast_rows: full chunks may take the operator's FAST form; order: the chunk
+// visiting order.
 template <int L, typename ST, typename Op>
-__device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fast_rows) {
+__device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fast_rows,
+                                  const ChunkOrder &order) {
+  constexpr int V = vec_of<ST>();
+  constexpr int CH = kThreads * V;
   using S = Sweep<L, ST, Op>;
   constexpr int ND = S::ND;
   __shared__ double lds[4 * ND];
@@ -76,24 +82,26 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   for (int m = 0; m < ND; ++m) acc[m] = 0.0;
   const int first = L == 1 ? 0 : 1;
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, first); it.c < it.end; it.c += it.step) {
-    const int base = it.c * kChunk;
-    const int idx = base + threadIdx.x * kVec;
-    if (fast_rows && base + kChunk <= a.n)
-      S::template chunk<true>(a, op, idx, t, cf, acc);
+    const int base = order.phys(it.c) * CH;
+    const int idx = base + threadIdx.x * V;
+    if (fast_rows && base + CH <= a.n)
+      S::template chunk<V, true>(a, op, idx, t, cf, acc);
     else
-      S::template chunk<false>(a, op, idx, t, cf, acc);
+      S::template chunk<V, false>(a, op, idx, t, cf, acc);
   }
   store_partials<ND>(acc, a.part_out, a.pstride, blockIdx.x - first, lds, red);
 }
 
 template <int L, bool D3, typename ST>
 __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST>(a, ConstOp<D3, ST>{Grid{a.n, a.nx, a.ny, a.nz}}, (a.nx & 1) == 0);
+  const Grid g{a.n, a.nx, a.ny, a.nz};
+  plcg_sweep<L, ST>(a, ConstOp<D3, ST>{g}, a.nx % vec_of<ST>() == 0,
+                    chunk_order(g, D3, kThreads * vec_of<ST>()));
 }
 
 template <int L, typename ST>
 __global__ __launch_bounds__(kThreads) void plcg_diag_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST>(a, DiagOp<ST>{a.dg}, true);
+  plcg_sweep<L, ST>(a, DiagOp<ST>{a.dg}, true, ChunkOrder{0, 0, 0});
 }
 
 // ---------------------------------------------------------------------------
@@ -158,8 +166,9 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       v1 += beta * po.v[1];
     }
   };
+  const ChunkOrder order = chunk_order(g, D3, kChunk);
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
-    const int base = it.c * kChunk;
+    const int base = order.phys(it.c) * kChunk;
     const int idx0 = base + threadIdx.x * kVec;
     if (fast_rows && base + kChunk <= a.n) {
       // Same layout as the p(l)-CG fast path: pairs in one row, x-neighbours
@@ -349,8 +358,9 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, con
   __shared__ double lds[4];
   __shared__ double red[1];
   double acc[1] = {0.0};
+  const ChunkOrder order = chunk_order(g, D3, kChunk);
   for (ChunkIter it = xcd_chunks(nchunks, nstream, 0); it.c < it.end; it.c += it.step) {
-    const int idx0 = it.c * kChunk + threadIdx.x * kVec;
+    const int idx0 = order.phys(it.c) * kChunk + threadIdx.x * kVec;
 #pragma unroll
     for (int v = 0; v < kVec; ++v) {
       const int p = idx0 + v;

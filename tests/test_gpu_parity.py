@@ -116,8 +116,10 @@ def test_solve_parity_64_manufactured(dev, method, l):
     s.close()
 
 
+# (32, 48, 5) and (64, 160, 6): planes of whole chunks, visited by column tiles
 @pytest.mark.parametrize("dims", [(100, 37), (37, 100), (1, 700), (700, 1), (20, 13, 7),
-                                  (5, 9, 11), (1, 1, 600)])
+                                  (5, 9, 11), (1, 1, 600), (32, 48, 5), (64, 160, 6),
+                                  (102, 30)])
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
 def test_solve_parity_ragged(dev, dims, method, l):
     A = operators.laplacian(dims)
@@ -353,10 +355,14 @@ def _mixed_oracle(dims, l, b, tol, inner_tol, maxit=20000, max_outer=50):
                          inner_tol, maxit, max_outer=max_outer)
 
 
+# FP32 storage: 4 unknowns per thread; (102, 30) takes the per-unknown stencil
+# (nx not a multiple of 4), (64, 160, 6) the column-tiled chunk order
 @pytest.mark.parametrize("dims,l,tol,inner_tol", [((48, 48, 48), 3, 1e-10, 1e-3),
                                                   ((48, 48, 48), 3, 1e-10, 1e-5),
                                                   ((64, 64), 1, 1e-10, 1e-3),
-                                                  ((100, 37), 2, 1e-10, 1e-4)])
+                                                  ((100, 37), 2, 1e-10, 1e-4),
+                                                  ((102, 30), 2, 1e-10, 1e-4),
+                                                  ((64, 160, 6), 3, 1e-10, 1e-4)])
 def test_mixed_precision_against_oracle(dev, dims, l, tol, inner_tol):
     """FP32-stored inner p(l)-CG inside FP64 refinement against the oracle's
     model of the same arithmetic (oracle.refine): both reach the FP64 tolerance,
