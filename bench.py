@@ -328,7 +328,7 @@ def main():
                     help="headline method: l of p(l)-CG, or m<l> for FP32-refined p(l)-CG")
     ap.add_argument("--inner-tol", type=float, default=1e-3,
                     help="inner tolerance of the FP32-refined methods (m<l>)")
-    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--cpu-iters", type=int, default=250)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
