@@ -277,8 +277,10 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
   double acc[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) acc[m] = 0.0;
-  const int step = S.nblocks * kChunk;
-  const int start = lb * kChunk + threadIdx.x * kVec;
+  // one 16-byte access per thread and vector: 2 doubles or 4 floats
+  constexpr int V = vec_of<ST>();
+  const int step = S.nblocks * kThreads * V;
+  const int start = lb * kThreads * V + threadIdx.x * V;
 
   if (phase == kSweep) {
     const int i = in->i;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
     SweepArgsT<ST> sa;
     slot_sweep_args<L, ST>(S, i, sa);
     using SW = Sweep<L, ST, VarOp>;
-    for (int idx = start; idx < S.n; idx += step) SW::template chunk<kVec, false>(sa, op, idx, t, cf, acc);
+    for (int idx = start; idx < S.n; idx += step) SW::template chunk<V, false>(sa, op, idx, t, cf, acc);
     store_partials<ND>(acc, part_out, kMaxStream, lb, lds, red);
     return;
   }
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
   const double inv_beta = phase == kScale ? 1.0 / in->d.beta : 0.0;
   for (int base = start; base < S.n; base += step) {
 #pragma unroll
-    for (int v = 0; v < kVec; ++v) {
+    for (int v = 0; v < V; ++v) {
       const int p = base + v;
       if (p >= S.n) break;
       if (phase == kInit) {

@@ -667,8 +667,7 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   // their size rounded up to 64 KiB plus a stagger, so that the many streams
   // of a sweep do not start on the same HBM channel when n*8 is a power of two.
   const size_t vb = (size_t)n * sizeof(double);
-  size_t stagger = 4096 + 256;
-  if (const char *env = std::getenv("PLCG_VECTOR_STAGGER")) stagger = (size_t)std::atoll(env) & ~size_t(255);
+  const size_t stagger = 4096 + 256;
   const size_t vstride = ((vb + 65535) / 65536) * 65536 + stagger;
   const bool mixed = h->precision == PLCG_PREC_FP32_REFINED;
   const size_t vb32 = (size_t)n * sizeof(float);
