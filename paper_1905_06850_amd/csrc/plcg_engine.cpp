@@ -14,6 +14,7 @@
 
 #include "../../include/plcg.h"
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -475,6 +476,14 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   a.nstream = h->blocks;
   a.nparts_in = h->blocks;
   a.pstride = kMaxStream;
+  // 3D grids whose planes are whole chunks (and even nx): sweep A marches each
+  // chunk-sized tile through zseg planes, about one tile-segment per workgroup.
+  a.zseg = 0;
+  if (h->d3 && h->dg == nullptr && h->op.nz >= 2 && (h->op.nx & 1) == 0 &&
+      ((long long)h->op.nx * h->op.ny) % kChunk == 0) {
+    const long long tiles = (long long)h->op.nx * h->op.ny / kChunk;
+    a.zseg = (int)std::max(1LL, tiles * h->op.nz / h->blocks);
+  }
   auto set_a = [&](int k, int work) {
     a.k = k;
     a.work = work;

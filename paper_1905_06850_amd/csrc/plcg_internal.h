@@ -89,6 +89,8 @@ struct CgArgs {
   DevState *st_out;
   HostStatus *hs;
   int32_t k, n, nx, ny, nz, d3, nchunks, nstream, nparts_in, pstride, work;
+  int32_t zseg;              // > 0: 3D sweep A marches tiles through zseg planes
+  int32_t pad;
 };
 
 // Launchers (plcg_kernels.hip).

@@ -166,6 +166,77 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       v1 += beta * po.v[1];
     }
   };
+  if (D3 && a.zseg > 0) {
+    // z-march (3D, planes of whole chunks, even nx): a workgroup takes one
+    // chunk-sized tile of a plane through zseg consecutive planes and keeps p_k
+    // of the planes below, at and above the current one in registers, so every
+    // r and p_{k-1} value is loaded once per plane it is the centre of (the
+    // rows above and below come from the tile's own or its neighbours' loads in
+    // L2).  Same neighbour-sum order as the chunk path below.
+    const int plane = g.nx * g.ny;
+    const int ntiles = plane / kChunk;
+    const int nitems = ntiles * ((g.nz + a.zseg - 1) / a.zseg);
+    const int lane = threadIdx.x & 63;
+    for (ChunkIter it = xcd_chunks(nitems, a.nstream, 0); it.c < it.end; it.c += it.step) {
+      const int seg = it.c / ntiles;
+      const int off = (it.c - seg * ntiles) * kChunk + threadIdx.x * kVec;   // in the plane
+      const int x = off % g.nx;
+      const int y = off / g.nx;
+      const int z0 = seg * a.zseg;
+      const int z1 = min(g.nz, z0 + a.zseg);
+      double m0 = 0.0, m1 = 0.0, c0, c1, n0 = 0.0, n1 = 0.0;
+      if (z0 > 0) pk2(off + (z0 - 1) * plane, m0, m1);
+      pk2(off + z0 * plane, c0, c1);
+      for (int zz = z0; zz < z1; ++zz) {
+        const int idx0 = off + zz * plane;
+        if (zz + 1 < g.nz) {
+          pk2(idx0 + plane, n0, n1);
+        } else {
+          n0 = 0.0;
+          n1 = 0.0;
+        }
+        double left = __shfl_up(c1, 1, 64);
+        double right = __shfl_down(c0, 1, 64);
+        if (lane == 0 && x > 0) left = pk1(idx0 - 1);
+        if (lane == 63 && x + 2 < g.nx) right = pk1(idx0 + 2);
+        double s0 = (x > 0 ? left : 0.0) + c1;
+        double s1 = c0 + (x + 2 < g.nx ? right : 0.0);
+        double u0, u1;
+        if (y > 0) {
+          pk2(idx0 - g.nx, u0, u1);
+          s0 += u0;
+          s1 += u1;
+        }
+        if (y < g.ny - 1) {
+          pk2(idx0 + g.nx, u0, u1);
+          s0 += u0;
+          s1 += u1;
+        }
+        if (zz > 0) {
+          s0 += m0;
+          s1 += m1;
+        }
+        if (zz < g.nz - 1) {
+          s0 += n0;
+          s1 += n1;
+        }
+        Vals<2> pn, qv;
+        pn.v[0] = c0;
+        pn.v[1] = c1;
+        qv.v[0] = diag * c0 - s0;
+        qv.v[1] = diag * c1 - s1;
+        pn.store(a.p_new + idx0);
+        qv.store(a.q + idx0);
+        acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
+        m0 = c0;
+        m1 = c1;
+        c0 = n0;
+        c1 = n1;
+      }
+    }
+    store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
+    return;
+  }
   const ChunkOrder order = chunk_order(g, D3, kChunk);
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
     const int base = order.phys(it.c) * kChunk;

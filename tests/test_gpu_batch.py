@@ -306,3 +306,69 @@ def test_mixed_batch_alone_equals_in_the_mix(dev):
         assert np.array_equal(alone[0][1], mix[k][1])
     for k in range(len(systems)):
         assert np.array_equal(graph[k][1], mix[k][1])
+
+
+# --------------------------------------------------- batch512 at full size --
+
+def test_batch512_sampled_systems_against_stored_oracle(dev):
+    """The whole batch512 workload in the benchmark's launch configuration (arena
+    sized by the footprints, graph replay, autotuned workgroup size), with four of
+    its systems (the smallest, the largest and two more) compared with the
+    oracle's stored solution of each alone (tests/golden/batch512_*.json):
+    iterations within 2, scaled and original residuals close, sampled x within
+    1e-8 of the oracle's."""
+    import json
+    import os
+    goldens = []
+    for k in range(4):
+        path = os.path.join(os.path.dirname(__file__), "golden", f"batch512_{k}.json")
+        if not os.path.exists(path):
+            pytest.skip("no stored oracle result for batch512")
+        with open(path) as f:
+            goldens.append(json.load(f))
+    plcg = _plcg()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    recipe = synth.batch_recipe(512)
+    systems = []
+    for dims, cseed, bseed in recipe:
+        cx, cy, _ = synth.edge_coefficients(dims, cseed)
+        systems.append((dims, cx, cy, bseed))
+    probe = plcg.Batch(l=2, max_slots=1, arena_bytes=1 << 20)
+    need = sum(probe.footprint(d, cx, cy) for d, cx, cy, _ in systems)
+    probe.close()
+    print(f"[gpu] batch512 full size, arena {need / 2**30:.1f} GiB", flush=True)
+    batch = plcg.Batch(l=2, max_slots=512, arena_bytes=need + (64 << 20), use_graph=True)
+    bufs, tickets = [], {}
+    for j, (dims, cx, cy, bseed) in enumerate(systems):
+        n = dims[0] * dims[1]
+        bt = torch.from_numpy(synth.uniform(n, bseed)).to(dev)
+        xt = torch.zeros(n, dtype=torch.float64, device=dev)
+        t = batch.add(dims, bt.data_ptr(), xt.data_ptr(), 1e-8, 100000, stream, cx, cy)
+        assert t is not None
+        bufs.append((bt, xt))
+        tickets[t] = j
+    batch.autotune(8, stream)
+    results = {}
+    guard = 0
+    while tickets:
+        batch.step(64, stream)
+        torch.cuda.synchronize()
+        for t in list(tickets):
+            r = batch.poll(t)
+            if r is not None:
+                results[tickets.pop(t)] = r
+        guard += 1
+        assert guard < 10000
+    batch.close()
+    assert all(r.reason == 1 for r in results.values())
+    for g in goldens:
+        j = g["system"]
+        r = results[j]
+        x = bufs[j][1].cpu().numpy()
+        assert abs(r.iters - g["iters"]) <= 2, (j, r.iters, g["iters"])
+        assert r.rec_relres <= 10 * g["true_relres"]
+        assert abs(r.true_relres - g["orig_relres"]) <= 0.1 * g["orig_relres"]
+        idx = np.array(g["sample_idx"])
+        ref = np.array(g["sample_x"])
+        est = np.sqrt(x.size / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
+        assert est < 1e-8, (j, est)

@@ -104,3 +104,33 @@ def test_diag_rejects_nonpositive_entries(dev):
         with pytest.raises(plcg.PlcgError) as ei:
             plcg.Solver("diag", (1000,), method="plcg", l=2, diag=dt.data_ptr())
         assert ei.value.status == plcg.PLCG_E_INVALID
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result {name}")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["diag2048_cg", "diag2048_p1", "diag2048_p2"])
+def test_diag_full_size_against_stored_oracle(dev, name):
+    """The 2048^2 toy as the benchmark runs it, against the oracle's stored result
+    (tests/golden, written from the oracle only): iterations within 1, true
+    residual within 10x, sampled ||x - x_oracle|| / ||x_oracle|| < 1e-8."""
+    g = _golden(name)
+    d = synth.spectrum_diagonal(tuple(g["dims"]))
+    n = d.size
+    b = synth.uniform(n, g["seed"])
+    x, res = gpu_solve(dev, d, g["method"], max(int(g["l"]), 1), b, np.zeros(n), g["tol"],
+                       100000)
+    assert res.reason == 1 and g["reason"] == "converged"
+    assert abs(res.iters - g["iters"]) <= 1
+    assert res.true_relres <= 10 * g["true_relres"] and g["true_relres"] <= 10 * res.true_relres
+    idx = np.array(g["sample_idx"])
+    ref = np.array(g["sample_x"])
+    est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
+    assert est < 1e-8

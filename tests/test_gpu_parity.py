@@ -152,6 +152,28 @@ def test_early_iterates(dev, method, l):
         s.close()
 
 
+@pytest.mark.parametrize("dims", [(64, 64, 256), (32, 48, 1100)])
+def test_cg_3d_zmarch_iterates(dev, dims):
+    """3D CG whose sweep A marches tiles through several planes (2 and 3 planes
+    per workgroup here; the second grid ends with a shorter segment): early
+    iterates against the oracle to rounding, and (64, 64, 256) solved through."""
+    A = operators.laplacian(dims)
+    b = synth.uniform(A.n, 12)
+    x0 = np.zeros(A.n)
+    for m in (1, 2, 5, 20):
+        ref = oracle_solve(dims, "cg", 1, b, x0, 1e-30, m)
+        x, res, s = gpu_solve(dev, dims, "cg", 1, b, x0, 1e-30, m)
+        assert res.iters == m == ref.iters
+        assert _rel(x, ref.x) < 1e-13
+        s.close()
+    if dims == (64, 64, 256):
+        ref = oracle_solve(dims, "cg", 1, b, x0, 1e-8, 5000)
+        x, res, s = gpu_solve(dev, dims, "cg", 1, b, x0, 1e-8, 5000)
+        assert res.reason == 1 and abs(res.iters - ref.iters) <= 1
+        assert _rel(x, ref.x) < 1e-8
+        s.close()
+
+
 def _fsum_dot(a, b):
     return math.fsum(a * b)
 
@@ -319,7 +341,7 @@ def _golden(name):
 
 @pytest.mark.parametrize("name", ["poisson2048_cg", "poisson2048_p1", "poisson2048_p2",
                                   "poisson2048_p3", "poisson2048_p4", "poisson2048_p5",
-                                  "poisson3d256_p3"])
+                                  "poisson3d256_p3", "poisson3d256_cg"])
 def test_full_size_against_stored_oracle(dev, name):
     """The benchmark workloads at full size, in the launch configuration the
     benchmark times, against the oracle's stored result (tests/golden,
@@ -395,3 +417,27 @@ def test_mixed_precision_first_inner_steps(dev):
         assert res.iters == m == ref.inner_iters and res.outer == 1 == ref.outer
         assert _rel(x, ref.x) < 1e-6
         s.close()
+
+
+def test_full_size_mixed_against_stored_oracle(dev):
+    """The 256^3 workload with FP32-stored p(3)-CG in FP64 refinement (inner tol
+    1e-4), as the benchmark runs it, against the oracle's stored model of the same
+    arithmetic: refinement steps within 1, inner iterations within 10 %, true
+    residual below tol, and the sampled x within kappa * 2 * tol of the oracle's."""
+    g = _golden("poisson3d256_m3")
+    dims = tuple(g["dims"])
+    n = int(np.prod(dims))
+    b = synth.uniform(n, g["seed"])
+    x, res, s = gpu_solve(dev, dims, "plcg", 3, b, np.zeros(n), g["tol"], 100000,
+                          interval=tuple(g["interval"]), precision="fp32",
+                          inner_tol=g["inner_tol"])
+    assert res.reason == 1 and g["reason"] == "converged"
+    assert abs(res.outer - g["outer"]) <= 1
+    assert abs(res.iters - g["iters"]) <= 0.1 * g["iters"] + 2
+    assert res.true_relres < g["tol"] and g["true_relres"] < g["tol"]
+    lmin, lmax = operators.laplacian_extremes(dims)
+    idx = np.array(g["sample_idx"])
+    ref = np.array(g["sample_x"])
+    est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
+    assert est <= (lmax / lmin) * 2 * g["tol"]
+    s.close()
