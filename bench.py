@@ -390,6 +390,13 @@ def main():
     # the one-point-stencil toy: diagonal operator holding the Laplacian's spectrum
     dg = (torch.from_numpy(synth.spectrum_diagonal(dims)).to(dev) if kind == "diag" else None)
     dptr = dg.data_ptr() if dg is not None else None
+    if wl["rhs"] == "manufactured":
+        # b = A x*, x* uniform (seed 0), formed with the library's operator
+        xs = b.clone()
+        op = plcg.Solver(kind, dims, method="cg", diag=dptr)
+        op.apply(xs.data_ptr(), b.data_ptr(), sp)
+        torch.cuda.synchronize()
+        op.close()
 
     if args.profile_run:
         profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods, dptr)
@@ -456,6 +463,8 @@ def main():
             if method != "cg" else None,
             "spmvs": r.spmvs,
             "outer": r.outer,
+            "host_waits": r.host_waits,
+            "launches_per_iter": kernels_per_iter,
             "solves_per_s": args.steps / dt,
         }
         if not args.quiet:

@@ -24,6 +24,10 @@
  *    (plcg_submit: until plcg_poll reports completion).
  *  - Errors are returned as negative plcg_status codes; plcg_last_error()
  *    gives a message for the calling thread.  Nothing aborts the process.
+ *  - A handle serves one caller at a time: while a solve runs on it
+ *    (plcg_solve, or plcg_submit until plcg_poll reports completion) other
+ *    solves return PLCG_E_BUSY; plcg_destroy waits for a submitted solve.
+ *    Calls on one batch are not safe to make from several threads at once.
  */
 #ifndef PLCG_H
 #define PLCG_H
@@ -113,7 +117,9 @@ typedef struct {
                              return at once and are left out) */
   int64_t sweeps;         /* with timing enabled: number of launches in sweep_ms */
   int32_t outer;          /* FP32_REFINED: refinement steps (0 otherwise) */
-  int32_t pad;
+  int32_t host_waits;     /* plcg_solve: times the host blocked on the device (stream and
+                             event synchronisations): about (iterations + l) / check_every
+                             plus a few per restart or refinement step; 0 from batches */
 } plcg_result;
 
 /* Create a solver for one operator and one configuration.

@@ -103,8 +103,10 @@ struct plcg_handle {
   std::atomic<bool> busy{false};
   uint64_t next_ticket = 1, cur_ticket = 0;
   plcg_status async_status = PLCG_OK;
+  std::string async_error;
   plcg_result async_result{};
   int last_hist_count = 0;
+  int host_waits = 0;             // host blocking waits of the current call
 };
 
 namespace {
@@ -133,10 +135,20 @@ void release(plcg_handle *h) {
 
 volatile HostStatus *hstat(plcg_handle *h) { return h->hs_host; }
 
+// Every place where the host blocks on the device goes through here or
+// throttle(), so that plcg_result.host_waits counts them.
+hipError_t wait_stream(plcg_handle *h, hipStream_t s) {
+  ++h->host_waits;
+  return hipStreamSynchronize(s);
+}
+
 // Keep at most two groups of iterations in flight; returns the device status.
 plcg_status throttle(plcg_handle *h, hipStream_t s, int group, int *status) {
   PLCG_HIP(hipEventRecord(h->chunk_ev[group & 1], s));
-  if (group >= 1) PLCG_HIP(hipEventSynchronize(h->chunk_ev[(group - 1) & 1]));
+  if (group >= 1) {
+    ++h->host_waits;
+    PLCG_HIP(hipEventSynchronize(h->chunk_ev[(group - 1) & 1]));
+  }
   *status = hstat(h)->status;
   return PLCG_OK;
 }
@@ -293,7 +305,7 @@ plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S 
     if ((e = throttle(h, s, group, &status)) != PLCG_OK) return e;
     if (status != kRunning) break;
   }
-  PLCG_HIP(hipStreamSynchronize(s));
+  PLCG_HIP(wait_stream(h, s));
   out->final_slot = last_i & 1;
   DevState ds;
   PLCG_HIP(hipMemcpy(&ds, h->st[out->final_slot], sizeof(ds), hipMemcpyDeviceToHost));
@@ -326,7 +338,7 @@ plcg_status solve_mixed(plcg_handle *h, const double *b, double *x, double tol, 
     PLCG_HIP(launch_scale(h->r64, h->ring32[0], h->basis32[0][0], (float *)nullptr, h->st[1], h->n,
                           s));
     PLCG_HIP(hipMemsetAsync(h->d32, 0, sizeof(float) * (size_t)h->n, s));
-    PLCG_HIP(hipStreamSynchronize(s));
+    PLCG_HIP(wait_stream(h, s));
     spmvs += 1;
     *final_slot = 1;
     rn = std::sqrt(hstat(h)->sumsq);
@@ -382,7 +394,7 @@ plcg_status solve_plcg(plcg_handle *h, const double *b, double *x, double tol, i
     plcg_status e = residual(h, b, x, h->ring[0], 1, 0, tol, rref, s);
     if (e != PLCG_OK) return e;
     PLCG_HIP(launch_scale(h->ring[0], h->ring[0], h->basis[0][0], nullptr, h->st[1], h->n, s));
-    PLCG_HIP(hipStreamSynchronize(s));
+    PLCG_HIP(wait_stream(h, s));
     spmvs += 1;
     *final_slot = 1;
     const int st0 = hstat(h)->status;
@@ -443,7 +455,7 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   // sweep B the other way round.  The segment start writes copy 1.
   plcg_status e = residual(h, b, x, h->cg_r, 1, 1, tol, -1.0, s);
   if (e != PLCG_OK) return e;
-  PLCG_HIP(hipStreamSynchronize(s));
+  PLCG_HIP(wait_stream(h, s));
   *final_slot = 1;
   const double rref = hstat(h)->rref;
   res->rnorm0 = rref;
@@ -531,7 +543,7 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
     PLCG_HIP(launch_cg_sweep_a(a, s));
     *final_slot = 0;
   }
-  PLCG_HIP(hipStreamSynchronize(s));
+  PLCG_HIP(wait_stream(h, s));
   if (stopped) *final_slot = 1;
   DevState ds;
   PLCG_HIP(hipMemcpy(&ds, h->st[*final_slot], sizeof(ds), hipMemcpyDeviceToHost));
@@ -566,6 +578,7 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   if (maxit < 0) return fail(PLCG_E_INVALID, "maxit must be >= 0");
   PLCG_HIP(hipSetDevice(h->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  h->host_waits = 0;
   TimedLaunch tl{h, s};
   int final_slot = 1;
   if (h->method == PLCG_METHOD_CG)
@@ -580,7 +593,7 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   }
   // True residual ||b - A x|| in FP64 (one more operator application).
   if ((e = residual(h, b, x, nullptr, final_slot, 2, tol, -1.0, s)) != PLCG_OK) return e;
-  PLCG_HIP(hipStreamSynchronize(s));
+  PLCG_HIP(wait_stream(h, s));
   res.spmvs += 1;
   res.true_relres = res.rnorm0 > 0 ? std::sqrt(hstat(h)->sumsq) / res.rnorm0 : 0.0;
   if (h->timing) {
@@ -590,6 +603,7 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
     res.sweep_ms = ms;
     res.sweeps = count;
   }
+  res.host_waits = h->host_waits;
   res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = res;
   return PLCG_OK;
@@ -816,6 +830,8 @@ plcg_status plcg_submit(plcg_handle *h, const double *d_b, double *d_x, double t
     plcg_status st = do_solve(h, d_b, d_x, tol, maxit, stream, &r);
     h->async_result = r;
     h->async_status = st;
+    // the worker's error message, handed to the thread that polls
+    h->async_error = st != PLCG_OK ? g_last_error : std::string();
     h->busy = false;
   });
   return PLCG_OK;
@@ -828,7 +844,8 @@ plcg_status plcg_poll(plcg_handle *h, uint64_t ticket, plcg_result *out) {
   if (h->busy) return PLCG_NOT_READY;
   if (h->worker.joinable()) h->worker.join();
   if (out) *out = h->async_result;
-  if (h->async_status != PLCG_OK) return fail(h->async_status, "submitted solve failed");
+  if (h->async_status != PLCG_OK)
+    return fail(h->async_status, "submitted solve failed: " + h->async_error);
   return PLCG_OK;
 }
 

@@ -55,7 +55,7 @@ class plcg_result(ctypes.Structure):
                 ("rnorm0", ctypes.c_double), ("rec_relres", ctypes.c_double),
                 ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweeps", ctypes.c_int64),
-                ("outer", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("outer", ctypes.c_int32), ("host_waits", ctypes.c_int32)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}

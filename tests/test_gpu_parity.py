@@ -299,6 +299,8 @@ def test_timing_counts_sweeps(dev):
         group = 64 * per
         assert work >= group
         assert r.sweeps == group * (work // group)
+        # the host waits about once per group of 64 iterations, plus setup and end
+        assert 1 <= r.host_waits <= work // group + 6
         s.close()
 
 
