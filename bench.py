@@ -50,8 +50,12 @@ import numpy as np
 import synth
 from oracle import operators, shifts, plcg
 wl = synth.WORKLOADS[{workload!r}]
-A = (operators.diagonal(synth.spectrum_diagonal(wl["dims"])) if wl["kind"] == "diag"
-     else operators.laplacian(wl["dims"]))
+if wl["kind"] == "diag":
+    A = operators.diagonal(synth.spectrum_diagonal(wl["dims"]))
+elif wl["kind"] == "csr":
+    A = operators.csr(*synth.csr_variable_laplacian(wl["dims"]))
+else:
+    A = operators.laplacian(wl["dims"])
 b = synth.uniform(A.n, 0)
 x0 = np.zeros(A.n)
 sig = shifts.chebyshev_shifts({l}, *wl["interval"])
@@ -109,7 +113,7 @@ def measured_traffic(workload: str, kernel: str):
     return float(v) if v is not None else None
 
 
-def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None):
+def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None, csr=None):
     import torch
     n = b.numel()
     y = torch.empty_like(b)
@@ -119,7 +123,7 @@ def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None):
     for m in methods.split(","):
         method, l = ("cg", 1) if m == "cg" else ("plcg", int(m.lstrip("m")))
         s = plcg.Solver(kind, dims, method=method, l=l, lmin=lo, lmax=hi,
-                        precision="fp32" if m.startswith("m") else "fp64", diag=diag)
+                        precision="fp32" if m.startswith("m") else "fp64", diag=diag, csr=csr)
         x.zero_()
         s.solve(b.data_ptr(), x.data_ptr(), 1e-30, 100, sp)
         torch.cuda.synchronize()
@@ -390,16 +394,26 @@ def main():
     # the one-point-stencil toy: diagonal operator holding the Laplacian's spectrum
     dg = (torch.from_numpy(synth.spectrum_diagonal(dims)).to(dev) if kind == "diag" else None)
     dptr = dg.data_ptr() if dg is not None else None
+    # a general sparse matrix: the grid operator assembled in CSR
+    csr_t, csr_arg, op_bytes = None, None, 0
+    if kind == "csr":
+        rp, ci, va = synth.csr_variable_laplacian(dims)
+        csr_t = [torch.from_numpy(a).to(dev) for a in (rp, ci, va)]
+        csr_arg = (csr_t[0].data_ptr(), csr_t[1].data_ptr(), csr_t[2].data_ptr(), len(ci))
+        op_bytes = 12 * len(ci) + 8 * (n + 1)     # values, column indices, row offsets
+        del rp, ci, va
+    elif kind == "diag":
+        op_bytes = 8 * n
     if wl["rhs"] == "manufactured":
         # b = A x*, x* uniform (seed 0), formed with the library's operator
         xs = b.clone()
-        op = plcg.Solver(kind, dims, method="cg", diag=dptr)
+        op = plcg.Solver(kind, dims, method="cg", diag=dptr, csr=csr_arg)
         op.apply(xs.data_ptr(), b.data_ptr(), sp)
         torch.cuda.synchronize()
         op.close()
 
     if args.profile_run:
-        profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods, dptr)
+        profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods, dptr, csr_arg)
         return
 
     def parse(tok):
@@ -419,7 +433,7 @@ def main():
         name = {"cg": "cg", "plcg": f"p{l}", "mixed": f"m{l}"}[method]
         s = plcg.Solver(kind, dims, method="cg" if method == "cg" else "plcg", l=max(l, 1),
                         lmin=lo, lmax=hi, precision="fp32" if method == "mixed" else "fp64",
-                        inner_tol=args.inner_tol, diag=dptr)
+                        inner_tol=args.inner_tol, diag=dptr, csr=csr_arg)
         for _ in range(args.warmup):
             x.zero_()
             s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
@@ -444,11 +458,10 @@ def main():
         s.close()
         r = results[-1]
         its = total_iters / dt
-        # the diagonal operator reads d once more per SpMV
-        passes = vector_passes("cg" if method == "cg" else "plcg", l) + (kind == "diag")
-        # (d stays FP64 when the vectors are stored in FP32)
-        bytes_iter = ((passes - (kind == "diag")) * (4 if method == "mixed" else 8)
-                      + 8 * (kind == "diag")) * n
+        passes = vector_passes("cg" if method == "cg" else "plcg", l)
+        # vector passes in the storage precision, plus the operator's own data
+        # read once per SpMV (FP64 d, or the CSR arrays)
+        bytes_iter = passes * (4 if method == "mixed" else 8) * n + op_bytes
         kernel_us = 1e3 * rt.sweep_ms / max(rt.sweeps, 1)
         kernels_per_iter = 2 if method == "cg" else 1
         rows[name] = {
@@ -456,7 +469,7 @@ def main():
             "true_relres": r.true_relres, "rec_relres": r.rec_relres,
             "ms_per_solve": 1e3 * dt / args.steps, "iters_per_s": its,
             "bytes_per_iter": bytes_iter,
-            "us_per_iter": 1e6 / its, "vector_passes": passes,
+            "us_per_iter": 1e6 / its, "vector_passes": passes, "operator_bytes": op_bytes,
             "alg_GBps": bytes_iter * its / 1e9,
             "kernel_us": kernel_us, "kernels_per_iter": kernels_per_iter,
             "kernel_GBps": (bytes_iter / kernels_per_iter) / (kernel_us * 1e-6) / 1e9
@@ -471,10 +484,15 @@ def main():
             print(f"# {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
 
     opname = {"2d5": "2D 5-point Dirichlet Poisson", "3d7": "3D 7-point Dirichlet Poisson",
-              "diag": "diagonal one-point-stencil toy with the 2D Laplacian's spectrum on"}[kind]
-    kname = (f"plcg_diag_sweep_kernel<{head_method[1]},"
-             if kind == "diag" else
-             f"plcg_sweep_kernel<{head_method[1]},{'true' if kind == '3d7' else 'false'},")
+              "diag": "diagonal one-point-stencil toy with the 2D Laplacian's spectrum on",
+              "csr": "2D 5-point Dirichlet Poisson assembled in CSR,"}[kind]
+    if kind == "diag":
+        kname = f"plcg_diag_sweep_kernel<{head_method[1]},"
+    elif kind == "csr":
+        kname = f"plcg_csr_sweep_kernel<{head_method[1]},"
+    else:
+        kname = (f"plcg_sweep_kernel<{head_method[1]},"
+                 f"{'true' if kind == '3d7' else 'false'},")
     head = {"plcg": "p", "mixed": "m"}[head_method[0]] + str(head_method[1])
     hl = head_method[1]
     hr = rows[head]

@@ -59,7 +59,10 @@ enum {
 enum {
   PLCG_OP_STENCIL2D5 = 1,  /* (Au) = 4u - u(x-1) - u(x+1) - u(y-1) - u(y+1) */
   PLCG_OP_STENCIL3D7 = 2,  /* (Au) = 6u - sum of the six face neighbours    */
-  PLCG_OP_DIAG = 3         /* (Au)_p = d_p u_p, d given in plcg_operator_desc.diag */
+  PLCG_OP_DIAG = 3,        /* (Au)_p = d_p u_p, d given in plcg_operator_desc.diag */
+  PLCG_OP_CSR = 4          /* a general sparse matrix in compressed sparse rows (the
+                              assembled matrices the paper's PETSc runs use); it must be
+                              symmetric positive definite */
 };
 
 enum { PLCG_METHOD_CG = 0, PLCG_METHOD_PLCG = 1 };
@@ -87,6 +90,15 @@ typedef struct {
                              FP64 entries, each finite and > 0 (else
                              PLCG_E_INVALID).  Copied at plcg_create; the caller
                              keeps ownership and may free it afterwards. */
+  int64_t nnz;            /* PLCG_OP_CSR only: stored entries */
+  const int64_t *rowptr;  /* PLCG_OP_CSR, device: n + 1 offsets, rowptr[0] = 0,
+                             nondecreasing, rowptr[n] = nnz */
+  const int32_t *colind;  /* PLCG_OP_CSR, device: nnz column indices in [0, n) */
+  const double *vals;     /* PLCG_OP_CSR, device: nnz finite FP64 values.  The three
+                             arrays are checked and copied at plcg_create (violations
+                             give PLCG_E_INVALID); symmetry and definiteness are not
+                             checked: a matrix that is not SPD shows up as breakdowns
+                             (restart limit) or, for CG, PLCG_REASON_BREAKDOWN. */
 } plcg_operator_desc;
 
 typedef struct {

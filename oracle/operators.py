@@ -66,6 +66,19 @@ def diagonal(d):
     return apply
 
 
+def csr(rowptr, colind, vals):
+    """A sparse matrix given in compressed sparse rows, applied with scipy."""
+    import scipy.sparse as sp
+    n = len(rowptr) - 1
+    M = sp.csr_matrix((np.asarray(vals, float), np.asarray(colind), np.asarray(rowptr)),
+                      shape=(n, n))
+
+    def apply(u):
+        return M @ u
+    apply.n = n
+    return apply
+
+
 def assemble(apply) -> np.ndarray:
     """Dense matrix of a (small) operator, column by column."""
     n = apply.n

@@ -407,6 +407,27 @@ struct DiagOp {
   }
 };
 
+// General sparse operator in CSR form, one row per unknown: (A z)_p =
+// sum over the stored entries j of row p of va[j] * z[ci[j]] (FP64 values,
+// stored order).
+template <typename S>
+struct CsrOp {
+  const int64_t *rp;
+  const int32_t *ci;
+  const double *va;
+  __device__ inline double row(const S *z, int p) const {
+    double s = 0.0;
+    const int64_t e = rp[p + 1];
+    for (int64_t j = rp[p]; j < e; ++j) s += va[j] * (double)z[ci[j]];
+    return s;
+  }
+  template <int V, bool FAST>
+  __device__ inline void apply(const S *z, int idx, const Vals<V, S> &, double (&w)[V]) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v) w[v] = row(z, idx + v);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // p(l)-CG sweep: iteration i of Alg. 1
 // ---------------------------------------------------------------------------

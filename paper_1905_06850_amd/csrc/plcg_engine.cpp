@@ -73,7 +73,7 @@ struct plcg_handle {
   int hist_cap = 0;
   int n = 0, nchunks = 0, blocks = 0;
   bool d3 = false;
-  double *dg = nullptr;           // diagonal operator: library copy of d; NULL for stencils
+  OpData od{nullptr, nullptr, nullptr, nullptr};   // library copies of d / the CSR arrays
   int device = 0;
   // device buffers
   std::vector<void *> allocs;
@@ -240,7 +240,7 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
   a.v0 = (i == l - 1) ? basis[0][0] : nullptr;
   a.p = p;
   a.x = x;
-  a.dg = h->dg;
+  a.od = h->od;
   a.part_in = h->part[(i + 1) & 1];
   a.part_out = h->part[i & 1];
   a.st_in = h->st[(i + 1) & 1];
@@ -268,7 +268,7 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
 plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r, int slot,
                      int mode, double tol, double rref_in, hipStream_t s) {
   PLCG_HIP(launch_residual(b, x, r, h->part[0], h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
-                           h->dg, h->nchunks, h->blocks, s));
+                           h->od, h->nchunks, h->blocks, s));
   PLCG_HIP(launch_start(h->part[0], h->blocks, h->st[slot], h->hs_dev, mode, tol, rref_in, s));
   return PLCG_OK;
 }
@@ -477,7 +477,7 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   a.x = x;
   a.r = h->cg_r;
   a.q = h->cg_q;
-  a.dg = h->dg;
+  a.od = h->od;
   a.hs = h->hs_dev;
   a.n = h->n;
   a.nx = h->op.nx;
@@ -491,7 +491,7 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   // 3D grids whose planes are whole chunks (and even nx): sweep A marches each
   // chunk-sized tile through zseg planes, about one tile-segment per workgroup.
   a.zseg = 0;
-  if (h->d3 && h->dg == nullptr && h->op.nz >= 2 && (h->op.nx & 1) == 0 &&
+  if (h->op.kind == PLCG_OP_STENCIL3D7 && h->op.nz >= 2 && (h->op.nx & 1) == 0 &&
       ((long long)h->op.nx * h->op.ny) % kChunk == 0) {
     const long long tiles = (long long)h->op.nx * h->op.ny / kChunk;
     a.zseg = (int)std::max(1LL, tiles * h->op.nz / h->blocks);
@@ -609,6 +609,52 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   return PLCG_OK;
 }
 
+// Library copy of a CSR operator, checked once on the host: rowptr[0] = 0,
+// nondecreasing, rowptr[n] = nnz, every column index in [0, n), every value
+// finite.  (Symmetry and definiteness are the caller's promise.)
+plcg_status copy_csr(plcg_handle *h, const plcg_operator_desc *op) {
+  const size_t n = (size_t)h->n, nnz = (size_t)op->nnz;
+  if (nnz >= (size_t)1 << 40) return fail(PLCG_E_INVALID, "nnz too large");
+  std::vector<int64_t> rp(n + 1);
+  std::vector<int32_t> ci(nnz);
+  std::vector<double> va(nnz);
+  hipError_t he;
+  if ((he = hipMemcpy(rp.data(), op->rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost)) !=
+          hipSuccess ||
+      (nnz > 0 && (he = hipMemcpy(ci.data(), op->colind, sizeof(int32_t) * nnz,
+                                  hipMemcpyDeviceToHost)) != hipSuccess) ||
+      (nnz > 0 && (he = hipMemcpy(va.data(), op->vals, sizeof(double) * nnz,
+                                  hipMemcpyDeviceToHost)) != hipSuccess))
+    return fail(PLCG_E_HIP, std::string("hipMemcpy(CSR): ") + hipGetErrorString(he));
+  if (rp[0] != 0 || rp[n] != (int64_t)nnz)
+    return fail(PLCG_E_INVALID, "CSR rowptr must start at 0 and end at nnz");
+  for (size_t p = 0; p < n; ++p)
+    if (rp[p + 1] < rp[p]) return fail(PLCG_E_INVALID, "CSR rowptr must be nondecreasing");
+  for (size_t j = 0; j < nnz; ++j) {
+    if (ci[j] < 0 || (size_t)ci[j] >= n)
+      return fail(PLCG_E_INVALID, "CSR column index out of range");
+    if (!std::isfinite(va[j])) return fail(PLCG_E_INVALID, "CSR values must be finite");
+  }
+  int64_t *drp = nullptr;
+  int32_t *dci = nullptr;
+  double *dva = nullptr;
+  plcg_status e = dev_alloc(h, reinterpret_cast<void **>(&drp), sizeof(int64_t) * (n + 1));
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dci), sizeof(int32_t) * (nnz + 1));
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dva), sizeof(double) * (nnz + 1));
+  if (e != PLCG_OK) return e;
+  if ((he = hipMemcpy(drp, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (nnz > 0 && (he = hipMemcpy(dci, ci.data(), sizeof(int32_t) * nnz,
+                                  hipMemcpyHostToDevice)) != hipSuccess) ||
+      (nnz > 0 && (he = hipMemcpy(dva, va.data(), sizeof(double) * nnz,
+                                  hipMemcpyHostToDevice)) != hipSuccess))
+    return fail(PLCG_E_HIP, std::string("hipMemcpy(CSR): ") + hipGetErrorString(he));
+  h->od.rp = drp;
+  h->od.ci = dci;
+  h->od.va = dva;
+  return PLCG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -622,10 +668,13 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   *out = nullptr;
   if (op == nullptr || cfg == nullptr) return fail(PLCG_E_INVALID, "NULL descriptor or config");
   if (op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7 &&
-      op->kind != PLCG_OP_DIAG)
+      op->kind != PLCG_OP_DIAG && op->kind != PLCG_OP_CSR)
     return fail(PLCG_E_INVALID, "unknown operator kind");
   if (op->kind == PLCG_OP_DIAG && op->diag == nullptr)
     return fail(PLCG_E_INVALID, "diagonal operator needs diag");
+  if (op->kind == PLCG_OP_CSR &&
+      (op->rowptr == nullptr || op->colind == nullptr || op->vals == nullptr || op->nnz < 0))
+    return fail(PLCG_E_INVALID, "CSR operator needs rowptr, colind, vals and nnz >= 0");
   const int nz = op->kind == PLCG_OP_STENCIL2D5 ? 1 : op->nz;
   if (op->nx < 1 || op->ny < 1 || nz < 1) return fail(PLCG_E_INVALID, "grid extents must be >= 1");
   if (op->kind == PLCG_OP_STENCIL2D5 && op->nz > 1)
@@ -753,12 +802,15 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
           break;
         }
     }
-    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->dg), sizeof(double) * (size_t)n);
+    double *dg = nullptr;
+    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dg), sizeof(double) * (size_t)n);
     if (e == PLCG_OK &&
-        (he = hipMemcpy(h->dg, d.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice)) !=
+        (he = hipMemcpy(dg, d.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice)) !=
             hipSuccess)
       e = fail(PLCG_E_HIP, std::string("hipMemcpy(diag): ") + hipGetErrorString(he));
+    h->od.dg = dg;
   }
+  if (e == PLCG_OK && op->kind == PLCG_OP_CSR) e = copy_csr(h, op);
   if (e != PLCG_OK) {
     release(h);
     delete h;
@@ -866,7 +918,7 @@ plcg_status plcg_apply(plcg_handle *h, const double *d_x, double *d_y, void *str
   if (h == nullptr || d_x == nullptr || d_y == nullptr)
     return fail(PLCG_E_INVALID, "NULL argument");
   if (d_x == d_y) return fail(PLCG_E_INVALID, "x and y must be distinct");
-  PLCG_HIP(launch_apply(d_x, d_y, h->n, h->op.nx, h->op.ny, h->op.nz, h->d3, h->dg,
+  PLCG_HIP(launch_apply(d_x, d_y, h->n, h->op.nx, h->op.ny, h->op.nz, h->d3, h->od,
                         reinterpret_cast<hipStream_t>(stream)));
   return PLCG_OK;
 }

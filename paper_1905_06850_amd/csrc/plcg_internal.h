@@ -18,6 +18,15 @@ constexpr int kMaxStream = 1024;      // streaming blocks per launch (multiple o
 
 enum Status : int32_t { kRunning = 0, kConverged = 1, kBroken = 2, kNonFinite = 3, kCgBreak = 4 };
 
+// Operator data beyond the grid extents (device pointers; all NULL for the
+// constant-coefficient stencils).
+struct OpData {
+  const double *dg;    // diagonal operator: d (n)
+  const int64_t *rp;   // CSR: row offsets (n+1)
+  const int32_t *ci;   // CSR: column indices (nnz)
+  const double *va;    // CSR: values (nnz)
+};
+
 // Host-visible progress record, written by the device into pinned host memory
 // (mapped) by the block that owns the scalar state.
 struct HostStatus {
@@ -63,7 +72,7 @@ struct SweepArgsT {
   S *copy_dst;               // i < l-1: basis i+1 slot receiving z^{(l)}_{i+1}; else NULL
   const S *v0;               // i == l-1: z^{(0)}_0 for the product (u_l, v_0)
   S *p, *x;
-  const double *dg;          // diagonal operator: d (FP64); NULL for the stencils
+  OpData od;                 // diagonal or CSR operator data; all NULL for the stencils
   const double *part_in;     // partials of sweep i-1, [l+1][pstride]
   double *part_out;          // partials of sweep i
   const DevState *st_in;     // state after column i-1
@@ -82,7 +91,7 @@ using SweepArgs = SweepArgsT<double>;
 struct CgArgs {
   const double *b;
   double *x, *r, *p_old, *p_new, *q;
-  const double *dg;          // diagonal operator: d; NULL for the stencils
+  OpData od;                 // diagonal or CSR operator data; all NULL for the stencils
   const double *part_in;
   double *part_out;
   const DevState *st_in;
@@ -99,9 +108,9 @@ hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s);
 hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s);
 hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s);
 // r = b - A x (r may be NULL); per-block partial sums of r.r into part_out.
-// A is the stencil of (nx, ny, nz, d3), or diag(dg) when dg is not NULL.
+// A is the stencil of (nx, ny, nz, d3), or the diagonal / CSR matrix of od.
 hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out,
-                           int n, int nx, int ny, int nz, bool d3, const double *dg, int nchunks,
+                           int n, int nx, int ny, int nz, bool d3, const OpData &od, int nchunks,
                            int nstream, hipStream_t s);
 // One block: sum the residual partials and start a segment in *st:
 // mode 0 = p(l)-CG (G, beta, status), 1 = CG (rho), 2 = only report the sum.
@@ -115,7 +124,7 @@ hipError_t launch_scale(const double *r, float *d0, float *d1, float *d2, const 
 // x += d (FP64 += FP32).
 hipError_t launch_add_correction(double *x, const float *d, int n, hipStream_t s);
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
-                        const double *dg, hipStream_t s);
+                        const OpData &od, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);
 
 }  // namespace plcg

@@ -101,7 +101,12 @@ __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) 
 
 template <int L, typename ST>
 __global__ __launch_bounds__(kThreads) void plcg_diag_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST>(a, DiagOp<ST>{a.dg}, true, ChunkOrder{0, 0, 0});
+  plcg_sweep<L, ST>(a, DiagOp<ST>{a.od.dg}, true, ChunkOrder{0, 0, 0});
+}
+
+template <int L, typename ST>
+__global__ __launch_bounds__(kThreads) void plcg_csr_sweep_kernel(SweepArgsT<ST> a) {
+  plcg_sweep<L, ST>(a, CsrOp<ST>{a.od.rp, a.od.ci, a.od.va}, true, ChunkOrder{0, 0, 0});
 }
 
 // ---------------------------------------------------------------------------
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
     if (idx + 1 < a.n) {
       Vals<2> r, d, pn, q;
       r.load(a.r + idx);
-      d.load(a.dg + idx);
+      d.load(a.od.dg + idx);
       if (first) {
         pn = r;
       } else {
@@ -352,9 +357,39 @@ __global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
       q.store(a.q + idx);
     } else if (idx < a.n) {
       const double pc = first ? a.r[idx] : a.r[idx] + beta * a.p_old[idx];
-      const double q = a.dg[idx] * pc;
+      const double q = a.od.dg[idx] * pc;
       a.p_new[idx] = pc;
       a.q[idx] = q;
+      acc[0] += pc * q;
+    }
+  }
+  store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
+}
+
+// Sweep A for a CSR operator: q = A p_k with p_k formed at every column index
+// from r and p_{k-1}.
+__global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
+  __shared__ double lds[4];
+  __shared__ double red[1];
+  __shared__ DevState sh;
+  if (!cg_a_prologue(a, sh, lds, red)) return;
+
+  const bool first = a.k == 0;
+  const double beta = first ? 0.0 : sh.cg_beta;
+  auto pk1 = [&](int q) { return first ? a.r[q] : a.r[q] + beta * a.p_old[q]; };
+  double acc[1] = {0.0};
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
+    const int idx0 = it.c * kChunk + threadIdx.x * kVec;
+#pragma unroll
+    for (int v = 0; v < kVec; ++v) {
+      const int p = idx0 + v;
+      if (p >= a.n) break;
+      const double pc = pk1(p);
+      double q = 0.0;
+      const int64_t e = a.od.rp[p + 1];
+      for (int64_t j = a.od.rp[p]; j < e; ++j) q += a.od.va[j] * pk1(a.od.ci[j]);
+      a.p_new[p] = pc;
+      a.q[p] = q;
       acc[0] += pc * q;
     }
   }
@@ -420,12 +455,25 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
 // Residual, segment start, scaling, operator application, copy
 // ---------------------------------------------------------------------------
 
-// DG: the diagonal operator diag(dg) instead of the stencil.
-template <bool D3, bool DG>
+// (A x)_p for operator kind K: 0 the 2D stencil, 1 the 3D stencil, 2 the
+// diagonal, 3 the CSR matrix of od.
+template <int K>
+__device__ inline double op_at(const double *x, int p, const Grid &g, const OpData &od) {
+  if constexpr (K == 2) {
+    return od.dg[p] * x[p];
+  } else if constexpr (K == 3) {
+    return CsrOp<double>{od.rp, od.ci, od.va}.row(x, p);
+  } else {
+    return (K == 1 ? 6.0 : 4.0) * x[p] - neighbour_sum<K == 1>(x, p, g);
+  }
+}
+
+template <int K>
 __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, const double *x,
                                                             double *r, double *part_out, Grid g,
-                                                            const double *dg, int nchunks,
+                                                            OpData od, int nchunks,
                                                             int nstream) {
+  constexpr bool D3 = K == 1;
   __shared__ double lds[4];
   __shared__ double red[1];
   double acc[1] = {0.0};
@@ -436,8 +484,7 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, con
     for (int v = 0; v < kVec; ++v) {
       const int p = idx0 + v;
       if (p >= g.n) break;
-      const double ax = DG ? dg[p] * x[p] : (D3 ? 6.0 : 4.0) * x[p] - neighbour_sum<D3>(x, p, g);
-      const double rv = b[p] - ax;
+      const double rv = b[p] - op_at<K>(x, p, g, od);
       if (r != nullptr) r[p] = rv;
       acc[0] += rv * rv;
     }
@@ -504,12 +551,11 @@ __global__ __launch_bounds__(kThreads) void add_correction_kernel(double *x, con
     x[p] += (double)d[p];
 }
 
-template <bool D3, bool DG>
+template <int K>
 __global__ __launch_bounds__(kThreads) void apply_kernel(const double *x, double *y, Grid g,
-                                                         const double *dg) {
-  const double diag = D3 ? 6.0 : 4.0;
+                                                         OpData od) {
   for (int p = blockIdx.x * kThreads + threadIdx.x; p < g.n; p += gridDim.x * kThreads)
-    y[p] = DG ? dg[p] * x[p] : diag * x[p] - neighbour_sum<D3>(x, p, g);
+    y[p] = op_at<K>(x, p, g, od);
 }
 
 __global__ __launch_bounds__(kThreads) void copy_kernel(const double *src, double *dst, int64_t n) {
@@ -534,7 +580,9 @@ static int simple_blocks(int64_t n) {
 template <int L, typename S>
 static hipError_t launch_sweep_l(const SweepArgsT<S> &a, hipStream_t s) {
   const int grid = a.nstream + (L >= 2 ? 1 : 0);
-  if (a.dg != nullptr)
+  if (a.od.rp != nullptr)
+    hipLaunchKernelGGL((plcg_csr_sweep_kernel<L, S>), dim3(grid), dim3(kThreads), 0, s, a);
+  else if (a.od.dg != nullptr)
     hipLaunchKernelGGL((plcg_diag_sweep_kernel<L, S>), dim3(grid), dim3(kThreads), 0, s, a);
   else if (a.d3)
     hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S>), dim3(grid), dim3(kThreads), 0, s, a);
@@ -567,7 +615,9 @@ hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s) {
 }
 
 hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s) {
-  if (a.dg != nullptr)
+  if (a.od.rp != nullptr)
+    hipLaunchKernelGGL(cg_csr_sweep_a_kernel, dim3(a.nstream), dim3(kThreads), 0, s, a);
+  else if (a.od.dg != nullptr)
     hipLaunchKernelGGL(cg_diag_sweep_a_kernel, dim3(a.nstream), dim3(kThreads), 0, s, a);
   else if (a.d3)
     hipLaunchKernelGGL((cg_sweep_a_kernel<true>), dim3(a.nstream), dim3(kThreads), 0, s, a);
@@ -582,18 +632,17 @@ hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out, int n,
-                           int nx, int ny, int nz, bool d3, const double *dg, int nchunks,
+                           int nx, int ny, int nz, bool d3, const OpData &od, int nchunks,
                            int nstream, hipStream_t s) {
   const Grid g{n, nx, ny, nz};
-  if (dg != nullptr)
-    hipLaunchKernelGGL((residual_kernel<false, true>), dim3(nstream), dim3(kThreads), 0, s, b, x,
-                       r, part_out, g, dg, nchunks, nstream);
-  else if (d3)
-    hipLaunchKernelGGL((residual_kernel<true, false>), dim3(nstream), dim3(kThreads), 0, s, b, x,
-                       r, part_out, g, dg, nchunks, nstream);
-  else
-    hipLaunchKernelGGL((residual_kernel<false, false>), dim3(nstream), dim3(kThreads), 0, s, b, x,
-                       r, part_out, g, dg, nchunks, nstream);
+  const int k = od.rp != nullptr ? 3 : od.dg != nullptr ? 2 : d3 ? 1 : 0;
+  const dim3 grid(nstream), block(kThreads);
+  switch (k) {
+    case 3: hipLaunchKernelGGL(residual_kernel<3>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
+    case 2: hipLaunchKernelGGL(residual_kernel<2>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
+    case 1: hipLaunchKernelGGL(residual_kernel<1>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
+    default: hipLaunchKernelGGL(residual_kernel<0>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
+  }
   return hipGetLastError();
 }
 
@@ -624,15 +673,16 @@ hipError_t launch_add_correction(double *x, const float *d, int n, hipStream_t s
 }
 
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
-                        const double *dg, hipStream_t s) {
+                        const OpData &od, hipStream_t s) {
   const Grid g{n, nx, ny, nz};
-  const dim3 grid(simple_blocks(n));
-  if (dg != nullptr)
-    hipLaunchKernelGGL((apply_kernel<false, true>), grid, dim3(kThreads), 0, s, x, y, g, dg);
-  else if (d3)
-    hipLaunchKernelGGL((apply_kernel<true, false>), grid, dim3(kThreads), 0, s, x, y, g, dg);
-  else
-    hipLaunchKernelGGL((apply_kernel<false, false>), grid, dim3(kThreads), 0, s, x, y, g, dg);
+  const int k = od.rp != nullptr ? 3 : od.dg != nullptr ? 2 : d3 ? 1 : 0;
+  const dim3 grid(simple_blocks(n)), block(kThreads);
+  switch (k) {
+    case 3: hipLaunchKernelGGL(apply_kernel<3>, grid, block, 0, s, x, y, g, od); break;
+    case 2: hipLaunchKernelGGL(apply_kernel<2>, grid, block, 0, s, x, y, g, od); break;
+    case 1: hipLaunchKernelGGL(apply_kernel<1>, grid, block, 0, s, x, y, g, od); break;
+    default: hipLaunchKernelGGL(apply_kernel<0>, grid, block, 0, s, x, y, g, od); break;
+  }
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ PLCG_E_NONFINITE = -5
 PLCG_OP_STENCIL2D5 = 1
 PLCG_OP_STENCIL3D7 = 2
 PLCG_OP_DIAG = 3
+PLCG_OP_CSR = 4
 PLCG_METHOD_CG = 0
 PLCG_METHOD_PLCG = 1
 PLCG_PREC_FP64 = 0
@@ -37,7 +38,9 @@ REASONS = {0: "none", 1: "converged", 2: "maxit", 3: "breakdown_limit", 4: "nonf
 
 class plcg_operator_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
-                ("nz", ctypes.c_int32), ("diag", ctypes.c_void_p)]
+                ("nz", ctypes.c_int32), ("diag", ctypes.c_void_p), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
+                ("vals", ctypes.c_void_p)]
 
 
 class plcg_config(ctypes.Structure):
@@ -182,15 +185,19 @@ def check(status, where):
     return status
 
 
-def _dims_desc(kind, dims, diag=None):
+def _dims_desc(kind, dims, diag=None, csr=None):
     dims = tuple(int(d) for d in dims)
     if kind in ("2d5", PLCG_OP_STENCIL2D5):
-        return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1, None)
+        return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1)
     if kind in ("3d7", PLCG_OP_STENCIL3D7):
-        return plcg_operator_desc(PLCG_OP_STENCIL3D7, dims[0], dims[1], dims[2], None)
+        return plcg_operator_desc(PLCG_OP_STENCIL3D7, dims[0], dims[1], dims[2])
+    dims = dims + (1,) * (3 - len(dims))
     if kind in ("diag", PLCG_OP_DIAG):
-        dims = dims + (1,) * (3 - len(dims))
         return plcg_operator_desc(PLCG_OP_DIAG, dims[0], dims[1], dims[2], diag)
+    if kind in ("csr", PLCG_OP_CSR):
+        rowptr, colind, vals, nnz = csr if csr is not None else (None, None, None, 0)
+        return plcg_operator_desc(PLCG_OP_CSR, dims[0], dims[1], dims[2], None, int(nnz),
+                                  rowptr, colind, vals)
     raise ValueError(f"unknown operator kind {kind!r}")
 
 
@@ -199,10 +206,12 @@ class Solver:
 
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
                  check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
-                 inner_tol=0.0, diag=None):
-        """kind "2d5", "3d7" or "diag"; for "diag", `diag` is the device address
-        of the n FP64 diagonal entries (copied by plcg_create)."""
-        self.desc = _dims_desc(kind, dims, diag)
+                 inner_tol=0.0, diag=None, csr=None):
+        """kind "2d5", "3d7", "diag" or "csr"; for "diag", `diag` is the device
+        address of the n FP64 diagonal entries; for "csr", `csr` is (rowptr,
+        colind, vals, nnz) with device addresses of int64 / int32 / FP64 arrays
+        (copied by plcg_create)."""
+        self.desc = _dims_desc(kind, dims, diag, csr)
         self._shifts = None
         sp = None
         if shifts is not None:

@@ -51,6 +51,10 @@ WORKLOADS = {
                         interval=(0.0, 8.0), tol=1e-8),
     "poisson3d256": dict(kind="3d7", dims=(256, 256, 256), rhs="uniform",
                          interval=(0.0, 12.0), tol=1e-10),
+    # the 2048^2 Poisson problem assembled in CSR (a general sparse matrix, as
+    # the paper's PETSc runs store it)
+    "csr2048": dict(kind="csr", dims=(2048, 2048), rhs="uniform",
+                    interval=(0.0, 8.0), tol=1e-8),
     # the one-point-stencil toy: diagonal with the 2048^2 Laplacian's spectrum,
     # the same right-hand side as poisson2048
     "diag2048": dict(kind="diag", dims=(2048, 2048), rhs="uniform",
@@ -79,6 +83,52 @@ def spectrum_diagonal(dims) -> np.ndarray:
         f = 4.0 * np.sin(k * np.pi / (2.0 * (int(n) + 1))) ** 2
         d = (f[:, None] + d[None, :]).reshape(-1)
     return d
+
+
+def _csr(n, rows, cols, vals):
+    """CSR arrays (rowptr int64, colind int32, vals float64) from coordinate
+    triplets, columns ascending within each row."""
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
+    return rowptr, cols.astype(np.int32), vals.astype(np.float64)
+
+
+def csr_variable_laplacian(dims, cx=None, cy=None, cz=None):
+    """The grid operator (A u)_p = sum over the edges (p, q) at p of c_pq (u_p - u_q),
+    u = 0 outside (boundary edges add to the diagonal), assembled in CSR.  Edge
+    layouts as in edge_coefficients; None means all coefficients 1, which gives
+    the unscaled 5-point (7-point) Dirichlet Laplacian.  An operator definition
+    (input data)."""
+    dims = tuple(int(d) for d in dims)
+    d3 = len(dims) == 3
+    nx, ny = dims[0], dims[1]
+    nz = dims[2] if d3 else 1
+    n = nx * ny * nz
+    CX = np.ones((nz, ny, nx + 1)) if cx is None else np.asarray(cx, float).reshape(nz, ny, nx + 1)
+    CY = np.ones((nz, ny + 1, nx)) if cy is None else np.asarray(cy, float).reshape(nz, ny + 1, nx)
+    if d3:
+        CZ = (np.ones((nz + 1, ny, nx)) if cz is None
+              else np.asarray(cz, float).reshape(nz + 1, ny, nx))
+    idx = np.arange(n).reshape(nz, ny, nx)
+    diag = CX[:, :, :-1] + CX[:, :, 1:] + CY[:, :-1, :] + CY[:, 1:, :]
+    if d3:
+        diag = diag + CZ[:-1] + CZ[1:]
+    rows = [idx.reshape(-1)]
+    cols = [idx.reshape(-1)]
+    vals = [diag.reshape(-1)]
+
+    def couple(a, b, c):          # symmetric entries -c between unknowns a and b
+        rows.extend([a.reshape(-1), b.reshape(-1)])
+        cols.extend([b.reshape(-1), a.reshape(-1)])
+        vals.extend([-c.reshape(-1), -c.reshape(-1)])
+
+    couple(idx[:, :, :-1], idx[:, :, 1:], CX[:, :, 1:-1])
+    couple(idx[:, :-1, :], idx[:, 1:, :], CY[:, 1:-1, :])
+    if d3:
+        couple(idx[:-1], idx[1:], CZ[1:-1])
+    return _csr(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
 
 
 def sample_indices(n: int, count: int = 512, seed: int = 12345) -> np.ndarray:

@@ -42,7 +42,7 @@ def _create(kind=1, nx=8, ny=8, nz=1, method=1, l=2, lmin=0.0, lmax=8.0):
 @pytest.mark.parametrize("kwargs", [
     dict(kind=7), dict(nx=0), dict(ny=-3), dict(kind=2, nz=0), dict(kind=1, nz=4),
     dict(l=0), dict(l=9), dict(method=5), dict(lmin=1.0, lmax=1.0), dict(lmin=3.0, lmax=2.0),
-    dict(nx=65536, ny=65536), dict(kind=3),
+    dict(nx=65536, ny=65536), dict(kind=3), dict(kind=4),
 ])
 def test_create_rejects_bad_arguments(kwargs):
     from paper_1905_06850_amd import plcg

@@ -372,3 +372,65 @@ def test_batch512_sampled_systems_against_stored_oracle(dev):
         ref = np.array(g["sample_x"])
         est = np.sqrt(x.size / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
         assert est < 1e-8, (j, est)
+
+
+# ------------------------------------------------------------- edge cases --
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_edge_cases(dev, precision):
+    """Zero right-hand side (converged at once, x = 0), maxit = 0 (reason maxit,
+    x = x0 = 0), a NaN in b (reason non-finite), a 1x1 system, and a nonzero x0
+    against the oracle started from the same x0, all in one batch."""
+    plcg = _plcg()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    s = _system((30, 20), 41, 42)
+    n = s["n"]
+    one = _system((1, 1), 43, 44)
+    x0 = 0.5 * synth.uniform(n, 45)
+    cases = {
+        "zero": (s, np.zeros(n), np.zeros(n), 1e-8, 1000),
+        "maxit0": (s, s["b"], np.zeros(n), 1e-8, 0),
+        "nan": (s, np.where(np.arange(n) == 7, np.nan, s["b"]), np.zeros(n), 1e-8, 1000),
+        "one": (one, one["b"], np.zeros(1), 1e-8, 1000),
+        "x0": (s, s["b"], x0, 1e-9, 5000),
+    }
+    print(f"[gpu] batch edge cases {precision}", flush=True)
+    batch = plcg.Batch(l=2, max_slots=8, arena_bytes=1 << 26, precision=precision,
+                       inner_tol=1e-4)
+    bufs, tickets = {}, {}
+    for name, (sys_, b, xi, tol, maxit) in cases.items():
+        bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+        xt = torch.from_numpy(xi.copy()).to(dev)
+        t = batch.add(sys_["dims"], bt.data_ptr(), xt.data_ptr(), tol, maxit, stream,
+                      sys_["cx"], sys_["cy"], sys_["cz"])
+        assert t is not None
+        bufs[name] = (bt, xt)
+        tickets[t] = name
+    res = {}
+    for _ in range(2000):
+        batch.step(16, stream)
+        torch.cuda.synchronize()
+        for t in list(tickets):
+            r = batch.poll(t)
+            if r is not None:
+                res[tickets.pop(t)] = r
+        if not tickets:
+            break
+    batch.close()
+    assert not tickets
+    x = {k: v[1].cpu().numpy() for k, v in bufs.items()}
+    assert res["zero"].reason == 1 and res["zero"].iters == 0 and np.all(x["zero"] == 0)
+    assert res["maxit0"].reason == 2 and res["maxit0"].iters == 0 and np.all(x["maxit0"] == 0)
+    assert res["nan"].reason == 4
+    assert res["one"].reason in (1, 3) and np.all(np.isfinite(x["one"]))
+    r = res["x0"]
+    assert r.reason == 1
+    A, As, dis = operators.variable_laplacian(s["dims"], s["cx"], s["cy"], s["cz"])
+    if precision == "fp64":
+        ref = oplcg.plcg(As, dis * s["b"], x0 / dis, 2, shifts.chebyshev_shifts(2, 0.0, 2.0),
+                         1e-9, 5000)
+        assert abs(r.iters - ref.iters) <= 2
+        assert np.linalg.norm(x["x0"] - dis * ref.x) <= 1e-8 * np.linalg.norm(dis * ref.x)
+    # the original-space residual reported is that of the returned x
+    true = np.linalg.norm(s["b"] - A(x["x0"])) / np.linalg.norm(s["b"] - A(x0))
+    assert abs(r.true_relres - true) <= 1e-3 * true + 1e-15

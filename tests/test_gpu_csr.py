@@ -1,0 +1,169 @@
+"""General sparse (CSR) operators through the C ABI against the oracle: the
+assembled Poisson matrices, variable-coefficient matrices Jacobi-scaled by the
+test, FP32-stored inner solves, and invalid matrices."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cg as ocg
+from oracle import operators, refine, shifts
+from oracle import plcg as oplcg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _plcg():
+    from paper_1905_06850_amd import plcg
+    return plcg
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+class Csr:
+    """A CSR matrix copied to the device (kept alive while a solver is created)."""
+
+    def __init__(self, dev, rp, ci, va):
+        self.n = len(rp) - 1
+        self.nnz = len(ci)
+        self.t = (torch.from_numpy(np.ascontiguousarray(rp)).to(dev),
+                  torch.from_numpy(np.ascontiguousarray(ci)).to(dev),
+                  torch.from_numpy(np.ascontiguousarray(va)).to(dev))
+
+    def arg(self):
+        return (self.t[0].data_ptr(), self.t[1].data_ptr(), self.t[2].data_ptr(), self.nnz)
+
+
+def gpu_solve(dev, csr, method, l, b, x0, tol, maxit, lo=0.0, hi=8.0, **kw):
+    plcg = _plcg()
+    print(f"[gpu] csr {method} l={l} n={csr.n} nnz={csr.nnz} tol={tol} maxit={maxit}", flush=True)
+    s = plcg.Solver("csr", (csr.n,), method=method, l=l, lmin=lo, lmax=hi, csr=csr.arg(), **kw)
+    bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x0).copy()).to(dev)
+    res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit,
+                  torch.cuda.current_stream(dev).cuda_stream)
+    x = xt.cpu().numpy()
+    s.close()
+    return x, res
+
+
+def oracle_solve(A, method, l, b, x0, tol, maxit, lo=0.0, hi=8.0):
+    if method == "cg":
+        return ocg.cg(A, b, x0, tol, maxit)
+    return oplcg.plcg(A, b, x0, l, shifts.chebyshev_shifts(l, lo, hi), tol, maxit)
+
+
+def scaled_variable(dims, seed):
+    """D^{-1/2} A D^{-1/2} of a variable-coefficient operator, assembled here."""
+    cx, cy, cz = synth.edge_coefficients(dims, seed)
+    rp, ci, va = synth.csr_variable_laplacian(dims, cx, cy, cz)
+    A, As, dis = operators.variable_laplacian(dims, cx, cy, cz)
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    return (rp, ci, va * dis[rows] * dis[ci]), As
+
+
+@pytest.mark.parametrize("dims", [(64, 64), (37, 29), (9, 7, 5), (1, 1), (1, 300)])
+def test_csr_apply_matches_oracle(dev, dims):
+    plcg = _plcg()
+    rp, ci, va = synth.csr_variable_laplacian(dims)
+    csr = Csr(dev, rp, ci, va)
+    s = plcg.Solver("csr", (csr.n,), method="cg", csr=csr.arg())
+    x = synth.uniform(csr.n, 71)
+    xt = torch.from_numpy(x).to(dev)
+    yt = torch.empty_like(xt)
+    s.apply(xt.data_ptr(), yt.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    ref = operators.laplacian(dims)(x)
+    assert np.abs(yt.cpu().numpy() - ref).max() <= 16 * np.finfo(float).eps * 8
+    s.close()
+
+
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3),
+                                      ("plcg", 5)])
+def test_csr_poisson_solve_parity(dev, method, l):
+    dims = (64, 64)
+    A = operators.laplacian(dims)
+    csr = Csr(dev, *synth.csr_variable_laplacian(dims))
+    xs = synth.uniform(A.n, 0)
+    b = A(xs)
+    x0 = np.zeros(A.n)
+    ref = oracle_solve(A, method, l, b, x0, 1e-8, 5000)
+    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-8, 5000)
+    assert res.reason == 1 and abs(res.iters - ref.iters) <= 1
+    assert res.true_relres <= 10 * ref.true_relres and ref.true_relres <= 10 * res.true_relres
+    assert _rel(x, ref.x) < 1e-8
+
+
+@pytest.mark.parametrize("dims", [(48, 40), (37, 29), (9, 7, 5)])
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
+def test_csr_scaled_variable_solve_parity(dev, dims, method, l):
+    """Jacobi-scaled variable-coefficient matrices (spectrum in (0, 2)): the
+    preconditioned method of reading 15 on a general sparse matrix."""
+    (rp, ci, va), As = scaled_variable(dims, 72)
+    csr = Csr(dev, rp, ci, va)
+    b = synth.uniform(As.n, 73)
+    x0 = 0.1 * synth.uniform(As.n, 74)
+    ref = oracle_solve(As, method, l, b, x0, 1e-8, 20000, 0.0, 2.0)
+    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-8, 20000, 0.0, 2.0)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.iters - ref.iters) <= 1
+    assert _rel(x, ref.x) < 1e-8
+
+
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 4)])
+def test_csr_early_iterates(dev, method, l):
+    (rp, ci, va), As = scaled_variable((40, 30), 75)
+    csr = Csr(dev, rp, ci, va)
+    b = synth.uniform(As.n, 76)
+    x0 = np.zeros(As.n)
+    for m in (1, 2, 5, 20):
+        ref = oracle_solve(As, method, l, b, x0, 1e-30, m, 0.0, 2.0)
+        x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-30, m, 0.0, 2.0)
+        assert res.iters == m == ref.iters
+        assert _rel(x, ref.x) < 1e-13
+
+
+def test_csr_mixed_precision_against_oracle(dev):
+    """FP32-stored inner p(2)-CG in FP64 refinement on a scaled CSR matrix."""
+    (rp, ci, va), As = scaled_variable((60, 50), 77)
+    csr = Csr(dev, rp, ci, va)
+    b = synth.uniform(As.n, 78)
+    tol, inner = 1e-10, 1e-4
+    ref = refine.refine(As, b, np.zeros(As.n), 2, shifts.chebyshev_shifts(2, 0.0, 2.0), tol,
+                        inner, 20000)
+    x, res = gpu_solve(dev, csr, "plcg", 2, b, np.zeros(As.n), tol, 20000, 0.0, 2.0,
+                       precision="fp32", inner_tol=inner)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.outer - ref.outer) <= 1
+    assert abs(res.iters - ref.inner_iters) <= 0.1 * ref.inner_iters + 2
+    assert res.true_relres < tol
+    lam_min = np.linalg.eigvalsh(operators.assemble(As))[0]
+    assert np.linalg.norm(x - ref.x) <= 2 * (res.true_relres + ref.true_relres) * ref.rnorm0 / lam_min
+
+
+def test_csr_rejects_invalid_matrices(dev):
+    plcg = _plcg()
+    rp, ci, va = synth.csr_variable_laplacian((6, 5))
+    bad = {
+        "rowptr start": (rp + 1, ci, va),
+        "rowptr decreasing": (np.where(np.arange(len(rp)) == 5, rp[3], rp), ci, va),
+        "column range": (rp, np.where(np.arange(len(ci)) == 9, 30, ci).astype(np.int32), va),
+        "negative column": (rp, np.where(np.arange(len(ci)) == 9, -1, ci).astype(np.int32), va),
+        "nan value": (rp, ci, np.where(np.arange(len(va)) == 3, np.nan, va)),
+    }
+    for name, (r, c, v) in bad.items():
+        print(f"[gpu] invalid CSR: {name}", flush=True)
+        csr = Csr(dev, r.astype(np.int64), c, v)
+        with pytest.raises(plcg.PlcgError) as ei:
+            plcg.Solver("csr", (30,), method="plcg", l=2, csr=csr.arg())
+        assert ei.value.status == plcg.PLCG_E_INVALID, name
