@@ -400,7 +400,7 @@ def main():
         rp, ci, va = synth.csr_variable_laplacian(dims)
         csr_t = [torch.from_numpy(a).to(dev) for a in (rp, ci, va)]
         csr_arg = (csr_t[0].data_ptr(), csr_t[1].data_ptr(), csr_t[2].data_ptr(), len(ci))
-        op_bytes = 12 * len(ci) + 8 * (n + 1)     # values, column indices, row offsets
+        op_bytes = 12 * len(ci)                   # the entries: FP64 value + int32 column
         del rp, ci, va
     elif kind == "diag":
         op_bytes = 8 * n

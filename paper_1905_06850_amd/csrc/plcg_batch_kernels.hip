@@ -102,7 +102,7 @@ __device__ inline void slot_sweep_args(const SlotDesc &S, int i, SweepArgsT<T> &
     a.x = S.x;
   else
     a.x = svec<T>(S, 2 * L + R + 1);
-  a.od = OpData{nullptr, nullptr, nullptr, nullptr};
+  a.od = OpData{nullptr, nullptr, nullptr, nullptr, 0, 0};
   a.i = i;
   a.l = L;
   a.n = S.n;

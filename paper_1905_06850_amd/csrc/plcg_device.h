@@ -407,24 +407,64 @@ struct DiagOp {
   }
 };
 
-// General sparse operator in CSR form, one row per unknown: (A z)_p =
-// sum over the stored entries j of row p of va[j] * z[ci[j]] (FP64 values,
-// stored order).
+// General sparse operator in CSR form, one row per unknown: (A z)_p = sum over
+// the stored entries j of row p of va[j] * z[ci[j]] (FP64 values, stored
+// order).  With ell_k > 0 the entries come from the padded column-major ELL
+// copy instead (entry j of row p at j * ell_ld + p): consecutive rows are then
+// read by consecutive lanes, one coalesced access per entry index for the V
+// rows of a thread.  Both forms add the same products in the same order
+// (padding adds exact zeros), so their results are identical.
 template <typename S>
 struct CsrOp {
   const int64_t *rp;
   const int32_t *ci;
   const double *va;
+  int ell_k, ell_ld;
   __device__ inline double row(const S *z, int p) const {
     double s = 0.0;
-    const int64_t e = rp[p + 1];
-    for (int64_t j = rp[p]; j < e; ++j) s += va[j] * (double)z[ci[j]];
+    if (ell_k > 0) {
+      for (int j = 0; j < ell_k; ++j) {
+        const size_t e = (size_t)j * ell_ld + p;
+        s += va[e] * (double)z[ci[e]];
+      }
+    } else {
+      const int64_t e = rp[p + 1];
+      for (int64_t j = rp[p]; j < e; ++j) s += va[j] * (double)z[ci[j]];
+    }
     return s;
   }
   template <int V, bool FAST>
   __device__ inline void apply(const S *z, int idx, const Vals<V, S> &, double (&w)[V]) const {
+    if (ell_k > 0 && V >= 2) {
+      // idx is a multiple of V and ell_ld of 4: aligned vector accesses
 #pragma unroll
-    for (int v = 0; v < V; ++v) w[v] = row(z, idx + v);
+      for (int v = 0; v < V; ++v) w[v] = 0.0;
+      for (int j = 0; j < ell_k; ++j) {
+        const size_t e = (size_t)j * ell_ld + idx;
+        Vals<V, double> vv;
+        vv.load(va + e);
+        int c[V];
+        if constexpr (V == 2) {
+          const int2 t = *reinterpret_cast<const int2 *>(ci + e);
+          c[0] = t.x;
+          c[1] = t.y;
+        } else if constexpr (V == 4) {
+          const int4 t = *reinterpret_cast<const int4 *>(ci + e);
+          c[0] = t.x;
+          c[1] = t.y;
+          c[2] = t.z;
+          c[3] = t.w;
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) c[v] = ci[e + v];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) w[v] += vv.v[v] * (double)z[c[v]];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) w[v] = row(z, idx + v);
+    }
   }
 };
 

@@ -73,7 +73,7 @@ struct plcg_handle {
   int hist_cap = 0;
   int n = 0, nchunks = 0, blocks = 0;
   bool d3 = false;
-  OpData od{nullptr, nullptr, nullptr, nullptr};   // library copies of d / the CSR arrays
+  OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0};   // library copies of d / the CSR arrays
   int device = 0;
   // device buffers
   std::vector<void *> allocs;
@@ -635,23 +635,48 @@ plcg_status copy_csr(plcg_handle *h, const plcg_operator_desc *op) {
       return fail(PLCG_E_INVALID, "CSR column index out of range");
     if (!std::isfinite(va[j])) return fail(PLCG_E_INVALID, "CSR values must be finite");
   }
+  // Rows of nearly equal length (stencil-like matrices): keep a padded
+  // column-major ELLPACK copy instead, so that consecutive lanes read
+  // consecutive rows' j-th entries.  Entry order within a row is the CSR order;
+  // padding is the row's own column with value 0.
+  int64_t kmax = 0;
+  for (size_t p = 0; p < n; ++p) kmax = std::max<int64_t>(kmax, rp[p + 1] - rp[p]);
+  const size_t ld = (n + 3) / 4 * 4;
+  const bool ell = n > 0 && kmax > 0 && kmax <= 64 && (size_t)kmax * ld <= 2 * nnz + 4 * n;
+  if (ell) {
+    std::vector<int32_t> eci((size_t)kmax * ld);
+    std::vector<double> eva((size_t)kmax * ld, 0.0);
+    for (size_t p = 0; p < ld; ++p) {
+      const int64_t b0 = p < n ? rp[p] : 0, len = p < n ? rp[p + 1] - rp[p] : 0;
+      for (int64_t j = 0; j < kmax; ++j) {
+        const size_t e = (size_t)j * ld + p;
+        eci[e] = j < len ? ci[b0 + j] : (int32_t)(p < n ? p : 0);
+        if (j < len) eva[e] = va[b0 + j];
+      }
+    }
+    ci.swap(eci);
+    va.swap(eva);
+  }
+  const size_t stored = ell ? (size_t)kmax * ld : nnz;
   int64_t *drp = nullptr;
   int32_t *dci = nullptr;
   double *dva = nullptr;
   plcg_status e = dev_alloc(h, reinterpret_cast<void **>(&drp), sizeof(int64_t) * (n + 1));
-  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dci), sizeof(int32_t) * (nnz + 1));
-  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dva), sizeof(double) * (nnz + 1));
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dci), sizeof(int32_t) * (stored + 1));
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dva), sizeof(double) * (stored + 1));
   if (e != PLCG_OK) return e;
   if ((he = hipMemcpy(drp, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) !=
           hipSuccess ||
-      (nnz > 0 && (he = hipMemcpy(dci, ci.data(), sizeof(int32_t) * nnz,
-                                  hipMemcpyHostToDevice)) != hipSuccess) ||
-      (nnz > 0 && (he = hipMemcpy(dva, va.data(), sizeof(double) * nnz,
-                                  hipMemcpyHostToDevice)) != hipSuccess))
+      (stored > 0 && (he = hipMemcpy(dci, ci.data(), sizeof(int32_t) * stored,
+                                     hipMemcpyHostToDevice)) != hipSuccess) ||
+      (stored > 0 && (he = hipMemcpy(dva, va.data(), sizeof(double) * stored,
+                                     hipMemcpyHostToDevice)) != hipSuccess))
     return fail(PLCG_E_HIP, std::string("hipMemcpy(CSR): ") + hipGetErrorString(he));
   h->od.rp = drp;
   h->od.ci = dci;
   h->od.va = dva;
+  h->od.ell_k = ell ? (int32_t)kmax : 0;
+  h->od.ell_ld = ell ? (int32_t)ld : 0;
   return PLCG_OK;
 }
 

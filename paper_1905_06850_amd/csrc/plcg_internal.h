@@ -23,8 +23,12 @@ enum Status : int32_t { kRunning = 0, kConverged = 1, kBroken = 2, kNonFinite = 
 struct OpData {
   const double *dg;    // diagonal operator: d (n)
   const int64_t *rp;   // CSR: row offsets (n+1)
-  const int32_t *ci;   // CSR: column indices (nnz)
-  const double *va;    // CSR: values (nnz)
+  const int32_t *ci;   // CSR: column indices (nnz), or the ELL copy below
+  const double *va;    // CSR: values (nnz), or the ELL copy below
+  int32_t ell_k;       // > 0: ci / va hold a padded column-major ELLPACK copy: entry j of
+                       // row p at j * ell_ld + p (CSR order within the row; padding is
+                       // column p with value 0), j < ell_k
+  int32_t ell_ld;      // ELL leading dimension: n rounded up to a multiple of 4
 };
 
 // Host-visible progress record, written by the device into pinned host memory

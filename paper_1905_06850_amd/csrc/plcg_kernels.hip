@@ -106,7 +106,8 @@ __global__ __launch_bounds__(kThreads) void plcg_diag_sweep_kernel(SweepArgsT<ST
 
 template <int L, typename ST>
 __global__ __launch_bounds__(kThreads) void plcg_csr_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST>(a, CsrOp<ST>{a.od.rp, a.od.ci, a.od.va}, true, ChunkOrder{0, 0, 0});
+  plcg_sweep<L, ST>(a, CsrOp<ST>{a.od.rp, a.od.ci, a.od.va, a.od.ell_k, a.od.ell_ld}, true,
+                    ChunkOrder{0, 0, 0});
 }
 
 // ---------------------------------------------------------------------------
@@ -386,8 +387,15 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
       if (p >= a.n) break;
       const double pc = pk1(p);
       double q = 0.0;
-      const int64_t e = a.od.rp[p + 1];
-      for (int64_t j = a.od.rp[p]; j < e; ++j) q += a.od.va[j] * pk1(a.od.ci[j]);
+      if (a.od.ell_k > 0) {
+        for (int j = 0; j < a.od.ell_k; ++j) {
+          const size_t e = (size_t)j * a.od.ell_ld + p;
+          q += a.od.va[e] * pk1(a.od.ci[e]);
+        }
+      } else {
+        const int64_t e = a.od.rp[p + 1];
+        for (int64_t j = a.od.rp[p]; j < e; ++j) q += a.od.va[j] * pk1(a.od.ci[j]);
+      }
       a.p_new[p] = pc;
       a.q[p] = q;
       acc[0] += pc * q;
@@ -462,7 +470,7 @@ __device__ inline double op_at(const double *x, int p, const Grid &g, const OpDa
   if constexpr (K == 2) {
     return od.dg[p] * x[p];
   } else if constexpr (K == 3) {
-    return CsrOp<double>{od.rp, od.ci, od.va}.row(x, p);
+    return CsrOp<double>{od.rp, od.ci, od.va, od.ell_k, od.ell_ld}.row(x, p);
   } else {
     return (K == 1 ? 6.0 : 4.0) * x[p] - neighbour_sum<K == 1>(x, p, g);
   }

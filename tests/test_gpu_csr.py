@@ -167,3 +167,35 @@ def test_csr_rejects_invalid_matrices(dev):
         with pytest.raises(plcg.PlcgError) as ei:
             plcg.Solver("csr", (30,), method="plcg", l=2, csr=csr.arg())
         assert ei.value.status == plcg.PLCG_E_INVALID, name
+
+
+def _arrow(n, seed):
+    """SPD arrow matrix: diagonal d_p in [2, 4), row and column 0 coupled to every
+    unknown with weight 1/n (diagonally dominant).  Its rows have very uneven
+    lengths, so the library keeps the CSR layout instead of the ELL copy."""
+    d = 3.0 + synth.uniform(n, seed)
+    rows, cols, vals = [0], [0], [d[0] + 1.0]
+    for p in range(1, n):
+        rows += [0, p, p]
+        cols += [p, 0, p]
+        vals += [1.0 / n, 1.0 / n, d[p]]
+    rows, cols, vals = np.array(rows), np.array(cols), np.array(vals)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return rp, cols.astype(np.int32), vals
+
+
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
+def test_csr_uneven_rows_parity(dev, method, l):
+    rp, ci, va = _arrow(3001, 79)
+    A = operators.csr(rp, ci, va)
+    csr = Csr(dev, rp, ci, va)
+    b = synth.uniform(A.n, 80)
+    x0 = np.zeros(A.n)
+    ref = oracle_solve(A, method, l, b, x0, 1e-10, 2000, 1.9, 4.2)
+    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-10, 2000, 1.9, 4.2)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.iters - ref.iters) <= 1
+    assert _rel(x, ref.x) < 1e-8
