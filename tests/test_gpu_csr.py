@@ -199,3 +199,31 @@ def test_csr_uneven_rows_parity(dev, method, l):
     assert res.reason == 1 and ref.reason == "converged"
     assert abs(res.iters - ref.iters) <= 1
     assert _rel(x, ref.x) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["poisson2048_cg", "poisson2048_p1", "poisson2048_p2"])
+def test_csr_full_size_against_stored_oracle(dev, name):
+    """The 2048^2 Poisson matrix assembled in CSR (the csr2048 benchmark
+    workload) against the oracle's stored result for the same problem
+    (tests/golden, written from the oracle only): iterations within 1, true
+    residual within 10x, sampled ||x - x_oracle|| / ||x_oracle|| < 1e-8."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result {name}")
+    with open(path) as f:
+        g = json.load(f)
+    dims = tuple(g["dims"])
+    csr = Csr(dev, *synth.csr_variable_laplacian(dims))
+    n = csr.n
+    b = synth.uniform(n, g["seed"])
+    lo, hi = g["interval"]
+    x, res = gpu_solve(dev, csr, g["method"], max(int(g["l"]), 1), b, np.zeros(n), g["tol"],
+                       100000, lo, hi)
+    assert res.reason == 1 and abs(res.iters - g["iters"]) <= 1
+    assert res.true_relres <= 10 * g["true_relres"] and g["true_relres"] <= 10 * res.true_relres
+    idx = np.array(g["sample_idx"])
+    ref = np.array(g["sample_x"])
+    est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
+    assert est < 1e-8
