@@ -99,6 +99,16 @@ typedef struct {
                              give PLCG_E_INVALID); symmetry and definiteness are not
                              checked: a matrix that is not SPD shows up as breakdowns
                              (restart limit) or, for CG, PLCG_REASON_BREAKDOWN. */
+  int32_t jacobi;         /* PLCG_OP_CSR only (else must be 0): 1 = Jacobi-preconditioned
+                             solve, which is Alg. 1 with M = diag(A) (Sec. 2.2) in its
+                             symmetrically scaled form: the library stores
+                             D^{-1/2} A D^{-1/2} (d_p = a_pp > 0, else PLCG_E_INVALID),
+                             solves for y = D^{1/2} x from D^{-1/2} b (x is transformed in
+                             place on entry and back on exit), stops on the scaled residual
+                             |zeta_t| < tol ||D^{-1/2}(b - A x0)|| and reports rec_relres in
+                             that norm, rnorm0 and true_relres in the original one.  The
+                             Chebyshev interval refers to the scaled matrix ([0, 2] holds its
+                             spectrum when A is a weakly diagonally dominant M-matrix). */
 } plcg_operator_desc;
 
 typedef struct {

@@ -74,6 +74,9 @@ struct plcg_handle {
   int n = 0, nchunks = 0, blocks = 0;
   bool d3 = false;
   OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0};   // library copies of d / the CSR arrays
+  bool jacobi = false;            // CSR solved in Jacobi-scaled form D^{-1/2} A D^{-1/2}
+  double *dis = nullptr;          // D^{-1/2} (jacobi)
+  double *bs = nullptr;           // D^{-1/2} b of the current solve (jacobi)
   int device = 0;
   // device buffers
   std::vector<void *> allocs;
@@ -266,9 +269,10 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
 // r = b - A x (r may be NULL) and ||r||^2 into state copy `slot`; mode as in
 // launch_start.
 plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r, int slot,
-                     int mode, double tol, double rref_in, hipStream_t s) {
+                     int mode, double tol, double rref_in, hipStream_t s,
+                     const double *wdiv = nullptr) {
   PLCG_HIP(launch_residual(b, x, r, h->part[0], h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
-                           h->od, h->nchunks, h->blocks, s));
+                           h->od, wdiv, h->nchunks, h->blocks, s));
   PLCG_HIP(launch_start(h->part[0], h->blocks, h->st[slot], h->hs_dev, mode, tol, rref_in, s));
   return PLCG_OK;
 }
@@ -581,20 +585,37 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   h->host_waits = 0;
   TimedLaunch tl{h, s};
   int final_slot = 1;
+  // Jacobi-scaled CSR: solve D^{-1/2} A D^{-1/2} y = D^{-1/2} b for y = D^{1/2} x
+  // (x transformed in place, and back at the end); the original-space residual
+  // norm ||b - A x|| = ||(D^{-1/2} b - A~ y) / D^{-1/2}|| is reported beside it.
+  const double *bb = b;
+  double rnorm0_orig = 0.0;
+  if (h->jacobi) {
+    PLCG_HIP(launch_jacobi_in(b, h->dis, h->bs, x, h->n, s));
+    bb = h->bs;
+    if ((e = residual(h, bb, x, nullptr, 1, 2, tol, -1.0, s, h->dis)) != PLCG_OK) return e;
+    PLCG_HIP(wait_stream(h, s));
+    rnorm0_orig = std::sqrt(hstat(h)->sumsq);
+  }
   if (h->method == PLCG_METHOD_CG)
-    e = solve_cg(h, b, x, tol, maxit, s, &res, tl, &final_slot);
+    e = solve_cg(h, bb, x, tol, maxit, s, &res, tl, &final_slot);
   else if (h->precision == PLCG_PREC_FP32_REFINED)
-    e = solve_mixed(h, b, x, tol, maxit, s, &res, tl, &final_slot);
+    e = solve_mixed(h, bb, x, tol, maxit, s, &res, tl, &final_slot);
   else
-    e = solve_plcg(h, b, x, tol, maxit, s, &res, tl, &final_slot);
+    e = solve_plcg(h, bb, x, tol, maxit, s, &res, tl, &final_slot);
   if (e != PLCG_OK) {
+    if (h->jacobi) (void)launch_jacobi_out(x, h->dis, h->n, s);
     if (out) *out = res;
     return e;
   }
   // True residual ||b - A x|| in FP64 (one more operator application).
-  if ((e = residual(h, b, x, nullptr, final_slot, 2, tol, -1.0, s)) != PLCG_OK) return e;
+  if ((e = residual(h, bb, x, nullptr, final_slot, 2, tol, -1.0, s,
+                    h->jacobi ? h->dis : nullptr)) != PLCG_OK)
+    return e;
+  if (h->jacobi) PLCG_HIP(launch_jacobi_out(x, h->dis, h->n, s));
   PLCG_HIP(wait_stream(h, s));
-  res.spmvs += 1;
+  res.spmvs += h->jacobi ? 2 : 1;
+  if (h->jacobi) res.rnorm0 = rnorm0_orig;
   res.true_relres = res.rnorm0 > 0 ? std::sqrt(hstat(h)->sumsq) / res.rnorm0 : 0.0;
   if (h->timing) {
     double ms = 0;
@@ -635,6 +656,29 @@ plcg_status copy_csr(plcg_handle *h, const plcg_operator_desc *op) {
       return fail(PLCG_E_INVALID, "CSR column index out of range");
     if (!std::isfinite(va[j])) return fail(PLCG_E_INVALID, "CSR values must be finite");
   }
+  if (h->jacobi) {
+    // d_p = a_pp (sum of the stored diagonal entries of row p), which must be
+    // positive; a_pq <- a_pq d_p^{-1/2} d_q^{-1/2}.
+    std::vector<double> dis(n, 0.0);
+    for (size_t p = 0; p < n; ++p)
+      for (int64_t j = rp[p]; j < rp[p + 1]; ++j)
+        if ((size_t)ci[j] == p) dis[p] += va[j];
+    for (size_t p = 0; p < n; ++p) {
+      if (!(dis[p] > 0.0) || !std::isfinite(dis[p]))
+        return fail(PLCG_E_INVALID, "Jacobi scaling needs a positive diagonal");
+      dis[p] = 1.0 / std::sqrt(dis[p]);
+    }
+    for (size_t p = 0; p < n; ++p)
+      for (int64_t j = rp[p]; j < rp[p + 1]; ++j) va[j] *= dis[p] * dis[ci[j]];
+    double *ddis = nullptr, *dbs = nullptr;
+    plcg_status e = dev_alloc(h, reinterpret_cast<void **>(&ddis), sizeof(double) * n);
+    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dbs), sizeof(double) * n);
+    if (e != PLCG_OK) return e;
+    if ((he = hipMemcpy(ddis, dis.data(), sizeof(double) * n, hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(PLCG_E_HIP, std::string("hipMemcpy(D^-1/2): ") + hipGetErrorString(he));
+    h->dis = ddis;
+    h->bs = dbs;
+  }
   // Rows of nearly equal length (stencil-like matrices): keep a padded
   // column-major ELLPACK copy instead, so that consecutive lanes read
   // consecutive rows' j-th entries.  Entry order within a row is the CSR order;
@@ -662,7 +706,8 @@ plcg_status copy_csr(plcg_handle *h, const plcg_operator_desc *op) {
   int32_t *dci = nullptr;
   double *dva = nullptr;
   plcg_status e = dev_alloc(h, reinterpret_cast<void **>(&drp), sizeof(int64_t) * (n + 1));
-  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dci), sizeof(int32_t) * (stored + 1));
+  if (e == PLCG_OK)
+    e = dev_alloc(h, reinterpret_cast<void **>(&dci), sizeof(int32_t) * (stored + 1));
   if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dva), sizeof(double) * (stored + 1));
   if (e != PLCG_OK) return e;
   if ((he = hipMemcpy(drp, rp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) !=
@@ -700,6 +745,8 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   if (op->kind == PLCG_OP_CSR &&
       (op->rowptr == nullptr || op->colind == nullptr || op->vals == nullptr || op->nnz < 0))
     return fail(PLCG_E_INVALID, "CSR operator needs rowptr, colind, vals and nnz >= 0");
+  if (op->jacobi != 0 && op->kind != PLCG_OP_CSR)
+    return fail(PLCG_E_INVALID, "Jacobi scaling is offered for CSR operators");
   const int nz = op->kind == PLCG_OP_STENCIL2D5 ? 1 : op->nz;
   if (op->nx < 1 || op->ny < 1 || nz < 1) return fail(PLCG_E_INVALID, "grid extents must be >= 1");
   if (op->kind == PLCG_OP_STENCIL2D5 && op->nz > 1)
@@ -730,6 +777,7 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   plcg_handle *h = new plcg_handle();
   h->op = *op;
   h->op.nz = nz;
+  h->jacobi = op->kind == PLCG_OP_CSR && op->jacobi != 0;
   h->d3 = op->kind == PLCG_OP_STENCIL3D7;
   h->device = dev;
   h->method = cfg->method;

@@ -111,11 +111,16 @@ hipError_t launch_plcg_sweep(const SweepArgsT<double> &a, hipStream_t s);
 hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s);
 hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s);
 hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s);
-// r = b - A x (r may be NULL); per-block partial sums of r.r into part_out.
-// A is the stencil of (nx, ny, nz, d3), or the diagonal / CSR matrix of od.
+// r = b - A x (r may be NULL); per-block partial sums of r.r into part_out, or
+// of (r / wdiv)^2 when wdiv is not NULL.  A is the stencil of (nx, ny, nz, d3),
+// or the diagonal / CSR matrix of od.
 hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out,
-                           int n, int nx, int ny, int nz, bool d3, const OpData &od, int nchunks,
-                           int nstream, hipStream_t s);
+                           int n, int nx, int ny, int nz, bool d3, const OpData &od,
+                           const double *wdiv, int nchunks, int nstream, hipStream_t s);
+// bs = dis * b, x = x / dis (into a Jacobi-scaled solve); x = x * dis (out of it).
+hipError_t launch_jacobi_in(const double *b, const double *dis, double *bs, double *x, int n,
+                            hipStream_t s);
+hipError_t launch_jacobi_out(double *x, const double *dis, int n, hipStream_t s);
 // One block: sum the residual partials and start a segment in *st:
 // mode 0 = p(l)-CG (G, beta, status), 1 = CG (rho), 2 = only report the sum.
 hipError_t launch_start(const double *part_in, int nparts, DevState *st, HostStatus *hs,

@@ -476,11 +476,13 @@ __device__ inline double op_at(const double *x, int p, const Grid &g, const OpDa
   }
 }
 
+// wdiv (optional): accumulate (r_p / wdiv_p)^2 instead of r_p^2 (the
+// original-space norm of a Jacobi-scaled residual, wdiv = D^{-1/2}).
 template <int K>
 __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, const double *x,
                                                             double *r, double *part_out, Grid g,
-                                                            OpData od, int nchunks,
-                                                            int nstream) {
+                                                            OpData od, const double *wdiv,
+                                                            int nchunks, int nstream) {
   constexpr bool D3 = K == 1;
   __shared__ double lds[4];
   __shared__ double red[1];
@@ -494,7 +496,8 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, con
       if (p >= g.n) break;
       const double rv = b[p] - op_at<K>(x, p, g, od);
       if (r != nullptr) r[p] = rv;
-      acc[0] += rv * rv;
+      const double rw = wdiv != nullptr ? rv / wdiv[p] : rv;
+      acc[0] += rw * rw;
     }
   }
   store_partials<1>(acc, part_out, kMaxStream, blockIdx.x, lds, red);
@@ -551,6 +554,21 @@ __global__ __launch_bounds__(kThreads) void scale_kernel(const double *r, T *d0,
     if (d1) d1[p] = v;
     if (d2) d2[p] = v;
   }
+}
+
+// Jacobi scaling of a solve: bs = D^{-1/2} b and y = D^{1/2} x in place (dis = D^{-1/2}).
+__global__ __launch_bounds__(kThreads) void jacobi_in_kernel(const double *b, const double *dis,
+                                                             double *bs, double *x, int n) {
+  for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads) {
+    bs[p] = b[p] * dis[p];
+    x[p] = x[p] / dis[p];
+  }
+}
+
+// Back to the caller's variables: x = D^{-1/2} y in place.
+__global__ __launch_bounds__(kThreads) void jacobi_out_kernel(double *x, const double *dis, int n) {
+  for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads)
+    x[p] = x[p] * dis[p];
 }
 
 // x += d: the FP32 correction of one refinement step added to the FP64 iterate.
@@ -640,16 +658,16 @@ hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out, int n,
-                           int nx, int ny, int nz, bool d3, const OpData &od, int nchunks,
-                           int nstream, hipStream_t s) {
+                           int nx, int ny, int nz, bool d3, const OpData &od, const double *wdiv,
+                           int nchunks, int nstream, hipStream_t s) {
   const Grid g{n, nx, ny, nz};
   const int k = od.rp != nullptr ? 3 : od.dg != nullptr ? 2 : d3 ? 1 : 0;
   const dim3 grid(nstream), block(kThreads);
   switch (k) {
-    case 3: hipLaunchKernelGGL(residual_kernel<3>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
-    case 2: hipLaunchKernelGGL(residual_kernel<2>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
-    case 1: hipLaunchKernelGGL(residual_kernel<1>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
-    default: hipLaunchKernelGGL(residual_kernel<0>, grid, block, 0, s, b, x, r, part_out, g, od, nchunks, nstream); break;
+    case 3: hipLaunchKernelGGL(residual_kernel<3>, grid, block, 0, s, b, x, r, part_out, g, od, wdiv, nchunks, nstream); break;
+    case 2: hipLaunchKernelGGL(residual_kernel<2>, grid, block, 0, s, b, x, r, part_out, g, od, wdiv, nchunks, nstream); break;
+    case 1: hipLaunchKernelGGL(residual_kernel<1>, grid, block, 0, s, b, x, r, part_out, g, od, wdiv, nchunks, nstream); break;
+    default: hipLaunchKernelGGL(residual_kernel<0>, grid, block, 0, s, b, x, r, part_out, g, od, wdiv, nchunks, nstream); break;
   }
   return hipGetLastError();
 }
@@ -672,6 +690,18 @@ hipError_t launch_scale(const double *r, float *d0, float *d1, float *d2, const 
                         hipStream_t s) {
   hipLaunchKernelGGL(scale_kernel<float>, dim3(simple_blocks(n)), dim3(kThreads), 0, s, r, d0, d1,
                      d2, st, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_in(const double *b, const double *dis, double *bs, double *x, int n,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_in_kernel, dim3(simple_blocks(n)), dim3(kThreads), 0, s, b, dis, bs, x,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_out(double *x, const double *dis, int n, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_out_kernel, dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, dis, n);
   return hipGetLastError();
 }
 

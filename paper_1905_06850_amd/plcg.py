@@ -40,7 +40,7 @@ class plcg_operator_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("diag", ctypes.c_void_p), ("nnz", ctypes.c_int64),
                 ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
-                ("vals", ctypes.c_void_p)]
+                ("vals", ctypes.c_void_p), ("jacobi", ctypes.c_int32)]
 
 
 class plcg_config(ctypes.Structure):
@@ -185,7 +185,7 @@ def check(status, where):
     return status
 
 
-def _dims_desc(kind, dims, diag=None, csr=None):
+def _dims_desc(kind, dims, diag=None, csr=None, jacobi=False):
     dims = tuple(int(d) for d in dims)
     if kind in ("2d5", PLCG_OP_STENCIL2D5):
         return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1)
@@ -197,7 +197,7 @@ def _dims_desc(kind, dims, diag=None, csr=None):
     if kind in ("csr", PLCG_OP_CSR):
         rowptr, colind, vals, nnz = csr if csr is not None else (None, None, None, 0)
         return plcg_operator_desc(PLCG_OP_CSR, dims[0], dims[1], dims[2], None, int(nnz),
-                                  rowptr, colind, vals)
+                                  rowptr, colind, vals, 1 if jacobi else 0)
     raise ValueError(f"unknown operator kind {kind!r}")
 
 
@@ -206,12 +206,12 @@ class Solver:
 
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
                  check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
-                 inner_tol=0.0, diag=None, csr=None):
+                 inner_tol=0.0, diag=None, csr=None, jacobi=False):
         """kind "2d5", "3d7", "diag" or "csr"; for "diag", `diag` is the device
         address of the n FP64 diagonal entries; for "csr", `csr` is (rowptr,
         colind, vals, nnz) with device addresses of int64 / int32 / FP64 arrays
-        (copied by plcg_create)."""
-        self.desc = _dims_desc(kind, dims, diag, csr)
+        (copied by plcg_create); jacobi=True solves a CSR matrix Jacobi-preconditioned."""
+        self.desc = _dims_desc(kind, dims, diag, csr, jacobi)
         self._shifts = None
         sp = None
         if shifts is not None:

@@ -62,3 +62,13 @@ def test_null_arguments():
     assert plcg.plcg_copy(0, 0, 10, None) == plcg.PLCG_E_INVALID
     assert plcg.plcg_destroy(None) == plcg.PLCG_OK
     assert plcg.plcg_size(None) == -1
+
+
+def test_jacobi_flag_needs_a_csr_operator():
+    from paper_1905_06850_amd import plcg
+    desc = plcg.plcg_operator_desc(1, 8, 8, 1, None, 0, None, None, None, 1)
+    cfg = plcg.plcg_config(1, 2, 0.0, 8.0, None, 0, -1, 0)
+    h = ctypes.c_void_p()
+    assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
+        plcg.PLCG_E_INVALID
+    assert not h.value

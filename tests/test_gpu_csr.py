@@ -227,3 +227,95 @@ def test_csr_full_size_against_stored_oracle(dev, name):
     ref = np.array(g["sample_x"])
     est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
     assert est < 1e-8
+
+
+# ------------------------------------------------------- Jacobi-scaled CSR --
+
+def _unscaled_variable(dims, seed):
+    cx, cy, cz = synth.edge_coefficients(dims, seed)
+    rp, ci, va = synth.csr_variable_laplacian(dims, cx, cy, cz)
+    A, As, dis = operators.variable_laplacian(dims, cx, cy, cz)
+    return (rp, ci, va), A, As, dis
+
+
+def gpu_solve_jacobi(dev, csr, method, l, b, x0, tol, maxit, **kw):
+    plcg = _plcg()
+    print(f"[gpu] csr jacobi {method} l={l} n={csr.n} tol={tol} maxit={maxit}", flush=True)
+    s = plcg.Solver("csr", (csr.n,), method=method, l=l, lmin=0.0, lmax=2.0, csr=csr.arg(),
+                    jacobi=True, **kw)
+    bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x0).copy()).to(dev)
+    res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit,
+                  torch.cuda.current_stream(dev).cuda_stream)
+    x = xt.cpu().numpy()
+    s.close()
+    return x, res
+
+
+@pytest.mark.parametrize("dims", [(48, 40), (9, 7, 5)])
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
+def test_csr_jacobi_parity(dev, dims, method, l):
+    """Jacobi-preconditioned solve of an unscaled variable-coefficient matrix
+    against the oracle on the scaled system from the scaled x0 (the same method,
+    reading 15): iterations within 1, x within 1e-8, both residual norms."""
+    (rp, ci, va), A, As, dis = _unscaled_variable(dims, 81)
+    csr = Csr(dev, rp, ci, va)
+    b = synth.uniform(A.n, 82)
+    x0 = 0.1 * synth.uniform(A.n, 83)
+    ref = oracle_solve(As, method, l, dis * b, x0 / dis, 1e-8, 20000, 0.0, 2.0)
+    x, res = gpu_solve_jacobi(dev, csr, method, l, b, x0, 1e-8, 20000)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.iters - ref.iters) <= 1
+    xr = dis * ref.x
+    assert _rel(x, xr) < 1e-8
+    assert res.rec_relres <= 10 * ref.true_relres
+    r0 = np.linalg.norm(b - A(x0))
+    assert abs(res.rnorm0 - r0) <= 1e-12 * r0
+    true = np.linalg.norm(b - A(x)) / r0
+    assert abs(res.true_relres - true) <= 1e-3 * true + 1e-15
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_csr_jacobi_is_preconditioned_alg1(dev, l):
+    """The first iterates equal those of Alg. 1 with M = diag(A) (u != z,
+    M-inner products) run by the oracle on the unscaled matrix."""
+    (rp, ci, va), A, As, dis = _unscaled_variable((40, 30), 84)
+    csr = Csr(dev, rp, ci, va)
+    b = synth.uniform(A.n, 85)
+    x0 = np.zeros(A.n)
+    dinv = dis * dis
+    sig = shifts.chebyshev_shifts(l, 0.0, 2.0)
+    for m in (1, 5, 20):
+        ref = oplcg.alg1(A, b, x0, l, sig, 0.0, m, Minv=lambda u: dinv * u)
+        x, res = gpu_solve_jacobi(dev, csr, "plcg", l, b, x0, 1e-30, m)
+        assert res.iters == m == ref.t_done
+        assert _rel(x, ref.x) < 1e-12
+
+
+def test_csr_jacobi_mixed_precision(dev):
+    (rp, ci, va), A, As, dis = _unscaled_variable((60, 50), 86)
+    csr = Csr(dev, rp, ci, va)
+    b = synth.uniform(A.n, 87)
+    tol, inner = 1e-10, 1e-4
+    ref = refine.refine(As, dis * b, np.zeros(A.n), 2, shifts.chebyshev_shifts(2, 0.0, 2.0), tol,
+                        inner, 20000)
+    x, res = gpu_solve_jacobi(dev, csr, "plcg", 2, b, np.zeros(A.n), tol, 20000,
+                              precision="fp32", inner_tol=inner)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.outer - ref.outer) <= 1
+    assert abs(res.iters - ref.inner_iters) <= 0.1 * ref.inner_iters + 2
+    lam_min = np.linalg.eigvalsh(operators.assemble(As))[0]
+    y, yref = x / dis, ref.x
+    assert np.linalg.norm(y - yref) <= 2 * (res.rec_relres + ref.true_relres) * ref.rnorm0 / lam_min
+
+
+def test_csr_jacobi_needs_a_positive_diagonal(dev):
+    plcg = _plcg()
+    rp, ci, va = synth.csr_variable_laplacian((6, 5))
+    va = va.copy()
+    diag_entry = [j for j in range(rp[3], rp[4]) if ci[j] == 3][0]
+    va[diag_entry] = -1.0
+    csr = Csr(dev, rp, ci, va)
+    with pytest.raises(plcg.PlcgError) as ei:
+        plcg.Solver("csr", (30,), method="plcg", l=2, csr=csr.arg(), jacobi=True)
+    assert ei.value.status == plcg.PLCG_E_INVALID
