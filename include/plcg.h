@@ -17,6 +17,7 @@
  *  - Vectors are contiguous float64 arrays in device memory, 16-byte aligned,
  *    indexed row-major with x fastest (index = x + nx*(y + ny*z)).  Values
  *    outside the grid are zero (homogeneous Dirichlet boundary eliminated).
+ *  - A system has at most 2^31 - 2^23 unknowns (larger: PLCG_E_INVALID).
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work of a call is enqueued on that stream.
  *  - The library allocates its own workspace at plcg_create and frees it at

@@ -145,7 +145,7 @@ int32_t layout(const plcg_batch *b, const plcg_system_desc *sys, Layout *L) {
   const int64_t nx = sys->nx, ny = sys->ny, nz = d3 ? sys->nz : 1;
   if (nx < 1 || ny < 1 || nz < 1 || (!d3 && sys->nz > 1)) return PLCG_E_INVALID;
   L->n = nx * ny * nz;
-  if (L->n >= (1LL << 31) - 4 * kChunk) return PLCG_E_INVALID;
+  if (L->n > kMaxUnknowns) return PLCG_E_INVALID;
   const size_t w = word_bytes(b);
   L->vstride = round_up((size_t)L->n * w, kAlign) / w;
   L->vec_bytes = (size_t)work_vectors(b) * L->vstride * w;

@@ -752,7 +752,7 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   if (op->kind == PLCG_OP_STENCIL2D5 && op->nz > 1)
     return fail(PLCG_E_INVALID, "2D operator needs nz = 1");
   const long long n = (long long)op->nx * op->ny * nz;
-  if (n >= (1LL << 31) - 4 * kChunk) return fail(PLCG_E_INVALID, "grid too large (n >= 2^31)");
+  if (n > kMaxUnknowns) return fail(PLCG_E_INVALID, "too many unknowns (n > 2^31 - 2^23)");
   if (cfg->method != PLCG_METHOD_CG && cfg->method != PLCG_METHOD_PLCG)
     return fail(PLCG_E_INVALID, "unknown method");
   const bool pl = cfg->method == PLCG_METHOD_PLCG;

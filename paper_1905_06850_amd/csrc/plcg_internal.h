@@ -15,6 +15,9 @@ constexpr int kVec = 2;               // consecutive unknowns per thread and chu
 constexpr int kChunk = kThreads * kVec;
 constexpr int kXcds = 8;              // MI355X: workgroups are dealt round-robin to 8 XCDs
 constexpr int kMaxStream = 1024;      // streaming blocks per launch (multiple of kXcds)
+// Largest number of unknowns: indices are int32, and a loop that has reached
+// the last unknown may still add one launch's stride (< 2^22) before its test.
+constexpr long long kMaxUnknowns = (1LL << 31) - (1LL << 23);
 
 enum Status : int32_t { kRunning = 0, kConverged = 1, kBroken = 2, kNonFinite = 3, kCgBreak = 4 };
 

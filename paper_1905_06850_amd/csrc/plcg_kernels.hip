@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void scale_kernel(const double *r, T *d0,
                                                           const DevState *st, int n) {
   if (st->status != kRunning) return;
   const double inv = 1.0 / st->beta;
-  for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads) {
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
     const T v = (T)(r[p] * inv);
     if (d0) d0[p] = v;
     if (d1) d1[p] = v;
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(kThreads) void scale_kernel(const double *r, T *d0,
 // Jacobi scaling of a solve: bs = D^{-1/2} b and y = D^{1/2} x in place (dis = D^{-1/2}).
 __global__ __launch_bounds__(kThreads) void jacobi_in_kernel(const double *b, const double *dis,
                                                              double *bs, double *x, int n) {
-  for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads) {
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads) {
     bs[p] = b[p] * dis[p];
     x[p] = x[p] / dis[p];
   }
@@ -567,21 +567,22 @@ __global__ __launch_bounds__(kThreads) void jacobi_in_kernel(const double *b, co
 
 // Back to the caller's variables: x = D^{-1/2} y in place.
 __global__ __launch_bounds__(kThreads) void jacobi_out_kernel(double *x, const double *dis, int n) {
-  for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads)
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads)
     x[p] = x[p] * dis[p];
 }
 
 // x += d: the FP32 correction of one refinement step added to the FP64 iterate.
 __global__ __launch_bounds__(kThreads) void add_correction_kernel(double *x, const float *d, int n) {
-  for (int p = blockIdx.x * kThreads + threadIdx.x; p < n; p += gridDim.x * kThreads)
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kThreads)
     x[p] += (double)d[p];
 }
 
 template <int K>
 __global__ __launch_bounds__(kThreads) void apply_kernel(const double *x, double *y, Grid g,
                                                          OpData od) {
-  for (int p = blockIdx.x * kThreads + threadIdx.x; p < g.n; p += gridDim.x * kThreads)
-    y[p] = op_at<K>(x, p, g, od);
+  for (int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x; p < g.n;
+       p += (int64_t)gridDim.x * kThreads)
+    y[p] = op_at<K>(x, (int)p, g, od);
 }
 
 __global__ __launch_bounds__(kThreads) void copy_kernel(const double *src, double *dst, int64_t n) {
