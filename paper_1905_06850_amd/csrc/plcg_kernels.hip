@@ -381,6 +381,37 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
   double acc[1] = {0.0};
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
     const int idx0 = it.c * kChunk + threadIdx.x * kVec;
+    if (a.od.ell_k > 0 && idx0 + 1 < a.n) {
+      // ELL: the thread's two rows' j-th entries with one 16-byte value access
+      // and one 8-byte index access (consecutive lanes, consecutive rows)
+      Vals<2> rr;
+      rr.load(a.r + idx0);
+      double c0 = rr.v[0], c1 = rr.v[1];
+      if (!first) {
+        Vals<2> po;
+        po.load(a.p_old + idx0);
+        c0 += beta * po.v[0];
+        c1 += beta * po.v[1];
+      }
+      double q0 = 0.0, q1 = 0.0;
+      for (int j = 0; j < a.od.ell_k; ++j) {
+        const size_t e = (size_t)j * a.od.ell_ld + idx0;
+        Vals<2> vv;
+        vv.load(a.od.va + e);
+        const int2 cc = *reinterpret_cast<const int2 *>(a.od.ci + e);
+        q0 += vv.v[0] * pk1(cc.x);
+        q1 += vv.v[1] * pk1(cc.y);
+      }
+      Vals<2> pn, qv;
+      pn.v[0] = c0;
+      pn.v[1] = c1;
+      qv.v[0] = q0;
+      qv.v[1] = q1;
+      pn.store(a.p_new + idx0);
+      qv.store(a.q + idx0);
+      acc[0] += c0 * q0 + c1 * q1;
+      continue;
+    }
 #pragma unroll
     for (int v = 0; v < kVec; ++v) {
       const int p = idx0 + v;
