@@ -331,7 +331,11 @@ typedef struct {
  * footprint), enqueues ticks_per_round launches, retires finished solves, and
  * repeats until every request is done or time_limit_s has passed.  Request k
  * solves with operator op_ids[system] and right-hand side d_b[system] (device,
- * shared, read only), x0 = 0.  Timings and results go to out[k]. */
+ * shared, read only), x0 = 0; the solution stays inside the batch (this loop
+ * measures service, it does not hand solutions back).  Timings and results go
+ * to out[k].  Solves still running when the time limit passes keep their slots
+ * until the batch is destroyed.  PLCG_E_INVALID for unsorted arrivals, an
+ * unknown system or a request that does not fit an empty batch. */
 plcg_status plcg_serve(plcg_batch *b, const int32_t *op_ids, const double *const *d_b,
                        int32_t nops, const plcg_request *reqs, int32_t nreq,
                        int32_t ticks_per_round, double time_limit_s, void *stream,

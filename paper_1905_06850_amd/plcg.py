@@ -32,6 +32,12 @@ PLCG_METHOD_PLCG = 1
 PLCG_PREC_FP64 = 0
 PLCG_PREC_FP32_REFINED = 1
 
+PLCG_REASON_NONE = 0
+PLCG_REASON_CONVERGED = 1
+PLCG_REASON_MAXIT = 2
+PLCG_REASON_BREAKDOWN_LIMIT = 3
+PLCG_REASON_NONFINITE = 4
+PLCG_REASON_BREAKDOWN = 5
 REASONS = {0: "none", 1: "converged", 2: "maxit", 3: "breakdown_limit", 4: "nonfinite",
            5: "breakdown"}
 
