@@ -37,5 +37,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+C_EXAMPLE = os.path.join(ROOT, "tests", "c", "solve_file.c")
+C_EXAMPLE_BIN = os.path.join(ROOT, "tests", "c", "solve_file")
+
+
+def build_c_caller(verbose: bool = False) -> str:
+    """The plain C caller used by the tests (host code only, linked to libplcg.so)."""
+    cmd = [HIPCC, "-x", "hip", *[f for f in FLAGS if f not in ("-fPIC", "-shared")], C_EXAMPLE,
+           "-o", C_EXAMPLE_BIN + ".tmp", "-L", HERE, "-lplcg",
+           "-Wl,-rpath,$ORIGIN/../../" + os.path.basename(HERE)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    proc = subprocess.run(cmd, capture_output=True, text=True)
+    if proc.returncode != 0:
+        sys.stderr.write(proc.stdout + proc.stderr)
+        raise RuntimeError("hipcc failed building the C caller")
+    os.replace(C_EXAMPLE_BIN + ".tmp", C_EXAMPLE_BIN)
+    return C_EXAMPLE_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_c_caller(verbose=True))
