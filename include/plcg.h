@@ -71,7 +71,8 @@ enum { PLCG_METHOD_CG = 0, PLCG_METHOD_PLCG = 1 };
 /* Arithmetic of p(l)-CG.  FP32_REFINED: iterative refinement in FP64 around an
  * inner p(l)-CG whose vectors (bases, p, correction) are stored in FP32 and whose
  * dot products, G, T and LU scalars are FP64; each refinement step recomputes
- * r = b - A x in FP64, solves A d = r to inner_tol, and adds x += d in FP64. */
+ * r_k = b - A x in FP64, solves A d = r_k to |zeta| < max(inner_tol ||r_k||,
+ * tol ||r_0|| / 2), and adds x += d in FP64, until ||r_k|| < tol ||r_0||. */
 enum { PLCG_PREC_FP64 = 0, PLCG_PREC_FP32_REFINED = 1 };
 
 enum {

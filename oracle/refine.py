@@ -7,8 +7,10 @@ products, G, T and the LU scalars stay in FP64 (values read from FP32 storage
 are exact in FP64).  The outer loop is classical iterative refinement in FP64:
 
     r_k = b - A x_k  (FP64);  stop when ||r_k|| < tol ||r_0||
-    solve A d = r_k with the inner solver from d = 0 to |zeta_t| < inner_tol ||r_k||
-    (an inner breakdown ends that inner solve with its last iterate)
+    solve A d = r_k with the inner solver from d = 0 to
+        |zeta_t| < max(inner_tol ||r_k||, final_factor tol ||r_0||)
+    (the last correction need not be more accurate than the outer goal; an inner
+    breakdown ends that inner solve with its last iterate)
     x_{k+1} = x_k + d  (FP64)
 
 The recursive residual of an FP32-stored solve drifts away from the true one
@@ -42,7 +44,9 @@ class RefineResult:
     inner: list = field(default_factory=list)
 
 
-def refine(A, b, x0, l, sigma, tol, inner_tol, maxit, max_outer=50) -> RefineResult:
+def refine(A, b, x0, l, sigma, tol, inner_tol, maxit, max_outer=50,
+           final_factor=0.5) -> RefineResult:
+    """final_factor None: every inner solve runs to inner_tol ||r_k||."""
     x = x0.copy()
     r = b - A(x)
     rnorm0 = math.sqrt(np.dot(r, r))
@@ -57,7 +61,10 @@ def refine(A, b, x0, l, sigma, tol, inner_tol, maxit, max_outer=50) -> RefineRes
             break
         if outer >= max_outer or total >= maxit:
             break
-        seg = _plcg.alg1(A, r, np.zeros_like(x), l, sigma, inner_tol * rn, maxit - total,
+        abs_tol = inner_tol * rn
+        if final_factor is not None:
+            abs_tol = max(abs_tol, final_factor * tol * rnorm0)
+        seg = _plcg.alg1(A, r, np.zeros_like(x), l, sigma, abs_tol, maxit - total,
                          store=round_fp32)
         inner.append((seg.t_done, seg.reason))
         total += seg.t_done

@@ -139,9 +139,11 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
         }
         d.beta = beta;
         // FP64: Alg. 1 stops at tol ||r~_0||.  FP32-refined: the inner solve
-        // stops at inner_tol ||r_k||; the refinement at tol ||r~_0||.
+        // stops at max(inner_tol ||r_k||, tol ||r~_0|| / 2) (the last correction
+        // need not be more accurate than the outer goal); the refinement at
+        // tol ||r~_0||.
         const double outer_tol = S.tol * d.rref;
-        d.abs_tol = S.mixed ? S.inner_tol * beta : outer_tol;
+        d.abs_tol = S.mixed ? fmax(S.inner_tol * beta, 0.5 * outer_tol) : outer_tol;
         d.cols = 0;
         d.last_t = -1;
         for (int c = 0; c < kGRing; ++c)

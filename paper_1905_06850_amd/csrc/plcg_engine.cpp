@@ -270,10 +270,11 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
 // launch_start.
 plcg_status residual(plcg_handle *h, const double *b, const double *x, double *r, int slot,
                      int mode, double tol, double rref_in, hipStream_t s,
-                     const double *wdiv = nullptr) {
+                     const double *wdiv = nullptr, double abs_floor = 0.0) {
   PLCG_HIP(launch_residual(b, x, r, h->part[0], h->n, h->op.nx, h->op.ny, h->op.nz, h->d3,
                            h->od, wdiv, h->nchunks, h->blocks, s));
-  PLCG_HIP(launch_start(h->part[0], h->blocks, h->st[slot], h->hs_dev, mode, tol, rref_in, s));
+  PLCG_HIP(launch_start(h->part[0], h->blocks, h->st[slot], h->hs_dev, mode, tol, rref_in,
+                        abs_floor, s));
   return PLCG_OK;
 }
 
@@ -337,8 +338,13 @@ plcg_status solve_mixed(plcg_handle *h, const double *b, double *x, double tol, 
   plcg_status e;
   *final_slot = 1;
   while (true) {
-    // r = b - A x in FP64; the inner solve starts from z_0 = r / ||r|| (FP32).
-    if ((e = residual(h, b, x, h->r64, 1, 0, h->inner_tol, -1.0, s)) != PLCG_OK) return e;
+    // r = b - A x in FP64; the inner solve starts from z_0 = r / ||r|| (FP32) and
+    // stops at max(inner_tol ||r||, tol ||r_0|| / 2): the last correction need
+    // not be more accurate than the outer goal.
+    const double floor_abs = rref > 0 ? 0.5 * tol * rref : 0.0;
+    if ((e = residual(h, b, x, h->r64, 1, 0, h->inner_tol, -1.0, s, nullptr, floor_abs)) !=
+        PLCG_OK)
+      return e;
     PLCG_HIP(launch_scale(h->r64, h->ring32[0], h->basis32[0][0], (float *)nullptr, h->st[1], h->n,
                           s));
     PLCG_HIP(hipMemsetAsync(h->d32, 0, sizeof(float) * (size_t)h->n, s));

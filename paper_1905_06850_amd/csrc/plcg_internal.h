@@ -126,8 +126,9 @@ hipError_t launch_jacobi_in(const double *b, const double *dis, double *bs, doub
 hipError_t launch_jacobi_out(double *x, const double *dis, int n, hipStream_t s);
 // One block: sum the residual partials and start a segment in *st:
 // mode 0 = p(l)-CG (G, beta, status), 1 = CG (rho), 2 = only report the sum.
+// The stopping threshold is max(tol * rref, abs_floor).
 hipError_t launch_start(const double *part_in, int nparts, DevState *st, HostStatus *hs,
-                        int mode, double tol, double rref_in, hipStream_t s);
+                        int mode, double tol, double rref_in, double abs_floor, hipStream_t s);
 // z = r / beta written to up to three destinations (beta from st); no-op unless running.
 hipError_t launch_scale(const double *r, double *d0, double *d1, double *d2, const DevState *st,
                         int n, hipStream_t s);

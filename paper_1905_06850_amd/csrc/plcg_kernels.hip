@@ -537,7 +537,8 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, con
 // One workgroup: ||b - A x||^2 from the residual partials; starts a segment.
 __global__ __launch_bounds__(kThreads) void start_kernel(const double *part_in, int nparts,
                                                          DevState *st, HostStatus *hs, int mode,
-                                                         double tol, double rref_in) {
+                                                         double tol, double rref_in,
+                                                         double abs_floor) {
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
@@ -550,7 +551,7 @@ __global__ __launch_bounds__(kThreads) void start_kernel(const double *part_in, 
       const double beta = sqrt(ss);
       sh.beta = beta;
       sh.rref = rref_in > 0.0 ? rref_in : beta;
-      sh.abs_tol = tol * sh.rref;
+      sh.abs_tol = fmax(tol * sh.rref, abs_floor);
       sh.cols = 0;
       sh.last_t = 0;
       if (!isfinite(beta)) {
@@ -705,9 +706,9 @@ hipError_t launch_residual(const double *b, const double *x, double *r, double *
 }
 
 hipError_t launch_start(const double *part_in, int nparts, DevState *st, HostStatus *hs, int mode,
-                        double tol, double rref_in, hipStream_t s) {
+                        double tol, double rref_in, double abs_floor, hipStream_t s) {
   hipLaunchKernelGGL(start_kernel, dim3(1), dim3(kThreads), 0, s, part_in, nparts, st, hs, mode,
-                     tol, rref_in);
+                     tol, rref_in, abs_floor);
   return hipGetLastError();
 }
 

@@ -65,3 +65,18 @@ def test_refinement_matches_fp64_accuracy(inner_tol):
     assert rm.true_relres < 1e-10 and r64.true_relres < 1e-9
     lmin, lmax = operators.laplacian_extremes((24, 24, 24))
     assert np.linalg.norm(rm.x - r64.x) <= (lmax / lmin) * 2e-10 * np.linalg.norm(r64.x)
+
+
+def test_last_correction_is_not_oversolved():
+    """With the inner stop floored at tol ||r_0|| / 2 the refinement ends just
+    below tol instead of inner_tol times below the previous residual, in fewer
+    inner iterations; without the floor it overshoots by orders of magnitude."""
+    A, b = _problem((24, 24, 24), seed=3)
+    sig = shifts.chebyshev_shifts(3, 0, 12)
+    tol = 1e-10
+    floored = refine.refine(A, b, np.zeros(A.n), 3, sig, tol, 1e-4, 20000)
+    plain = refine.refine(A, b, np.zeros(A.n), 3, sig, tol, 1e-4, 20000, final_factor=None)
+    assert floored.reason == plain.reason == "converged"
+    assert 1e-3 * tol < floored.true_relres < tol
+    assert plain.true_relres < 0.1 * floored.true_relres
+    assert floored.inner_iters < plain.inner_iters
