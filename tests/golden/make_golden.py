@@ -108,7 +108,7 @@ def run(name):
     elif method == "mixed":
         r = refine.refine(A, b, x0, l, shifts.chebyshev_shifts(l, lo, hi), wl["tol"],
                           MIXED_INNER_TOL, 100000)
-        extra = {"outer": r.outer, "inner_tol": MIXED_INNER_TOL}
+        extra = {"outer": r.outer, "inner_tol": MIXED_INNER_TOL, "final_factor": 0.5}
         r.iters = r.inner_iters
         r.rec_relres = r.true_relres
     else:

