@@ -265,7 +265,8 @@ def serve_bench(args, plcg, torch, dev, sp):
             dims = (side, side, side)
         pool.append(dims)
     batch = plcg.Batch(l=args.batch_l, max_slots=args.serve_slots,
-                       arena_bytes=int(args.serve_arena_gb * (1 << 30)), use_graph=True)
+                       arena_bytes=int(args.serve_arena_gb * (1 << 30)), use_graph=True,
+                       precision=args.batch_precision, inner_tol=args.inner_tol)
     ops, bs = [], []
     for k, dims in enumerate(pool):
         cx, cy, cz = synth.edge_coefficients(dims, 5000 + k)
@@ -310,11 +311,16 @@ def serve_bench(args, plcg, torch, dev, sp):
         "metric": "served solves/s and p99 latency (" + METRIC + ")",
         "value": head["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": head["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None,
+        "dtype": "f64" if args.batch_precision == "fp64" else "f32-storage/f64-dots",
+        "data": "synthetic",
         "config": {"workload": "serving stream: Poisson arrivals, 70 % 2D 5-point side 64..2048, "
                                "30 % 3D 7-point side 32..256, lognormal(0,1) edge coefficients "
                                "(Jacobi-scaled), tol uniform in {1e-6, 1e-8, 1e-10}",
-                   "method": f"p({args.batch_l})-CG, continuous batching, admission by HBM footprint",
+                   "method": (f"p({args.batch_l})-CG" if args.batch_precision == "fp64" else
+                              f"FP32-stored p({args.batch_l})-CG in FP64 refinement (inner tol "
+                              f"{args.inner_tol:g})")
+                             + ", continuous batching, admission by HBM footprint",
                    "pool": [list(d) for d in pool], "slots": args.serve_slots,
                    "arena_gb": args.serve_arena_gb, "runs": results},
     }
