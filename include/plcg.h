@@ -147,7 +147,8 @@ typedef struct {
 } plcg_result;
 
 /* Create a solver for one operator and one configuration.
- * Validates the descriptor (extents >= 1, nx*ny*nz < 2^31) and the config
+ * Validates the descriptor (extents >= 1, n = nx*ny*nz <= 2^31 - 2^23; the
+ * diagonal or CSR arrays as described at plcg_operator_desc) and the config
  * (l in 1..8, lambda_min < lambda_max unless explicit shifts are given),
  * computes the shifts (Eq. chebyshev, i = 0..l-1, so sigma_0 is the largest)
  * and allocates all device workspace on the current HIP device.
@@ -157,7 +158,8 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg,
 
 /* Solve A x = b.  d_b: n doubles (read only).  d_x: n doubles, holds x0 on entry
  * and the final iterate on return.  Stops when the recursive residual norm
- * |zeta_t| (Alg. 1) falls below tol * ||b - A x0||, after maxit x-updates, or
+ * |zeta_t| (Alg. 1; CG: its recursive ||r_k||) falls below tol * ||b - A x0||
+ * (Jacobi-scaled CSR: both norms of the scaled system), after maxit x-updates, or
  * after max_restarts explicit restarts (restart = Alg. 1 from the latest
  * iterate).  In FP32_REFINED mode the test is on the FP64 residual recomputed
  * at every refinement step, and maxit bounds the inner x-updates.  Blocks the
