@@ -41,6 +41,8 @@ class CGResult:
 
 
 def cg(A, b, x0, tol, maxit, record_iterates=False) -> CGResult:
+    """Classic CG (Sec. 1; Table 1, row CG) from x0, at most maxit x updates, stopping
+    when the recursive ||r_k|| < tol ||r_0||; the recurrence in the module docstring."""
     x = x0.copy()
     r = b - A(x)
     spmvs = 1

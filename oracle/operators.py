@@ -30,7 +30,9 @@ def _neighbour_sum(U: np.ndarray) -> np.ndarray:
 
 
 def laplacian(dims):
-    """Return ``A(u)`` for the Dirichlet Laplacian on a grid of shape ``dims``.
+    """Return ``A(u)`` for the Dirichlet Laplacian on a grid of shape ``dims``: the
+    finite-difference test problems of Sec. 4.2 (2D 5-point) and its 3D 7-point
+    counterpart, unscaled.
 
     ``dims`` is (nx, ny) for the 5-point stencil or (nx, ny, nz) for the 7-point
     stencil; the operator acts on flat vectors of length prod(dims).
@@ -67,7 +69,8 @@ def diagonal(d):
 
 
 def csr(rowptr, colind, vals):
-    """A sparse matrix given in compressed sparse rows, applied with scipy."""
+    """A sparse matrix given in compressed sparse rows, applied with scipy (the
+    assembled matrices of the paper's PETSc runs, Sec. 4)."""
     import scipy.sparse as sp
     n = len(rowptr) - 1
     M = sp.csr_matrix((np.asarray(vals, float), np.asarray(colind), np.asarray(rowptr)),
@@ -124,7 +127,9 @@ def laplacian_extremes(dims):
 
 
 def variable_laplacian(dims, cx, cy, cz=None):
-    """Variable-coefficient Dirichlet Laplacian and its Jacobi scaling.
+    """Variable-coefficient Dirichlet Laplacian and its Jacobi scaling (the
+    operator of the batched workloads; scaling = Alg. 1 with M = diag(A) in its
+    symmetric form, Sec. 2.2 on preconditioning).
 
     (A u)_p = sum over the grid edges (p, q) incident to p of c_pq (u_p - u_q),
     with u = 0 outside the grid, so the diagonal d_p is the sum of all edges at

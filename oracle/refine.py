@@ -46,7 +46,9 @@ class RefineResult:
 
 def refine(A, b, x0, l, sigma, tol, inner_tol, maxit, max_outer=50,
            final_factor=0.5) -> RefineResult:
-    """final_factor None: every inner solve runs to inner_tol ||r_k||."""
+    """FP64 iterative refinement around FP32-stored Alg. 1 (module docstring; the
+    residual gap it repairs is the one of Sec. 2.2, 'Residual norm').
+    final_factor None: every inner solve runs to inner_tol ||r_k||."""
     x = x0.copy()
     r = b - A(x)
     rnorm0 = math.sqrt(np.dot(r, r))

@@ -14,6 +14,7 @@ import math
 
 
 def chebyshev_shifts(l: int, lmin: float, lmax: float) -> list:
+    """sigma_0 .. sigma_{l-1} of Eq. (chebyshev), Sec. 2.2, on [lmin, lmax]."""
     if l < 1:
         raise ValueError("pipeline length l must be >= 1")
     mid = 0.5 * (lmax + lmin)
