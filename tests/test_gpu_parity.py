@@ -117,6 +117,21 @@ def test_solve_parity_64_manufactured(dev, method, l):
 
 
 # (32, 48, 5) and (64, 160, 6): planes of whole chunks, visited by column tiles
+@pytest.mark.parametrize("l", [6, 7, 8])
+def test_deep_pipelines_solve_parity(dev, l):
+    """The deepest pipelines the library offers, solved through at 64^2."""
+    dims = (64, 64)
+    A = operators.laplacian(dims)
+    b = A(synth.uniform(A.n, 0))
+    x0 = np.zeros(A.n)
+    ref = oracle_solve(dims, "plcg", l, b, x0, 1e-8, 5000)
+    x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, 1e-8, 5000)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.iters - ref.iters) <= 1 and res.restarts == ref.restarts == 0
+    assert _rel(x, ref.x) < 1e-8
+    s.close()
+
+
 @pytest.mark.parametrize("dims", [(100, 37), (37, 100), (1, 700), (700, 1), (20, 13, 7),
                                   (5, 9, 11), (1, 1, 600), (32, 48, 5), (64, 160, 6),
                                   (102, 30)])
@@ -386,7 +401,9 @@ def _mixed_oracle(dims, l, b, tol, inner_tol, maxit=20000, max_outer=50):
                                                   ((64, 64), 1, 1e-10, 1e-3),
                                                   ((100, 37), 2, 1e-10, 1e-4),
                                                   ((102, 30), 2, 1e-10, 1e-4),
-                                                  ((64, 160, 6), 3, 1e-10, 1e-4)])
+                                                  ((64, 160, 6), 3, 1e-10, 1e-4),
+                                                  ((60, 50), 4, 1e-10, 1e-4),
+                                                  ((60, 50), 5, 1e-10, 1e-4)])
 def test_mixed_precision_against_oracle(dev, dims, l, tol, inner_tol):
     """FP32-stored inner p(l)-CG inside FP64 refinement against the oracle's
     model of the same arithmetic (oracle.refine): both reach the FP64 tolerance,
