@@ -481,6 +481,7 @@ def main():
             "kernel_GBps": (bytes_iter / kernels_per_iter) / (kernel_us * 1e-6) / 1e9
             if method != "cg" else None,
             "spmvs": r.spmvs,
+            "spmvs_per_s": r.spmvs * args.steps / dt,   # p(l)-CG adds l fill/drain SpMVs
             "outer": r.outer,
             "host_waits": r.host_waits,
             "launches_per_iter": kernels_per_iter,
