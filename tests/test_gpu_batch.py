@@ -92,7 +92,7 @@ SYSTEMS = [((40, 40), 1, 2), ((57, 33), 3, 4), ((96, 96), 5, 6), ((12, 10, 9), 7
            ((130, 70), 9, 10), ((20, 20, 20), 11, 12), ((6, 11), 13, 14), ((1, 200), 15, 16)]
 
 
-@pytest.mark.parametrize("l", [2, 3])
+@pytest.mark.parametrize("l", [2, 3, 4, 5])
 def test_batch_against_oracle(dev, l):
     systems = [_system(*s) for s in SYSTEMS]
     res = run_batch(dev, systems, l, 1e-8)
