@@ -207,8 +207,35 @@ def _dims_desc(kind, dims, diag=None, csr=None, jacobi=False):
     raise ValueError(f"unknown operator kind {kind!r}")
 
 
+def _vec(v, n, name):
+    """A device address from an int, or from a contiguous float64 GPU tensor of n
+    elements (anything with data_ptr(), dtype, is_cuda, numel, is_contiguous)."""
+    if v is None or isinstance(v, int):
+        return v
+    if not hasattr(v, "data_ptr"):
+        raise TypeError(f"{name}: expected a device address or a tensor")
+    if str(v.dtype) != "torch.float64" or not v.is_cuda or not v.is_contiguous():
+        raise ValueError(f"{name}: needs a contiguous float64 tensor on the GPU")
+    if n is not None and v.numel() != n:
+        raise ValueError(f"{name}: has {v.numel()} elements, the operator has {n}")
+    return v.data_ptr()
+
+
+def _stream(stream):
+    """None: torch's current stream on the current device (0 if torch is absent)."""
+    if stream is not None:
+        return stream
+    try:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        return 0
+
+
 class Solver:
-    """Convenience owner of one plcg_handle."""
+    """Convenience owner of one plcg_handle.  b and x may be given as device
+    addresses or as contiguous float64 GPU tensors; stream None means torch's
+    current stream."""
 
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
                  check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
@@ -234,17 +261,18 @@ class Solver:
                           ctypes.byref(self.handle)), "plcg_create")
         self.n = plcg_size(self.handle)
 
-    def solve(self, b_ptr, x_ptr, tol, maxit, stream=0):
+    def solve(self, b, x, tol, maxit, stream=None):
         res = plcg_result()
-        st = plcg_solve(self.handle, b_ptr, x_ptr, float(tol), int(maxit), stream,
-                        ctypes.byref(res))
+        st = plcg_solve(self.handle, _vec(b, self.n, "b"), _vec(x, self.n, "x"), float(tol),
+                        int(maxit), _stream(stream), ctypes.byref(res))
         check(st, "plcg_solve")
         return res
 
-    def submit(self, b_ptr, x_ptr, tol, maxit, stream=0):
+    def submit(self, b, x, tol, maxit, stream=None):
+        """b and x must stay alive until poll() returns a result."""
         t = ctypes.c_uint64(0)
-        check(plcg_submit(self.handle, b_ptr, x_ptr, float(tol), int(maxit), stream,
-                          ctypes.byref(t)), "plcg_submit")
+        check(plcg_submit(self.handle, _vec(b, self.n, "b"), _vec(x, self.n, "x"), float(tol),
+                          int(maxit), _stream(stream), ctypes.byref(t)), "plcg_submit")
         return t.value
 
     def poll(self, ticket):
@@ -255,8 +283,9 @@ class Solver:
         check(st, "plcg_poll")
         return res
 
-    def apply(self, x_ptr, y_ptr, stream=0):
-        check(plcg_apply(self.handle, x_ptr, y_ptr, stream), "plcg_apply")
+    def apply(self, x, y, stream=None):
+        check(plcg_apply(self.handle, _vec(x, self.n, "x"), _vec(y, self.n, "y"),
+                         _stream(stream)), "plcg_apply")
 
     def shifts(self):
         out = (ctypes.c_double * max(self.l, 1))()

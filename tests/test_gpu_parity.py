@@ -462,3 +462,24 @@ def test_full_size_mixed_against_stored_oracle(dev):
     est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
     assert est <= (lmax / lmin) * 2 * g["tol"]
     s.close()
+
+
+def test_tensor_arguments(dev):
+    """The binding also takes GPU tensors (and torch's current stream by default):
+    same result as with device addresses; wrong dtype, device or length refused
+    before any call into the library."""
+    plcg = _plcg()
+    dims = (64, 64)
+    b = synth.uniform(4096, 7)
+    s = plcg.Solver("2d5", dims, method="plcg", l=2)
+    bt = torch.from_numpy(b).to(dev)
+    x1 = torch.zeros(4096, dtype=torch.float64, device=dev)
+    x2 = torch.zeros(4096, dtype=torch.float64, device=dev)
+    r1 = s.solve(bt, x1, 1e-8, 5000)
+    r2 = s.solve(bt.data_ptr(), x2.data_ptr(), 1e-8, 5000,
+                 torch.cuda.current_stream(dev).cuda_stream)
+    assert r1.iters == r2.iters and torch.equal(x1, x2)
+    for bad in (bt.float(), bt.cpu(), bt[:100], bt[::2]):
+        with pytest.raises(ValueError):
+            s.solve(bad, x1, 1e-8, 10)
+    s.close()
