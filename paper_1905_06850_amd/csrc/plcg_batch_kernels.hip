@@ -50,11 +50,73 @@ struct VarOp {
     }
     return (double)u[p] - s;
   }
+  // FAST (a full chunk, nx a multiple of V): the thread's V unknowns share a
+  // row; x-neighbours come from its own values and the adjacent lanes, the rows
+  // and planes above and below and the y/z edge weights with 16-byte accesses.
+  // The terms are added in the order of at(), so both forms give the same bits.
   template <int V, bool FAST, typename S>
   __device__ inline void apply(const S *z, int idx, const Vals<V, S> &zc,
                                double (&w)[V]) const {
+    if constexpr (FAST && V >= 2) {
+      const int x = idx % nx;
+      const int rest = idx / nx;
+      const int y = d3 ? rest % ny : rest;
+      const int zz = d3 ? rest / ny : 0;
+      const int plane = nx * ny;
+      const int lane = threadIdx.x & 63;
+      double left = __shfl_up(zc.v[V - 1], 1, 64);    // z[idx-1] held by the previous lane
+      double right = __shfl_down(zc.v[0], 1, 64);     // z[idx+V] held by the next lane
+      if (lane == 0 && x > 0) left = (double)z[idx - 1];
+      if (lane == 63 && x + V < nx) right = (double)z[idx + V];
+      const int xe = rest * (nx + 1) + x;             // edge left of idx in its row
+      const int ye = idx + zz * nx;                   // edge below idx in its column
+      // one neighbour direction at a time (few values live at once); each
+      // unknown's sum still takes its terms in the order of at()
+      double s[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) w[v] = at(z, idx + v);
+      for (int k = 0; k < V; ++k) {
+        s[k] = 0.0;
+        if (x + k > 0) s[k] += sx[xe + k] * (k > 0 ? zc.v[k - 1] : left);
+        if (x + k < nx - 1) s[k] += sx[xe + k + 1] * (k < V - 1 ? zc.v[k + 1] : right);
+      }
+      if (y > 0) {
+        Vals<V, S> u;
+        Vals<V, double> c;
+        u.load(z + idx - nx);
+        c.load(sy + ye);
+#pragma unroll
+        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
+      }
+      if (y < ny - 1) {
+        Vals<V, S> u;
+        Vals<V, double> c;
+        u.load(z + idx + nx);
+        c.load(sy + ye + nx);
+#pragma unroll
+        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
+      }
+      if (d3 && zz > 0) {
+        Vals<V, S> u;
+        Vals<V, double> c;
+        u.load(z + idx - plane);
+        c.load(sz + idx);
+#pragma unroll
+        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
+      }
+      if (d3 && zz < nz - 1) {
+        Vals<V, S> u;
+        Vals<V, double> c;
+        u.load(z + idx + plane);
+        c.load(sz + idx + plane);
+#pragma unroll
+        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
+      }
+#pragma unroll
+      for (int k = 0; k < V; ++k) w[k] = zc.v[k] - s[k];
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) w[v] = at(z, idx + v);
+    }
   }
 };
 
@@ -293,7 +355,16 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
     SweepArgsT<ST> sa;
     slot_sweep_args<L, ST>(S, i, sa);
     using SW = Sweep<L, ST, VarOp>;
-    for (int idx = start; idx < S.n; idx += step) SW::template chunk<V, false>(sa, op, idx, t, cf, acc);
+    // Chunk by chunk so that the FAST test is uniform over the workgroup.
+    constexpr int CH = kThreads * V;
+    const bool fast_rows = S.nx % V == 0;
+    for (int base = lb * CH; base < S.n; base += step) {
+      const int idx = base + threadIdx.x * V;
+      if (fast_rows && base + CH <= S.n)
+        SW::template chunk<V, true>(sa, op, idx, t, cf, acc);
+      else
+        SW::template chunk<V, false>(sa, op, idx, t, cf, acc);
+    }
     store_partials<ND>(acc, part_out, kMaxStream, lb, lds, red);
     return;
   }
