@@ -53,7 +53,7 @@ struct VarOp {
   // FAST (a full chunk, nx a multiple of V): the thread's V unknowns share a
   // row; x-neighbours come from its own values and the adjacent lanes, the rows
   // and planes above and below and the y/z edge weights with 16-byte accesses.
-  // The terms are added in the order of at(), so both forms give the same bits.
+  // Each unknown's terms are added in the order of at().
   template <int V, bool FAST, typename S>
   __device__ inline void apply(const S *z, int idx, const Vals<V, S> &zc,
                                double (&w)[V]) const {
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
         const double ro = r / S.dis[p];       // D^{1/2} r~ = b - A x
         acc[1] += ro * ro;
       } else if (phase == kScale) {
-        // z_0 = r / ||r||; the FP32 path recomputes r in FP64 (same bits as
+        // z_0 = r / ||r||; the FP32 path recomputes r in FP64 (the same expression as
         // kResid) instead of keeping an FP64 copy, and clears the correction.
         const double r = kMixed ? S.dis[p] * S.b[p] - op.at(S.x, p) : (double)r0[p];
         const ST z = (ST)(r * inv_beta);

@@ -413,7 +413,7 @@ struct DiagOp {
 // copy instead (entry j of row p at j * ell_ld + p): consecutive rows are then
 // read by consecutive lanes, one coalesced access per entry index for the V
 // rows of a thread.  Both forms add the same products in the same order
-// (padding adds exact zeros), so their results are identical.
+// (padding adds exact zeros).
 template <typename S>
 struct CsrOp {
   const int64_t *rp;
