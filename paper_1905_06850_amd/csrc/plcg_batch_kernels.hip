@@ -322,7 +322,10 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
   __shared__ double lds[4 * ND];
   __shared__ double red[ND];
   __shared__ BatchState sh;
-  const int2 e = a.sched[blockIdx.x];
+  // Odd ticks dispatch the schedule back to front, so a tick starts on the
+  // systems the previous tick touched last (still in the memory-side cache).
+  // A workgroup's share of the work is the same either way.
+  const int2 e = a.sched[(a.tick & 1) ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
   const int slot = e.x;
   const int lb = e.y;
   const SlotDesc &S = a.slots[slot];

@@ -13,18 +13,24 @@ namespace plcg {
 
 struct ChunkIter {
   int c, end, step;
+  int flip;   // >= 0: positions are mirrored inside the band, at() = flip - c
+  __device__ inline int at() const { return flip >= 0 ? flip - c : c; }
 };
 
 // Streaming workgroups are blockIdx.x = first .. first + nstream - 1 (first is 0
 // or 1, nstream a multiple of 8); workgroup b sits on XCD b % 8 and takes band
-// b % 8 of the chunks.
-__device__ inline ChunkIter xcd_chunks(int nchunks, int nstream, int first) {
+// b % 8 of the chunks.  The workgroups of a band move through it together, so
+// a sweep touches each band front to back; with rev the band is walked back to
+// front.  Alternating the two from one sweep to the next starts every sweep on
+// the data the previous one touched last, which is what the 256 MB memory-side
+// cache still holds when a solve's vectors only just outgrow it.
+__device__ inline ChunkIter xcd_chunks(int nchunks, int nstream, int first, bool rev = false) {
   const int band = blockIdx.x % kXcds;
   const int lb = (blockIdx.x - first) / kXcds;
   const int nlb = nstream / kXcds;
   const int lo = (int)(((long long)band * nchunks) / kXcds);
   const int hi = (int)(((long long)(band + 1) * nchunks) / kXcds);
-  return ChunkIter{lo + lb, hi, nlb};
+  return ChunkIter{lo + lb, hi, nlb, rev ? lo + hi - 1 : -1};
 }
 
 struct Grid {

@@ -81,8 +81,9 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
 #pragma unroll
   for (int m = 0; m < ND; ++m) acc[m] = 0.0;
   const int first = L == 1 ? 0 : 1;
-  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, first); it.c < it.end; it.c += it.step) {
-    const int base = order.phys(it.c) * CH;
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, first, (i & 1) != 0); it.c < it.end;
+       it.c += it.step) {
+    const int base = order.phys(it.at()) * CH;
     const int idx = base + threadIdx.x * V;
     if (fast_rows && base + CH <= a.n)
       S::template chunk<V, true>(a, op, idx, t, cf, acc);
@@ -464,8 +465,9 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
 
   const double alpha = sh.cg_alpha;
   double acc[1] = {0.0};
-  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
-    const int idx = it.c * kChunk + threadIdx.x * kVec;
+  // Sweep A walks the bands front to back, sweep B back to front.
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0, true); it.c < it.end; it.c += it.step) {
+    const int idx = it.at() * kChunk + threadIdx.x * kVec;
     if (idx + 1 < a.n) {
       Vals<2> x, p, r, q;
       x.load(a.x + idx);
