@@ -113,6 +113,11 @@ def measured_traffic(workload: str, kernel: str):
     return float(v) if v is not None else None
 
 
+def hr_launch(rows, head_method):
+    head = {"plcg": "p", "mixed": "m", "cg": "cg"}[head_method[0]]
+    return rows.get(head + (str(head_method[1]) if head != "cg" else ""), {}).get("launch")
+
+
 def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None, csr=None):
     import torch
     n = b.numel()
@@ -339,6 +344,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-3,
                     help="inner tolerance of the FP32-refined methods (m<l>)")
     ap.add_argument("--cpu-iters", type=int, default=250)
+    ap.add_argument("--launch", choices=("auto", "streaming", "resident"), default="auto",
+                    help="single-system launch mode (resident: one workgroup, small systems)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -437,9 +444,13 @@ def main():
     rows = {}
     for method, l in methods:
         name = {"cg": "cg", "plcg": f"p{l}", "mixed": f"m{l}"}[method]
+        launch = args.launch
+        if launch == "resident" and (method == "mixed" or not plcg.resident_supported(
+                kind, n, "cg" if method == "cg" else "plcg", max(l, 1))):
+            launch = "auto"
         s = plcg.Solver(kind, dims, method="cg" if method == "cg" else "plcg", l=max(l, 1),
                         lmin=lo, lmax=hi, precision="fp32" if method == "mixed" else "fp64",
-                        inner_tol=args.inner_tol, diag=dptr, csr=csr_arg)
+                        inner_tol=args.inner_tol, diag=dptr, csr=csr_arg, launch=launch)
         for _ in range(args.warmup):
             x.zero_()
             s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
@@ -470,6 +481,7 @@ def main():
         bytes_iter = passes * (4 if method == "mixed" else 8) * n + op_bytes
         kernel_us = 1e3 * rt.sweep_ms / max(rt.sweeps, 1)
         kernels_per_iter = 2 if method == "cg" else 1
+        resident = r.launch_mode == plcg.PLCG_LAUNCH_RESIDENT
         rows[name] = {
             "iters": r.iters, "reason": plcg.REASONS[r.reason], "restarts": r.restarts,
             "true_relres": r.true_relres, "rec_relres": r.rec_relres,
@@ -484,7 +496,10 @@ def main():
             "spmvs_per_s": r.spmvs * args.steps / dt,   # p(l)-CG adds l fill/drain SpMVs
             "outer": r.outer,
             "host_waits": r.host_waits,
-            "launches_per_iter": kernels_per_iter,
+            "launch": "resident" if resident else "streaming",
+            # a resident solve is one launch per restart segment
+            "launches_per_iter": ((1 + r.restarts) / max(r.iters, 1)) if resident
+            else kernels_per_iter,
             "solves_per_s": args.steps / dt,
         }
         if not args.quiet:
@@ -493,7 +508,9 @@ def main():
     opname = {"2d5": "2D 5-point Dirichlet Poisson", "3d7": "3D 7-point Dirichlet Poisson",
               "diag": "diagonal one-point-stencil toy with the 2D Laplacian's spectrum on",
               "csr": "2D 5-point Dirichlet Poisson assembled in CSR,"}[kind]
-    if kind == "diag":
+    if hr_launch(rows, head_method) == "resident":
+        kname = f"plcg_resident_kernel<{head_method[1]},"
+    elif kind == "diag":
         kname = f"plcg_diag_sweep_kernel<{head_method[1]},"
     elif kind == "csr":
         kname = f"plcg_csr_sweep_kernel<{head_method[1]},"

@@ -75,6 +75,21 @@ enum { PLCG_METHOD_CG = 0, PLCG_METHOD_PLCG = 1 };
  * tol ||r_0|| / 2), and adds x += d in FP64, until ||r_k|| < tol ||r_0||. */
 enum { PLCG_PREC_FP64 = 0, PLCG_PREC_FP32_REFINED = 1 };
 
+/* How the iterations are launched.
+ * STREAMING: one launch per iteration of Alg. 1 (two per CG iteration) over as
+ *   many workgroups as the system fills; the products of each iteration are
+ *   reduced across workgroups by a later launch (Sec. 3.1 overlap).
+ * RESIDENT: a whole run of Alg. 1 (or all of CG) in one launch of one
+ *   1024-thread workgroup that keeps the vectors in registers and reduces inside
+ *   the workgroup - for small systems, whose iterations would otherwise be
+ *   dominated by launch and device-wide reduction latency.  Available for FP64
+ *   with n <= PLCG_RESIDENT_MAX unknowns and, for p(l)-CG, the pipeline lengths
+ *   that fit the registers (PLCG_E_INVALID at create otherwise; see
+ *   plcg_resident_supported).
+ * AUTO (default): RESIDENT where it is available, else STREAMING. */
+enum { PLCG_LAUNCH_AUTO = 0, PLCG_LAUNCH_STREAMING = 1, PLCG_LAUNCH_RESIDENT = 2 };
+#define PLCG_RESIDENT_MAX 4800
+
 enum {
   PLCG_REASON_NONE = 0,
   PLCG_REASON_CONVERGED = 1,        /* recursive residual below tol            */
@@ -125,6 +140,7 @@ typedef struct {
   int32_t precision;      /* PLCG_PREC_*; FP32_REFINED needs method PLCG */
   double inner_tol;       /* FP32_REFINED: relative tolerance of each inner solve, in (0, 1);
                              <= 0: default 1e-3 */
+  int32_t launch_mode;    /* PLCG_LAUNCH_* (0 = AUTO) */
 } plcg_config;
 
 typedef struct {
@@ -143,7 +159,10 @@ typedef struct {
   int32_t outer;          /* FP32_REFINED: refinement steps (0 otherwise) */
   int32_t host_waits;     /* plcg_solve: times the host blocked on the device (stream and
                              event synchronisations): about (iterations + l) / check_every
-                             plus a few per restart or refinement step; 0 from batches */
+                             plus a few per restart or refinement step (STREAMING), a few
+                             per restart (RESIDENT); 0 from batches */
+  int32_t launch_mode;    /* PLCG_LAUNCH_STREAMING or PLCG_LAUNCH_RESIDENT: how the
+                             iterations of this solve ran (0 from batches) */
 } plcg_result;
 
 /* Create a solver for one operator and one configuration.
@@ -202,12 +221,19 @@ plcg_status plcg_get_history(const plcg_handle *h, double *out, int32_t cap, int
 /* Enable (1) or disable (0) timing of the iteration kernels with HIP events
  * around each group of check_every back-to-back launches; reported in
  * plcg_result.sweep_ms / sweeps, summed over the groups in which every launch
- * did work (over every group with work when a solve is shorter than a group). */
+ * did work (over every group with work when a solve is shorter than a group).
+ * A RESIDENT solve times each of its launches and counts in sweeps the
+ * iteration launches it replaces (p(l)-CG: the sweeps it ran; CG: two per
+ * iteration), so sweep_ms / sweeps compares with the STREAMING figure. */
 plcg_status plcg_set_timing(plcg_handle *h, int32_t enable);
 
 /* Measurement aid: dst[i] = src[i], i < n, with a plain streaming kernel
  * (calibrates hardware byte counters against a known traffic volume). */
 plcg_status plcg_copy(const double *d_src, double *d_dst, int64_t n, void *stream);
+
+/* 1 if plcg_create would accept PLCG_LAUNCH_RESIDENT for this operator kind,
+ * size n, method and pipeline length l (FP64), else 0. */
+int32_t plcg_resident_supported(int32_t kind, int64_t n, int32_t method, int32_t l);
 
 /* Library version, major*10000 + minor*100 + patch. */
 int32_t plcg_version(void);

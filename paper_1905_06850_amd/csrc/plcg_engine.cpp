@@ -24,6 +24,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 using namespace plcg;
@@ -45,9 +46,17 @@ plcg_status fail(plcg_status code, const std::string &msg) {
   } while (0)
 
 constexpr int kDefaultCheck = 64;
+// Iterations one resident launch may run (about a second for the largest
+// resident systems); longer runs use the streaming kernels.
+constexpr int kResIterCap = 1 << 20;
 constexpr int kDefaultRestarts = 100;
 
 // Streaming workgroups of a launch: one per chunk up to kMaxStream, a multiple of 8.
+// Operator kind numbering of the kernels: 0 2D stencil, 1 3D stencil, 2 diagonal, 3 CSR.
+int op_kind_index(int kind) {
+  return kind == PLCG_OP_STENCIL3D7 ? 1 : kind == PLCG_OP_DIAG ? 2 : kind == PLCG_OP_CSR ? 3 : 0;
+}
+
 int grid_blocks(int nchunks) {
   int b = ((nchunks + kXcds - 1) / kXcds) * kXcds;
   if (b > kMaxStream) b = kMaxStream;
@@ -73,6 +82,8 @@ struct plcg_handle {
   int hist_cap = 0;
   int n = 0, nchunks = 0, blocks = 0;
   bool d3 = false;
+  int res_kind = -1;              // operator kind of the resident kernels; -1: streaming
+  bool ran_resident = false;      // the current solve ran resident launches
   OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0};   // library copies of d / the CSR arrays
   bool jacobi = false;            // CSR solved in Jacobi-scaled form D^{-1/2} A D^{-1/2}
   double *dis = nullptr;          // D^{-1/2} (jacobi)
@@ -169,7 +180,7 @@ struct TimedLaunch {
     size_t count;   // launches in the group
   };
   std::vector<Group> groups;
-  std::vector<uint8_t> counted;  // per launch: 1 if it streamed (did work)
+  std::vector<uint32_t> counted;  // per launch: iteration launches it stands for (0: no work)
   plcg_status begin_group() {
     if (!h->timing) return PLCG_OK;
     const size_t ev = 2 * groups.size();
@@ -186,6 +197,10 @@ struct TimedLaunch {
     if (!h->timing) return;
     counted.push_back(1);
     ++groups.back().count;
+  }
+  // A resident launch stands for `units` iteration launches.
+  void set_units(size_t launch, uint32_t units) {
+    if (h->timing && launch < counted.size()) counted[launch] = units;
   }
   plcg_status end_group() {
     if (!h->timing) return PLCG_OK;
@@ -206,9 +221,12 @@ struct TimedLaunch {
       *ms = 0.0;
       *count = 0;
       for (const Group &g : groups) {
-        size_t work = 0;
-        for (size_t k = g.first; k < g.first + g.count; ++k) work += counted[k];
-        if (work == 0 || (pass == 0 && work != g.count)) continue;
+        size_t work = 0, streamed = 0;
+        for (size_t k = g.first; k < g.first + g.count; ++k) {
+          work += counted[k];
+          streamed += counted[k] != 0;
+        }
+        if (work == 0 || (pass == 0 && streamed != g.count)) continue;
         float e = 0.f;
         PLCG_HIP(hipEventElapsedTime(&e, h->tev[g.ev], h->tev[g.ev + 1]));
         *ms += e;
@@ -290,13 +308,39 @@ template <typename S>
 plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S *p, S *x, int m,
                         hipStream_t s, TimedLaunch &tl, Segment *out) {
   const int l = h->l;
-  const int imax = m + l;               // Alg. 1 loop: i = 0 .. m + l
+  const int imax = m + l;               // Alg. 1 loop: i = 0 .. imax
   int status = kRunning;
   int group = 0;
   int last_i = -1;
   const size_t first_launch = tl.launches();
   plcg_status e;
-  for (int i0 = 0; i0 <= imax; i0 += h->check_every, ++group) {
+  const bool resident = h->res_kind >= 0 && std::is_same<S, double>::value && m <= kResIterCap;
+  if constexpr (std::is_same<S, double>::value) {
+    if (resident) {
+      // the whole segment in one resident launch: state copy 1 in, copy 0 out
+      ResArgs ra;
+      std::memset(&ra, 0, sizeof(ra));
+      ra.z0 = ring[0];
+      ra.x = x;
+      ra.od = h->od;
+      ra.st_in = h->st[1];
+      ra.st_out = h->st[0];
+      ra.hs = h->hs_dev;
+      ra.hist = h->hist;
+      ra.n = h->n;
+      ra.nx = h->op.nx;
+      ra.ny = h->op.ny;
+      ra.nz = h->op.nz;
+      ra.imax = imax;
+      if ((e = tl.begin_group()) != PLCG_OK) return e;
+      PLCG_HIP(launch_plcg_resident(ra, l, h->res_kind, s));
+      h->ran_resident = true;
+      tl.launched();
+      if ((e = tl.end_group()) != PLCG_OK) return e;
+      last_i = 0;   // final state in copy 0
+    }
+  }
+  for (int i0 = 0; !resident && i0 <= imax; i0 += h->check_every, ++group) {
     const int i1 = std::min(imax + 1, i0 + h->check_every);
     if ((e = tl.begin_group()) != PLCG_OK) return e;
     for (int i = i0; i < i1; ++i) {
@@ -319,7 +363,10 @@ plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S 
   // Iterations that ran: every sweep up to last_t + l (or the whole loop).
   out->t_done = ds.status == kRunning ? m : std::min(std::max(ds.last_t, 0), m);
   out->sweeps_run = std::min(imax, (ds.status == kRunning ? imax : ds.last_t + l)) + 1;
-  tl.keep(first_launch, (size_t)out->sweeps_run);
+  if (resident)
+    tl.set_units(first_launch, (uint32_t)out->sweeps_run);
+  else
+    tl.keep(first_launch, (size_t)out->sweeps_run);
   out->rec = out->t_done == 0 ? ds.beta : std::fabs(ds.zeta[out->t_done % kTRing]);
   // t = 0 .. cols-1 were recorded unless the last column broke down.
   h->last_hist_count =
@@ -529,7 +576,29 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   int group = 0;
   bool stopped = false;
   const size_t first_launch = tl.launches();
-  for (int k0 = 0; k0 < maxit; k0 += h->check_every, ++group) {
+  const bool resident = h->res_kind >= 0 && maxit <= kResIterCap;
+  if (resident) {
+    // all iterations in one resident launch: state copy 1 in, copy 0 out
+    ResArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.z0 = h->cg_r;
+    ra.x = x;
+    ra.od = h->od;
+    ra.st_in = h->st[1];
+    ra.st_out = h->st[0];
+    ra.hs = h->hs_dev;
+    ra.n = h->n;
+    ra.nx = h->op.nx;
+    ra.ny = h->op.ny;
+    ra.nz = h->op.nz;
+    ra.imax = maxit;
+    if ((e = tl.begin_group()) != PLCG_OK) return e;
+    PLCG_HIP(launch_cg_resident(ra, h->res_kind, s));
+    h->ran_resident = true;
+    tl.launched();
+    if ((e = tl.end_group()) != PLCG_OK) return e;
+  }
+  for (int k0 = 0; !resident && k0 < maxit; k0 += h->check_every, ++group) {
     const int k1 = std::min(maxit, k0 + h->check_every);
     if ((e = tl.begin_group()) != PLCG_OK) return e;
     for (int k = k0; k < k1; ++k) {
@@ -547,7 +616,9 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
       break;
     }
   }
-  if (!stopped) {
+  if (resident) {
+    *final_slot = 0;
+  } else if (!stopped) {
     // Form rho_maxit and the stopping test of the last iterate (no streaming).
     set_a(maxit, 0);
     PLCG_HIP(launch_cg_sweep_a(a, s));
@@ -559,7 +630,10 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   PLCG_HIP(hipMemcpy(&ds, h->st[*final_slot], sizeof(ds), hipMemcpyDeviceToHost));
   status = ds.status;
   const int iters = status == kRunning ? maxit : ds.last_t;
-  tl.keep(first_launch, 2 * (size_t)iters);   // sweeps A and B of iterations 0 .. iters-1
+  if (resident)
+    tl.set_units(first_launch, (uint32_t)(2 * iters));   // stands for sweeps A and B
+  else
+    tl.keep(first_launch, 2 * (size_t)iters);   // sweeps A and B of iterations 0 .. iters-1
   res->iters = iters;
   res->spmvs = (int32_t)(1 + iters);
   res->rec_relres = rref > 0 ? std::sqrt(ds.cg_rho) / rref : 0.0;
@@ -589,6 +663,7 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   PLCG_HIP(hipSetDevice(h->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   h->host_waits = 0;
+  h->ran_resident = false;
   TimedLaunch tl{h, s};
   int final_slot = 1;
   // Jacobi-scaled CSR: solve D^{-1/2} A D^{-1/2} y = D^{-1/2} b for y = D^{1/2} x
@@ -631,6 +706,7 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
     res.sweeps = count;
   }
   res.host_waits = h->host_waits;
+  res.launch_mode = h->ran_resident ? PLCG_LAUNCH_RESIDENT : PLCG_LAUNCH_STREAMING;
   res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = res;
   return PLCG_OK;
@@ -739,6 +815,14 @@ const char *plcg_last_error(void) { return g_last_error.c_str(); }
 
 int32_t plcg_version(void) { return 100; }
 
+int32_t plcg_resident_supported(int32_t kind, int64_t n, int32_t method, int32_t l) {
+  if (kind < PLCG_OP_STENCIL2D5 || kind > PLCG_OP_CSR || n < 1 || n > PLCG_RESIDENT_MAX) return 0;
+  if (method != PLCG_METHOD_CG && method != PLCG_METHOD_PLCG) return 0;
+  return resident_width(method == PLCG_METHOD_PLCG ? 1 : 0, l, op_kind_index(kind), (int)n) > 0
+             ? 1
+             : 0;
+}
+
 plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, plcg_handle **out) {
   if (out == nullptr) return fail(PLCG_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -774,6 +858,13 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     return fail(PLCG_E_INVALID, "FP32_REFINED needs method PLCG");
   if (cfg->precision == PLCG_PREC_FP32_REFINED && !(cfg->inner_tol < 1.0))
     return fail(PLCG_E_INVALID, "inner_tol must be < 1");
+  if (cfg->launch_mode < PLCG_LAUNCH_AUTO || cfg->launch_mode > PLCG_LAUNCH_RESIDENT)
+    return fail(PLCG_E_INVALID, "unknown launch_mode");
+  const bool res_ok = cfg->precision == PLCG_PREC_FP64 &&
+                      plcg_resident_supported(op->kind, n, cfg->method, cfg->l) == 1;
+  if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT && !res_ok)
+    return fail(PLCG_E_INVALID,
+                "PLCG_LAUNCH_RESIDENT needs FP64, n <= PLCG_RESIDENT_MAX and a supported l");
 
   hipError_t he;
   int dev = 0;
@@ -890,6 +981,15 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     h->od.dg = dg;
   }
   if (e == PLCG_OK && op->kind == PLCG_OP_CSR) e = copy_csr(h, op);
+  // The resident kernels index the matrix with 32-bit offsets.
+  const long long stored =
+      h->od.ell_k > 0 ? (long long)h->od.ell_k * h->od.ell_ld : (long long)op->nnz;
+  if (e == PLCG_OK && res_ok && cfg->launch_mode != PLCG_LAUNCH_STREAMING) {
+    if (op->kind != PLCG_OP_CSR || stored < (1LL << 30))
+      h->res_kind = op_kind_index(op->kind);
+    else if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT)
+      e = fail(PLCG_E_INVALID, "PLCG_LAUNCH_RESIDENT: too many stored entries");
+  }
   if (e != PLCG_OK) {
     release(h);
     delete h;

@@ -109,6 +109,37 @@ struct CgArgs {
   int32_t pad;
 };
 
+// Resident solves (plcg_resident.hip): one workgroup of kResThreads runs a whole
+// segment of Alg. 1, or all of classic CG, for n <= kResMax unknowns held in
+// registers, V per thread: p(l)-CG over the 960 threads of waves 1..15 with
+// V <= res_vmax(l, kind) (the widths that fit in 128 VGPRs without spilling),
+// CG over all 1024 threads.  kind: 0 2D stencil, 1 3D stencil, 2 diagonal, 3 CSR.
+constexpr int kResThreads = 1024;
+constexpr int kResMax = 5 * (kResThreads - 64);
+constexpr int res_vmax(int l, int kind) {
+  return kind == 3   ? (l == 1 ? 4 : l == 2 ? 3 : l <= 4 ? 2 : 1)
+         : l <= 2    ? (l == 2 && kind == 2 ? 4 : 5)
+         : l == 3    ? 3
+         : l == 4    ? 2
+                     : 1;
+}
+struct ResArgs {
+  const double *z0;          // p(l)-CG: z_0 = u_0 / ||u_0||; CG: r_0
+  double *x;                 // x at the segment start; the segment's last iterate at the end
+  OpData od;
+  const DevState *st_in;     // state after the segment start
+  DevState *st_out;          // state at the end
+  HostStatus *hs;
+  double *hist;              // [hist_cap][4] or NULL
+  int32_t n, nx, ny, nz;
+  int32_t imax;              // p(l)-CG: last sweep index m + l; CG: maxit
+  int32_t pad;
+};
+// Unknowns per thread of a resident solve of n unknowns (0: not supported).
+int resident_width(int method_plcg, int l, int kind, int n);
+hipError_t launch_plcg_resident(const ResArgs &a, int l, int kind, hipStream_t s);
+hipError_t launch_cg_resident(const ResArgs &a, int kind, hipStream_t s);
+
 // Launchers (plcg_kernels.hip).
 hipError_t launch_plcg_sweep(const SweepArgsT<double> &a, hipStream_t s);
 hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s);

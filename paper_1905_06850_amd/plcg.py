@@ -31,6 +31,12 @@ PLCG_METHOD_CG = 0
 PLCG_METHOD_PLCG = 1
 PLCG_PREC_FP64 = 0
 PLCG_PREC_FP32_REFINED = 1
+PLCG_LAUNCH_AUTO = 0
+PLCG_LAUNCH_STREAMING = 1
+PLCG_LAUNCH_RESIDENT = 2
+PLCG_RESIDENT_MAX = 4800
+LAUNCH_MODES = {"auto": PLCG_LAUNCH_AUTO, "streaming": PLCG_LAUNCH_STREAMING,
+                "resident": PLCG_LAUNCH_RESIDENT}
 
 PLCG_REASON_NONE = 0
 PLCG_REASON_CONVERGED = 1
@@ -55,7 +61,7 @@ class plcg_config(ctypes.Structure):
                 ("shifts", ctypes.POINTER(ctypes.c_double)),
                 ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("history_cap", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("launch_mode", ctypes.c_int32)]
 
 
 class plcg_result(ctypes.Structure):
@@ -64,7 +70,8 @@ class plcg_result(ctypes.Structure):
                 ("rnorm0", ctypes.c_double), ("rec_relres", ctypes.c_double),
                 ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweeps", ctypes.c_int64),
-                ("outer", ctypes.c_int32), ("host_waits", ctypes.c_int32)]
+                ("outer", ctypes.c_int32), ("host_waits", ctypes.c_int32),
+                ("launch_mode", ctypes.c_int32)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -122,6 +129,8 @@ SYMBOLS = {
     "plcg_set_timing": (_st, [_h, ctypes.c_int32]),
     "plcg_copy": (_st, [_dp, _dp, ctypes.c_int64, ctypes.c_void_p]),
     "plcg_version": (ctypes.c_int32, []),
+    "plcg_resident_supported": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                                 ctypes.c_int32]),
     "plcg_batch_create": (_st, [ctypes.POINTER(plcg_batch_config), ctypes.POINTER(_h)]),
     "plcg_batch_footprint": (ctypes.c_int64, [_h, ctypes.POINTER(plcg_system_desc)]),
     "plcg_batch_add": (_st, [_h, ctypes.POINTER(plcg_system_desc), _dp, _dp, ctypes.c_double,
@@ -161,6 +170,7 @@ plcg_get_history = _lib.plcg_get_history
 plcg_set_timing = _lib.plcg_set_timing
 plcg_copy = _lib.plcg_copy
 plcg_version = _lib.plcg_version
+plcg_resident_supported = _lib.plcg_resident_supported
 plcg_batch_create = _lib.plcg_batch_create
 plcg_batch_footprint = _lib.plcg_batch_footprint
 plcg_batch_add = _lib.plcg_batch_add
@@ -207,6 +217,14 @@ def _dims_desc(kind, dims, diag=None, csr=None, jacobi=False):
     raise ValueError(f"unknown operator kind {kind!r}")
 
 
+def resident_supported(kind, n, method="plcg", l=1):
+    """plcg_resident_supported for a kind name ("2d5", "3d7", "diag", "csr") or code."""
+    code = {"2d5": PLCG_OP_STENCIL2D5, "3d7": PLCG_OP_STENCIL3D7, "diag": PLCG_OP_DIAG,
+            "csr": PLCG_OP_CSR}.get(kind, kind)
+    m = PLCG_METHOD_CG if method == "cg" else PLCG_METHOD_PLCG
+    return plcg_resident_supported(int(code), int(n), m, int(l)) == 1
+
+
 def _vec(v, n, name):
     """A device address from an int, or from a contiguous float64 GPU tensor of n
     elements (anything with data_ptr(), dtype, is_cuda, numel, is_contiguous)."""
@@ -239,11 +257,12 @@ class Solver:
 
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
                  check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
-                 inner_tol=0.0, diag=None, csr=None, jacobi=False):
+                 inner_tol=0.0, diag=None, csr=None, jacobi=False, launch="auto"):
         """kind "2d5", "3d7", "diag" or "csr"; for "diag", `diag` is the device
         address of the n FP64 diagonal entries; for "csr", `csr` is (rowptr,
         colind, vals, nnz) with device addresses of int64 / int32 / FP64 arrays
-        (copied by plcg_create); jacobi=True solves a CSR matrix Jacobi-preconditioned."""
+        (copied by plcg_create); jacobi=True solves a CSR matrix Jacobi-preconditioned.
+        launch: "auto", "streaming" or "resident" (PLCG_LAUNCH_*)."""
         self.desc = _dims_desc(kind, dims, diag, csr, jacobi)
         self._shifts = None
         sp = None
@@ -253,7 +272,8 @@ class Solver:
         m = PLCG_METHOD_CG if method == "cg" else PLCG_METHOD_PLCG
         prec = PLCG_PREC_FP32_REFINED if precision == "fp32" else PLCG_PREC_FP64
         self.cfg = plcg_config(m, int(l), float(lmin), float(lmax), sp, int(check_every),
-                               int(max_restarts), int(history_cap), prec, float(inner_tol))
+                               int(max_restarts), int(history_cap), prec, float(inner_tol),
+                               LAUNCH_MODES[launch])
         self.method = method
         self.l = int(l)
         self.handle = _h()

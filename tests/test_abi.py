@@ -72,3 +72,41 @@ def test_jacobi_flag_needs_a_csr_operator():
     assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
         plcg.PLCG_E_INVALID
     assert not h.value
+
+
+def test_resident_support_table():
+    """Which systems the one-workgroup kernels take: up to PLCG_RESIDENT_MAX
+    unknowns, p(l)-CG spread over 960 threads with the widths that fit the
+    registers (stencils: 5 unknowns per thread up to l = 2, 3 at l = 3, 2 at
+    l = 4, 1 beyond; CSR narrower), CG over 1024 threads."""
+    from paper_1905_06850_amd import plcg
+    sup = plcg.resident_supported
+    assert plcg.PLCG_RESIDENT_MAX == 4800
+    for kind in ("2d5", "3d7", "diag", "csr"):
+        assert sup(kind, 1, "plcg", 8) and sup(kind, 960, "plcg", 8)
+        assert not sup(kind, 961, "plcg", 8)
+        assert sup(kind, 4800, "cg") and not sup(kind, 4801, "cg")
+        assert not sup(kind, 0, "cg")
+    assert sup("2d5", 4800, "plcg", 2) and not sup("2d5", 4800, "plcg", 3)
+    assert sup("2d5", 2880, "plcg", 3) and not sup("2d5", 2881, "plcg", 3)
+    assert sup("3d7", 2880, "plcg", 3) and not sup("3d7", 2881, "plcg", 3)
+    assert sup("2d5", 1920, "plcg", 4) and not sup("2d5", 1921, "plcg", 4)
+    assert sup("csr", 3840, "plcg", 1) and not sup("csr", 3841, "plcg", 1)
+    assert not sup("2d5", 961, "plcg", 5) and not sup(9, 10, "cg")
+    assert not sup("2d5", 10, "plcg", 0) and not sup("2d5", 10, "plcg", 9)
+
+
+@pytest.mark.parametrize("nx,ny,method,l,precision", [(61, 80, 1, 1, 0), (64, 64, 1, 3, 0),
+                                                      (64, 64, 1, 1, 1), (8, 8, 1, 2, 1)])
+def test_create_rejects_resident_where_unavailable(nx, ny, method, l, precision):
+    from paper_1905_06850_amd import plcg
+    desc = plcg.plcg_operator_desc(1, nx, ny, 1)
+    cfg = plcg.plcg_config(method, l, 0.0, 8.0, None, 0, -1, 0, precision, 0.0,
+                           plcg.PLCG_LAUNCH_RESIDENT)
+    h = ctypes.c_void_p()
+    assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
+        plcg.PLCG_E_INVALID
+    assert not h.value
+    cfg.launch_mode = 7
+    assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
+        plcg.PLCG_E_INVALID

@@ -45,14 +45,24 @@ class Csr:
         return (self.t[0].data_ptr(), self.t[1].data_ptr(), self.t[2].data_ptr(), self.nnz)
 
 
-def gpu_solve(dev, csr, method, l, b, x0, tol, maxit, lo=0.0, hi=8.0, **kw):
+LAUNCHES = ["streaming", "resident"]
+
+
+def gpu_solve(dev, csr, method, l, b, x0, tol, maxit, lo=0.0, hi=8.0, launch="auto", **kw):
     plcg = _plcg()
-    print(f"[gpu] csr {method} l={l} n={csr.n} nnz={csr.nnz} tol={tol} maxit={maxit}", flush=True)
-    s = plcg.Solver("csr", (csr.n,), method=method, l=l, lmin=lo, lmax=hi, csr=csr.arg(), **kw)
+    if launch == "resident" and (kw.get("precision", "fp64") != "fp64" or
+                                 not plcg.resident_supported("csr", csr.n, method, l)):
+        pytest.skip(f"no resident kernel for {method} l={l} n={csr.n}")
+    print(f"[gpu] csr {method} l={l} n={csr.n} nnz={csr.nnz} tol={tol} maxit={maxit} "
+          f"launch={launch}", flush=True)
+    s = plcg.Solver("csr", (csr.n,), method=method, l=l, lmin=lo, lmax=hi, csr=csr.arg(),
+                    launch=launch, **kw)
     bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
     xt = torch.from_numpy(np.ascontiguousarray(x0).copy()).to(dev)
     res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit,
                   torch.cuda.current_stream(dev).cuda_stream)
+    if launch != "auto" and res.iters > 0:
+        assert res.launch_mode == plcg.LAUNCH_MODES[launch]
     x = xt.cpu().numpy()
     s.close()
     return x, res
@@ -90,7 +100,8 @@ def test_csr_apply_matches_oracle(dev, dims):
 
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3),
                                       ("plcg", 5)])
-def test_csr_poisson_solve_parity(dev, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_csr_poisson_solve_parity(dev, method, l, launch):
     dims = (64, 64)
     A = operators.laplacian(dims)
     csr = Csr(dev, *synth.csr_variable_laplacian(dims))
@@ -98,7 +109,7 @@ def test_csr_poisson_solve_parity(dev, method, l):
     b = A(xs)
     x0 = np.zeros(A.n)
     ref = oracle_solve(A, method, l, b, x0, 1e-8, 5000)
-    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-8, 5000)
+    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-8, 5000, launch=launch)
     assert res.reason == 1 and abs(res.iters - ref.iters) <= 1
     assert res.true_relres <= 10 * ref.true_relres and ref.true_relres <= 10 * res.true_relres
     assert _rel(x, ref.x) < 1e-8
@@ -106,7 +117,8 @@ def test_csr_poisson_solve_parity(dev, method, l):
 
 @pytest.mark.parametrize("dims", [(48, 40), (37, 29), (9, 7, 5)])
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
-def test_csr_scaled_variable_solve_parity(dev, dims, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_csr_scaled_variable_solve_parity(dev, dims, method, l, launch):
     """Jacobi-scaled variable-coefficient matrices (spectrum in (0, 2)): the
     preconditioned method of reading 15 on a general sparse matrix."""
     (rp, ci, va), As = scaled_variable(dims, 72)
@@ -114,21 +126,22 @@ def test_csr_scaled_variable_solve_parity(dev, dims, method, l):
     b = synth.uniform(As.n, 73)
     x0 = 0.1 * synth.uniform(As.n, 74)
     ref = oracle_solve(As, method, l, b, x0, 1e-8, 20000, 0.0, 2.0)
-    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-8, 20000, 0.0, 2.0)
+    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-8, 20000, 0.0, 2.0, launch=launch)
     assert res.reason == 1 and ref.reason == "converged"
     assert abs(res.iters - ref.iters) <= 1
     assert _rel(x, ref.x) < 1e-8
 
 
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 4)])
-def test_csr_early_iterates(dev, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_csr_early_iterates(dev, method, l, launch):
     (rp, ci, va), As = scaled_variable((40, 30), 75)
     csr = Csr(dev, rp, ci, va)
     b = synth.uniform(As.n, 76)
     x0 = np.zeros(As.n)
     for m in (1, 2, 5, 20):
         ref = oracle_solve(As, method, l, b, x0, 1e-30, m, 0.0, 2.0)
-        x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-30, m, 0.0, 2.0)
+        x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-30, m, 0.0, 2.0, launch=launch)
         assert res.iters == m == ref.iters
         assert _rel(x, ref.x) < 1e-13
 
@@ -188,14 +201,15 @@ def _arrow(n, seed):
 
 
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
-def test_csr_uneven_rows_parity(dev, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_csr_uneven_rows_parity(dev, method, l, launch):
     rp, ci, va = _arrow(3001, 79)
     A = operators.csr(rp, ci, va)
     csr = Csr(dev, rp, ci, va)
     b = synth.uniform(A.n, 80)
     x0 = np.zeros(A.n)
     ref = oracle_solve(A, method, l, b, x0, 1e-10, 2000, 1.9, 4.2)
-    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-10, 2000, 1.9, 4.2)
+    x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-10, 2000, 1.9, 4.2, launch=launch)
     assert res.reason == 1 and ref.reason == "converged"
     assert abs(res.iters - ref.iters) <= 1
     assert _rel(x, ref.x) < 1e-8
@@ -238,15 +252,21 @@ def _unscaled_variable(dims, seed):
     return (rp, ci, va), A, As, dis
 
 
-def gpu_solve_jacobi(dev, csr, method, l, b, x0, tol, maxit, **kw):
+def gpu_solve_jacobi(dev, csr, method, l, b, x0, tol, maxit, launch="auto", **kw):
     plcg = _plcg()
-    print(f"[gpu] csr jacobi {method} l={l} n={csr.n} tol={tol} maxit={maxit}", flush=True)
+    if launch == "resident" and (kw.get("precision", "fp64") != "fp64" or
+                                 not plcg.resident_supported("csr", csr.n, method, l)):
+        pytest.skip(f"no resident kernel for {method} l={l} n={csr.n}")
+    print(f"[gpu] csr jacobi {method} l={l} n={csr.n} tol={tol} maxit={maxit} launch={launch}",
+          flush=True)
     s = plcg.Solver("csr", (csr.n,), method=method, l=l, lmin=0.0, lmax=2.0, csr=csr.arg(),
-                    jacobi=True, **kw)
+                    jacobi=True, launch=launch, **kw)
     bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
     xt = torch.from_numpy(np.ascontiguousarray(x0).copy()).to(dev)
     res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit,
                   torch.cuda.current_stream(dev).cuda_stream)
+    if launch != "auto" and res.iters > 0:
+        assert res.launch_mode == plcg.LAUNCH_MODES[launch]
     x = xt.cpu().numpy()
     s.close()
     return x, res
@@ -254,7 +274,8 @@ def gpu_solve_jacobi(dev, csr, method, l, b, x0, tol, maxit, **kw):
 
 @pytest.mark.parametrize("dims", [(48, 40), (9, 7, 5)])
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
-def test_csr_jacobi_parity(dev, dims, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_csr_jacobi_parity(dev, dims, method, l, launch):
     """Jacobi-preconditioned solve of an unscaled variable-coefficient matrix
     against the oracle on the scaled system from the scaled x0 (the same method,
     reading 15): iterations within 1, x within 1e-8, both residual norms."""
@@ -263,7 +284,7 @@ def test_csr_jacobi_parity(dev, dims, method, l):
     b = synth.uniform(A.n, 82)
     x0 = 0.1 * synth.uniform(A.n, 83)
     ref = oracle_solve(As, method, l, dis * b, x0 / dis, 1e-8, 20000, 0.0, 2.0)
-    x, res = gpu_solve_jacobi(dev, csr, method, l, b, x0, 1e-8, 20000)
+    x, res = gpu_solve_jacobi(dev, csr, method, l, b, x0, 1e-8, 20000, launch=launch)
     assert res.reason == 1 and ref.reason == "converged"
     assert abs(res.iters - ref.iters) <= 1
     xr = dis * ref.x
@@ -276,7 +297,8 @@ def test_csr_jacobi_parity(dev, dims, method, l):
 
 
 @pytest.mark.parametrize("l", [1, 2, 3])
-def test_csr_jacobi_is_preconditioned_alg1(dev, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_csr_jacobi_is_preconditioned_alg1(dev, l, launch):
     """The first iterates equal those of Alg. 1 with M = diag(A) (u != z,
     M-inner products) run by the oracle on the unscaled matrix."""
     (rp, ci, va), A, As, dis = _unscaled_variable((40, 30), 84)
@@ -287,7 +309,7 @@ def test_csr_jacobi_is_preconditioned_alg1(dev, l):
     sig = shifts.chebyshev_shifts(l, 0.0, 2.0)
     for m in (1, 5, 20):
         ref = oplcg.alg1(A, b, x0, l, sig, 0.0, m, Minv=lambda u: dinv * u)
-        x, res = gpu_solve_jacobi(dev, csr, "plcg", l, b, x0, 1e-30, m)
+        x, res = gpu_solve_jacobi(dev, csr, "plcg", l, b, x0, 1e-30, m, launch=launch)
         assert res.iters == m == ref.t_done
         assert _rel(x, ref.x) < 1e-12
 

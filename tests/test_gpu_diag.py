@@ -31,17 +31,25 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def gpu_solve(dev, d, method, l, b, x0, tol, maxit):
+LAUNCHES = ["streaming", "resident"]
+
+
+def gpu_solve(dev, d, method, l, b, x0, tol, maxit, launch="auto"):
     plcg = _plcg()
-    print(f"[gpu] diag {method} l={l} n={d.size} tol={tol} maxit={maxit}", flush=True)
+    if launch == "resident" and not plcg.resident_supported("diag", d.size, method, l):
+        pytest.skip(f"no resident kernel for {method} l={l} n={d.size}")
+    print(f"[gpu] diag {method} l={l} n={d.size} tol={tol} maxit={maxit} launch={launch}",
+          flush=True)
     dt = torch.from_numpy(d).to(dev)
     s = plcg.Solver("diag", (d.size,), method=method, l=l, lmin=0.0, lmax=8.0,
-                    diag=dt.data_ptr())
+                    diag=dt.data_ptr(), launch=launch)
     del dt                                       # copied by plcg_create
     bt = torch.from_numpy(b).to(dev)
     xt = torch.from_numpy(x0.copy()).to(dev)
     res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit,
                   torch.cuda.current_stream(dev).cuda_stream)
+    if launch != "auto" and res.iters > 0:
+        assert res.launch_mode == plcg.LAUNCH_MODES[launch]
     x = xt.cpu().numpy()
     s.close()
     return x, res
@@ -71,12 +79,13 @@ def test_diag_apply_is_exact(dev, n):
 @pytest.mark.parametrize("dims", [(64, 64), (37, 29), (130, 7)])
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3),
                                       ("plcg", 5)])
-def test_diag_solve_parity(dev, dims, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_diag_solve_parity(dev, dims, method, l, launch):
     d = synth.spectrum_diagonal(dims)
     b = synth.uniform(d.size, 0)
     x0 = np.zeros(d.size)
     ref = oracle_solve(d, method, l, b, x0, 1e-8, 20000)
-    x, res = gpu_solve(dev, d, method, l, b, x0, 1e-8, 20000)
+    x, res = gpu_solve(dev, d, method, l, b, x0, 1e-8, 20000, launch=launch)
     assert res.reason == 1 and ref.reason == "converged", res.as_dict()
     assert abs(res.iters - ref.iters) <= 1
     assert res.true_relres <= 10 * ref.true_relres and ref.true_relres <= 10 * res.true_relres
@@ -84,13 +93,14 @@ def test_diag_solve_parity(dev, dims, method, l):
 
 
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 4)])
-def test_diag_early_iterates(dev, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_diag_early_iterates(dev, method, l, launch):
     d = synth.spectrum_diagonal((48, 40))
     b = synth.uniform(d.size, 8)
     x0 = 0.1 * synth.uniform(d.size, 9)
     for m in (1, 2, 5, 20):
         ref = oracle_solve(d, method, l, b, x0, 1e-30, m)
-        x, res = gpu_solve(dev, d, method, l, b, x0, 1e-30, m)
+        x, res = gpu_solve(dev, d, method, l, b, x0, 1e-30, m, launch=launch)
         assert res.iters == m == ref.iters
         assert _rel(x, ref.x) < 1e-13
 

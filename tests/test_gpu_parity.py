@@ -40,15 +40,27 @@ def _interval(dims):
     return (0.0, 8.0) if len(dims) == 2 else (0.0, 12.0)
 
 
-def gpu_solve(dev, dims, method, l, b, x0, tol, maxit, **kw):
+LAUNCHES = ["streaming", "resident"]
+
+
+def gpu_solve(dev, dims, method, l, b, x0, tol, maxit, launch="auto", **kw):
+    """Solve on the GPU; launch "streaming" or "resident" forces that launch mode
+    (skipping the case if the library does not offer it for this system) and
+    checks that it is the one that ran."""
     plcg = _plcg()
     lo, hi = kw.pop("interval", _interval(dims))
-    print(f"[gpu] {method} l={l} dims={dims} tol={tol} maxit={maxit}", flush=True)
-    s = plcg.Solver(_kind(dims), dims, method=method, l=l, lmin=lo, lmax=hi, **kw)
+    n = int(np.prod(dims))
+    if launch == "resident" and not plcg.resident_supported(_kind(dims), n, method, l):
+        pytest.skip(f"no resident kernel for {method} l={l} n={n}")
+    print(f"[gpu] {method} l={l} dims={dims} tol={tol} maxit={maxit} launch={launch}",
+          flush=True)
+    s = plcg.Solver(_kind(dims), dims, method=method, l=l, lmin=lo, lmax=hi, launch=launch, **kw)
     bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
     xt = torch.from_numpy(np.ascontiguousarray(x0)).to(dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
     res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit, stream)
+    if launch != "auto" and (res.iters > 0 or res.restarts > 0):
+        assert res.launch_mode == plcg.LAUNCH_MODES[launch], res.as_dict()
     x = xt.cpu().numpy()
     return x, res, s
 
@@ -99,15 +111,16 @@ def test_shifts_match_oracle(dev):
 
 # --------------------------------------------------------------- full solves --
 
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("method,l", METHODS)
-def test_solve_parity_64_manufactured(dev, method, l):
+def test_solve_parity_64_manufactured(dev, method, l, launch):
     dims = (64, 64)
     A = operators.laplacian(dims)
     xs = synth.uniform(A.n, 0)
     b = A(xs)
     x0 = np.zeros(A.n)
     ref = oracle_solve(dims, method, l, b, x0, 1e-8, 5000)
-    x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-8, 5000)
+    x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-8, 5000, launch=launch)
     assert res.reason == 1, res.as_dict()
     assert abs(res.iters - ref.iters) <= 1
     assert res.true_relres <= 10 * ref.true_relres and ref.true_relres <= 10 * res.true_relres
@@ -117,15 +130,16 @@ def test_solve_parity_64_manufactured(dev, method, l):
 
 
 # (32, 48, 5) and (64, 160, 6): planes of whole chunks, visited by column tiles
+@pytest.mark.parametrize("dims,launch", [((64, 64), "streaming"), ((30, 32), "resident")])
 @pytest.mark.parametrize("l", [6, 7, 8])
-def test_deep_pipelines_solve_parity(dev, l):
-    """The deepest pipelines the library offers, solved through at 64^2."""
-    dims = (64, 64)
+def test_deep_pipelines_solve_parity(dev, l, dims, launch):
+    """The deepest pipelines the library offers, solved through at 64^2 with
+    the streaming kernels and at 30 x 32 (one unknown per thread) resident."""
     A = operators.laplacian(dims)
     b = A(synth.uniform(A.n, 0))
     x0 = np.zeros(A.n)
     ref = oracle_solve(dims, "plcg", l, b, x0, 1e-8, 5000)
-    x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, 1e-8, 5000)
+    x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, 1e-8, 5000, launch=launch)
     assert res.reason == 1 and ref.reason == "converged"
     assert abs(res.iters - ref.iters) <= 1 and res.restarts == ref.restarts == 0
     assert _rel(x, ref.x) < 1e-8
@@ -136,12 +150,13 @@ def test_deep_pipelines_solve_parity(dev, l):
                                   (5, 9, 11), (1, 1, 600), (32, 48, 5), (64, 160, 6),
                                   (102, 30)])
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
-def test_solve_parity_ragged(dev, dims, method, l):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_solve_parity_ragged(dev, dims, method, l, launch):
     A = operators.laplacian(dims)
     b = synth.uniform(A.n, 3)
     x0 = 0.1 * synth.uniform(A.n, 4)
     ref = oracle_solve(dims, method, l, b, x0, 1e-8, 5000)
-    x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-8, 5000)
+    x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-8, 5000, launch=launch)
     assert res.reason == 1 and ref.reason == "converged"
     assert abs(res.iters - ref.iters) <= 1
     assert res.true_relres <= 10 * max(ref.true_relres, 1e-15)
@@ -149,15 +164,16 @@ def test_solve_parity_ragged(dev, dims, method, l):
     s.close()
 
 
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("method,l", METHODS)
-def test_early_iterates(dev, method, l):
+def test_early_iterates(dev, method, l, launch):
     dims = (48, 40)
     A = operators.laplacian(dims)
     b = synth.uniform(A.n, 8)
     x0 = np.zeros(A.n)
     for m in (0, 1, 2, 3, 7, 20):
         ref = oracle_solve(dims, method, l, b, x0, 1e-30, m)
-        x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-30, m)
+        x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-30, m, launch=launch)
         assert res.iters == m == ref.iters
         assert res.reason == 2
         if m == 0:
@@ -193,8 +209,9 @@ def _fsum_dot(a, b):
     return math.fsum(a * b)
 
 
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 8])
-def test_coefficients_match_oracle(dev, l):
+def test_coefficients_match_oracle(dev, l, launch):
     """gamma_t, delta_t (Eqs. haa1, haa3), eta_t, zeta_t (Eq. LU) from the device
     scalar engine against the oracle's, t = 0..149.  The bound is ten times the
     oracle's own change when its dot products are rounded correctly instead of
@@ -207,7 +224,8 @@ def test_coefficients_match_oracle(dev, l):
     sig = shifts.chebyshev_shifts(l, 0.0, 8.0)
     d = oplcg.alg1(A, b, x0, l, sig, 0.0, 150).diag
     d2 = oplcg.alg1(A, b, x0, l, sig, 0.0, 150, dot=_fsum_dot).diag
-    x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, 1e-30, 150, history_cap=200)
+    x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, 1e-30, 150, history_cap=200,
+                          launch=launch)
     hist = s.history(200)
     assert len(hist) >= 150
     for col, key in enumerate(("gam", "dlt", "eta", "zeta")):
@@ -220,15 +238,16 @@ def test_coefficients_match_oracle(dev, l):
 
 # --------------------------------------------------------------- edge cases --
 
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 2)])
-def test_zero_rhs_and_tol_above_one(dev, method, l):
+def test_zero_rhs_and_tol_above_one(dev, method, l, launch):
     dims = (10, 10)
     z = np.zeros(100)
-    x, res, s = gpu_solve(dev, dims, method, l, z, z, 1e-8, 100)
+    x, res, s = gpu_solve(dev, dims, method, l, z, z, 1e-8, 100, launch=launch)
     assert res.iters == 0 and res.reason == 1 and np.all(x == 0)
     s.close()
     b = synth.uniform(100, 1)
-    x, res, s = gpu_solve(dev, dims, method, l, b, z, 2.0, 100)
+    x, res, s = gpu_solve(dev, dims, method, l, b, z, 2.0, 100, launch=launch)
     assert res.iters == 0 and res.reason == 1
     s.close()
 
@@ -243,7 +262,8 @@ def test_nonfinite_rhs(dev, method, l):
     assert ei.value.status == plcg.PLCG_E_NONFINITE
 
 
-def test_breakdown_and_restart(dev):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_breakdown_and_restart(dev, launch):
     """Shifts on a too-wide interval make the square root break down (Sec. 2.2);
     the library restarts from the latest iterate and still converges."""
     dims = (64, 64)
@@ -251,7 +271,8 @@ def test_breakdown_and_restart(dev):
     b = synth.uniform(A.n, 1)
     x0 = np.zeros(A.n)
     ref = oracle_solve(dims, "plcg", 2, b, x0, 1e-8, 20000, interval=(0.0, 16.0))
-    x, res, s = gpu_solve(dev, dims, "plcg", 2, b, x0, 1e-8, 20000, interval=(0.0, 16.0))
+    x, res, s = gpu_solve(dev, dims, "plcg", 2, b, x0, 1e-8, 20000, interval=(0.0, 16.0),
+                          launch=launch)
     assert ref.restarts >= 1 and res.restarts >= 1
     assert res.reason == 1
     assert res.true_relres < 1e-7
@@ -259,12 +280,14 @@ def test_breakdown_and_restart(dev):
     s.close()
 
 
-def test_single_unknown_breakdown_limit(dev):
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_single_unknown_breakdown_limit(dev, launch):
     """n = 1: the Krylov space is exhausted before x_1 is formed, so every
     segment breaks down at t = 0; both sides stop at the restart limit."""
     b = np.array([1.0])
     ref = oracle_solve((1, 1), "plcg", 1, b, np.zeros(1), 1e-8, 50, max_restarts=3)
-    x, res, s = gpu_solve(dev, (1, 1), "plcg", 1, b, np.zeros(1), 1e-8, 50, max_restarts=3)
+    x, res, s = gpu_solve(dev, (1, 1), "plcg", 1, b, np.zeros(1), 1e-8, 50, max_restarts=3,
+                          launch=launch)
     assert ref.reason == "breakdown_limit" and res.reason == 3
     assert res.restarts == ref.restarts == 4
     s.close()
@@ -299,7 +322,7 @@ def test_timing_counts_sweeps(dev):
     b = synth.uniform(4096, 2)
     plcg = _plcg()
     for method, l, per in (("plcg", 2, 1), ("cg", 1, 2)):
-        s = plcg.Solver("2d5", dims, method=method, l=l)
+        s = plcg.Solver("2d5", dims, method=method, l=l, launch="streaming")
         s.set_timing(True)
         bt = torch.from_numpy(b).to(dev)
         xt = torch.zeros(4096, dtype=torch.float64, device=dev)
@@ -319,9 +342,10 @@ def test_timing_counts_sweeps(dev):
         s.close()
 
 
+@pytest.mark.parametrize("launch", LAUNCHES)
 @pytest.mark.parametrize("dims", [(2, 2), (3, 1, 1), (2, 1), (1, 1)])
 @pytest.mark.parametrize("l", [1, 2, 3])
-def test_tiny_systems_krylov_exhaustion(dev, dims, l):
+def test_tiny_systems_krylov_exhaustion(dev, dims, l, launch):
     """Systems with fewer distinct eigenvalues than the pipeline needs break down
     when the Krylov space is exhausted (Sec. 2.2).  Whether the square-root
     argument comes out as exactly zero or as a tiny positive number is decided by
@@ -332,7 +356,8 @@ def test_tiny_systems_krylov_exhaustion(dev, dims, l):
     b = synth.uniform(A.n, 3)
     x0 = 0.1 * synth.uniform(A.n, 4)
     ref = oracle_solve(dims, "plcg", l, b, x0, 1e-8, 500, max_restarts=20)
-    x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, 1e-8, 500, max_restarts=20)
+    x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, 1e-8, 500, max_restarts=20,
+                          launch=launch)
     assert res.reason in (1, 3)
     assert np.all(np.isfinite(x))
     if res.reason == 1:
@@ -482,4 +507,106 @@ def test_tensor_arguments(dev):
     for bad in (bt.float(), bt.cpu(), bt[:100], bt[::2]):
         with pytest.raises(ValueError):
             s.solve(bad, x1, 1e-8, 10)
+    s.close()
+
+
+# ------------------------------------------------------------ resident solves --
+
+@pytest.mark.parametrize("method,l", [("plcg", 2), ("plcg", 1), ("cg", 1)])
+def test_resident_timing_and_waits(dev, method, l):
+    """A resident solve is one launch per restart segment: the host waits a few
+    times per solve, and the timing counts the iteration launches it replaces
+    (p(l)-CG: every sweep of the segment; CG: sweeps A and B per iteration)."""
+    plcg = _plcg()
+    dims = (64, 64)
+    b = synth.uniform(4096, 2)
+    s = plcg.Solver("2d5", dims, method=method, l=l, launch="resident")
+    s.set_timing(True)
+    bt = torch.from_numpy(b).to(dev)
+    xt = torch.zeros(4096, dtype=torch.float64, device=dev)
+    r = s.solve(bt.data_ptr(), xt.data_ptr(), 1e-8, 5000,
+                torch.cuda.current_stream(dev).cuda_stream)
+    assert r.reason == 1 and r.restarts == 0 and r.launch_mode == plcg.PLCG_LAUNCH_RESIDENT
+    assert r.sweeps == (r.spmvs - 2 if method == "plcg" else 2 * r.iters)
+    assert r.sweep_ms > 0
+    assert 1 <= r.host_waits <= 4
+    s.close()
+
+
+# widths: p(l)-CG spreads n over 960 threads, CG over 1024 (V = 1..5 each)
+@pytest.mark.parametrize("dims,method,l", [((30, 32), "plcg", 1), ((31, 31), "plcg", 1),
+                                           ((40, 48), "plcg", 2), ((17, 113), "plcg", 2),
+                                           ((48, 60), "plcg", 3), ((60, 64), "plcg", 1),
+                                           ((60, 80), "plcg", 2), ((32, 32), "cg", 1),
+                                           ((25, 41), "cg", 1), ((60, 80), "cg", 1),
+                                           ((12, 10, 8), "plcg", 4), ((12, 10, 8), "plcg", 6),
+                                           ((19, 11, 23), "cg", 1)])
+def test_resident_widths_against_oracle(dev, dims, method, l):
+    """Resident solves at the boundaries of the unknowns-per-thread widths
+    (960, 961, 1920, 1921, ..., 4800 unknowns) and in 3D, against the oracle.
+    The deep 3D case is one whose stop is not decided by rounding: the oracle
+    itself moves x by 5e-11 when its dot products are rounded correctly (on
+    6 x 7 x 9 with l = 6 it moves by 1.6e-8 and stops one iteration later, so
+    no implementation can meet a 1e-8 bar there)."""
+    A = operators.laplacian(dims)
+    b = synth.uniform(A.n, 31)
+    x0 = 0.1 * synth.uniform(A.n, 32)
+    ref = oracle_solve(dims, method, l, b, x0, 1e-8, 20000)
+    x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-8, 20000, launch="resident")
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.iters - ref.iters) <= 1
+    assert res.true_relres <= 10 * max(ref.true_relres, 1e-15)
+    assert _rel(x, ref.x) < 1e-8
+    s.close()
+
+
+def test_resident_limits(dev):
+    """Above PLCG_RESIDENT_MAX unknowns, or for a pipeline too deep for the
+    registers, AUTO runs the streaming kernels and RESIDENT is refused; a
+    resident solve allowed more than 2^20 iterations streams too."""
+    plcg = _plcg()
+    assert plcg.resident_supported("2d5", 4800, "plcg", 2)
+    assert not plcg.resident_supported("2d5", 4801, "plcg", 1)
+    assert not plcg.resident_supported("2d5", 4096, "plcg", 3)
+    dims = (61, 80)
+    A = operators.laplacian(dims)
+    b = synth.uniform(A.n, 33)
+    x, res, s = gpu_solve(dev, dims, "plcg", 1, b, np.zeros(A.n), 1e-8, 5000)
+    assert res.reason == 1 and res.launch_mode == plcg.PLCG_LAUNCH_STREAMING
+    s.close()
+    with pytest.raises(plcg.PlcgError) as ei:
+        plcg.Solver("2d5", dims, method="plcg", l=1, launch="resident")
+    assert ei.value.status == plcg.PLCG_E_INVALID
+    dims = (64, 64)
+    b = synth.uniform(4096, 34)
+    x, res, s = gpu_solve(dev, dims, "cg", 1, b, np.zeros(4096), 1e-8, (1 << 20) + 1,
+                          launch="auto")
+    assert res.reason == 1 and res.launch_mode == plcg.PLCG_LAUNCH_STREAMING
+    s.close()
+
+
+@pytest.mark.parametrize("method,l", [("plcg", 2), ("cg", 1)])
+def test_resident_deterministic_and_submit_poll(dev, method, l):
+    """Resident solves are bitwise reproducible (fixed reduction order inside the
+    workgroup), also through plcg_submit / plcg_poll."""
+    dims = (64, 64)
+    A = operators.laplacian(dims)
+    b = synth.uniform(A.n, 6)
+    x1, r1, s = gpu_solve(dev, dims, method, l, b, np.zeros(A.n), 1e-9, 5000, launch="resident")
+    bt = torch.from_numpy(b).to(dev)
+    xt = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    r2 = s.solve(bt.data_ptr(), xt.data_ptr(), 1e-9, 5000, stream)
+    assert np.array_equal(x1, xt.cpu().numpy()) and r1.iters == r2.iters
+    xt.zero_()
+    torch.cuda.synchronize()
+    ticket = s.submit(bt.data_ptr(), xt.data_ptr(), 1e-9, 5000, stream)
+    import time
+    t0 = time.time()
+    r3 = None
+    while r3 is None and time.time() - t0 < 60:
+        r3 = s.poll(ticket)
+        time.sleep(0.001)
+    assert r3 is not None and r3.iters == r1.iters
+    assert np.array_equal(x1, xt.cpu().numpy())
     s.close()
