@@ -95,8 +95,10 @@ def measured_traffic(workload: str, kernel: str):
     hash the counters were taken with, and `<kernel> <bytes>` per launch (FETCH_SIZE
     plus WRITE_SIZE, each scaled by the copy-kernel calibration factor), the kernel
     named without namespace, argument list or spaces, e.g.
-    `plcg_sweep_kernel<1,false,double>`.  A different source hash means the kernel
-    changed since: None.
+    `plcg_sweep_kernel<1,false,double,0>`.  `kernel` may leave out the last
+    template argument (the streaming cache hints the library picked for the
+    workload): the one kernel of that family in the file is taken.  A different
+    source hash means the kernel changed since: None.  Returns (name, bytes).
     """
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
@@ -109,8 +111,10 @@ def measured_traffic(workload: str, kernel: str):
                 vals[parts[0]] = parts[1]
     if vals.get("source_sha256_16") != kernel_source_hash():
         return None
-    v = vals.get(kernel)
-    return float(v) if v is not None else None
+    if kernel in vals:
+        return kernel, float(vals[kernel])
+    family = [k for k in vals if k.startswith(kernel[:-1] + ",")]
+    return (family[0], float(vals[family[0]])) if len(family) == 1 else None
 
 
 def hr_launch(rows, head_method):
@@ -524,6 +528,7 @@ def main():
     word = 4 if head_method[0] == "mixed" else 8
     bytes_launch = hr["bytes_per_iter"]
     achieved = bytes_launch / (hr["kernel_us"] * 1e-6) / 1e9
+    traffic = measured_traffic(args.workload, kname + ("double>" if word == 8 else "float>"))
     line = {
         "metric": METRIC,
         "value": hr["iters_per_s"],
@@ -553,9 +558,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload,
-                                        kname + ("double>" if word == 8 else "float>")),
-            "kernel": kname + ("double>" if word == 8 else "float>"),
+            "traffic": traffic[1] if traffic else None,
+            "kernel": traffic[0] if traffic else kname + ("double>" if word == 8 else "float>"),
             "kernel_us": hr["kernel_us"],
             "bytes_per_launch": bytes_launch,
         },

@@ -314,7 +314,7 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
 
 // ST: storage type of the inner solver's vectors (double, or float for an
 // FP32-refined batch).  y, b, D^{-1/2} and the edge weights are FP64 either way.
-template <int L, typename ST>
+template <int L, typename ST, int H>
 __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
   constexpr int ND = L + 1;
   constexpr bool kMixed = std::is_same<ST, float>::value;
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
     read_coef<L>(in->d, i, t, cf);
     SweepArgsT<ST> sa;
     slot_sweep_args<L, ST>(S, i, sa);
-    using SW = Sweep<L, ST, VarOp>;
+    using SW = Sweep<L, ST, VarOp, H>;
     // Chunk by chunk so that the FAST test is uniform over the workgroup.
     constexpr int CH = kThreads * V;
     const bool fast_rows = S.nx % V == 0;
@@ -407,13 +407,22 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
   if (phase == kResid || phase == kFinal) store_partials<ND>(acc, part_out, kMaxStream, lb, lds, red);
 }
 
+template <int L, int H>
+static hipError_t launch_tick_lh(const BatchArgs &a, int blocks, hipStream_t s) {
+  if (a.mixed)
+    hipLaunchKernelGGL((batch_tick_kernel<L, float, H>), dim3(blocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((batch_tick_kernel<L, double, H>), dim3(blocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int L>
 static hipError_t launch_tick_l(const BatchArgs &a, int blocks, hipStream_t s) {
-  if (a.mixed)
-    hipLaunchKernelGGL((batch_tick_kernel<L, float>), dim3(blocks), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((batch_tick_kernel<L, double>), dim3(blocks), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
+  switch (a.hint) {
+    case 0: return launch_tick_lh<L, 0>(a, blocks, s);
+    case kHintLoads | kHintStores: return launch_tick_lh<L, kHintLoads | kHintStores>(a, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_batch_tick(const BatchArgs &a, int blocks, hipStream_t s) {

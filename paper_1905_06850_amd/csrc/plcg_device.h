@@ -73,6 +73,11 @@ constexpr int vec_of() { return 16 / (int)sizeof(S); }
 // Stencil
 // ---------------------------------------------------------------------------
 
+// Vector types for the non-temporal load/store builtins.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+
 // V consecutive values held in FP64 registers; S is the storage type in memory
 // (double, or float for the FP32-stored inner solver), converted on load/store.
 // V is 1, 2 or 4; p is aligned to V elements.
@@ -116,6 +121,55 @@ struct Vals {
 #pragma unroll
       for (int k = 0; k < V; ++k) p[k] = (S)v[k];
     }
+  }
+  // The same accesses with the non-temporal hint.
+  __device__ inline void load_nt(const S *p) {
+    if constexpr (sizeof(S) == 8 && V % 2 == 0) {
+#pragma unroll
+      for (int k = 0; k < V / 2; ++k) {
+        const nt_double2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_double2 *>(p) + k);
+        v[2 * k] = t.x;
+        v[2 * k + 1] = t.y;
+      }
+    } else if constexpr (sizeof(S) == 4 && V == 4) {
+      const nt_float4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(p));
+      v[0] = (double)t.x;
+      v[1] = (double)t.y;
+      v[2] = (double)t.z;
+      v[3] = (double)t.w;
+    } else if constexpr (sizeof(S) == 4 && V == 2) {
+      const nt_float2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_float2 *>(p));
+      v[0] = (double)t.x;
+      v[1] = (double)t.y;
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; ++k) v[k] = (double)__builtin_nontemporal_load(p + k);
+    }
+  }
+  __device__ inline void store_nt(S *p) const {
+    if constexpr (sizeof(S) == 8 && V % 2 == 0) {
+#pragma unroll
+      for (int k = 0; k < V / 2; ++k)
+        __builtin_nontemporal_store(nt_double2{v[2 * k], v[2 * k + 1]},
+                                    reinterpret_cast<nt_double2 *>(p) + k);
+    } else if constexpr (sizeof(S) == 4 && V == 4) {
+      __builtin_nontemporal_store(nt_float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]},
+                                  reinterpret_cast<nt_float4 *>(p));
+    } else if constexpr (sizeof(S) == 4 && V == 2) {
+      __builtin_nontemporal_store(nt_float2{(float)v[0], (float)v[1]},
+                                  reinterpret_cast<nt_float2 *>(p));
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; ++k) __builtin_nontemporal_store((S)v[k], p + k);
+    }
+  }
+  template <bool NT>
+  __device__ inline void ld(const S *p) {
+    if constexpr (NT) load_nt(p); else load(p);
+  }
+  template <bool NT>
+  __device__ inline void st(S *p) const {
+    if constexpr (NT) store_nt(p); else store(p);
   }
   __device__ inline void zero() {
 #pragma unroll
@@ -420,7 +474,7 @@ struct DiagOp {
 // read by consecutive lanes, one coalesced access per entry index for the V
 // rows of a thread.  Both forms add the same products in the same order
 // (padding adds exact zeros).
-template <typename S>
+template <typename S, bool NT = false>
 struct CsrOp {
   const int64_t *rp;
   const int32_t *ci;
@@ -448,7 +502,7 @@ struct CsrOp {
       for (int j = 0; j < ell_k; ++j) {
         const size_t e = (size_t)j * ell_ld + idx;
         Vals<V, double> vv;
-        vv.load(va + e);
+        vv.template ld<NT>(va + e);
         int c[V];
         if constexpr (V == 2) {
           const int2 t = *reinterpret_cast<const int2 *>(ci + e);
@@ -480,10 +534,12 @@ struct CsrOp {
 
 // The recurrences of one p(l)-CG iteration for V consecutive unknowns.  Op is
 // the operator: Op::apply<V, FAST>(z, idx, zc, w) sets w = A z at idx .. idx+V-1.
-template <int L, typename S, typename Op>
+template <int L, typename S, typename Op, int H = 0>
 struct Sweep {
   using Args = SweepArgsT<S>;
   static constexpr int ND = L + 1;
+  static constexpr bool NTL = (H & kHintLoads) != 0;
+  static constexpr bool NTS = (H & kHintStores) != 0;
 
   // Steady state, i >= l: K1 (SpMV of z^{(l)}_i), K4 (all basis recurrences,
   // Eqs. all_z_rec2 and specific_z_rec), K6 (p_t, x_t; Eqs. pdir, x_a2) and
@@ -493,7 +549,7 @@ struct Sweep {
                                        const Coef<L> &cf, double (&acc)[ND]) {
     Vals<V, S> zc, zp;
     zc.load(a.zl[0] + idx);
-    zp.load(a.zl[1] + idx);
+    zp.template ld<NTL>(a.zl[1] + idx);
     double w[V];
     op.template apply<V, FAST>(a.zl[0], idx, zc, w);
     double zn[V];
@@ -504,7 +560,7 @@ struct Sweep {
 #pragma unroll
     for (int m = 1; m <= L - 3; ++m) {
       Vals<V, S> zh;
-      zh.load(a.zl[L - 1 - m] + idx);
+      zh.template ld<NTL>(a.zl[L - 1 - m] + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[m] += zn[v] * zh.v[v];
     }
@@ -514,13 +570,13 @@ struct Sweep {
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
       Vals<V, S> ck, pk;
-      ck.load(a.zk_cur[k] + idx);
-      if (t >= 1) pk.load(a.zk_prev[k] + idx); else pk.zero();
+      ck.template ld<NTL>(a.zk_cur[k] + idx);
+      if (t >= 1) pk.template ld<NTL>(a.zk_prev[k] + idx); else pk.zero();
       Vals<V, S> nk;
       const double sk = cf.sig[k] - cf.gam;
 #pragma unroll
       for (int v = 0; v < V; ++v) nk.v[v] = ((above[v] + sk * ck.v[v]) - cf.dm1 * pk.v[v]) * cf.inv_del;
-      nk.store(a.zk_prev[k] + idx);
+      nk.template st<NTS>(a.zk_prev[k] + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) above[v] = ck.v[v];
       if (k == 0) {
@@ -537,20 +593,20 @@ struct Sweep {
       for (int v = 0; v < V; ++v) pv.v[v] = vt[v] * cf.inv_eta;
     } else {
       Vals<V, S> xv;
-      pv.load(a.p + idx);
-      xv.load(a.x + idx);
+      pv.template ld<NTL>(a.p + idx);
+      xv.template ld<NTL>(a.x + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         xv.v[v] += cf.zm1 * pv.v[v];
         pv.v[v] = (vt[v] - cf.dm1 * pv.v[v]) * cf.inv_eta;
       }
-      xv.store(a.x + idx);
+      xv.template st<NTS>(a.x + idx);
     }
-    pv.store(a.p + idx);
+    pv.template st<NTS>(a.p + idx);
     Vals<V, S> out;
 #pragma unroll
     for (int v = 0; v < V; ++v) out.v[v] = zn[v];
-    out.store(a.zl_out + idx);
+    out.template st<NTS>(a.zl_out + idx);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       acc[0] += zn[v] * vnew[v];                    // (z_{i+1}, v_{t+1})
@@ -577,19 +633,19 @@ struct Sweep {
       const int h = L - 1 - m;
       if (h <= i) {
         Vals<V, S> zh;
-        zh.load(a.zl[h] + idx);
+        zh.template ld<NTL>(a.zl[h] + idx);
 #pragma unroll
         for (int v = 0; v < V; ++v) acc[m] += zn.v[v] * zh.v[v];
       }
     }
     if (a.v0 != nullptr) {
       Vals<V, S> vz;
-      vz.load(a.v0 + idx);
+      vz.template ld<NTL>(a.v0 + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[0] += zn.v[v] * vz.v[v];
     }
-    zn.store(a.zl_out + idx);
-    if (a.copy_dst != nullptr) zn.store(a.copy_dst + idx);
+    zn.template st<NTS>(a.zl_out + idx);
+    if (a.copy_dst != nullptr) zn.template st<NTS>(a.copy_dst + idx);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       acc[L] += zn.v[v] * zn.v[v];

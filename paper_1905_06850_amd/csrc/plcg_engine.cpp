@@ -46,12 +46,30 @@ plcg_status fail(plcg_status code, const std::string &msg) {
   } while (0)
 
 constexpr int kDefaultCheck = 64;
+constexpr long long kCacheBytes = 256LL << 20;   // MI355X memory-side (Infinity) cache
+constexpr long long kLargeVector = 96LL << 20;   // vectors worth storing non-temporally
 // Iterations one resident launch may run (about a second for the largest
 // resident systems); longer runs use the streaming kernels.
 constexpr int kResIterCap = 1 << 20;
 constexpr int kDefaultRestarts = 100;
 
 // Streaming workgroups of a launch: one per chunk up to kMaxStream, a multiple of 8.
+// Streaming cache hints for the sweeps of a solver whose vectors are `word`
+// bytes per unknown (measured on 2048^2 and 256^3 Poisson, the 2048^2 CSR
+// matrix and diagonal toy): non-temporal loads pay once the vectors and
+// operator data a solver streams outgrow the 256 MiB memory-side cache (up to
+// 12 % per iteration), and cost up to 16 % while they fit, because the
+// alternating sweep order then finds them there; non-temporal stores pay
+// only when each vector alone is large (3D 256^3 FP64: another 3-5 %) and cost
+// up to 9 % at 2048^2, whose freshly written vectors the next sweep re-reads
+// from that cache.
+int pick_hint(long long n, int method, int l, int R, int word, long long op_bytes) {
+  const long long vecs = method == PLCG_METHOD_CG ? 5 : 2LL * l + R + 2;
+  const long long bytes = vecs * n * word + op_bytes;
+  if (bytes <= kCacheBytes) return 0;
+  return n * word > kLargeVector ? (kHintLoads | kHintStores) : kHintLoads;
+}
+
 // Operator kind numbering of the kernels: 0 2D stencil, 1 3D stencil, 2 diagonal, 3 CSR.
 int op_kind_index(int kind) {
   return kind == PLCG_OP_STENCIL3D7 ? 1 : kind == PLCG_OP_DIAG ? 2 : kind == PLCG_OP_CSR ? 3 : 0;
@@ -83,6 +101,7 @@ struct plcg_handle {
   int n = 0, nchunks = 0, blocks = 0;
   bool d3 = false;
   int res_kind = -1;              // operator kind of the resident kernels; -1: streaming
+  int hint64 = 0, hint32 = 0;     // streaming cache hints of the FP64 / FP32-stored sweeps
   bool ran_resident = false;      // the current solve ran resident launches
   OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0};   // library copies of d / the CSR arrays
   bool jacobi = false;            // CSR solved in Jacobi-scaled form D^{-1/2} A D^{-1/2}
@@ -282,6 +301,7 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
   a.nparts_in = i >= 1 ? h->blocks : 0;
   a.pstride = kMaxStream;
   a.work = 1;
+  a.hint = sizeof(S) == 8 ? h->hint64 : h->hint32;
 }
 
 // r = b - A x (r may be NULL) and ||r||^2 into state copy `slot`; mode as in
@@ -545,6 +565,7 @@ plcg_status solve_cg(plcg_handle *h, const double *b, double *x, double tol, int
   a.nstream = h->blocks;
   a.nparts_in = h->blocks;
   a.pstride = kMaxStream;
+  a.hint = h->hint64;
   // 3D grids whose planes are whole chunks (and even nx): sweep A marches each
   // chunk-sized tile through zseg planes, about one tile-segment per workgroup.
   a.zseg = 0;
@@ -981,6 +1002,13 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     h->od.dg = dg;
   }
   if (e == PLCG_OK && op->kind == PLCG_OP_CSR) e = copy_csr(h, op);
+  {
+    const long long op_bytes = op->kind == PLCG_OP_CSR  ? 12LL * op->nnz
+                               : op->kind == PLCG_OP_DIAG ? 8LL * n
+                                                          : 0;
+    h->hint64 = pick_hint(n, h->method, h->l, h->R, 8, op_bytes);
+    h->hint32 = pick_hint(n, h->method, h->l, h->R, 4, op_bytes);
+  }
   // The resident kernels index the matrix with 32-bit offsets.
   const long long stored =
       h->od.ell_k > 0 ? (long long)h->od.ell_k * h->od.ell_ld : (long long)op->nnz;

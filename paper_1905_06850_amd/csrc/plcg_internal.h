@@ -67,6 +67,15 @@ struct DevState {
   int32_t pad[3];
 };
 
+// Streaming cache hints of a sweep (bits): kHintLoads - the vectors a thread
+// reads only at its own unknowns are loaded non-temporally (never the operator's
+// input vector, whose rows and planes other workgroups read again through L2);
+// kHintStores - every vector is stored non-temporally.  The host picks none,
+// kHintLoads, or both, by working-set size: they pay where the vectors cannot
+// stay in the memory-side cache anyway.
+constexpr int kHintLoads = 1;
+constexpr int kHintStores = 2;
+
 // Arguments of one p(l)-CG sweep (iteration i of Alg. 1).  S is the storage
 // type of the vectors (double; float for the FP32-stored inner solver of the
 // mixed-precision mode).  Partial sums and the scalar state are always FP64.
@@ -92,6 +101,7 @@ struct SweepArgsT {
   int32_t nparts_in;         // partials per product in part_in
   int32_t pstride;
   int32_t work;              // 0: only carry the scalar state forward
+  int32_t hint;              // streaming cache hints (kHint* bits)
 };
 using SweepArgs = SweepArgsT<double>;
 
@@ -106,7 +116,7 @@ struct CgArgs {
   HostStatus *hs;
   int32_t k, n, nx, ny, nz, d3, nchunks, nstream, nparts_in, pstride, work;
   int32_t zseg;              // > 0: 3D sweep A marches tiles through zseg planes
-  int32_t pad;
+  int32_t hint;              // streaming cache hints (kHint* bits)
 };
 
 // Resident solves (plcg_resident.hip): one workgroup of kResThreads runs a whole
@@ -243,7 +253,8 @@ struct BatchArgs {
   SlotReport *reports;     // mapped host memory
   const uint64_t *tickets; // per slot
   int32_t tick, l;
-  int32_t mixed, pad;      // FP32-refined batch: vectors stored in FP32
+  int32_t mixed;           // FP32-refined batch: vectors stored in FP32
+  int32_t hint;            // streaming cache hints of the sweep phase (kHint* bits)
 };
 
 hipError_t launch_batch_tick(const BatchArgs &a, int blocks, hipStream_t s);

@@ -30,12 +30,12 @@ namespace plcg {
 // vector: 2 doubles, or 4 floats for the FP32-stored inner solver).
 // fast_rows: full chunks may take the operator's FAST form; order: the chunk
 // visiting order.
-template <int L, typename ST, typename Op>
+template <int L, typename ST, int H, typename Op>
 __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fast_rows,
                                   const ChunkOrder &order) {
   constexpr int V = vec_of<ST>();
   constexpr int CH = kThreads * V;
-  using S = Sweep<L, ST, Op>;
+  using S = Sweep<L, ST, Op, H>;
   constexpr int ND = S::ND;
   __shared__ double lds[4 * ND];
   __shared__ double red[ND];
@@ -93,22 +93,23 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   store_partials<ND>(acc, a.part_out, a.pstride, blockIdx.x - first, lds, red);
 }
 
-template <int L, bool D3, typename ST>
+template <int L, bool D3, typename ST, int H>
 __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) {
   const Grid g{a.n, a.nx, a.ny, a.nz};
-  plcg_sweep<L, ST>(a, ConstOp<D3, ST>{g}, a.nx % vec_of<ST>() == 0,
-                    chunk_order(g, D3, kThreads * vec_of<ST>()));
+  plcg_sweep<L, ST, H>(a, ConstOp<D3, ST>{g}, a.nx % vec_of<ST>() == 0,
+                       chunk_order(g, D3, kThreads * vec_of<ST>()));
 }
 
-template <int L, typename ST>
+template <int L, typename ST, int H>
 __global__ __launch_bounds__(kThreads) void plcg_diag_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST>(a, DiagOp<ST>{a.od.dg}, true, ChunkOrder{0, 0, 0});
+  plcg_sweep<L, ST, H>(a, DiagOp<ST>{a.od.dg}, true, ChunkOrder{0, 0, 0});
 }
 
-template <int L, typename ST>
+template <int L, typename ST, int H>
 __global__ __launch_bounds__(kThreads) void plcg_csr_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST>(a, CsrOp<ST>{a.od.rp, a.od.ci, a.od.va, a.od.ell_k, a.od.ell_ld}, true,
-                    ChunkOrder{0, 0, 0});
+  plcg_sweep<L, ST, H>(
+      a, CsrOp<ST, (H & kHintLoads) != 0>{a.od.rp, a.od.ci, a.od.va, a.od.ell_k, a.od.ell_ld},
+      true, ChunkOrder{0, 0, 0});
 }
 
 // ---------------------------------------------------------------------------
@@ -146,8 +147,9 @@ __device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds,
   return sh.status == kRunning && a.work;
 }
 
-template <bool D3>
+template <bool D3, int H>
 __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
+  constexpr bool NTS = (H & kHintStores) != 0;
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
@@ -232,8 +234,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
         pn.v[1] = c1;
         qv.v[0] = diag * c0 - s0;
         qv.v[1] = diag * c1 - s1;
-        pn.store(a.p_new + idx0);
-        qv.store(a.q + idx0);
+        pn.template st<NTS>(a.p_new + idx0);
+        qv.template st<NTS>(a.q + idx0);
         acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
         m0 = c0;
         m1 = c1;
@@ -293,8 +295,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       pn.v[1] = c1;
       qv.v[0] = diag * c0 - s0;
       qv.v[1] = diag * c1 - s1;
-      pn.store(a.p_new + idx0);
-      qv.store(a.q + idx0);
+      pn.template st<NTS>(a.p_new + idx0);
+      qv.template st<NTS>(a.q + idx0);
       acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
       continue;
     }
@@ -327,7 +329,10 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
 }
 
 // Sweep A for the diagonal operator: q = d * p_k.
+template <int H>
 __global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
+  constexpr bool NTL = (H & kHintLoads) != 0;
+  constexpr bool NTS = (H & kHintStores) != 0;
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
@@ -340,13 +345,13 @@ __global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
     const int idx = it.c * kChunk + threadIdx.x * kVec;
     if (idx + 1 < a.n) {
       Vals<2> r, d, pn, q;
-      r.load(a.r + idx);
-      d.load(a.od.dg + idx);
+      r.template ld<NTL>(a.r + idx);
+      d.template ld<NTL>(a.od.dg + idx);
       if (first) {
         pn = r;
       } else {
         Vals<2> po;
-        po.load(a.p_old + idx);
+        po.template ld<NTL>(a.p_old + idx);
 #pragma unroll
         for (int v = 0; v < 2; ++v) pn.v[v] = r.v[v] + beta * po.v[v];
       }
@@ -355,8 +360,8 @@ __global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
         q.v[v] = d.v[v] * pn.v[v];
         acc[0] += pn.v[v] * q.v[v];
       }
-      pn.store(a.p_new + idx);
-      q.store(a.q + idx);
+      pn.template st<NTS>(a.p_new + idx);
+      q.template st<NTS>(a.q + idx);
     } else if (idx < a.n) {
       const double pc = first ? a.r[idx] : a.r[idx] + beta * a.p_old[idx];
       const double q = a.od.dg[idx] * pc;
@@ -370,7 +375,10 @@ __global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
 
 // Sweep A for a CSR operator: q = A p_k with p_k formed at every column index
 // from r and p_{k-1}.
+template <int H>
 __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
+  constexpr bool NTL = (H & kHintLoads) != 0;
+  constexpr bool NTS = (H & kHintStores) != 0;
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
@@ -398,7 +406,7 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
       for (int j = 0; j < a.od.ell_k; ++j) {
         const size_t e = (size_t)j * a.od.ell_ld + idx0;
         Vals<2> vv;
-        vv.load(a.od.va + e);
+        vv.template ld<NTL>(a.od.va + e);
         const int2 cc = *reinterpret_cast<const int2 *>(a.od.ci + e);
         q0 += vv.v[0] * pk1(cc.x);
         q1 += vv.v[1] * pk1(cc.y);
@@ -408,8 +416,8 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
       pn.v[1] = c1;
       qv.v[0] = q0;
       qv.v[1] = q1;
-      pn.store(a.p_new + idx0);
-      qv.store(a.q + idx0);
+      pn.template st<NTS>(a.p_new + idx0);
+      qv.template st<NTS>(a.q + idx0);
       acc[0] += c0 * q0 + c1 * q1;
       continue;
     }
@@ -439,7 +447,10 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
 // Sweep B of iteration k.  Prologue: alpha_k = rho_k / (p_k, q) from sweep A
 // (breakdown if (p_k, A p_k) <= 0).  Then x += alpha p_k, r -= alpha q and the
 // product (r_{k+1}, r_{k+1}).
+template <int H>
 __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
+  constexpr bool NTL = (H & kHintLoads) != 0;
+  constexpr bool NTS = (H & kHintStores) != 0;
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
@@ -470,18 +481,18 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
     const int idx = it.at() * kChunk + threadIdx.x * kVec;
     if (idx + 1 < a.n) {
       Vals<2> x, p, r, q;
-      x.load(a.x + idx);
-      p.load(a.p_new + idx);
-      r.load(a.r + idx);
-      q.load(a.q + idx);
+      x.template ld<NTL>(a.x + idx);
+      p.template ld<NTL>(a.p_new + idx);
+      r.template ld<NTL>(a.r + idx);
+      q.template ld<NTL>(a.q + idx);
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         x.v[v] += alpha * p.v[v];
         r.v[v] -= alpha * q.v[v];
         acc[0] += r.v[v] * r.v[v];
       }
-      x.store(a.x + idx);
-      r.store(a.r + idx);
+      x.template st<NTS>(a.x + idx);
+      r.template st<NTS>(a.r + idx);
     } else if (idx < a.n) {
       a.x[idx] += alpha * a.p_new[idx];
       const double rv = a.r[idx] - alpha * a.q[idx];
@@ -638,18 +649,28 @@ static int simple_blocks(int64_t n) {
   return (int)b;
 }
 
-template <int L, typename S>
-static hipError_t launch_sweep_l(const SweepArgsT<S> &a, hipStream_t s) {
+template <int L, typename S, int H>
+static hipError_t launch_sweep_lh(const SweepArgsT<S> &a, hipStream_t s) {
   const int grid = a.nstream + (L >= 2 ? 1 : 0);
   if (a.od.rp != nullptr)
-    hipLaunchKernelGGL((plcg_csr_sweep_kernel<L, S>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_csr_sweep_kernel<L, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
   else if (a.od.dg != nullptr)
-    hipLaunchKernelGGL((plcg_diag_sweep_kernel<L, S>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_diag_sweep_kernel<L, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
   else if (a.d3)
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, false, S>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, false, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+template <int L, typename S>
+static hipError_t launch_sweep_l(const SweepArgsT<S> &a, hipStream_t s) {
+  switch (a.hint) {
+    case 0: return launch_sweep_lh<L, S, 0>(a, s);
+    case kHintLoads: return launch_sweep_lh<L, S, kHintLoads>(a, s);
+    case kHintLoads | kHintStores: return launch_sweep_lh<L, S, kHintLoads | kHintStores>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename S>
@@ -675,21 +696,41 @@ hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s) {
   return launch_sweep_any<float>(a, s);
 }
 
-hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s) {
+template <int H>
+static hipError_t launch_cg_a_h(const CgArgs &a, hipStream_t s) {
   if (a.od.rp != nullptr)
-    hipLaunchKernelGGL(cg_csr_sweep_a_kernel, dim3(a.nstream), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((cg_csr_sweep_a_kernel<H>), dim3(a.nstream), dim3(kThreads), 0, s, a);
   else if (a.od.dg != nullptr)
-    hipLaunchKernelGGL(cg_diag_sweep_a_kernel, dim3(a.nstream), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((cg_diag_sweep_a_kernel<H>), dim3(a.nstream), dim3(kThreads), 0, s, a);
   else if (a.d3)
-    hipLaunchKernelGGL((cg_sweep_a_kernel<true>), dim3(a.nstream), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((cg_sweep_a_kernel<true, H>), dim3(a.nstream), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((cg_sweep_a_kernel<false>), dim3(a.nstream), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((cg_sweep_a_kernel<false, H>), dim3(a.nstream), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s) {
+  switch (a.hint) {
+    case 0: return launch_cg_a_h<0>(a, s);
+    case kHintLoads: return launch_cg_a_h<kHintLoads>(a, s);
+    case kHintLoads | kHintStores: return launch_cg_a_h<kHintLoads | kHintStores>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int H>
+static hipError_t launch_cg_b_h(const CgArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL((cg_sweep_b_kernel<H>), dim3(a.nstream), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(cg_sweep_b_kernel, dim3(a.nstream), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
+  switch (a.hint) {
+    case 0: return launch_cg_b_h<0>(a, s);
+    case kHintLoads: return launch_cg_b_h<kHintLoads>(a, s);
+    case kHintLoads | kHintStores: return launch_cg_b_h<kHintLoads | kHintStores>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_residual(const double *b, const double *x, double *r, double *part_out, int n,
