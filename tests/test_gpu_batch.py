@@ -65,8 +65,8 @@ def run_batch(dev, systems, l, tol, maxit=20000, use_graph=False, cpb=0, max_slo
             s = systems[k]
             bt = torch.from_numpy(s["b"]).to(dev)
             xt = torch.zeros(s["n"], dtype=torch.float64, device=dev)
-            t = batch.add(s["dims"], bt.data_ptr(), xt.data_ptr(), tol, maxit, stream,
-                          s["cx"], s["cy"], s["cz"])
+            t = batch.add(s["dims"], bt.data_ptr(), xt.data_ptr(), tol, s.get("maxit", maxit),
+                          stream, s["cx"], s["cy"], s["cz"])
             if t is None:
                 break
             bufs.append((bt, xt))
@@ -121,6 +121,23 @@ def test_alone_equals_in_the_mix(dev):
     for k in range(len(systems)):
         assert np.array_equal(waves[k][1], mix[k][1])
         assert np.array_equal(graph[k][1], mix[k][1])
+
+
+def test_cache_hints_leave_results_unchanged(dev):
+    """A large system admitted beside the small ones (3.1 M unknowns, ~300 MB of
+    vectors and weights) makes the batch stream with non-temporal hints; the
+    small systems' results are bitwise those of the same systems alone (hints
+    change where lines are cached, never a value)."""
+    systems = [_system(*s) for s in SYSTEMS[:4]]
+    ballast = _system((2048, 1536), 17, 18)
+    ballast["maxit"] = 40
+    alone = run_batch(dev, systems, 2, 1e-9)
+    mixed = run_batch(dev, systems + [ballast], 2, 1e-9)
+    assert mixed[len(systems)][0].iters == 40
+    for k in range(len(systems)):
+        assert alone[k][0].reason == mixed[k][0].reason == 1
+        assert alone[k][0].iters == mixed[k][0].iters
+        assert np.array_equal(alone[k][1], mixed[k][1])
 
 
 def test_autotune_keeps_results(dev):

@@ -317,6 +317,35 @@ def test_deterministic_and_submit_poll(dev):
     s.close()
 
 
+@pytest.mark.parametrize("method,l,dims,launch", [("plcg", 2, (96, 80), "streaming"),
+                                                  ("cg", 1, (96, 80), "streaming"),
+                                                  ("plcg", 3, (64, 64, 80), "streaming"),
+                                                  ("plcg", 2, (64, 64), "resident"),
+                                                  ("cg", 1, (64, 64), "resident")])
+def test_bitwise_reproducible_10_replays(dev, method, l, dims, launch):
+    """Ten solves of the same system give the same bits (every reduction is a
+    fixed-order sum; no atomics on values)."""
+    plcg = _plcg()
+    n = int(np.prod(dims))
+    b = synth.uniform(n, 41)
+    s = plcg.Solver(_kind(dims), dims, method=method, l=l, lmin=0.0,
+                    lmax=8.0 if len(dims) == 2 else 12.0, launch=launch)
+    bt = torch.from_numpy(b).to(dev)
+    xt = torch.zeros(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    first = None
+    for rep in range(10):
+        xt.zero_()
+        r = s.solve(bt, xt, 1e-9, 20000, stream)
+        assert r.reason == 1
+        x = xt.cpu().numpy()
+        if first is None:
+            first = (r.iters, r.rec_relres, x)
+        else:
+            assert (r.iters, r.rec_relres) == first[:2] and np.array_equal(x, first[2]), rep
+    s.close()
+
+
 def test_timing_counts_sweeps(dev):
     dims = (64, 64)
     b = synth.uniform(4096, 2)
