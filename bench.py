@@ -375,8 +375,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the solver has no multi-GPU "
-              "path (see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print("bench.py: libplcg solves on one GPU; it has no multi-GPU path (a system "
+              "would shard by slabs with one halo exchange and one small all-reduce per "
+              "iteration, not implemented), so only --gpus 1 runs.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
