@@ -241,7 +241,7 @@ __device__ void owner_step(const BatchArgs &a, int slot, const SlotDesc &S, cons
       case kSweep: {
         DevState &d = b.d;
         const int i = b.i;
-        if (i >= 1 && d.status == kRunning) engine_column(d, red, i, nullptr);
+        if (i >= 1 && d.status == kRunning) engine_column_l<L>(d, red, i, nullptr);
         // The next sweep has t' = i + 1 - l; stop once nothing is left to do.
         // FP32-refined: every end of the inner solve adds its correction
         // (kCorrect) and returns to the FP64 residual, where kStart decides.

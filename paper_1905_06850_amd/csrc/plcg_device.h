@@ -337,7 +337,7 @@ __device__ inline void publish(const DevState &s, HostStatus *hs, double zeta, i
 // Scalar engine of p(l)-CG: one column of G, one column of T, one LU step
 // ---------------------------------------------------------------------------
 
-__device__ inline double &gref(DevState &s, int r, int c) {
+__host__ __device__ inline double &gref(DevState &s, int r, int c) {
   return s.g[c % kGRing][r - c + 2 * kLMax];
 }
 
@@ -347,8 +347,11 @@ __device__ inline double &gref(DevState &s, int r, int c) {
 // c-l+1 .. c-1 and the square root for the diagonal (Alg. 1, update of G);
 // then gamma_t, delta_t (Eqs. haa1, haa3) and eta_t, zeta_t (Eq. LU and the
 // recursion for zeta) for t = c-1, and the breakdown / convergence tests.
-// Runs in one thread.
-__device__ inline void engine_column(DevState &s, const double *raw, int c, double *hist) {
+// Runs in one thread.  This is the form for any l; the kernels run
+// engine_column_l<L> below, which a host replay test checks against it, state
+// byte for state byte, on recorded dot-product streams.
+__host__ __device__ inline void engine_column(DevState &s, const double *raw, int c,
+                                              double *hist) {
   const int l = s.l;
   const int t = c - 1;
   const int lo = c - 2 * l > 0 ? c - 2 * l : 0;
@@ -393,6 +396,99 @@ __device__ inline void engine_column(DevState &s, const double *raw, int c, doub
       broken = !(isfinite(eta) && eta > 0.0 && isfinite(zeta));
     }
   }
+  s.cols = c;
+  if (broken) {
+    s.status = kBroken;
+    s.last_t = t - 1;
+    return;
+  }
+  s.gam[t % kTRing] = gam;
+  s.dlt[t % kTRing] = dlt;
+  s.eta[t % kTRing] = eta;
+  s.zeta[t % kTRing] = zeta;
+  if (hist != nullptr && t < s.hist_cap) {
+    hist[4 * t + 0] = gam;
+    hist[4 * t + 1] = dlt;
+    hist[4 * t + 2] = eta;
+    hist[4 * t + 3] = zeta;
+  }
+  if (t >= 1 && fabs(zeta) < s.abs_tol) {
+    s.status = kConverged;
+    s.last_t = t;
+  }
+}
+
+// engine_column for a pipeline length L known at compile time: the same
+// operations on the same operands in the same order (so the same bits), with
+// the new column c held in registers (row r at gc[r - c + 2L]) instead of
+// being written and re-read through the state's G ring, and stored once at the
+// end.  Finalised columns are only read, so their loads need not wait for the
+// new column's updates.
+template <int L>
+__host__ __device__ inline void engine_column_l(DevState &s, const double *raw, int c,
+                                                double *hist) {
+  constexpr int W = 2 * L + 1;
+  const int t = c - 1;
+  double gc[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q) gc[q] = 0.0;
+  // rows r = c-2L .. c-L-1 from Eq. (symmetry_G): g_{r,c} = g_{c-L, r+L}
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    const int r = c - 2 * L + q;
+    if (r >= 0) gc[q] = gref(s, c - L, r + L);
+  }
+  if (c - L >= 0) gc[L] = raw[0];
+#pragma unroll
+  for (int m = 1; m <= L; ++m)
+    if (c - L + m >= 0) gc[L + m] = raw[m];
+  // forward substitution for rows j = c-L+1 .. c-1, in increasing j
+#pragma unroll
+  for (int m = 1; m < L; ++m) {
+    const int j = c - L + m;
+    if (j < 0) continue;
+    double v = gc[L + m];
+#pragma unroll
+    for (int q = 0; q < L + m; ++q) {
+      const int k = c - 2 * L + q;
+      if (k >= 0) v -= gref(s, k, j) * gc[q];
+    }
+    gc[L + m] = v / gref(s, j, j);
+  }
+  double arg = gc[2 * L];
+#pragma unroll
+  for (int q = 0; q < 2 * L; ++q) {
+    const int k = c - 2 * L + q;
+    if (k >= 0) arg -= gc[q] * gc[q];
+  }
+  bool broken = !(isfinite(arg) && arg > 0.0);
+  double gam = 0.0, dlt = 0.0, eta = 0.0, zeta = 0.0;
+  if (!broken) {
+    gc[2 * L] = sqrt(arg);
+    const double gtt = gref(s, t, t);
+    const double corr = t >= 1 ? gref(s, t - 1, t) * s.dlt[(t - 1) % kTRing] : 0.0;
+    if (t < L) {
+      gam = (gc[2 * L - 1] + s.sigma[t] * gtt - corr) / gtt;
+      dlt = gc[2 * L] / gtt;
+    } else {
+      gam = (gtt * s.gam[(t - L) % kTRing] + gc[2 * L - 1] * s.dlt[(t - L) % kTRing] - corr) / gtt;
+      dlt = (gc[2 * L] * s.dlt[(t - L) % kTRing]) / gtt;
+    }
+    broken = !(isfinite(gam) && isfinite(dlt) && dlt > 0.0);
+    if (!broken) {
+      if (t == 0) {
+        eta = gam;
+        zeta = s.beta;
+      } else {
+        const double lam = s.dlt[(t - 1) % kTRing] / s.eta[(t - 1) % kTRing];
+        eta = gam - lam * s.dlt[(t - 1) % kTRing];
+        zeta = -lam * s.zeta[(t - 1) % kTRing];
+      }
+      broken = !(isfinite(eta) && eta > 0.0 && isfinite(zeta));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < W; ++q) gref(s, c - 2 * L + q, c) = gc[q];
   s.cols = c;
   if (broken) {
     s.status = kBroken;

@@ -50,7 +50,7 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
     state_load(a.st_in, &sh);
     if (a.i >= 1 && sh.status == kRunning && a.nparts_in > 0) {
       sum_partials<ND>(a.part_in, a.nparts_in, a.pstride, lds, red);
-      if (threadIdx.x == 0) engine_column(sh, red, a.i, owner ? a.hist : nullptr);
+      if (threadIdx.x == 0) engine_column_l<L>(sh, red, a.i, owner ? a.hist : nullptr);
       __syncthreads();
     }
     if (owner) {

@@ -104,7 +104,7 @@ __device__ inline void res_state_store(const DevState *src, DevState *dst) {
 
 // One run of Alg. 1: sweeps i = 0 .. imax, with the same per-unknown arithmetic
 // as Sweep<L>::steady / startup (K1, K4, K6, K5) and the same scalar engine
-// (engine_column: update of G, Eqs. haa1/haa3, LU, breakdown and stopping
+// (engine_column_l: update of G, Eqs. haa1/haa3, LU, breakdown and stopping
 // tests).
 //
 // Wave 0 is the owner: it adds up the products of each sweep and finalises
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kResThreads) void plcg_resident_kernel(ResArgs a) {
         double raw[ND];
 #pragma unroll
         for (int m = 0; m < ND; ++m) raw[m] = waves_total<ND>(red[(i - 1) & 1], m, kResWaves - 1);
-        if (tid == 0) engine_column(sh, raw, i, a.hist);
+        if (tid == 0) engine_column_l<L>(sh, raw, i, a.hist);
       }
       if (tid == 0) {
         ctl[i & 1][0] = sh.status;
