@@ -260,10 +260,32 @@ __device__ inline void apply_stencil(const S *z, int idx, const Vals<V, S> &zc, 
 // Deterministic block reductions
 // ---------------------------------------------------------------------------
 
+// v from the lane `CTRL` selects (a DPP lane pattern), 0 in the rows that
+// ROWS leaves out.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane (called by all 64).
+// Within each row of 16 lanes: neighbours (quad_perm [1,0,3,2]), pairs
+// (quad_perm [2,3,0,1]), half-row mirror, row mirror - after each step every
+// lane of the group holds the group's sum; then row 0's sum is added into row
+// 1 and row 2's into row 3 (row_bcast:15), rows 0+1 into row 3 (row_bcast:31),
+// and lane 63's total is broadcast.  Data-parallel-primitive moves instead of
+// LDS permutes: a few cycles per step.  Fixed order, so the same bits each time.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_move<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xF>(v);    // row_half_mirror
+  v += dpp_move<0x140, 0xF>(v);    // row_mirror
+  v += dpp_move<0x142, 0xA>(v);    // row_bcast:15 into rows 1, 3
+  v += dpp_move<0x143, 0xC>(v);    // row_bcast:31 into rows 2, 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Sum acc[0..ND-1] over the workgroup; out[] (LDS) holds the result afterwards.

@@ -8,8 +8,8 @@
 // the same XCD and hit its L2.
 //
 // Reductions: a kernel never waits for the other workgroups of the same launch.
-// Each workgroup reduces its products in a fixed order (per-thread sums, wave
-// butterfly, waves in order) and stores one partial per product.  The partials
+// Each workgroup reduces its products in a fixed order (per-thread sums,
+// wave_sum, waves in order) and stores one partial per product.  The partials
 // are added up by the next launch, after the kernel boundary has made them
 // visible: for p(1)-CG and classic CG, whose next iteration needs the result at
 // once, every workgroup adds them itself (same order, so every workgroup gets

@@ -7,8 +7,8 @@
 // threads keeps every vector of the method in registers (V unknowns per
 // streaming thread, strided by the number of streaming threads) and shares only
 // the vector the operator is applied to, through LDS.  The reductions stay inside the
-// workgroup: a butterfly within each wave, then one over the wave sums, so a
-// solve is bitwise reproducible.
+// workgroup: wave_sum within each wave, then once more over the wave sums, so
+// a solve is bitwise reproducible.
 //
 // Synchronisation per iteration (workgroup barriers):
 //   p(1)-CG: 2 - the coefficients of sweep i need the products of sweep i-1;
@@ -79,9 +79,9 @@ __device__ inline double res_apply(const double *z, int p, double zc, const Grid
   }
 }
 
-// Sum of the 16 wave sums of product m: lane w loads wave w's sum and the
-// wave adds them with the butterfly, so every lane of every wave that calls
-// this gets the same bits.
+// Sum of the wave sums of product m: lane w loads wave w's sum and the wave
+// adds them with wave_sum, so every lane of every wave that calls this gets the
+// same bits.
 template <int ND>
 __device__ inline double waves_total(const double (*red)[ND], int m, int nwaves = kResWaves) {
   const int lane = threadIdx.x & 63;
