@@ -64,8 +64,8 @@ struct VarOp {
       const int zz = d3 ? rest / ny : 0;
       const int plane = nx * ny;
       const int lane = threadIdx.x & 63;
-      double left = __shfl_up(zc.v[V - 1], 1, 64);    // z[idx-1] held by the previous lane
-      double right = __shfl_down(zc.v[0], 1, 64);     // z[idx+V] held by the next lane
+      double left = lane_prev(zc.v[V - 1]);    // z[idx-1] held by the previous lane
+      double right = lane_next(zc.v[0]);       // z[idx+V] held by the next lane
       if (lane == 0 && x > 0) left = (double)z[idx - 1];
       if (lane == 63 && x + V < nx) right = (double)z[idx + V];
       const int xe = rest * (nx + 1) + x;             // edge left of idx in its row

@@ -7,6 +7,20 @@
 
 namespace plcg {
 
+// v from the lane `CTRL` selects (a DPP lane pattern), 0 in the rows that
+// ROWS leaves out, and in lanes whose source lies outside the wave.  All 64
+// lanes must be active.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// v of the previous lane of the wave (wave_shr:1; 0 in lane 0) and of the next
+// lane (wave_shl:1; 0 in lane 63).
+__device__ inline double lane_prev(double v) { return dpp_move<0x138, 0xF>(v); }
+__device__ inline double lane_next(double v) { return dpp_move<0x130, 0xF>(v); }
+
 // ---------------------------------------------------------------------------
 // Chunk scheduling
 // ---------------------------------------------------------------------------
@@ -211,8 +225,8 @@ __device__ inline void apply_stencil(const S *z, int idx, const Vals<V, S> &zc, 
     const int rest = idx / g.nx;
     const int y = D3 ? rest % g.ny : rest;
     const int lane = threadIdx.x & 63;
-    double left = __shfl_up(zc.v[V - 1], 1, 64);   // z[idx-1] held by the previous lane
-    double right = __shfl_down(zc.v[0], 1, 64);    // z[idx+V] held by the next lane
+    double left = lane_prev(zc.v[V - 1]);   // z[idx-1] held by the previous lane
+    double right = lane_next(zc.v[0]);      // z[idx+V] held by the next lane
     if (lane == 0 && x > 0) left = (double)z[idx - 1];
     if (lane == 63 && x + V < g.nx) right = (double)z[idx + V];
     double s[V];
@@ -259,15 +273,6 @@ __device__ inline void apply_stencil(const S *z, int idx, const Vals<V, S> &zc, 
 // ---------------------------------------------------------------------------
 // Deterministic block reductions
 // ---------------------------------------------------------------------------
-
-// v from the lane `CTRL` selects (a DPP lane pattern), 0 in the rows that
-// ROWS leaves out.
-template <int CTRL, int ROWS>
-__device__ inline double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
 
 // Sum over the 64 lanes of a wave, returned to every lane (called by all 64).
 // Within each row of 16 lanes: neighbours (quad_perm [1,0,3,2]), pairs

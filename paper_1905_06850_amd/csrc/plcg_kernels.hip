@@ -204,8 +204,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
           n0 = 0.0;
           n1 = 0.0;
         }
-        double left = __shfl_up(c1, 1, 64);
-        double right = __shfl_down(c0, 1, 64);
+        double left = lane_prev(c1);
+        double right = lane_next(c0);
         if (lane == 0 && x > 0) left = pk1(idx0 - 1);
         if (lane == 63 && x + 2 < g.nx) right = pk1(idx0 + 2);
         double s0 = (x > 0 ? left : 0.0) + c1;
@@ -259,8 +259,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       const int rest = idx0 / g.nx;
       const int y = D3 ? rest % g.ny : rest;
       const int lane = threadIdx.x & 63;
-      double left = __shfl_up(c1, 1, 64);
-      double right = __shfl_down(c0, 1, 64);
+      double left = lane_prev(c1);
+      double right = lane_next(c0);
       if (lane == 0 && x > 0) left = pk1(idx0 - 1);
       if (lane == 63 && x + 2 < g.nx) right = pk1(idx0 + 2);
       double s0 = (x > 0 ? left : 0.0) + c1;
