@@ -25,20 +25,23 @@ METRIC = "iters/s + HBM GB/s, p(l)-CG vs CG at 1e-8 rel res; batched solves/s, p
 HBM_PEAK_GBS = 8000.0
 
 
-def vector_passes(method: str, l: int) -> int:
+def vector_passes(method: str, l: int, x_update_every: int = 1) -> float:
     # (mixed methods run the same sweep on 4-byte values: see bytes_per_pass)
     """Algorithmic vector passes per iteration (each pass = N doubles read or written).
 
     p(l)-CG fused sweep: reads z^{(l)}_i (stencil input, once), z^{(l)}_{i-1},
     the current and previous vector of each basis k < l, max(0, l-3) older
-    z^{(l)} vectors for the dot products, p and x; writes z^{(l)}_{i+1}, l new
-    basis vectors, p and x: 3l + 7 + max(0, l - 3).
+    z^{(l)} vectors for the dot products and p_{t-1}; writes z^{(l)}_{i+1}, l new
+    basis vectors and p_t: 3l + 5 + max(0, l - 3); plus reading and writing x:
+    3l + 7 + max(0, l - 3) with x_update_every = 1, and with x_update_every = 2
+    (x read and written with p_{t-2} on even t only) 1.5 instead of 2 more on
+    average: 3l + 6.5 + max(0, l - 3).
     Classic CG: sweep A reads r, p_{k-1}, writes p_k, A p_k (4); sweep B reads
     x, p, r, A p and writes x, r (6): 10 per iteration.
     """
     if method == "cg":
         return 10
-    return 3 * l + 7 + max(0, l - 3)
+    return 3 * l + 5 + max(0, l - 3) + (1.5 if x_update_every == 2 else 2)
 
 
 def cpu_baseline(workload: str, l: int, iters: int) -> dict:
@@ -230,6 +233,7 @@ def batch_bench(args, plcg, torch, dev, sp):
     # per unknown and (inner) iteration: the sweep's vector passes in the storage
     # precision plus the 2 FP64 edge-weight arrays of the 2D operator
     word = 4 if prec == "fp32" else 8
+    # (a batch sweep updates x every iteration)
     per_unknown = (3 * l + 7 + max(0, l - 3)) * word + 2 * 8
     sweep_bytes = sum(systems[k]["n"] * iters[k] * per_unknown for k in iters)
     line = {
@@ -480,7 +484,7 @@ def main():
         s.close()
         r = results[-1]
         its = total_iters / dt
-        passes = vector_passes("cg" if method == "cg" else "plcg", l)
+        passes = vector_passes("cg" if method == "cg" else "plcg", l, r.x_update_every)
         # vector passes in the storage precision, plus the operator's own data
         # read once per SpMV (FP64 d, or the CSR arrays)
         bytes_iter = passes * (4 if method == "mixed" else 8) * n + op_bytes
@@ -493,6 +497,7 @@ def main():
             "ms_per_solve": 1e3 * dt / args.steps, "iters_per_s": its,
             "bytes_per_iter": bytes_iter,
             "us_per_iter": 1e6 / its, "vector_passes": passes, "operator_bytes": op_bytes,
+            "x_update_every": r.x_update_every,
             "alg_GBps": bytes_iter * its / 1e9,
             "kernel_us": kernel_us, "kernels_per_iter": kernels_per_iter,
             "kernel_GBps": (bytes_iter / kernels_per_iter) / (kernel_us * 1e-6) / 1e9

@@ -90,6 +90,21 @@ enum { PLCG_PREC_FP64 = 0, PLCG_PREC_FP32_REFINED = 1 };
 enum { PLCG_LAUNCH_AUTO = 0, PLCG_LAUNCH_STREAMING = 1, PLCG_LAUNCH_RESIDENT = 2 };
 #define PLCG_RESIDENT_MAX 4800
 
+/* When the streaming p(l)-CG sweeps write the iterate x_t = x_{t-1} + zeta_{t-1} p_{t-1}
+ * (Eq. x_a2):
+ * EVERY: in every sweep (one p buffer).
+ * PAIRED: in every second sweep, both steps at once: p is kept in two buffers, an odd
+ *   sweep leaves x alone and an even one adds zeta_{t-2} p_{t-2} and zeta_{t-1} p_{t-1}
+ *   with the same two roundings, so x is bit for bit the one EVERY gives; a run that
+ *   ends after an odd step adds the last step in one more small kernel.  Half a vector
+ *   pass less per iteration, one more vector of device memory.
+ * AUTO (default): PAIRED where a vector is at least 16 MiB (below that the sweeps are
+ *   bound by launch and reduction latency, which the even sweep's extra loads
+ *   lengthen) and the second p buffer does not push a working set that fits the
+ *   256 MiB memory-side cache out of it; else EVERY.
+ * Classic CG, the resident launches and the batches ignore it. */
+enum { PLCG_X_AUTO = 0, PLCG_X_EVERY = 1, PLCG_X_PAIRED = 2 };
+
 enum {
   PLCG_REASON_NONE = 0,
   PLCG_REASON_CONVERGED = 1,        /* recursive residual below tol            */
@@ -141,6 +156,7 @@ typedef struct {
   double inner_tol;       /* FP32_REFINED: relative tolerance of each inner solve, in (0, 1);
                              <= 0: default 1e-3 */
   int32_t launch_mode;    /* PLCG_LAUNCH_* (0 = AUTO) */
+  int32_t x_update;       /* PLCG_X_* (0 = AUTO) */
 } plcg_config;
 
 typedef struct {
@@ -163,6 +179,9 @@ typedef struct {
                              per restart (RESIDENT); 0 from batches */
   int32_t launch_mode;    /* PLCG_LAUNCH_STREAMING or PLCG_LAUNCH_RESIDENT: how the
                              iterations of this solve ran (0 from batches) */
+  int32_t x_update_every; /* 2: the streaming p(l)-CG sweeps of this solve wrote x on
+                             every second sweep (PLCG_X_PAIRED), 1: on every sweep
+                             (also CG and resident launches); 0 from batches */
 } plcg_result;
 
 /* Create a solver for one operator and one configuration.

@@ -160,6 +160,8 @@ __device__ inline void slot_sweep_args(const SlotDesc &S, int i, SweepArgsT<T> &
   a.copy_dst = (i < L - 1) ? svec<T>(S, 2 * (i + 1) + ((i + 1) & 1)) : nullptr;
   a.v0 = (i == L - 1) ? svec<T>(S, 0) : nullptr;
   a.p = svec<T>(S, 2 * L + R);
+  a.p_out = a.p;
+  a.xmode = kXEvery;
   if constexpr (std::is_same<T, double>::value)
     a.x = S.x;
   else

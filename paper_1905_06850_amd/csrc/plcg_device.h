@@ -544,7 +544,7 @@ __host__ __device__ inline void engine_column_l(DevState &s, const double *raw, 
 
 template <int L>
 struct Coef {
-  double gam, dm1, inv_del, inv_eta, zm1, sigma_i;
+  double gam, dm1, inv_del, inv_eta, zm1, zm2, sigma_i;
   double sig[L];
 };
 
@@ -556,9 +556,10 @@ __device__ inline void read_coef(const DevState &s, int i, int t, Coef<L> &cf) {
     cf.dm1 = t >= 1 ? s.dlt[(t - 1) % kTRing] : 0.0;
     cf.inv_eta = 1.0 / s.eta[t % kTRing];
     cf.zm1 = t >= 1 ? s.zeta[(t - 1) % kTRing] : 0.0;
+    cf.zm2 = t >= 2 ? s.zeta[(t - 2) % kTRing] : 0.0;
     cf.sigma_i = 0.0;
   } else {
-    cf.gam = cf.inv_del = cf.dm1 = cf.inv_eta = cf.zm1 = 0.0;
+    cf.gam = cf.inv_del = cf.dm1 = cf.inv_eta = cf.zm1 = cf.zm2 = 0.0;
     cf.sigma_i = s.sigma[i];
   }
 #pragma unroll
@@ -657,7 +658,9 @@ struct CsrOp {
 
 // The recurrences of one p(l)-CG iteration for V consecutive unknowns.  Op is
 // the operator: Op::apply<V, FAST>(z, idx, zc, w) sets w = A z at idx .. idx+V-1.
-template <int L, typename S, typename Op, int H = 0>
+// PAIR: p in two buffers, x written on even t only (a.xmode kXSkip / kXPair);
+// else p in place and x written in every sweep.
+template <int L, typename S, typename Op, int H = 0, bool PAIR = false>
 struct Sweep {
   using Args = SweepArgsT<S>;
   static constexpr int ND = L + 1;
@@ -714,18 +717,37 @@ struct Sweep {
     if (t == 0) {
 #pragma unroll
       for (int v = 0; v < V; ++v) pv.v[v] = vt[v] * cf.inv_eta;
-    } else {
+    } else if constexpr (!PAIR) {
       Vals<V, S> xv;
       pv.template ld<NTL>(a.p + idx);
       xv.template ld<NTL>(a.x + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        xv.v[v] += cf.zm1 * pv.v[v];
+        xv.v[v] = fma(cf.zm1, pv.v[v], xv.v[v]);
         pv.v[v] = (vt[v] - cf.dm1 * pv.v[v]) * cf.inv_eta;
       }
       xv.template st<NTS>(a.x + idx);
+    } else {
+      pv.template ld<NTL>(a.p + idx);
+      if (a.xmode != kXSkip) {
+        Vals<V, S> xv;
+        xv.template ld<NTL>(a.x + idx);
+        if (a.xmode == kXPair) {
+          // x_{t-1} = x_{t-2} + zeta_{t-2} p_{t-2}, rounded to S as if stored;
+          // p_{t-2} sits in the buffer that receives p_t below
+          Vals<V, S> qv;
+          qv.template ld<NTL>(a.p_out + idx);
+#pragma unroll
+          for (int v = 0; v < V; ++v) xv.v[v] = (double)(S)fma(cf.zm2, qv.v[v], xv.v[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) xv.v[v] = fma(cf.zm1, pv.v[v], xv.v[v]);
+        xv.template st<NTS>(a.x + idx);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) pv.v[v] = (vt[v] - cf.dm1 * pv.v[v]) * cf.inv_eta;
     }
-    pv.template st<NTS>(a.p + idx);
+    pv.template st<NTS>((PAIR ? a.p_out : a.p) + idx);
     Vals<V, S> out;
 #pragma unroll
     for (int v = 0; v < V; ++v) out.v[v] = zn[v];

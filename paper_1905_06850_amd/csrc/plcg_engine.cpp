@@ -62,12 +62,27 @@ constexpr int kDefaultRestarts = 100;
 // alternating sweep order then finds them there; non-temporal stores pay
 // only when each vector alone is large (3D 256^3 FP64: another 3-5 %) and cost
 // up to 9 % at 2048^2, whose freshly written vectors the next sweep re-reads
-// from that cache.
+// from that cache.  The footprint counts one p buffer (the second one is used
+// only where it does not cross the cache size, see pair_x_updates).
 int pick_hint(long long n, int method, int l, int R, int word, long long op_bytes) {
   const long long vecs = method == PLCG_METHOD_CG ? 5 : 2LL * l + R + 2;
   const long long bytes = vecs * n * word + op_bytes;
   if (bytes <= kCacheBytes) return 0;
   return n * word > kLargeVector ? (kHintLoads | kHintStores) : kHintLoads;
+}
+
+// PLCG_X_AUTO: whether the streaming p(l)-CG sweeps keep p in two buffers and
+// update x on even t only (half a vector pass less per iteration: 2048^2 p(1)
+// and p(3) 2-3 % faster).  Not for vectors under 16 MiB, whose sweeps are bound
+// by launch and reduction latency (64^2 to 1024^2: from 2 % faster to 3 % slower
+// paired), and not where the extra buffer pushes a working set that fits the
+// memory-side cache out of it (2048^2 p(2)-CG, 8 vectors of exactly 256 MiB:
+// 16 % slower paired).
+constexpr long long kPairMinVector = 16LL << 20;
+bool pair_x_updates(long long n, int l, int R, int word, long long op_bytes) {
+  if (n * word < kPairMinVector) return false;
+  const long long one = (2LL * l + R + 2) * n * word + op_bytes;
+  return !(one <= kCacheBytes && one + n * word > kCacheBytes);
 }
 
 // Operator kind numbering of the kernels: 0 2D stencil, 1 3D stencil, 2 diagonal, 3 CSR.
@@ -102,6 +117,7 @@ struct plcg_handle {
   bool d3 = false;
   int res_kind = -1;              // operator kind of the resident kernels; -1: streaming
   int hint64 = 0, hint32 = 0;     // streaming cache hints of the FP64 / FP32-stored sweeps
+  bool pair64 = false, pair32 = false;   // the same sweeps update x on even t only
   bool ran_resident = false;      // the current solve ran resident launches
   OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0};   // library copies of d / the CSR arrays
   bool jacobi = false;            // CSR solved in Jacobi-scaled form D^{-1/2} A D^{-1/2}
@@ -112,14 +128,14 @@ struct plcg_handle {
   std::vector<void *> allocs;
   double *basis[kLMax][2] = {};   // basis k < l, slots by index parity
   double *ring[kLMax] = {};       // basis l, slot of z^{(l)}_j is j % R
-  double *p = nullptr;
+  double *p[2] = {nullptr, nullptr};   // p_t in p[t & 1]
   double *cg_r = nullptr, *cg_p[2] = {nullptr, nullptr}, *cg_q = nullptr;
   // FP32_REFINED: FP32 storage of the inner solver and the FP64 outer residual
   int precision = PLCG_PREC_FP64;
   double inner_tol = 1e-3;
   float *basis32[kLMax][2] = {};
   float *ring32[kLMax] = {};
-  float *p32 = nullptr, *d32 = nullptr;
+  float *p32[2] = {nullptr, nullptr}, *d32 = nullptr;
   double *r64 = nullptr;
   double *part[2] = {nullptr, nullptr};   // partials of launches with even / odd index
   DevState *st[2] = {nullptr, nullptr};   // scalar state read by odd / even launches
@@ -260,8 +276,8 @@ struct TimedLaunch {
 // Pointers of iteration i: ring roles, basis roles, start-up copies, and the
 // alternating partials / state copies (launch i reads copy (i-1)&1, writes i&1).
 template <typename S>
-void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring, S *p, S *x,
-                     SweepArgsT<S> &a) {
+void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring, S *const *p,
+                     S *x, SweepArgsT<S> &a) {
   std::memset(&a, 0, sizeof(a));
   const int l = h->l, R = h->R;
   const int t = i - l;
@@ -278,7 +294,16 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
   }
   a.copy_dst = (i < l - 1) ? basis[i + 1][(i + 1) & 1] : nullptr;
   a.v0 = (i == l - 1) ? basis[0][0] : nullptr;
-  a.p = p;
+  if (sizeof(S) == 8 ? h->pair64 : h->pair32) {
+    // p_t goes to p[t & 1] over p_{t-2}; x is updated on even t only, by both
+    // steps since the last even t (an odd last step is made by x_step at the end)
+    a.p = p[(t + 1) & 1];
+    a.p_out = p[t & 1];
+    a.xmode = (t & 1) ? kXSkip : kXPair;
+  } else {
+    a.p = a.p_out = p[0];
+    a.xmode = kXEvery;
+  }
   a.x = x;
   a.od = h->od;
   a.part_in = h->part[(i + 1) & 1];
@@ -323,10 +348,10 @@ struct Segment {
 
 // Sweeps i = 0 .. m + l of one run of Alg. 1 (setup already done; sweep 0 reads
 // state copy 1), with lagged status checks; stops early once the device reports
-// a stop.  t_done = x-updates made; rec = |zeta_{t_done}|.
+// a stop.  t_done = x-updates made; rec = |zeta_{t_done}|.  p: the two p buffers.
 template <typename S>
-plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S *p, S *x, int m,
-                        hipStream_t s, TimedLaunch &tl, Segment *out) {
+plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S *const *p, S *x,
+                        int m, hipStream_t s, TimedLaunch &tl, Segment *out) {
   const int l = h->l;
   const int imax = m + l;               // Alg. 1 loop: i = 0 .. imax
   int status = kRunning;
@@ -388,6 +413,12 @@ plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S 
   else
     tl.keep(first_launch, (size_t)out->sweeps_run);
   out->rec = out->t_done == 0 ? ds.beta : std::fabs(ds.zeta[out->t_done % kTRing]);
+  // The streaming sweeps left x at x_{t_done-1} if t_done is odd: add the last
+  // step zeta_{t_done-1} p_{t_done-1} (p_{t_done-1} is intact in its buffer).
+  if (!resident && (sizeof(S) == 8 ? h->pair64 : h->pair32) && (out->t_done & 1)) {
+    const int tl1 = out->t_done - 1;
+    PLCG_HIP(launch_x_step<S>(x, p[tl1 & 1], ds.zeta[tl1 % kTRing], h->n, s));
+  }
   // t = 0 .. cols-1 were recorded unless the last column broke down.
   h->last_hist_count =
       std::min(h->hist_cap, std::max(ds.cols - (ds.status == kBroken ? 1 : 0), 0));
@@ -728,6 +759,8 @@ plcg_status do_solve(plcg_handle *h, const double *b, double *x, double tol, int
   }
   res.host_waits = h->host_waits;
   res.launch_mode = h->ran_resident ? PLCG_LAUNCH_RESIDENT : PLCG_LAUNCH_STREAMING;
+  res.x_update_every =
+      h->ran_resident || (h->precision == PLCG_PREC_FP32_REFINED ? !h->pair32 : !h->pair64) ? 1 : 2;
   res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = res;
   return PLCG_OK;
@@ -881,6 +914,8 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     return fail(PLCG_E_INVALID, "inner_tol must be < 1");
   if (cfg->launch_mode < PLCG_LAUNCH_AUTO || cfg->launch_mode > PLCG_LAUNCH_RESIDENT)
     return fail(PLCG_E_INVALID, "unknown launch_mode");
+  if (cfg->x_update < PLCG_X_AUTO || cfg->x_update > PLCG_X_PAIRED)
+    return fail(PLCG_E_INVALID, "unknown x_update");
   const bool res_ok = cfg->precision == PLCG_PREC_FP64 &&
                       plcg_resident_supported(op->kind, n, cfg->method, cfg->l) == 1;
   if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT && !res_ok)
@@ -935,9 +970,9 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
   const bool mixed = h->precision == PLCG_PREC_FP32_REFINED;
   const size_t vb32 = (size_t)n * sizeof(float);
   const size_t vstride32 = ((vb32 + 65535) / 65536) * 65536 + stagger;
-  // FP64 vectors: bases + ring + p (p(l)-CG), r (mixed), r, p, p, q (CG).
-  const int nvec = mixed ? 1 : (pl ? 2 * h->l + h->R + 1 : 4);
-  const int nvec32 = mixed ? 2 * h->l + h->R + 2 : 0;
+  // FP64 vectors: bases + ring + 2 p (p(l)-CG), r (mixed), r, p, p, q (CG).
+  const int nvec = mixed ? 1 : (pl ? 2 * h->l + h->R + 2 : 4);
+  const int nvec32 = mixed ? 2 * h->l + h->R + 3 : 0;
   plcg_status e = PLCG_OK;
   char *arena = nullptr;
   e = dev_alloc(h, reinterpret_cast<void **>(&arena), vstride * nvec + vstride32 * nvec32);
@@ -956,7 +991,8 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
       vec32(&h->basis32[k][1]);
     }
     for (int k = 0; k < h->R; ++k) vec32(&h->ring32[k]);
-    vec32(&h->p32);
+    vec32(&h->p32[0]);
+    vec32(&h->p32[1]);
     vec32(&h->d32);
   } else if (pl) {
     for (int k = 0; k < h->l; ++k) {
@@ -964,7 +1000,8 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
       vec(&h->basis[k][1]);
     }
     for (int k = 0; k < h->R; ++k) vec(&h->ring[k]);
-    vec(&h->p);
+    vec(&h->p[0]);
+    vec(&h->p[1]);
   } else {
     vec(&h->cg_r);
     vec(&h->cg_p[0]);
@@ -1008,6 +1045,11 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
                                                           : 0;
     h->hint64 = pick_hint(n, h->method, h->l, h->R, 8, op_bytes);
     h->hint32 = pick_hint(n, h->method, h->l, h->R, 4, op_bytes);
+    const int xu = cfg->x_update;
+    h->pair64 = pl && (xu == PLCG_X_PAIRED ||
+                       (xu == PLCG_X_AUTO && pair_x_updates(n, h->l, h->R, 8, op_bytes)));
+    h->pair32 = pl && (xu == PLCG_X_PAIRED ||
+                       (xu == PLCG_X_AUTO && pair_x_updates(n, h->l, h->R, 4, op_bytes)));
   }
   // The resident kernels index the matrix with 32-bit offsets.
   const long long stored =

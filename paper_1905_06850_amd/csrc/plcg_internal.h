@@ -10,6 +10,10 @@ constexpr int kLMax = 8;              // largest pipeline length
 constexpr int kBand = 2 * kLMax + 1;  // stored rows per column of G (rows c-2l .. c)
 constexpr int kGRing = 16;            // columns of G kept (>= l+1 are read)
 constexpr int kTRing = 16;            // entries of gamma/delta/eta/zeta kept (>= l+1 are read)
+// x update of a sweep with t >= 1 (Eq. x_a2): every sweep adds zeta_{t-1} p_{t-1};
+// or, with two p buffers, odd sweeps skip it and even sweeps add zeta_{t-2}
+// p_{t-2} and zeta_{t-1} p_{t-1} (the same two roundings, half the x traffic).
+constexpr int kXEvery = 0, kXSkip = 1, kXPair = 2;
 constexpr int kThreads = 256;         // threads per block of every streaming kernel
 constexpr int kVec = 2;               // consecutive unknowns per thread and chunk
 constexpr int kChunk = kThreads * kVec;
@@ -87,7 +91,9 @@ struct SweepArgsT {
   S *zk_prev[kLMax];         // basis k < l: z^{(k)}_{t+k-1}; overwritten with z^{(k)}_{t+k+1}
   S *copy_dst;               // i < l-1: basis i+1 slot receiving z^{(l)}_{i+1}; else NULL
   const S *v0;               // i == l-1: z^{(0)}_0 for the product (u_l, v_0)
-  S *p, *x;
+  S *p;                      // p_{t-1}
+  S *p_out;                  // receives p_t: p itself, or the second p buffer (holding p_{t-2})
+  S *x;
   OpData od;                 // diagonal or CSR operator data; all NULL for the stencils
   const double *part_in;     // partials of sweep i-1, [l+1][pstride]
   double *part_out;          // partials of sweep i
@@ -102,6 +108,8 @@ struct SweepArgsT {
   int32_t pstride;
   int32_t work;              // 0: only carry the scalar state forward
   int32_t hint;              // streaming cache hints (kHint* bits)
+  int32_t xmode;             // kXEvery, kXSkip or kXPair
+  int32_t pad;
 };
 using SweepArgs = SweepArgsT<double>;
 
@@ -177,6 +185,9 @@ hipError_t launch_scale(const double *r, float *d0, float *d1, float *d2, const 
                         hipStream_t s);
 // x += d (FP64 += FP32).
 hipError_t launch_add_correction(double *x, const float *d, int n, hipStream_t s);
+// x += zeta p in the storage type S (double or float), one rounding.
+template <typename S>
+hipError_t launch_x_step(S *x, const S *p, double zeta, int n, hipStream_t s);
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
                         const OpData &od, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);

@@ -30,12 +30,12 @@ namespace plcg {
 // vector: 2 doubles, or 4 floats for the FP32-stored inner solver).
 // fast_rows: full chunks may take the operator's FAST form; order: the chunk
 // visiting order.
-template <int L, typename ST, int H, typename Op>
+template <int L, typename ST, int H, bool P, typename Op>
 __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fast_rows,
                                   const ChunkOrder &order) {
   constexpr int V = vec_of<ST>();
   constexpr int CH = kThreads * V;
-  using S = Sweep<L, ST, Op, H>;
+  using S = Sweep<L, ST, Op, H, P>;
   constexpr int ND = S::ND;
   __shared__ double lds[4 * ND];
   __shared__ double red[ND];
@@ -93,21 +93,22 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   store_partials<ND>(acc, a.part_out, a.pstride, blockIdx.x - first, lds, red);
 }
 
-template <int L, bool D3, typename ST, int H>
+// P: paired x updates (Sweep's PAIR).
+template <int L, bool D3, typename ST, int H, bool P>
 __global__ __launch_bounds__(kThreads) void plcg_sweep_kernel(SweepArgsT<ST> a) {
   const Grid g{a.n, a.nx, a.ny, a.nz};
-  plcg_sweep<L, ST, H>(a, ConstOp<D3, ST>{g}, a.nx % vec_of<ST>() == 0,
-                       chunk_order(g, D3, kThreads * vec_of<ST>()));
+  plcg_sweep<L, ST, H, P>(a, ConstOp<D3, ST>{g}, a.nx % vec_of<ST>() == 0,
+                          chunk_order(g, D3, kThreads * vec_of<ST>()));
 }
 
-template <int L, typename ST, int H>
+template <int L, typename ST, int H, bool P>
 __global__ __launch_bounds__(kThreads) void plcg_diag_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST, H>(a, DiagOp<ST>{a.od.dg}, true, ChunkOrder{0, 0, 0});
+  plcg_sweep<L, ST, H, P>(a, DiagOp<ST>{a.od.dg}, true, ChunkOrder{0, 0, 0});
 }
 
-template <int L, typename ST, int H>
+template <int L, typename ST, int H, bool P>
 __global__ __launch_bounds__(kThreads) void plcg_csr_sweep_kernel(SweepArgsT<ST> a) {
-  plcg_sweep<L, ST, H>(
+  plcg_sweep<L, ST, H, P>(
       a, CsrOp<ST, (H & kHintLoads) != 0>{a.od.rp, a.od.ci, a.od.va, a.od.ell_k, a.od.ell_ld},
       true, ChunkOrder{0, 0, 0});
 }
@@ -622,6 +623,14 @@ __global__ __launch_bounds__(kThreads) void add_correction_kernel(double *x, con
     x[p] += (double)d[p];
 }
 
+// x += zeta p, one rounding to S: the x update of an odd last sweep, which the
+// paired updates of the streaming sweeps leave to the end of a run.
+template <typename S>
+__global__ __launch_bounds__(kThreads) void x_step_kernel(S *x, const S *p, double zeta, int n) {
+  for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n; q += (int64_t)gridDim.x * kThreads)
+    x[q] = (S)fma(zeta, (double)p[q], (double)x[q]);
+}
+
 template <int K>
 __global__ __launch_bounds__(kThreads) void apply_kernel(const double *x, double *y, Grid g,
                                                          OpData od) {
@@ -649,18 +658,28 @@ static int simple_blocks(int64_t n) {
   return (int)b;
 }
 
-template <int L, typename S, int H>
-static hipError_t launch_sweep_lh(const SweepArgsT<S> &a, hipStream_t s) {
+template <int L, typename S, int H, bool P>
+static hipError_t launch_sweep_lhp(const SweepArgsT<S> &a, hipStream_t s) {
   const int grid = a.nstream + (L >= 2 ? 1 : 0);
   if (a.od.rp != nullptr)
-    hipLaunchKernelGGL((plcg_csr_sweep_kernel<L, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_csr_sweep_kernel<L, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
   else if (a.od.dg != nullptr)
-    hipLaunchKernelGGL((plcg_diag_sweep_kernel<L, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_diag_sweep_kernel<L, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
   else if (a.d3)
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, false, S, H>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((plcg_sweep_kernel<L, false, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+template <int L, typename S, int H>
+static hipError_t launch_sweep_lh(const SweepArgsT<S> &a, hipStream_t s) {
+  switch (a.xmode) {
+    case kXEvery: return launch_sweep_lhp<L, S, H, false>(a, s);
+    case kXSkip:
+    case kXPair: return launch_sweep_lhp<L, S, H, true>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int L, typename S>
@@ -785,6 +804,14 @@ hipError_t launch_add_correction(double *x, const float *d, int n, hipStream_t s
   hipLaunchKernelGGL(add_correction_kernel, dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, d, n);
   return hipGetLastError();
 }
+
+template <typename S>
+hipError_t launch_x_step(S *x, const S *p, double zeta, int n, hipStream_t s) {
+  hipLaunchKernelGGL(x_step_kernel<S>, dim3(simple_blocks(n)), dim3(kThreads), 0, s, x, p, zeta, n);
+  return hipGetLastError();
+}
+template hipError_t launch_x_step<double>(double *, const double *, double, int, hipStream_t);
+template hipError_t launch_x_step<float>(float *, const float *, double, int, hipStream_t);
 
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
                         const OpData &od, hipStream_t s) {

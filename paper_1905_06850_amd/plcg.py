@@ -35,8 +35,12 @@ PLCG_LAUNCH_AUTO = 0
 PLCG_LAUNCH_STREAMING = 1
 PLCG_LAUNCH_RESIDENT = 2
 PLCG_RESIDENT_MAX = 4800
+PLCG_X_AUTO = 0
+PLCG_X_EVERY = 1
+PLCG_X_PAIRED = 2
 LAUNCH_MODES = {"auto": PLCG_LAUNCH_AUTO, "streaming": PLCG_LAUNCH_STREAMING,
                 "resident": PLCG_LAUNCH_RESIDENT}
+X_UPDATES = {"auto": PLCG_X_AUTO, "every": PLCG_X_EVERY, "paired": PLCG_X_PAIRED}
 
 PLCG_REASON_NONE = 0
 PLCG_REASON_CONVERGED = 1
@@ -61,7 +65,8 @@ class plcg_config(ctypes.Structure):
                 ("shifts", ctypes.POINTER(ctypes.c_double)),
                 ("check_every", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("history_cap", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("launch_mode", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("launch_mode", ctypes.c_int32),
+                ("x_update", ctypes.c_int32)]
 
 
 class plcg_result(ctypes.Structure):
@@ -71,7 +76,7 @@ class plcg_result(ctypes.Structure):
                 ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweeps", ctypes.c_int64),
                 ("outer", ctypes.c_int32), ("host_waits", ctypes.c_int32),
-                ("launch_mode", ctypes.c_int32)]
+                ("launch_mode", ctypes.c_int32), ("x_update_every", ctypes.c_int32)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
@@ -257,12 +262,14 @@ class Solver:
 
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
                  check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
-                 inner_tol=0.0, diag=None, csr=None, jacobi=False, launch="auto"):
+                 inner_tol=0.0, diag=None, csr=None, jacobi=False, launch="auto",
+                 x_update="auto"):
         """kind "2d5", "3d7", "diag" or "csr"; for "diag", `diag` is the device
         address of the n FP64 diagonal entries; for "csr", `csr` is (rowptr,
         colind, vals, nnz) with device addresses of int64 / int32 / FP64 arrays
         (copied by plcg_create); jacobi=True solves a CSR matrix Jacobi-preconditioned.
-        launch: "auto", "streaming" or "resident" (PLCG_LAUNCH_*)."""
+        launch: "auto", "streaming" or "resident" (PLCG_LAUNCH_*); x_update: "auto",
+        "every" or "paired" (PLCG_X_*)."""
         self.desc = _dims_desc(kind, dims, diag, csr, jacobi)
         self._shifts = None
         sp = None
@@ -273,7 +280,7 @@ class Solver:
         prec = PLCG_PREC_FP32_REFINED if precision == "fp32" else PLCG_PREC_FP64
         self.cfg = plcg_config(m, int(l), float(lmin), float(lmax), sp, int(check_every),
                                int(max_restarts), int(history_cap), prec, float(inner_tol),
-                               LAUNCH_MODES[launch])
+                               LAUNCH_MODES[launch], X_UPDATES[x_update])
         self.method = method
         self.l = int(l)
         self.handle = _h()

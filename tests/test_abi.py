@@ -110,3 +110,15 @@ def test_create_rejects_resident_where_unavailable(nx, ny, method, l, precision)
     cfg.launch_mode = 7
     assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
         plcg.PLCG_E_INVALID
+
+
+def test_create_rejects_unknown_x_update():
+    from paper_1905_06850_amd import plcg
+    desc = plcg.plcg_operator_desc(1, 64, 64, 1)
+    assert plcg.X_UPDATES == {"auto": 0, "every": 1, "paired": 2}
+    for xu in (-1, 3):
+        cfg = plcg.plcg_config(1, 2, 0.0, 8.0, None, 0, -1, 0, 0, 0.0, 0, xu)
+        h = ctypes.c_void_p()
+        assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
+            plcg.PLCG_E_INVALID
+        assert not h.value

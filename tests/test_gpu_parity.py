@@ -164,23 +164,63 @@ def test_solve_parity_ragged(dev, dims, method, l, launch):
     s.close()
 
 
-@pytest.mark.parametrize("launch", LAUNCHES)
+@pytest.mark.parametrize("launch,x_update", [("streaming", "every"), ("streaming", "paired"),
+                                             ("resident", "auto")])
 @pytest.mark.parametrize("method,l", METHODS)
-def test_early_iterates(dev, method, l, launch):
+def test_early_iterates(dev, method, l, launch, x_update):
+    """x after exactly m steps against the oracle's x_m.  Odd and even m; with
+    x_update "paired" the streaming p(l)-CG sweeps write x on even t only (two
+    steps at once) and add an odd last step after the run."""
     dims = (48, 40)
     A = operators.laplacian(dims)
     b = synth.uniform(A.n, 8)
     x0 = np.zeros(A.n)
     for m in (0, 1, 2, 3, 7, 20):
         ref = oracle_solve(dims, method, l, b, x0, 1e-30, m)
-        x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-30, m, launch=launch)
+        x, res, s = gpu_solve(dev, dims, method, l, b, x0, 1e-30, m, launch=launch,
+                              x_update=x_update)
         assert res.iters == m == ref.iters
         assert res.reason == 2
+        assert m == 0 or res.x_update_every == (2 if method == "plcg" and x_update == "paired"
+                                                else 1)
         if m == 0:
             assert np.array_equal(x, x0)
         else:
             assert _rel(x, ref.x) < 1e-13
         s.close()
+
+
+@pytest.mark.parametrize("dims,l,precision,interval", [
+    ((64, 64), 1, "fp64", None), ((100, 37), 2, "fp64", None), ((20, 13, 7), 3, "fp64", None),
+    ((64, 64), 5, "fp64", None), ((48, 48), 3, "fp64", (6.0, 8.0)),
+    ((96, 80), 1, "fp32", None), ((60, 50), 2, "fp32", None)])
+def test_paired_x_updates_bitwise_equal(dev, dims, l, precision, interval):
+    """PLCG_X_PAIRED (x written every second sweep, two steps with the same two
+    roundings) against PLCG_X_EVERY: x, iteration and restart counts and both
+    residuals bit for bit equal, for runs that stop after an odd and an even
+    number of steps and runs to convergence (the (6, 8) interval on 48^2
+    breaks down and restarts; fp32: FP32-stored inner solves in refinement)."""
+    n = int(np.prod(dims))
+    b = synth.uniform(n, 5)
+    x0 = np.zeros(n)
+    kw = {"precision": precision, "inner_tol": 1e-4 if precision == "fp32" else 0.0}
+    if interval is not None:
+        kw["interval"] = interval
+    for tol, maxit in ((1e-30, 7), (1e-30, 8), (1e-9, 100000)):
+        out = []
+        for xu in ("every", "paired"):
+            x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, tol, maxit, launch="streaming",
+                                  x_update=xu, **dict(kw))
+            s.close()
+            assert res.x_update_every == (2 if xu == "paired" else 1)
+            out.append((x, res))
+        (xe, re_), (xp, rp) = out
+        assert np.array_equal(xe.view(np.uint64), xp.view(np.uint64))
+        assert (re_.iters, re_.restarts, re_.outer, re_.reason) == \
+            (rp.iters, rp.restarts, rp.outer, rp.reason)
+        assert re_.rec_relres == rp.rec_relres and re_.true_relres == rp.true_relres
+    if interval is not None:
+        assert re_.restarts > 0
 
 
 @pytest.mark.parametrize("dims", [(64, 64, 256), (32, 48, 1100)])
@@ -429,6 +469,9 @@ def test_full_size_against_stored_oracle(dev, name):
                           interval=tuple(g["interval"]))
     assert res.reason == 1
     assert abs(res.iters - g["iters"]) <= 1
+    # x on every second sweep, except CG and p(2) at 2048^2, whose 8 vectors
+    # fill the 256 MiB memory-side cache exactly (a second p buffer would not fit)
+    assert res.x_update_every == (1 if method == "cg" or name == "poisson2048_p2" else 2)
     assert res.true_relres <= 10 * g["true_relres"] and g["true_relres"] <= 10 * res.true_relres
     idx = np.array(g["sample_idx"])
     ref = np.array(g["sample_x"])
