@@ -37,10 +37,12 @@ def vector_passes(method: str, l: int, x_update_every: int = 1) -> float:
     (x read and written with p_{t-2} on even t only) 1.5 instead of 2 more on
     average: 3l + 6.5 + max(0, l - 3).
     Classic CG: sweep A reads r, p_{k-1}, writes p_k, A p_k (4); sweep B reads
-    x, p, r, A p and writes x, r (6): 10 per iteration.
+    x, p, r, A p and writes x, r (6): 10 per iteration; with x_update_every = 2
+    sweep B reads r, A p and writes r (3), and every second one also reads x,
+    p_k, p_{k-1} and writes x (7): 9 per iteration on average.
     """
     if method == "cg":
-        return 10
+        return 9 if x_update_every == 2 else 10
     return 3 * l + 5 + max(0, l - 3) + (1.5 if x_update_every == 2 else 2)
 
 

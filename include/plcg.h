@@ -91,7 +91,7 @@ enum { PLCG_LAUNCH_AUTO = 0, PLCG_LAUNCH_STREAMING = 1, PLCG_LAUNCH_RESIDENT = 2
 #define PLCG_RESIDENT_MAX 4800
 
 /* When the streaming p(l)-CG sweeps write the iterate x_t = x_{t-1} + zeta_{t-1} p_{t-1}
- * (Eq. x_a2):
+ * (Eq. x_a2), and classic CG's second sweep x_{k+1} = x_k + alpha_k p_k:
  * EVERY: in every sweep (one p buffer).
  * PAIRED: in every second sweep, both steps at once: p is kept in two buffers, an odd
  *   sweep leaves x alone and an even one adds zeta_{t-2} p_{t-2} and zeta_{t-1} p_{t-1}
@@ -102,7 +102,8 @@ enum { PLCG_LAUNCH_AUTO = 0, PLCG_LAUNCH_STREAMING = 1, PLCG_LAUNCH_RESIDENT = 2
  *   bound by launch and reduction latency, which the even sweep's extra loads
  *   lengthen) and the second p buffer does not push a working set that fits the
  *   256 MiB memory-side cache out of it; else EVERY.
- * Classic CG, the resident launches and the batches ignore it. */
+ * Classic CG pairs the same way with the two p buffers it has anyway (no extra memory;
+ *   AUTO: always).  The resident launches and the batches ignore it. */
 enum { PLCG_X_AUTO = 0, PLCG_X_EVERY = 1, PLCG_X_PAIRED = 2 };
 
 enum {
@@ -179,9 +180,9 @@ typedef struct {
                              per restart (RESIDENT); 0 from batches */
   int32_t launch_mode;    /* PLCG_LAUNCH_STREAMING or PLCG_LAUNCH_RESIDENT: how the
                              iterations of this solve ran (0 from batches) */
-  int32_t x_update_every; /* 2: the streaming p(l)-CG sweeps of this solve wrote x on
-                             every second sweep (PLCG_X_PAIRED), 1: on every sweep
-                             (also CG and resident launches); 0 from batches */
+  int32_t x_update_every; /* 2: the streaming sweeps of this solve wrote x on every
+                             second iteration (PLCG_X_PAIRED), 1: on every iteration
+                             (also resident launches); 0 from batches */
 } plcg_result;
 
 /* Create a solver for one operator and one configuration.

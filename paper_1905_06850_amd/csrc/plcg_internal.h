@@ -62,6 +62,7 @@ struct DevState {
   double rref;               // reference norm for the stopping test
   double abs_tol;            // tol * rref
   double cg_rho, cg_alpha, cg_beta;
+  double cg_alpha_prev;      // alpha_{k-1} (CG sweep B with paired x updates)
   double sumsq;
   int32_t l;
   int32_t status;
@@ -125,6 +126,7 @@ struct CgArgs {
   int32_t k, n, nx, ny, nz, d3, nchunks, nstream, nparts_in, pstride, work;
   int32_t zseg;              // > 0: 3D sweep A marches tiles through zseg planes
   int32_t hint;              // streaming cache hints (kHint* bits)
+  int32_t xmode;             // sweep B: kXEvery, kXSkip or kXPair
 };
 
 // Resident solves (plcg_resident.hip): one workgroup of kResThreads runs a whole

@@ -447,8 +447,10 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
 
 // Sweep B of iteration k.  Prologue: alpha_k = rho_k / (p_k, q) from sweep A
 // (breakdown if (p_k, A p_k) <= 0).  Then x += alpha p_k, r -= alpha q and the
-// product (r_{k+1}, r_{k+1}).
-template <int H>
+// product (r_{k+1}, r_{k+1}).  P: paired x updates - for even k (a.xmode kXSkip)
+// x is left alone; for odd k (kXPair) x += alpha_{k-1} p_{k-1}, then alpha_k p_k,
+// with p_{k-1} still in the other p buffer (the same two roundings).
+template <int H, bool P>
 __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
   constexpr bool NTL = (H & kHintLoads) != 0;
   constexpr bool NTS = (H & kHintStores) != 0;
@@ -464,6 +466,7 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
         sh.status = kCgBreak;
         sh.last_t = a.k;
       } else {
+        sh.cg_alpha_prev = sh.cg_alpha;
         sh.cg_alpha = sh.cg_rho / pq;
       }
     }
@@ -476,26 +479,52 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
   if (sh.status != kRunning || !a.work) return;
 
   const double alpha = sh.cg_alpha;
+  const double alpha_prev = sh.cg_alpha_prev;
+  const bool upd = a.xmode == kXPair;   // P: this sweep writes x
   double acc[1] = {0.0};
   // Sweep A walks the bands front to back, sweep B back to front.
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0, true); it.c < it.end; it.c += it.step) {
     const int idx = it.at() * kChunk + threadIdx.x * kVec;
     if (idx + 1 < a.n) {
-      Vals<2> x, p, r, q;
-      x.template ld<NTL>(a.x + idx);
-      p.template ld<NTL>(a.p_new + idx);
-      r.template ld<NTL>(a.r + idx);
-      q.template ld<NTL>(a.q + idx);
+      if constexpr (!P) {
+        Vals<2> x, p, r, q;
+        x.template ld<NTL>(a.x + idx);
+        p.template ld<NTL>(a.p_new + idx);
+        r.template ld<NTL>(a.r + idx);
+        q.template ld<NTL>(a.q + idx);
 #pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        x.v[v] += alpha * p.v[v];
-        r.v[v] -= alpha * q.v[v];
-        acc[0] += r.v[v] * r.v[v];
+        for (int v = 0; v < 2; ++v) {
+          x.v[v] = fma(alpha, p.v[v], x.v[v]);
+          r.v[v] -= alpha * q.v[v];
+          acc[0] += r.v[v] * r.v[v];
+        }
+        x.template st<NTS>(a.x + idx);
+        r.template st<NTS>(a.r + idx);
+      } else {
+        Vals<2> r, q;
+        r.template ld<NTL>(a.r + idx);
+        q.template ld<NTL>(a.q + idx);
+        if (upd) {
+          Vals<2> x, p, po;
+          x.template ld<NTL>(a.x + idx);
+          p.template ld<NTL>(a.p_new + idx);
+          po.template ld<NTL>(a.p_old + idx);
+#pragma unroll
+          for (int v = 0; v < 2; ++v) x.v[v] = fma(alpha, p.v[v], fma(alpha_prev, po.v[v], x.v[v]));
+          x.template st<NTS>(a.x + idx);
+        }
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          r.v[v] -= alpha * q.v[v];
+          acc[0] += r.v[v] * r.v[v];
+        }
+        r.template st<NTS>(a.r + idx);
       }
-      x.template st<NTS>(a.x + idx);
-      r.template st<NTS>(a.r + idx);
     } else if (idx < a.n) {
-      a.x[idx] += alpha * a.p_new[idx];
+      if (!P)
+        a.x[idx] = fma(alpha, a.p_new[idx], a.x[idx]);
+      else if (upd)
+        a.x[idx] = fma(alpha, a.p_new[idx], fma(alpha_prev, a.p_old[idx], a.x[idx]));
       const double rv = a.r[idx] - alpha * a.q[idx];
       a.r[idx] = rv;
       acc[0] += rv * rv;
@@ -582,6 +611,7 @@ __global__ __launch_bounds__(kThreads) void start_kernel(const double *part_in, 
       gref(sh, 0, 0) = 1.0;                    // g_00 = 1 (Alg. 1, first line)
       sh.cg_rho = ss;
       sh.cg_alpha = 0.0;
+      sh.cg_alpha_prev = 0.0;
       sh.cg_beta = 0.0;
     }
     publish(sh, hs, sqrt(ss), -1);
@@ -739,7 +769,16 @@ hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s) {
 
 template <int H>
 static hipError_t launch_cg_b_h(const CgArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL((cg_sweep_b_kernel<H>), dim3(a.nstream), dim3(kThreads), 0, s, a);
+  switch (a.xmode) {
+    case kXEvery:
+      hipLaunchKernelGGL((cg_sweep_b_kernel<H, false>), dim3(a.nstream), dim3(kThreads), 0, s, a);
+      break;
+    case kXSkip:
+    case kXPair:
+      hipLaunchKernelGGL((cg_sweep_b_kernel<H, true>), dim3(a.nstream), dim3(kThreads), 0, s, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

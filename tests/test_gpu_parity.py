@@ -181,8 +181,7 @@ def test_early_iterates(dev, method, l, launch, x_update):
                               x_update=x_update)
         assert res.iters == m == ref.iters
         assert res.reason == 2
-        assert m == 0 or res.x_update_every == (2 if method == "plcg" and x_update == "paired"
-                                                else 1)
+        assert m == 0 or res.x_update_every == (2 if x_update == "paired" else 1)
         if m == 0:
             assert np.array_equal(x, x0)
         else:
@@ -190,16 +189,20 @@ def test_early_iterates(dev, method, l, launch, x_update):
         s.close()
 
 
-@pytest.mark.parametrize("dims,l,precision,interval", [
-    ((64, 64), 1, "fp64", None), ((100, 37), 2, "fp64", None), ((20, 13, 7), 3, "fp64", None),
-    ((64, 64), 5, "fp64", None), ((48, 48), 3, "fp64", (6.0, 8.0)),
-    ((96, 80), 1, "fp32", None), ((60, 50), 2, "fp32", None)])
-def test_paired_x_updates_bitwise_equal(dev, dims, l, precision, interval):
-    """PLCG_X_PAIRED (x written every second sweep, two steps with the same two
-    roundings) against PLCG_X_EVERY: x, iteration and restart counts and both
+@pytest.mark.parametrize("method,dims,l,precision,interval", [
+    ("plcg", (64, 64), 1, "fp64", None), ("plcg", (100, 37), 2, "fp64", None),
+    ("plcg", (20, 13, 7), 3, "fp64", None), ("plcg", (64, 64), 5, "fp64", None),
+    ("plcg", (48, 48), 3, "fp64", (6.0, 8.0)), ("plcg", (96, 80), 1, "fp32", None),
+    ("plcg", (60, 50), 2, "fp32", None), ("cg", (64, 64), 1, "fp64", None),
+    ("cg", (100, 37), 1, "fp64", None), ("cg", (20, 13, 7), 1, "fp64", None),
+    ("cg", (64, 160, 6), 1, "fp64", None)])
+def test_paired_x_updates_bitwise_equal(dev, method, dims, l, precision, interval):
+    """PLCG_X_PAIRED (x written every second iteration, two steps with the same
+    two roundings) against PLCG_X_EVERY: x, iteration and restart counts and both
     residuals bit for bit equal, for runs that stop after an odd and an even
     number of steps and runs to convergence (the (6, 8) interval on 48^2
-    breaks down and restarts; fp32: FP32-stored inner solves in refinement)."""
+    breaks down and restarts; fp32: FP32-stored inner solves in refinement;
+    CG: its sweep B, with p_{k-1} in its second p buffer)."""
     n = int(np.prod(dims))
     b = synth.uniform(n, 5)
     x0 = np.zeros(n)
@@ -209,7 +212,7 @@ def test_paired_x_updates_bitwise_equal(dev, dims, l, precision, interval):
     for tol, maxit in ((1e-30, 7), (1e-30, 8), (1e-9, 100000)):
         out = []
         for xu in ("every", "paired"):
-            x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, tol, maxit, launch="streaming",
+            x, res, s = gpu_solve(dev, dims, method, l, b, x0, tol, maxit, launch="streaming",
                                   x_update=xu, **dict(kw))
             s.close()
             assert res.x_update_every == (2 if xu == "paired" else 1)
@@ -469,9 +472,9 @@ def test_full_size_against_stored_oracle(dev, name):
                           interval=tuple(g["interval"]))
     assert res.reason == 1
     assert abs(res.iters - g["iters"]) <= 1
-    # x on every second sweep, except CG and p(2) at 2048^2, whose 8 vectors
-    # fill the 256 MiB memory-side cache exactly (a second p buffer would not fit)
-    assert res.x_update_every == (1 if method == "cg" or name == "poisson2048_p2" else 2)
+    # x on every second sweep, except p(2) at 2048^2, whose 8 vectors fill the
+    # 256 MiB memory-side cache exactly (a second p buffer would not fit)
+    assert res.x_update_every == (1 if name == "poisson2048_p2" else 2)
     assert res.true_relres <= 10 * g["true_relres"] and g["true_relres"] <= 10 * res.true_relres
     idx = np.array(g["sample_idx"])
     ref = np.array(g["sample_x"])
