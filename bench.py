@@ -100,9 +100,10 @@ def measured_traffic(workload: str, kernel: str):
     hash the counters were taken with, and `<kernel> <bytes>` per launch (FETCH_SIZE
     plus WRITE_SIZE, each scaled by the copy-kernel calibration factor), the kernel
     named without namespace, argument list or spaces, e.g.
-    `plcg_sweep_kernel<1,false,double,0>`.  `kernel` may leave out the last
-    template argument (the streaming cache hints the library picked for the
-    workload): the one kernel of that family in the file is taken.  A different
+    `plcg_sweep_kernel<1,false,double,0,true>`.  `kernel` may leave out the
+    trailing template arguments (the streaming cache hints and the x update
+    pairing the library picked for the workload): the one kernel of that family
+    in the file is taken.  A different
     source hash means the kernel changed since: None.  Returns (name, bytes).
     """
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
