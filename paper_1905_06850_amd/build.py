@@ -1,9 +1,11 @@
 """Build libplcg.so for gfx950 with hipcc (in-tree, next to this file)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -23,17 +25,32 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+def _run(cmd, verbose, what):
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building libplcg.so")
+        raise RuntimeError(f"hipcc failed {what}")
     if verbose and proc.stderr.strip():
         sys.stderr.write(proc.stderr)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the translation units in parallel (each holds its own device
+    code; no relocatable device code), then link them into libplcg.so."""
+    tmp = LIB + ".tmp"
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="plcg_build_") as d:
+        objs = [os.path.join(d, os.path.basename(src) + ".o") for src in SOURCES]
+        jobs = [([HIPCC, *compile_flags, "-c", src, "-o", obj], f"compiling {src}")
+                for src, obj in zip(SOURCES, objs)]
+        workers = max(1, min(len(jobs), os.cpu_count() or 1))
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            for f in [ex.submit(_run, cmd, verbose, what) for cmd, what in jobs]:
+                f.result()
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose,
+             "linking libplcg.so")
     os.replace(tmp, LIB)
     return LIB
 
