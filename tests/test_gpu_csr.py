@@ -133,16 +133,21 @@ def test_csr_scaled_variable_solve_parity(dev, dims, method, l, launch):
 
 
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 4)])
-@pytest.mark.parametrize("launch", LAUNCHES)
-def test_csr_early_iterates(dev, method, l, launch):
+@pytest.mark.parametrize("launch,x_update", [("streaming", "every"), ("streaming", "paired"),
+                                             ("resident", "auto")])
+def test_csr_early_iterates(dev, method, l, launch, x_update):
+    """x after m steps against the oracle's x_m; streaming with x updated in
+    every iteration and paired (odd m end on the separate last step)."""
     (rp, ci, va), As = scaled_variable((40, 30), 75)
     csr = Csr(dev, rp, ci, va)
     b = synth.uniform(As.n, 76)
     x0 = np.zeros(As.n)
     for m in (1, 2, 5, 20):
         ref = oracle_solve(As, method, l, b, x0, 1e-30, m, 0.0, 2.0)
-        x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-30, m, 0.0, 2.0, launch=launch)
+        x, res = gpu_solve(dev, csr, method, l, b, x0, 1e-30, m, 0.0, 2.0, launch=launch,
+                           x_update=x_update)
         assert res.iters == m == ref.iters
+        assert res.x_update_every == (2 if x_update == "paired" else 1)
         assert _rel(x, ref.x) < 1e-13
 
 

@@ -34,7 +34,7 @@ def _rel(a, b):
 LAUNCHES = ["streaming", "resident"]
 
 
-def gpu_solve(dev, d, method, l, b, x0, tol, maxit, launch="auto"):
+def gpu_solve(dev, d, method, l, b, x0, tol, maxit, launch="auto", x_update="auto"):
     plcg = _plcg()
     if launch == "resident" and not plcg.resident_supported("diag", d.size, method, l):
         pytest.skip(f"no resident kernel for {method} l={l} n={d.size}")
@@ -42,7 +42,7 @@ def gpu_solve(dev, d, method, l, b, x0, tol, maxit, launch="auto"):
           flush=True)
     dt = torch.from_numpy(d).to(dev)
     s = plcg.Solver("diag", (d.size,), method=method, l=l, lmin=0.0, lmax=8.0,
-                    diag=dt.data_ptr(), launch=launch)
+                    diag=dt.data_ptr(), launch=launch, x_update=x_update)
     del dt                                       # copied by plcg_create
     bt = torch.from_numpy(b).to(dev)
     xt = torch.from_numpy(x0.copy()).to(dev)
@@ -93,15 +93,19 @@ def test_diag_solve_parity(dev, dims, method, l, launch):
 
 
 @pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 4)])
-@pytest.mark.parametrize("launch", LAUNCHES)
-def test_diag_early_iterates(dev, method, l, launch):
+@pytest.mark.parametrize("launch,x_update", [("streaming", "every"), ("streaming", "paired"),
+                                             ("resident", "auto")])
+def test_diag_early_iterates(dev, method, l, launch, x_update):
+    """x after m steps against the oracle's x_m; streaming with x updated in
+    every iteration and paired (odd m end on the separate last step)."""
     d = synth.spectrum_diagonal((48, 40))
     b = synth.uniform(d.size, 8)
     x0 = 0.1 * synth.uniform(d.size, 9)
     for m in (1, 2, 5, 20):
         ref = oracle_solve(d, method, l, b, x0, 1e-30, m)
-        x, res = gpu_solve(dev, d, method, l, b, x0, 1e-30, m, launch=launch)
+        x, res = gpu_solve(dev, d, method, l, b, x0, 1e-30, m, launch=launch, x_update=x_update)
         assert res.iters == m == ref.iters
+        assert res.x_update_every == (2 if x_update == "paired" else 1)
         assert _rel(x, ref.x) < 1e-13
 
 
