@@ -403,6 +403,28 @@ plcg_status run_segment(plcg_handle *h, S *const (*basis)[2], S *const *ring, S 
   out->final_slot = last_i & 1;
   DevState ds;
   PLCG_HIP(hipMemcpy(&ds, h->st[out->final_slot], sizeof(ds), hipMemcpyDeviceToHost));
+  // The stop can come from a launch near the end of the last group (the owner
+  // publishes it at the start of its launch), while x_{last_t} is complete only
+  // after sweep last_t + l: enqueue the sweeps up to there that were not
+  // enqueued yet.  They run as ordinary sweeps (t <= last_t) and carry the
+  // state forward.
+  if (!resident && ds.status != kRunning) {
+    const int need = std::min(imax, std::max(ds.last_t, -1) + l);
+    if (need > last_i) {
+      if ((e = tl.begin_group()) != PLCG_OK) return e;
+      for (int i = last_i + 1; i <= need; ++i) {
+        SweepArgsT<S> a;
+        fill_sweep_args<S>(h, i, basis, ring, p, x, a);
+        PLCG_HIP(launch_plcg_sweep(a, s));
+        tl.launched();
+        last_i = i;
+      }
+      if ((e = tl.end_group()) != PLCG_OK) return e;
+      PLCG_HIP(wait_stream(h, s));
+      out->final_slot = last_i & 1;
+      PLCG_HIP(hipMemcpy(&ds, h->st[out->final_slot], sizeof(ds), hipMemcpyDeviceToHost));
+    }
+  }
   out->status = ds.status;
   out->last_t = ds.last_t;
   // Iterations that ran: every sweep up to last_t + l (or the whole loop).

@@ -226,6 +226,50 @@ def test_paired_x_updates_bitwise_equal(dev, method, dims, l, precision, interva
         assert re_.restarts > 0
 
 
+@pytest.mark.parametrize("l", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("x_update,precision", [("every", "fp64"), ("paired", "fp64"),
+                                                ("paired", "fp32")])
+def test_stop_near_end_of_check_group(dev, l, x_update, precision):
+    """The host checks the device status after every `check_every` launches and
+    stops enqueueing once a stop is published; x_t is complete only after sweep
+    t + l, which may not have been enqueued by then.  With check_every = 1, 2, 3
+    the stop lands in the last launches of a group: x, counts and residuals must
+    be bit for bit those of check_every = 64 (convergence, and the breakdown +
+    restart of a too-narrow interval), and x must match the oracle."""
+    cases = [((128, 128), None, 1e-9)]
+    if precision == "fp64" and l in (2, 3):
+        cases.append(((64, 64), (0.0, 16.0), 1e-8) if l == 2 else ((48, 48), (6.0, 8.0), 1e-9))
+    for dims, interval, tol in cases:
+        n = int(np.prod(dims))
+        b = synth.uniform(n, 31)
+        x0 = np.zeros(n)
+        kw = {"precision": precision, "inner_tol": 1e-4 if precision == "fp32" else 0.0,
+              "x_update": x_update}
+        if interval is not None:
+            kw["interval"] = interval
+        runs = {}
+        for ce in (64, 1, 2, 3):
+            x, res, s = gpu_solve(dev, dims, "plcg", l, b, x0, tol, 100000, launch="streaming",
+                                  check_every=ce, **dict(kw))
+            s.close()
+            runs[ce] = (x, res)
+        xr, rr = runs[64]
+        assert rr.reason == 1, rr.as_dict()
+        for ce in (1, 2, 3):
+            x, res = runs[ce]
+            assert np.array_equal(x.view(np.uint64), xr.view(np.uint64)), (ce, res.as_dict())
+            assert (res.iters, res.restarts, res.outer, res.reason, res.spmvs) == \
+                (rr.iters, rr.restarts, rr.outer, rr.reason, rr.spmvs)
+            assert res.rec_relres == rr.rec_relres and res.true_relres == rr.true_relres
+        if precision == "fp64" and interval is None:
+            ref = oracle_solve(dims, "plcg", l, b, x0, tol, 100000)
+            assert abs(rr.iters - ref.iters) <= 1 and rr.restarts == ref.restarts == 0
+            assert _rel(xr, ref.x) < 1e-8
+        if interval is not None:
+            # restarts: the count depends on rounding; the solve must still reach tol
+            assert rr.restarts > 0 and rr.true_relres < 10 * tol
+
+
 @pytest.mark.parametrize("dims", [(64, 64, 256), (32, 48, 1100)])
 def test_cg_3d_zmarch_iterates(dev, dims):
     """3D CG whose sweep A marches tiles through several planes (2 and 3 planes
