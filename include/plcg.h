@@ -258,6 +258,39 @@ int32_t plcg_resident_supported(int32_t kind, int64_t n, int32_t method, int32_t
 /* Library version, major*10000 + minor*100 + patch. */
 int32_t plcg_version(void);
 
+/* Size of the static device workspace of plcg_solve_noalloc (64 MiB per GPU). */
+#define PLCG_NOALLOC_BYTES (64LL << 20)
+
+/* For callers that cannot allocate device or pinned host memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it): the
+ * solve of plcg_create + plcg_solve + plcg_destroy in one call, with every
+ * workspace buffer (work vectors, partial sums, scalar state, progress record)
+ * taken from a static device array of PLCG_NOALLOC_BYTES that each GPU holds
+ * from the library's first use of it until the process ends.  It calls no
+ * hipMalloc, hipFree or other allocating routine.
+ *  - op: PLCG_OP_STENCIL2D5 or PLCG_OP_STENCIL3D7 only (the other kinds need
+ *    library copies of their data); cfg as for plcg_create, history_cap = 0.
+ *    d_b, d_x, tol, maxit, stream and *out as for plcg_solve; the result and x
+ *    are bit for bit those of plcg_solve with the same op and cfg.  Timing is
+ *    not available (sweep_ms = 0).
+ *  - Limits: the work vectors must fit the array: about (2l + max(2, l-1) + 2)
+ *    n doubles for p(l)-CG (FP32_REFINED: that many floats plus n doubles), 4 n
+ *    doubles for CG, plus about 0.2 MiB (e.g. p(1)-CG up to ~1.3 M unknowns);
+ *    larger systems give PLCG_E_INVALID with the bytes needed in the message,
+ *    before any device work.
+ *  - Each call re-initialises the scalar state and clears the partial sums and
+ *    the progress record in the array (the array keeps the last call's
+ *    contents otherwise).  Calls on one GPU share its array: the library
+ *    serialises them within the process (a second caller blocks until the
+ *    first returns); they must not be captured into a graph (the call waits on
+ *    the host).
+ *  - The host reads the device's progress from an idle stream after every
+ *    check_every launches, so the device idles while the host enqueues the
+ *    next group (plcg_solve overlaps the two through pinned host memory). */
+plcg_status plcg_solve_noalloc(const plcg_operator_desc *op, const plcg_config *cfg,
+                               const double *d_b, double *d_x, double tol, int32_t maxit,
+                               void *stream, plcg_result *out);
+
 /* ------------------------------------------------------------------------
  * Batched and served solves.
  *

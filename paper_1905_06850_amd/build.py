@@ -13,6 +13,7 @@ LIB = os.path.join(HERE, "libplcg.so")
 SOURCES = [os.path.join(HERE, "csrc", "plcg_kernels.hip"),
            os.path.join(HERE, "csrc", "plcg_resident.hip"),
            os.path.join(HERE, "csrc", "plcg_batch_kernels.hip"),
+           os.path.join(HERE, "csrc", "plcg_noalloc.hip"),
            os.path.join(HERE, "csrc", "plcg_engine.cpp"),
            os.path.join(HERE, "csrc", "plcg_batch.cpp"),
            os.path.join(HERE, "csrc", "plcg_serve.cpp")]

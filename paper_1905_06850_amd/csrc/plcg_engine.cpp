@@ -140,8 +140,9 @@ struct plcg_handle {
   double *part[2] = {nullptr, nullptr};   // partials of launches with even / odd index
   DevState *st[2] = {nullptr, nullptr};   // scalar state read by odd / even launches
   double *hist = nullptr;
-  HostStatus *hs_host = nullptr;  // pinned, mapped
+  HostStatus *hs_host = nullptr;  // pinned, mapped (NULL: the record is in device memory)
   HostStatus *hs_dev = nullptr;
+  HostStatus hs_copy{};           // host copy of a device-memory record (see wait_stream)
   // timing
   bool timing = false;
   std::vector<hipEvent_t> tev;
@@ -182,17 +183,30 @@ void release(plcg_handle *h) {
     if (e) (void)hipEventDestroy(e);
 }
 
-volatile HostStatus *hstat(plcg_handle *h) { return h->hs_host; }
+// The device's progress record: mapped pinned host memory written by the
+// device (handles from plcg_create), or the host copy that wait_stream takes of
+// a record kept in device memory (workspace without host allocations).
+volatile HostStatus *hstat(plcg_handle *h) { return h->hs_host ? h->hs_host : &h->hs_copy; }
 
 // Every place where the host blocks on the device goes through here or
 // throttle(), so that plcg_result.host_waits counts them.
 hipError_t wait_stream(plcg_handle *h, hipStream_t s) {
   ++h->host_waits;
-  return hipStreamSynchronize(s);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess && h->hs_host == nullptr)
+    e = hipMemcpy(&h->hs_copy, h->hs_dev, sizeof(HostStatus), hipMemcpyDeviceToHost);
+  return e;
 }
 
 // Keep at most two groups of iterations in flight; returns the device status.
+// With the record in device memory the host can only read it from an idle
+// stream: it waits for every group before enqueueing the next.
 plcg_status throttle(plcg_handle *h, hipStream_t s, int group, int *status) {
+  if (h->hs_host == nullptr) {
+    PLCG_HIP(wait_stream(h, s));
+    *status = hstat(h)->status;
+    return PLCG_OK;
+  }
   PLCG_HIP(hipEventRecord(h->chunk_ev[group & 1], s));
   if (group >= 1) {
     ++h->host_waits;
@@ -890,25 +904,11 @@ plcg_status copy_csr(plcg_handle *h, const plcg_operator_desc *op) {
   return PLCG_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *plcg_last_error(void) { return g_last_error.c_str(); }
-
-int32_t plcg_version(void) { return 100; }
-
-int32_t plcg_resident_supported(int32_t kind, int64_t n, int32_t method, int32_t l) {
-  if (kind < PLCG_OP_STENCIL2D5 || kind > PLCG_OP_CSR || n < 1 || n > PLCG_RESIDENT_MAX) return 0;
-  if (method != PLCG_METHOD_CG && method != PLCG_METHOD_PLCG) return 0;
-  return resident_width(method == PLCG_METHOD_PLCG ? 1 : 0, l, op_kind_index(kind), (int)n) > 0
-             ? 1
-             : 0;
-}
-
-plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, plcg_handle **out) {
-  if (out == nullptr) return fail(PLCG_E_INVALID, "out is NULL");
-  *out = nullptr;
+// Checks the descriptor and the configuration and sets every parameter of a
+// solver that needs no device memory (makes no HIP call).  *res_ok: the
+// resident kernels could take this system.
+plcg_status setup_handle(const plcg_operator_desc *op, const plcg_config *cfg, plcg_handle *h,
+                         bool *res_ok) {
   if (op == nullptr || cfg == nullptr) return fail(PLCG_E_INVALID, "NULL descriptor or config");
   if (op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7 &&
       op->kind != PLCG_OP_DIAG && op->kind != PLCG_OP_CSR)
@@ -945,23 +945,16 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     return fail(PLCG_E_INVALID, "unknown launch_mode");
   if (cfg->x_update < PLCG_X_AUTO || cfg->x_update > PLCG_X_PAIRED)
     return fail(PLCG_E_INVALID, "unknown x_update");
-  const bool res_ok = cfg->precision == PLCG_PREC_FP64 &&
-                      plcg_resident_supported(op->kind, n, cfg->method, cfg->l) == 1;
-  if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT && !res_ok)
+  *res_ok = cfg->precision == PLCG_PREC_FP64 &&
+            plcg_resident_supported(op->kind, n, cfg->method, cfg->l) == 1;
+  if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT && !*res_ok)
     return fail(PLCG_E_INVALID,
                 "PLCG_LAUNCH_RESIDENT needs FP64, n <= PLCG_RESIDENT_MAX and a supported l");
 
-  hipError_t he;
-  int dev = 0;
-  if ((he = hipGetDevice(&dev)) != hipSuccess)
-    return fail(PLCG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
-
-  plcg_handle *h = new plcg_handle();
   h->op = *op;
   h->op.nz = nz;
   h->jacobi = op->kind == PLCG_OP_CSR && op->jacobi != 0;
   h->d3 = op->kind == PLCG_OP_STENCIL3D7;
-  h->device = dev;
   h->method = cfg->method;
   h->l = pl ? cfg->l : 1;
   h->R = h->l - 1 > 2 ? h->l - 1 : 2;
@@ -983,37 +976,53 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
         const double half = 0.5 * (cfg->lambda_max - cfg->lambda_min);
         h->sigma[i] = mid + half * std::cos((2 * i + 1) * M_PI / (2 * h->l));
       }
-      if (!std::isfinite(h->sigma[i])) {
-        delete h;
-        return fail(PLCG_E_INVALID, "shifts must be finite");
-      }
+      if (!std::isfinite(h->sigma[i])) return fail(PLCG_E_INVALID, "shifts must be finite");
     }
   }
+  return PLCG_OK;
+}
 
-  // All work vectors live in one allocation.  Consecutive vectors are spaced by
-  // their size rounded up to 64 KiB plus a stagger, so that the many streams
-  // of a sweep do not start on the same HBM channel when n*8 is a power of two.
-  const size_t vb = (size_t)n * sizeof(double);
+// A solver's workspace is one block of device memory: the work vectors, the
+// two sets of partial sums, the two copies of the scalar state, the history
+// and, where the library cannot allocate pinned host memory, the progress
+// record.  Consecutive vectors are spaced by their size rounded up to 64 KiB
+// plus a stagger, so that the many streams of a sweep do not start on the same
+// HBM channel when n*8 is a power of two.
+struct Workspace {
+  size_t vstride, vstride32;      // bytes between FP64 / FP32 vectors
+  int nvec, nvec32;
+  size_t vec32_at, part_at, st_at, hist_at, hs_at, total;   // offsets (bytes) and size
+};
+constexpr size_t kPartBytes = sizeof(double) * (kLMax + 1) * kMaxStream;
+
+Workspace workspace_layout(const plcg_handle *h, bool status_record) {
+  auto up = [](size_t v, size_t a) { return (v + a - 1) / a * a; };
+  Workspace w;
   const size_t stagger = 4096 + 256;
-  const size_t vstride = ((vb + 65535) / 65536) * 65536 + stagger;
+  w.vstride = up((size_t)h->n * sizeof(double), 65536) + stagger;
+  w.vstride32 = up((size_t)h->n * sizeof(float), 65536) + stagger;
+  const bool pl = h->method == PLCG_METHOD_PLCG;
   const bool mixed = h->precision == PLCG_PREC_FP32_REFINED;
-  const size_t vb32 = (size_t)n * sizeof(float);
-  const size_t vstride32 = ((vb32 + 65535) / 65536) * 65536 + stagger;
-  // FP64 vectors: bases + ring + 2 p (p(l)-CG), r (mixed), r, p, p, q (CG).
-  const int nvec = mixed ? 1 : (pl ? 2 * h->l + h->R + 2 : 4);
-  const int nvec32 = mixed ? 2 * h->l + h->R + 3 : 0;
-  plcg_status e = PLCG_OK;
-  char *arena = nullptr;
-  e = dev_alloc(h, reinterpret_cast<void **>(&arena), vstride * nvec + vstride32 * nvec32);
+  // FP64 vectors: bases + ring + 2 p (p(l)-CG), r (mixed), r, p, p, q (CG);
+  // FP32 (mixed): bases + ring + 2 p + the correction.
+  w.nvec = mixed ? 1 : (pl ? 2 * h->l + h->R + 2 : 4);
+  w.nvec32 = mixed ? 2 * h->l + h->R + 3 : 0;
+  w.vec32_at = w.vstride * w.nvec;
+  w.part_at = up(w.vec32_at + w.vstride32 * w.nvec32, 4096);
+  w.st_at = w.part_at + 2 * kPartBytes;
+  w.hist_at = up(w.st_at + 2 * sizeof(DevState), 256);
+  w.hs_at = up(w.hist_at + sizeof(double) * 4 * (size_t)h->hist_cap, 256);
+  w.total = w.hs_at + (status_record ? up(sizeof(HostStatus), 256) : 0);
+  return w;
+}
+
+void carve_workspace(plcg_handle *h, const Workspace &w, char *base, bool status_record) {
   int used = 0, used32 = 0;
-  auto vec = [&](double **dst) {
-    if (e == PLCG_OK) *dst = reinterpret_cast<double *>(arena + vstride * used++);
-  };
+  auto vec = [&](double **dst) { *dst = reinterpret_cast<double *>(base + w.vstride * used++); };
   auto vec32 = [&](float **dst) {
-    if (e == PLCG_OK)
-      *dst = reinterpret_cast<float *>(arena + vstride * nvec + vstride32 * used32++);
+    *dst = reinterpret_cast<float *>(base + w.vec32_at + w.vstride32 * used32++);
   };
-  if (mixed) {
+  if (h->precision == PLCG_PREC_FP32_REFINED) {
     vec(&h->r64);
     for (int k = 0; k < h->l; ++k) {
       vec32(&h->basis32[k][0]);
@@ -1023,7 +1032,7 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     vec32(&h->p32[0]);
     vec32(&h->p32[1]);
     vec32(&h->d32);
-  } else if (pl) {
+  } else if (h->method == PLCG_METHOD_PLCG) {
     for (int k = 0; k < h->l; ++k) {
       vec(&h->basis[k][0]);
       vec(&h->basis[k][1]);
@@ -1038,13 +1047,90 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     vec(&h->cg_q);
   }
   for (int k = 0; k < 2; ++k) {
-    if (e == PLCG_OK)
-      e = dev_alloc(h, reinterpret_cast<void **>(&h->part[k]),
-                    sizeof(double) * (kLMax + 1) * kMaxStream);
-    if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&h->st[k]), sizeof(DevState));
+    h->part[k] = reinterpret_cast<double *>(base + w.part_at + k * kPartBytes);
+    h->st[k] = reinterpret_cast<DevState *>(base + w.st_at + k * sizeof(DevState));
   }
-  if (e == PLCG_OK && h->hist_cap > 0)
-    e = dev_alloc(h, reinterpret_cast<void **>(&h->hist), sizeof(double) * 4 * h->hist_cap);
+  h->hist = h->hist_cap > 0 ? reinterpret_cast<double *>(base + w.hist_at) : nullptr;
+  if (status_record) h->hs_dev = reinterpret_cast<HostStatus *>(base + w.hs_at);
+}
+
+// Streaming cache hints, x-update cadence and launch mode, once the operator
+// data is in place.
+plcg_status finish_setup(plcg_handle *h, const plcg_operator_desc *op, const plcg_config *cfg,
+                         bool res_ok) {
+  const long long n = h->n;
+  const bool pl = h->method == PLCG_METHOD_PLCG;
+  const long long op_bytes = op->kind == PLCG_OP_CSR  ? 12LL * op->nnz
+                             : op->kind == PLCG_OP_DIAG ? 8LL * n
+                                                        : 0;
+  h->hint64 = pick_hint(n, h->method, h->l, h->R, 8, op_bytes);
+  h->hint32 = pick_hint(n, h->method, h->l, h->R, 4, op_bytes);
+  const int xu = cfg->x_update;
+  // CG pairs with the two p buffers it has anyway, at any size (streaming CG,
+  // paired against every iteration: 256^2 even, 1024^2 9 %, 2048^2 8.5 % and
+  // 256^3 11 % faster)
+  h->pair64 = xu == PLCG_X_PAIRED ||
+              (xu == PLCG_X_AUTO && (!pl || pair_x_updates(n, h->l, h->R, 8, op_bytes)));
+  h->pair32 = pl && (xu == PLCG_X_PAIRED ||
+                     (xu == PLCG_X_AUTO && pair_x_updates(n, h->l, h->R, 4, op_bytes)));
+  // The resident kernels index the matrix with 32-bit offsets.
+  const long long stored =
+      h->od.ell_k > 0 ? (long long)h->od.ell_k * h->od.ell_ld : (long long)op->nnz;
+  if (res_ok && cfg->launch_mode != PLCG_LAUNCH_STREAMING) {
+    if (op->kind != PLCG_OP_CSR || stored < (1LL << 30))
+      h->res_kind = op_kind_index(op->kind);
+    else if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT)
+      return fail(PLCG_E_INVALID, "PLCG_LAUNCH_RESIDENT: too many stored entries");
+  }
+  return PLCG_OK;
+}
+
+// Both copies of the scalar state start from this (shifts, l, history size).
+DevState initial_state(const plcg_handle *h) {
+  DevState init;
+  std::memset(&init, 0, sizeof(init));
+  init.l = h->l;
+  init.hist_cap = h->hist_cap;
+  for (int k = 0; k < kLMax; ++k) init.sigma[k] = h->sigma[k];
+  return init;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *plcg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t plcg_version(void) { return 100; }
+
+int32_t plcg_resident_supported(int32_t kind, int64_t n, int32_t method, int32_t l) {
+  if (kind < PLCG_OP_STENCIL2D5 || kind > PLCG_OP_CSR || n < 1 || n > PLCG_RESIDENT_MAX) return 0;
+  if (method != PLCG_METHOD_CG && method != PLCG_METHOD_PLCG) return 0;
+  return resident_width(method == PLCG_METHOD_PLCG ? 1 : 0, l, op_kind_index(kind), (int)n) > 0
+             ? 1
+             : 0;
+}
+
+plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, plcg_handle **out) {
+  if (out == nullptr) return fail(PLCG_E_INVALID, "out is NULL");
+  *out = nullptr;
+  plcg_handle *h = new plcg_handle();
+  bool res_ok = false;
+  plcg_status e = setup_handle(op, cfg, h, &res_ok);
+  if (e != PLCG_OK) {
+    delete h;
+    return e;
+  }
+  hipError_t he;
+  if ((he = hipGetDevice(&h->device)) != hipSuccess) {
+    delete h;
+    return fail(PLCG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  }
+  const long long n = h->n;
+  const Workspace w = workspace_layout(h, false);
+  char *arena = nullptr;
+  e = dev_alloc(h, reinterpret_cast<void **>(&arena), w.total);
+  if (e == PLCG_OK) carve_workspace(h, w, arena, false);
   if (e == PLCG_OK && op->kind == PLCG_OP_DIAG) {
     // The library keeps its own copy of d; every entry must be finite and > 0
     // (an SPD diagonal), checked once here on the host.
@@ -1068,30 +1154,7 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     h->od.dg = dg;
   }
   if (e == PLCG_OK && op->kind == PLCG_OP_CSR) e = copy_csr(h, op);
-  {
-    const long long op_bytes = op->kind == PLCG_OP_CSR  ? 12LL * op->nnz
-                               : op->kind == PLCG_OP_DIAG ? 8LL * n
-                                                          : 0;
-    h->hint64 = pick_hint(n, h->method, h->l, h->R, 8, op_bytes);
-    h->hint32 = pick_hint(n, h->method, h->l, h->R, 4, op_bytes);
-    const int xu = cfg->x_update;
-    // CG pairs with the two p buffers it has anyway, at any size (streaming CG,
-    // paired against every iteration: 256^2 even, 1024^2 9 %, 2048^2 8.5 % and
-    // 256^3 11 % faster)
-    h->pair64 = xu == PLCG_X_PAIRED ||
-                (xu == PLCG_X_AUTO && (!pl || pair_x_updates(n, h->l, h->R, 8, op_bytes)));
-    h->pair32 = pl && (xu == PLCG_X_PAIRED ||
-                       (xu == PLCG_X_AUTO && pair_x_updates(n, h->l, h->R, 4, op_bytes)));
-  }
-  // The resident kernels index the matrix with 32-bit offsets.
-  const long long stored =
-      h->od.ell_k > 0 ? (long long)h->od.ell_k * h->od.ell_ld : (long long)op->nnz;
-  if (e == PLCG_OK && res_ok && cfg->launch_mode != PLCG_LAUNCH_STREAMING) {
-    if (op->kind != PLCG_OP_CSR || stored < (1LL << 30))
-      h->res_kind = op_kind_index(op->kind);
-    else if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT)
-      e = fail(PLCG_E_INVALID, "PLCG_LAUNCH_RESIDENT: too many stored entries");
-  }
+  if (e == PLCG_OK) e = finish_setup(h, op, cfg, res_ok);
   if (e != PLCG_OK) {
     release(h);
     delete h;
@@ -1111,15 +1174,10 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     return fail(PLCG_E_HIP, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(he));
   }
   h->hs_dev = reinterpret_cast<HostStatus *>(dptr);
-  DevState init;
-  std::memset(&init, 0, sizeof(init));
-  init.l = h->l;
-  init.hist_cap = h->hist_cap;
-  for (int k = 0; k < kLMax; ++k) init.sigma[k] = h->sigma[k];
+  const DevState init = initial_state(h);
   bool ok = hipMemcpy(h->st[0], &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(h->st[1], &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemset(h->part[0], 0, sizeof(double) * (kLMax + 1) * kMaxStream) == hipSuccess &&
-            hipMemset(h->part[1], 0, sizeof(double) * (kLMax + 1) * kMaxStream) == hipSuccess &&
+            hipMemset(h->part[0], 0, 2 * kPartBytes) == hipSuccess &&
             hipEventCreateWithFlags(&h->chunk_ev[0], hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->chunk_ev[1], hipEventDisableTiming) == hipSuccess &&
             hipDeviceSynchronize() == hipSuccess;
@@ -1238,3 +1296,66 @@ plcg_status plcg_copy(const double *d_src, double *d_dst, int64_t n, void *strea
 }
 
 }  // extern "C"
+
+// A whole solve in a workspace the caller provides (device memory of ws_bytes
+// at ws): no device or pinned host memory is allocated.  The progress record
+// lives in the workspace, so the host reads it from an idle stream after each
+// group of launches; no history, no timing.  Constant-coefficient stencils
+// only: the other operators keep library copies of their data.
+namespace {
+
+// Arguments of a workspace solve: the checks of plcg_create plus its own limits
+// (no HIP call).  On success the handle holds every parameter and *w its layout.
+plcg_status check_workspace_solve(const plcg_operator_desc *op, const plcg_config *cfg,
+                                  size_t ws_bytes, plcg_handle *h, bool *res_ok, Workspace *w) {
+  if (op == nullptr || cfg == nullptr) return fail(PLCG_E_INVALID, "NULL descriptor or config");
+  if (op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7)
+    return fail(PLCG_E_INVALID,
+                "the allocation-free solve takes the 2D and 3D stencil operators only");
+  if (cfg->history_cap != 0)
+    return fail(PLCG_E_INVALID, "the allocation-free solve keeps no history (history_cap = 0)");
+  plcg_status e = setup_handle(op, cfg, h, res_ok);
+  if (e != PLCG_OK) return e;
+  *w = workspace_layout(h, true);
+  if (w->total > ws_bytes)
+    return fail(PLCG_E_INVALID, "the allocation-free solve needs " + std::to_string(w->total) +
+                                    " bytes of workspace for this system and configuration; "
+                                    "its static workspace holds " +
+                                    std::to_string(ws_bytes) +
+                                    " (use plcg_create / plcg_solve for larger systems)");
+  return PLCG_OK;
+}
+
+}  // namespace
+
+plcg_status plcg::check_workspace_solve(const plcg_operator_desc *op, const plcg_config *cfg,
+                                        size_t ws_bytes) {
+  plcg_handle h;
+  bool res_ok = false;
+  Workspace w;
+  return ::check_workspace_solve(op, cfg, ws_bytes, &h, &res_ok, &w);
+}
+
+plcg_status plcg::solve_in_workspace(const plcg_operator_desc *op, const plcg_config *cfg,
+                                     void *ws, size_t ws_bytes, const double *d_b, double *d_x,
+                                     double tol, int32_t maxit, void *stream, plcg_result *out) {
+  plcg_handle h;
+  bool res_ok = false;
+  Workspace w;
+  plcg_status e = ::check_workspace_solve(op, cfg, ws_bytes, &h, &res_ok, &w);
+  if (e != PLCG_OK) return e;
+  if (ws == nullptr) return fail(PLCG_E_INVALID, "NULL workspace");
+  PLCG_HIP(hipGetDevice(&h.device));
+  carve_workspace(&h, w, static_cast<char *>(ws), true);
+  if ((e = finish_setup(&h, op, cfg, res_ok)) != PLCG_OK) return e;
+  // The workspace holds whatever the previous call left: start both state
+  // copies afresh and clear the partial sums and the progress record.
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const DevState init = initial_state(&h);
+  PLCG_HIP(hipMemcpyAsync(h.st[0], &init, sizeof(init), hipMemcpyHostToDevice, s));
+  PLCG_HIP(hipMemcpyAsync(h.st[1], &init, sizeof(init), hipMemcpyHostToDevice, s));
+  PLCG_HIP(hipMemsetAsync(h.part[0], 0, 2 * kPartBytes, s));
+  PLCG_HIP(hipMemsetAsync(h.hs_dev, 0, sizeof(HostStatus), s));
+  PLCG_HIP(hipStreamSynchronize(s));
+  return do_solve(&h, d_b, d_x, tol, maxit, stream, out);
+}

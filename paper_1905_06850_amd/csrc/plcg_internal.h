@@ -2,7 +2,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "../../include/plcg.h"
 
 namespace plcg {
 
@@ -38,8 +41,9 @@ struct OpData {
   int32_t ell_ld;      // ELL leading dimension: n rounded up to a multiple of 4
 };
 
-// Host-visible progress record, written by the device into pinned host memory
-// (mapped) by the block that owns the scalar state.
+// Host-visible progress record, written by the block that owns the scalar
+// state into pinned host memory (mapped), or into device memory when the
+// library cannot allocate (the host then copies it from an idle stream).
 struct HostStatus {
   int32_t status;     // Status
   int32_t last_t;     // last index t whose x_t is (or will be) formed; -1: none
@@ -100,7 +104,7 @@ struct SweepArgsT {
   double *part_out;          // partials of sweep i
   const DevState *st_in;     // state after column i-1
   DevState *st_out;          // state after column i (written by the owning block)
-  HostStatus *hs;            // mapped pinned host memory
+  HostStatus *hs;            // progress record (mapped pinned host memory or device memory)
   double *hist;              // [hist_cap][4] or NULL
   int32_t i, l, n, nx, ny, nz, d3;
   int32_t nchunks;           // ceil(n / (kThreads * 16 / sizeof(S))): chunks of one 16-byte access per thread
@@ -274,5 +278,14 @@ hipError_t launch_batch_tick(const BatchArgs &a, int blocks, hipStream_t s);
 
 // Records msg as the calling thread's last error (plcg_last_error) and returns code.
 int32_t set_last_error(int32_t code, const char *msg);
+
+// A whole solve (as plcg_create + plcg_solve) in ws_bytes of device memory at
+// ws, with no device or pinned host allocation; 2D and 3D stencil operators.
+// check_workspace_solve makes the same argument checks without any HIP call.
+int32_t check_workspace_solve(const plcg_operator_desc *op, const plcg_config *cfg,
+                              size_t ws_bytes);
+int32_t solve_in_workspace(const plcg_operator_desc *op, const plcg_config *cfg, void *ws,
+                           size_t ws_bytes, const double *d_b, double *d_x, double tol,
+                           int32_t maxit, void *stream, plcg_result *out);
 
 }  // namespace plcg

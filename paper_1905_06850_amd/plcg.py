@@ -134,6 +134,9 @@ SYMBOLS = {
     "plcg_set_timing": (_st, [_h, ctypes.c_int32]),
     "plcg_copy": (_st, [_dp, _dp, ctypes.c_int64, ctypes.c_void_p]),
     "plcg_version": (ctypes.c_int32, []),
+    "plcg_solve_noalloc": (_st, [ctypes.POINTER(plcg_operator_desc), ctypes.POINTER(plcg_config),
+                                 _dp, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                 ctypes.POINTER(plcg_result)]),
     "plcg_resident_supported": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                                  ctypes.c_int32]),
     "plcg_batch_create": (_st, [ctypes.POINTER(plcg_batch_config), ctypes.POINTER(_h)]),
@@ -175,6 +178,8 @@ plcg_get_history = _lib.plcg_get_history
 plcg_set_timing = _lib.plcg_set_timing
 plcg_copy = _lib.plcg_copy
 plcg_version = _lib.plcg_version
+plcg_solve_noalloc = _lib.plcg_solve_noalloc
+PLCG_NOALLOC_BYTES = 64 << 20
 plcg_resident_supported = _lib.plcg_resident_supported
 plcg_batch_create = _lib.plcg_batch_create
 plcg_batch_footprint = _lib.plcg_batch_footprint

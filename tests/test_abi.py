@@ -122,3 +122,28 @@ def test_create_rejects_unknown_x_update():
         assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
             plcg.PLCG_E_INVALID
         assert not h.value
+
+
+@pytest.mark.parametrize("kind,nx,ny,nz,l,hist", [
+    (3, 8, 8, 1, 2, 0), (4, 8, 8, 1, 2, 0),     # diagonal / CSR: need library copies
+    (1, 8, 8, 1, 2, 16),                        # history needs a handle
+    (1, 8, 8, 1, 9, 0), (1, 0, 8, 1, 2, 0),     # the checks of plcg_create
+    (1, 2048, 2048, 1, 1, 0),                   # 6 vectors of 32 MiB: beyond the array
+    (2, 256, 256, 256, 3, 0),
+])
+def test_noalloc_rejects_before_device_work(kind, nx, ny, nz, l, hist):
+    """plcg_solve_noalloc refuses what it cannot do before touching the device
+    (so this runs without a GPU), with a message; the size limit names the
+    bytes the system would need."""
+    from paper_1905_06850_amd import plcg
+    desc = plcg.plcg_operator_desc(kind, nx, ny, nz)
+    cfg = plcg.plcg_config(1, l, 0.0, 8.0, None, 0, -1, hist)
+    res = plcg.plcg_result()
+    st = plcg.plcg_solve_noalloc(ctypes.byref(desc), ctypes.byref(cfg), 16, 32, 1e-8, 10, None,
+                                 ctypes.byref(res))
+    assert st == plcg.PLCG_E_INVALID
+    msg = plcg.plcg_last_error()
+    assert msg
+    if nx == 2048 or nz == 256:
+        assert b"bytes" in msg and str(plcg.PLCG_NOALLOC_BYTES).encode() in msg
+    assert plcg.plcg_solve_noalloc(None, None, 0, 0, 1e-8, 10, None, None) == plcg.PLCG_E_INVALID
