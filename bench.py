@@ -5,7 +5,10 @@ residual) of A x = b with b uniform[-1, 1) from seed 0, x0 = 0, stopped at
 relative residual 1e-8; b and x already live in GPU memory when the clock
 starts.  `value` is the iteration rate (x updates per second) of the headline
 method; the JSON line also carries every method's rate, the iteration kernel's
-duration against the HBM roofline, and the oracle's rate on the host CPU.
+duration against the HBM roofline (with its working set and whether that fits
+the 256 MiB memory-side cache), a block for the 256^3 3D problem at 1e-10
+(CG, p(1), p(3), FP32-refined p(3): working sets beyond that cache), and the
+oracle's rate on the host CPU.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--methods cg,1,2,3,4,5]
 """
@@ -46,14 +49,30 @@ def vector_passes(method: str, l: int, x_update_every: int = 1) -> float:
     return 3 * l + 5 + max(0, l - 3) + (1.5 if x_update_every == 2 else 2)
 
 
-def cpu_baseline(workload: str, l: int, iters: int) -> dict:
-    """Time the oracle on a bounded sample of the same workload (single thread)."""
-    code = f"""
-import sys, time, json
-sys.path.insert(0, {ROOT!r})
+_CPU_SCRIPT = """
+import json, os, resource, sys, time
+sys.path.insert(0, {root!r})
 import numpy as np
 import synth
 from oracle import operators, shifts, plcg
+from oracle import cg as ocg
+
+
+def cpu_s():
+    r = resource.getrusage(resource.RUSAGE_SELF)
+    return r.ru_utime + r.ru_stime
+
+
+def timed(fn, reps):
+    walls, cpus = [], []
+    for _ in range(reps):
+        c0, t0 = cpu_s(), time.perf_counter()
+        out = fn()
+        walls.append(time.perf_counter() - t0)
+        cpus.append(cpu_s() - c0)
+    return out, walls, cpus
+
+
 wl = synth.WORKLOADS[{workload!r}]
 if wl["kind"] == "diag":
     A = operators.diagonal(synth.spectrum_diagonal(wl["dims"]))
@@ -63,23 +82,75 @@ else:
     A = operators.laplacian(wl["dims"])
 b = synth.uniform(A.n, 0)
 x0 = np.zeros(A.n)
-sig = shifts.chebyshev_shifts({l}, *wl["interval"])
-plcg.plcg(A, b, x0, {l}, sig, 1e-30, 2)
-t0 = time.perf_counter()
-r = plcg.plcg(A, b, x0, {l}, sig, 1e-30, {iters})
-dt = time.perf_counter() - t0
-print(json.dumps(dict(iters=r.iters, seconds=dt)))
+l = {l}
+sig = shifts.chebyshev_shifts(l, *wl["interval"])
+plcg.plcg(A, b, x0, l, sig, 1e-30, 2)
+r, walls, cpus = timed(lambda: plcg.plcg(A, b, x0, l, sig, 1e-30, {iters}), {reps})
+# a whole solve of the 64 x 64 Poisson problem (b = A x*, x* uniform, seed 0), tol 1e-8
+A64 = operators.laplacian((64, 64))
+b64 = A64(synth.uniform(A64.n, 0))
+s64 = shifts.chebyshev_shifts(l, 0.0, 8.0)
+r64, w64, c64 = timed(lambda: plcg.plcg(A64, b64, np.zeros(A64.n), l, s64, 1e-8, 5000), {reps})
+print(json.dumps(dict(iters=r.iters, walls=walls, cpus=cpus, iters64=r64.iters, walls64=w64,
+                      cpus64=c64)))
 """
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr)
-    r = json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(workload: str, l: int, iters: int, reps: int = 5) -> dict:
+    """Time the oracle (numpy, FP64) on the host CPU: `reps` runs of its first
+    `iters` p(l)-CG iterations on `workload`, and `reps` whole solves of the
+    64 x 64 Poisson problem, once with one thread and once with every usable
+    host thread allowed (OMP / BLAS thread counts).  Best and median of the runs
+    (the paper's protocol takes the best of 5).  numpy runs the oracle's vector
+    updates and stencil on one core whatever the setting; only its BLAS dot
+    products can use more, so `cores` is the average number of cores the run
+    kept busy (CPU time / wall time), next to the threads allowed."""
+    import statistics
+    model, ncpu, usable = cpu_info()
+    runs = {}
+    for label, threads in (("one_thread", 1), ("all_threads", usable)):
+        t = str(threads)
+        env = dict(os.environ, OMP_NUM_THREADS=t, OPENBLAS_NUM_THREADS=t, MKL_NUM_THREADS=t)
+        code = _CPU_SCRIPT.format(root=ROOT, workload=workload, l=l, iters=iters, reps=reps)
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                             env=env, timeout=900)
+        if out.returncode != 0:
+            raise RuntimeError(out.stderr)
+        r = json.loads(out.stdout.strip().splitlines()[-1])
+        rates = [r["iters"] / w for w in r["walls"]]
+        runs[label] = {
+            "threads_allowed": threads,
+            "cores_busy": sum(r["cpus"]) / sum(r["walls"]),
+            "iters_per_s_best": max(rates), "iters_per_s_median": statistics.median(rates),
+            "solve64_s_best": min(r["walls64"]), "solve64_s_median": statistics.median(r["walls64"]),
+            "solve64_iters": r["iters64"],
+        }
+    best = max(runs.values(), key=lambda v: v["iters_per_s_best"])
     name = "CG" if l == 0 else f"p({l})-CG"
-    return {"value": r["iters"] / r["seconds"], "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r['iters']} iterations of {name} on {workload} "
-                      f"(numpy FP64 oracle, one thread), {r['seconds']:.1f} s"}
+    return {"value": best["iters_per_s_best"], "unit": "iters/s",
+            "cores": round(best["cores_busy"], 2), "kind": "oracle",
+            "sample": f"{reps} runs of the first {iters} iterations of {name} on {workload}, "
+                      f"best of {reps} (value) and median, with 1 and with {usable} threads "
+                      f"allowed; {reps} whole solves of the 64x64 Poisson problem (b = A x*, "
+                      f"tol 1e-8) likewise; numpy FP64 oracle",
+            "cpu_model": model, "nproc": ncpu, "usable_cpus": usable, "runs": runs}
 
 
 def kernel_source_hash() -> str:
@@ -102,8 +173,8 @@ def measured_traffic(workload: str, kernel: str):
     named without namespace, argument list or spaces, e.g.
     `plcg_sweep_kernel<1,false,double,0,true>`.  `kernel` may leave out the
     trailing template arguments (the streaming cache hints and the x update
-    pairing the library picked for the workload): the one kernel of that family
-    in the file is taken.  A different
+    pairing the library picked for the workload), or all of them (a name ending
+    in `<`): the one kernel of that family in the file is taken.  A different
     source hash means the kernel changed since: None.  Returns (name, bytes).
     """
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
@@ -119,7 +190,8 @@ def measured_traffic(workload: str, kernel: str):
         return None
     if kernel in vals:
         return kernel, float(vals[kernel])
-    family = [k for k in vals if k.startswith(kernel[:-1] + ",")]
+    prefix = kernel if kernel.endswith("<") else kernel[:-1] + ","
+    family = [k for k in vals if k.startswith(prefix)]
     return (family[0], float(vals[family[0]])) if len(family) == 1 else None
 
 
@@ -354,7 +426,14 @@ def main():
                     help="headline method: l of p(l)-CG, or m<l> for FP32-refined p(l)-CG")
     ap.add_argument("--inner-tol", type=float, default=1e-3,
                     help="inner tolerance of the FP32-refined methods (m<l>)")
-    ap.add_argument("--cpu-iters", type=int, default=250)
+    ap.add_argument("--cpu-iters", type=int, default=40,
+                    help="oracle iterations per CPU-baseline run (5 runs per thread setting)")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="poisson2048: leave out the 256^3 block")
+    ap.add_argument("--inner-tol-3d", type=float, default=1e-4,
+                    help="inner tolerance of the FP32-refined p(3)-CG in the 256^3 block")
+    ap.add_argument("--steps-3d", type=int, default=5,
+                    help="timed solves per method in the 256^3 block (at most --steps)")
     ap.add_argument("--launch", choices=("auto", "streaming", "resident"), default="auto",
                     help="single-system launch mode (resident: one workgroup, small systems)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -387,10 +466,8 @@ def main():
               "iteration, not implemented), so only --gpus 1 runs.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import synth
     from paper_1905_06850_amd import plcg
 
     if not torch.cuda.is_available():
@@ -406,16 +483,81 @@ def main():
     if args.workload == "serve":
         serve_bench(args, plcg, torch, dev, torch.cuda.current_stream(dev).cuda_stream)
         return
-    wl = synth.WORKLOADS[args.workload]
+    if args.profile_run:
+        ctx = setup_workload(plcg, torch, dev, args.workload)
+        profile_run(plcg, ctx["dims"], ctx["kind"], *ctx["interval"], ctx["b"], ctx["x"],
+                    ctx["sp"], args.methods, ctx["dptr"], ctx["csr_arg"])
+        return
+
+    methods = [parse_method(m) for m in args.methods.split(",")]
+    head_method = parse_method(args.headline)
+    if head_method not in methods:
+        methods.append(head_method)
+    ctx = setup_workload(plcg, torch, dev, args.workload)
+    rows = run_methods(args, plcg, torch, ctx, methods, args.steps, args.warmup)
+    kind, dims, n = ctx["kind"], ctx["dims"], ctx["n"]
+    lo, hi = ctx["interval"]
+    tol = ctx["tol"]
+    del ctx
+    torch.cuda.empty_cache()
+    opname = {"2d5": "2D 5-point Dirichlet Poisson", "3d7": "3D 7-point Dirichlet Poisson",
+              "diag": "diagonal one-point-stencil toy with the 2D Laplacian's spectrum on",
+              "csr": "2D 5-point Dirichlet Poisson assembled in CSR,"}[kind]
+    head = {"plcg": "p", "mixed": "m"}[head_method[0]] + str(head_method[1])
+    hl = head_method[1]
+    hr = rows[head]
+    line = {
+        "metric": METRIC,
+        "value": hr["iters_per_s"],
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hr["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head_method[0] != "mixed" else "f32-storage/f64-dots",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {opname} {'x'.join(str(d) for d in dims)} "
+                        f"({n} unknowns), b uniform[-1,1) seed 0, x0 = 0, stop at relative "
+                        f"residual {tol:g}; Chebyshev shifts on [{lo:g},{hi:g}]",
+            "method": (f"p({hl})-CG" if head_method[0] == "plcg"
+                       else f"FP32-stored p({hl})-CG in FP64 refinement"), "l": hl,
+            "iters_per_solve": hr["iters"], "true_relres": hr["true_relres"],
+            "alg_GBps": hr["alg_GBps"],
+            "cg_iters_per_s": rows["cg"]["iters_per_s"] if "cg" in rows else None,
+        },
+        "roofline": roofline(args.workload, kind, head_method, hr),
+        "methods": rows,
+    }
+    if args.workload == "poisson2048" and not args.no_3d:
+        line["poisson3d256"] = block_3d(args, plcg, torch, dev)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload, hl, args.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+def parse_method(tok):
+    if tok == "cg":
+        return ("cg", 0)
+    if tok.startswith("m"):
+        return ("mixed", int(tok[1:]))
+    return ("plcg", int(tok))
+
+
+def setup_workload(plcg, torch, dev, workload):
+    """Device inputs of a single-system workload: b (seed 0, or b = A x* for a
+    manufactured solution), x, and the operator data of the diagonal / CSR kinds."""
+    import synth
+    wl = synth.WORKLOADS[workload]
     dims = wl["dims"]
     kind = wl["kind"]
     n = synth.grid_size(dims)
-    lo, hi = wl["interval"]
-    tol = wl["tol"]
     b = torch.from_numpy(synth.uniform(n, 0)).to(dev)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream(dev)
-    sp = stream.cuda_stream
+    sp = torch.cuda.current_stream(dev).cuda_stream
     # the one-point-stencil toy: diagonal operator holding the Laplacian's spectrum
     dg = (torch.from_numpy(synth.spectrum_diagonal(dims)).to(dev) if kind == "diag" else None)
     dptr = dg.data_ptr() if dg is not None else None
@@ -436,23 +578,35 @@ def main():
         op.apply(xs.data_ptr(), b.data_ptr(), sp)
         torch.cuda.synchronize()
         op.close()
+    return dict(dims=dims, kind=kind, n=n, interval=wl["interval"], tol=wl["tol"], b=b, x=x,
+                sp=sp, dg=dg, dptr=dptr, csr_t=csr_t, csr_arg=csr_arg, op_bytes=op_bytes)
 
-    if args.profile_run:
-        profile_run(plcg, dims, kind, lo, hi, b, x, sp, args.methods, dptr, csr_arg)
-        return
 
-    def parse(tok):
-        if tok == "cg":
-            return ("cg", 0)
-        if tok.startswith("m"):
-            return ("mixed", int(tok[1:]))
-        return ("plcg", int(tok))
+CACHE_BYTES = 256 << 20     # MI355X memory-side (Infinity) cache
 
-    methods = [parse(m) for m in args.methods.split(",")]
-    head_method = parse(args.headline)
-    if head_method not in methods:
-        methods.append(head_method)
 
+def working_set(method, l, x_update_every, n, word, op_bytes):
+    """Bytes one iteration's sweeps touch: p(l)-CG: 2 vectors per basis k < l,
+    max(2, l-1) ring slots of z^(l), p (two buffers when x is updated every
+    second iteration) and x; CG: r, its two p buffers, A p and x; plus the
+    operator's data."""
+    if method == "cg":
+        vecs = 5
+    else:
+        vecs = 2 * l + max(2, l - 1) + (2 if x_update_every == 2 else 1) + 1
+    return vecs * n * word + op_bytes
+
+
+def run_methods(args, plcg, torch, ctx, methods, steps, warmup, tol=None, inner_tol=None):
+    """Each method: `warmup` untimed solves, `steps` timed solves (host clock
+    around them, device synchronised on both sides), then one solve with HIP
+    events around the iteration kernels for their average duration."""
+    dims, kind, n = ctx["dims"], ctx["kind"], ctx["n"]
+    lo, hi = ctx["interval"]
+    tol = ctx["tol"] if tol is None else tol
+    inner_tol = args.inner_tol if inner_tol is None else inner_tol
+    b, x, sp = ctx["b"], ctx["x"], ctx["sp"]
+    op_bytes = ctx["op_bytes"]
     rows = {}
     for method, l in methods:
         name = {"cg": "cg", "plcg": f"p{l}", "mixed": f"m{l}"}[method]
@@ -462,15 +616,16 @@ def main():
             launch = "auto"
         s = plcg.Solver(kind, dims, method="cg" if method == "cg" else "plcg", l=max(l, 1),
                         lmin=lo, lmax=hi, precision="fp32" if method == "mixed" else "fp64",
-                        inner_tol=args.inner_tol, diag=dptr, csr=csr_arg, launch=launch)
-        for _ in range(args.warmup):
+                        inner_tol=inner_tol, diag=ctx["dptr"], csr=ctx["csr_arg"],
+                        launch=launch)
+        for _ in range(warmup):
             x.zero_()
             s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
         torch.cuda.synchronize()
         total_iters = 0
         results = []
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             x.zero_()
             r = s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
             total_iters += r.iters
@@ -488,16 +643,18 @@ def main():
         r = results[-1]
         its = total_iters / dt
         passes = vector_passes("cg" if method == "cg" else "plcg", l, r.x_update_every)
+        word = 4 if method == "mixed" else 8
         # vector passes in the storage precision, plus the operator's own data
         # read once per SpMV (FP64 d, or the CSR arrays)
-        bytes_iter = passes * (4 if method == "mixed" else 8) * n + op_bytes
+        bytes_iter = passes * word * n + op_bytes
         kernel_us = 1e3 * rt.sweep_ms / max(rt.sweeps, 1)
         kernels_per_iter = 2 if method == "cg" else 1
         resident = r.launch_mode == plcg.PLCG_LAUNCH_RESIDENT
+        wset = working_set(method, l, r.x_update_every, n, word, op_bytes)
         rows[name] = {
             "iters": r.iters, "reason": plcg.REASONS[r.reason], "restarts": r.restarts,
             "true_relres": r.true_relres, "rec_relres": r.rec_relres,
-            "ms_per_solve": 1e3 * dt / args.steps, "iters_per_s": its,
+            "ms_per_solve": 1e3 * dt / steps, "iters_per_s": its,
             "bytes_per_iter": bytes_iter,
             "us_per_iter": 1e6 / its, "vector_passes": passes, "operator_bytes": op_bytes,
             "x_update_every": r.x_update_every,
@@ -505,78 +662,101 @@ def main():
             "kernel_us": kernel_us, "kernels_per_iter": kernels_per_iter,
             "kernel_GBps": (bytes_iter / kernels_per_iter) / (kernel_us * 1e-6) / 1e9
             if method != "cg" else None,
+            "working_set_bytes": wset, "cache_resident": wset <= CACHE_BYTES,
             "spmvs": r.spmvs,
-            "spmvs_per_s": r.spmvs * args.steps / dt,   # p(l)-CG adds l fill/drain SpMVs
+            "spmvs_per_s": r.spmvs * steps / dt,   # p(l)-CG adds l fill/drain SpMVs
             "outer": r.outer,
             "host_waits": r.host_waits,
             "launch": "resident" if resident else "streaming",
             # a resident solve is one launch per restart segment
             "launches_per_iter": ((1 + r.restarts) / max(r.iters, 1)) if resident
             else kernels_per_iter,
-            "solves_per_s": args.steps / dt,
+            "solves_per_s": steps / dt, "steps": steps, "warmup": warmup,
         }
         if not args.quiet:
             print(f"# {name}: {json.dumps(rows[name])}", file=sys.stderr, flush=True)
+    return rows
 
-    opname = {"2d5": "2D 5-point Dirichlet Poisson", "3d7": "3D 7-point Dirichlet Poisson",
-              "diag": "diagonal one-point-stencil toy with the 2D Laplacian's spectrum on",
-              "csr": "2D 5-point Dirichlet Poisson assembled in CSR,"}[kind]
-    if hr_launch(rows, head_method) == "resident":
+
+def roofline(workload, kind, head_method, hr):
+    """HBM roofline of the headline method's iteration kernel: algorithmic bytes
+    per launch over its average duration (HIP events), against 8 TB/s; traffic
+    from the committed counter summary when it was taken with these kernels;
+    and whether the kernel's working set fits the 256 MiB memory-side cache
+    (whose hits the achieved rate then includes)."""
+    d3 = 'true' if kind == '3d7' else 'false'
+    if head_method[0] == "cg" and hr["launch"] != "resident":
+        # two sweeps per iteration (A: 4 passes, B: 5 on average when paired):
+        # their mean duration against half the iteration's bytes
+        bytes_launch = hr["bytes_per_iter"] / 2
+        achieved = bytes_launch / (hr["kernel_us"] * 1e-6) / 1e9
+        ta = measured_traffic(workload, f"cg_sweep_a_kernel<{d3}>")
+        tb = measured_traffic(workload, "cg_sweep_b_kernel<")
+        return {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": (ta[1] + tb[1]) / 2 if ta and tb else None,
+            "traffic_sweep_a": ta[1] if ta else None,
+            "kernel": "mean of cg_sweep_a_kernel and cg_sweep_b_kernel",
+            "kernel_us": hr["kernel_us"], "bytes_per_launch": bytes_launch,
+            "working_set_bytes": hr["working_set_bytes"], "cache_resident": hr["cache_resident"],
+        }
+    if hr["launch"] == "resident":
         kname = f"plcg_resident_kernel<{head_method[1]},"
     elif kind == "diag":
         kname = f"plcg_diag_sweep_kernel<{head_method[1]},"
     elif kind == "csr":
         kname = f"plcg_csr_sweep_kernel<{head_method[1]},"
     else:
-        kname = (f"plcg_sweep_kernel<{head_method[1]},"
-                 f"{'true' if kind == '3d7' else 'false'},")
-    head = {"plcg": "p", "mixed": "m"}[head_method[0]] + str(head_method[1])
-    hl = head_method[1]
-    hr = rows[head]
-    ms_per_step = hr["ms_per_solve"]
+        kname = f"plcg_sweep_kernel<{head_method[1]},{d3},"
     word = 4 if head_method[0] == "mixed" else 8
     bytes_launch = hr["bytes_per_iter"]
     achieved = bytes_launch / (hr["kernel_us"] * 1e-6) / 1e9
-    traffic = measured_traffic(args.workload, kname + ("double>" if word == 8 else "float>"))
-    line = {
-        "metric": METRIC,
-        "value": hr["iters_per_s"],
-        "unit": "iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if word == 8 else "f32-storage/f64-dots",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload}: {opname} {'x'.join(str(d) for d in dims)} "
-                        f"({n} unknowns), b uniform[-1,1) seed 0, x0 = 0, stop at relative "
-                        f"residual {tol:g}; Chebyshev shifts on [{lo:g},{hi:g}]",
-            "method": (f"p({hl})-CG" if head_method[0] == "plcg"
-                       else f"FP32-stored p({hl})-CG in FP64 refinement"), "l": hl,
-            "iters_per_solve": hr["iters"], "true_relres": hr["true_relres"],
-            "alg_GBps": hr["alg_GBps"],
-            "cg_iters_per_s": rows["cg"]["iters_per_s"] if "cg" in rows else None,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic[1] if traffic else None,
-            "kernel": traffic[0] if traffic else kname + ("double>" if word == 8 else "float>"),
-            "kernel_us": hr["kernel_us"],
-            "bytes_per_launch": bytes_launch,
-        },
+    full = kname + ("double>" if word == 8 else "float>")
+    traffic = measured_traffic(workload, full)
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic[1] if traffic else None,
+        "kernel": traffic[0] if traffic else full,
+        "kernel_us": hr["kernel_us"],
+        "bytes_per_launch": bytes_launch,
+        "working_set_bytes": hr["working_set_bytes"],
+        "cache_resident": hr["cache_resident"],
+    }
+
+
+def block_3d(args, plcg, torch, dev):
+    """The 256^3 3D 7-point Poisson workload at relative residual 1e-10 (b
+    uniform, seed 0): CG, p(1)-CG and p(3)-CG in FP64 and FP32-stored p(3)-CG
+    in FP64 refinement, each solved to the same final accuracy; its working set
+    (1.3-1.6 GB in FP64) is far beyond the memory-side cache, so its roofline is
+    HBM-true.  Fewer steps than the headline (each solve takes 0.2-0.4 s)."""
+    ctx = setup_workload(plcg, torch, dev, "poisson3d256")
+    steps = max(1, min(args.steps, args.steps_3d))
+    rows = run_methods(args, plcg, torch, ctx, [("cg", 0), ("plcg", 1), ("plcg", 3),
+                                                 ("mixed", 3)], steps, 1,
+                       inner_tol=args.inner_tol_3d)
+    del ctx
+    torch.cuda.empty_cache()
+    p3 = rows["p3"]
+    return {
+        "workload": "poisson3d256: 3D 7-point Dirichlet Poisson 256x256x256 (16777216 "
+                    "unknowns), b uniform[-1,1) seed 0, x0 = 0, stop at relative residual "
+                    "1e-10; Chebyshev shifts on [0,12]",
+        "steps": steps, "warmup": 1,
+        "time_to_solution_ms": {k: v["ms_per_solve"] for k, v in rows.items()},
+        "true_relres": {k: v["true_relres"] for k, v in rows.items()},
+        "iters_per_s": {k: v["iters_per_s"] for k, v in rows.items()},
+        "mixed_inner_tol": args.inner_tol_3d,
+        "mixed_vs_fp64_p3": p3["ms_per_solve"] / rows["m3"]["ms_per_solve"],
+        "roofline": roofline("poisson3d256", "3d7", ("plcg", 3), p3),
+        "roofline_cg": roofline("poisson3d256", "3d7", ("cg", 0), rows["cg"]),
         "methods": rows,
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, hl, args.cpu_iters)
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

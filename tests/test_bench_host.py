@@ -40,3 +40,16 @@ def test_measured_traffic_lookup():
     # the counters agree with the algorithmic bytes to within 1 %
     assert abs(b / 318767104 - 1) < 0.01
     assert bench.measured_traffic("poisson2048", "no_such_kernel<1>") is None
+
+
+def test_working_set_and_cache_residency():
+    """The 2048^2 p(1)-CG sweep (paired x updates) touches 7 vectors of 32 MiB:
+    2 of basis 0, 2 ring slots, 2 p buffers and x = 224 MiB, inside the 256 MiB
+    memory-side cache; 256^3 p(3)-CG touches 11 vectors of 128 MiB."""
+    n2 = 2048 * 2048
+    assert bench.working_set("plcg", 1, 2, n2, 8, 0) == 7 * 8 * n2 <= bench.CACHE_BYTES
+    assert bench.working_set("plcg", 1, 1, n2, 8, 0) == 6 * 8 * n2
+    assert bench.working_set("cg", 0, 2, n2, 8, 0) == 5 * 8 * n2
+    n3 = 256 ** 3
+    assert bench.working_set("plcg", 3, 2, n3, 8, 0) == 11 * 8 * n3 > bench.CACHE_BYTES
+    assert bench.working_set("plcg", 5, 1, n3, 4, 0) == (10 + 4 + 1 + 1) * 4 * n3
