@@ -157,7 +157,8 @@ def kernel_source_hash() -> str:
     """Hash of the sources of the iteration kernels (device code of the single-system path)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("plcg_kernels.hip", "plcg_device.h", "plcg_internal.h"):
+    for name in ("plcg_kernels.hip", "plcg_var_kernels.hip", "plcg_sweep.h", "plcg_device.h",
+                 "plcg_internal.h"):
         with open(os.path.join(ROOT, "paper_1905_06850_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -132,16 +132,35 @@ typedef struct {
                              give PLCG_E_INVALID); symmetry and definiteness are not
                              checked: a matrix that is not SPD shows up as breakdowns
                              (restart limit) or, for CG, PLCG_REASON_BREAKDOWN. */
-  int32_t jacobi;         /* PLCG_OP_CSR only (else must be 0): 1 = Jacobi-preconditioned
-                             solve, which is Alg. 1 with M = diag(A) (Sec. 2.2) in its
-                             symmetrically scaled form: the library stores
-                             D^{-1/2} A D^{-1/2} (d_p = a_pp > 0, else PLCG_E_INVALID),
-                             solves for y = D^{1/2} x from D^{-1/2} b (x is transformed in
-                             place on entry and back on exit), stops on the scaled residual
-                             |zeta_t| < tol ||D^{-1/2}(b - A x0)|| and reports rec_relres in
-                             that norm, rnorm0 and true_relres in the original one.  The
-                             Chebyshev interval refers to the scaled matrix ([0, 2] holds its
-                             spectrum when A is a weakly diagonally dominant M-matrix). */
+  int32_t jacobi;         /* PLCG_OP_CSR, or a stencil kind with edge coefficients (else
+                             must be 0): 1 = Jacobi-preconditioned solve, which is Alg. 1
+                             with M = diag(A) (Sec. 2.2) in its symmetrically scaled form:
+                             the library stores D^{-1/2} A D^{-1/2} (d_p = a_pp > 0, else
+                             PLCG_E_INVALID), solves for y = D^{1/2} x from D^{-1/2} b (x is
+                             transformed in place on entry and back on exit), stops on the
+                             scaled residual |zeta_t| < tol ||D^{-1/2}(b - A x0)|| and
+                             reports rec_relres in that norm, rnorm0 and true_relres in the
+                             original one.  The Chebyshev interval refers to the scaled
+                             matrix ([0, 2] holds its spectrum when A is a weakly diagonally
+                             dominant M-matrix, e.g. every variable-coefficient stencil). */
+  const double *cx;       /* PLCG_OP_STENCIL2D5 / 3D7 only: NULL for the constant integer
+                             stencil; else device arrays of edge coefficients c > 0 of the
+                             variable-coefficient operator (A u)_p = sum over the grid edges
+                             (p, q) incident to p of c_pq (u_p - u_q), u = 0 outside (edges
+                             to the boundary included, so A is an SPD M-matrix; the paper's
+                             Sec. 4 problems are of this operator class).  cx: per row
+                             (y, z) nx+1 values, the first and last being boundary edges,
+                             x fastest; */
+  const double *cy;       /* per plane z: ny+1 rows of nx values (edge below row y at row
+                             y); required with cx; */
+  const double *cz;       /* 3D: nz+1 planes of nx*ny values (edge below plane z at plane
+                             z); required with cx in 3D, ignored in 2D.  Checked (finite,
+                             > 0; else PLCG_E_INVALID) and copied at plcg_create; the
+                             caller keeps ownership.  Each SpMV then reads 2 (2D) or 3 (3D)
+                             arrays of edge weights, plus the diagonal when jacobi = 0.
+                             The resident launch mode is not offered for these operators,
+                             and plcg_apply applies the operator the solver iterates with
+                             (the scaled one when jacobi = 1). */
 } plcg_operator_desc;
 
 typedef struct {
@@ -268,8 +287,9 @@ int32_t plcg_version(void);
  * taken from a static device array of PLCG_NOALLOC_BYTES that each GPU holds
  * from the library's first use of it until the process ends.  It calls no
  * hipMalloc, hipFree or other allocating routine.
- *  - op: PLCG_OP_STENCIL2D5 or PLCG_OP_STENCIL3D7 only (the other kinds need
- *    library copies of their data); cfg as for plcg_create, history_cap = 0.
+ *  - op: PLCG_OP_STENCIL2D5 or PLCG_OP_STENCIL3D7 with constant coefficients
+ *    only (cx, cy, cz NULL, jacobi 0: the other operators need library copies
+ *    of their data); cfg as for plcg_create, history_cap = 0.
  *    d_b, d_x, tol, maxit, stream and *out as for plcg_solve; the result and x
  *    are bit for bit those of plcg_solve with the same op and cfg.  Timing is
  *    not available (sweep_ms = 0).

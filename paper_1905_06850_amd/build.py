@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libplcg.so")
 SOURCES = [os.path.join(HERE, "csrc", "plcg_kernels.hip"),
+           os.path.join(HERE, "csrc", "plcg_var_kernels.hip"),
            os.path.join(HERE, "csrc", "plcg_resident.hip"),
            os.path.join(HERE, "csrc", "plcg_batch_kernels.hip"),
            os.path.join(HERE, "csrc", "plcg_noalloc.hip"),

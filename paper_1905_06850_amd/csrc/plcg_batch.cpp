@@ -160,6 +160,76 @@ int32_t layout(const plcg_batch *b, const plcg_system_desc *sys, Layout *L) {
   return PLCG_OK;
 }
 
+}  // namespace
+
+// Host: the edge weights VarOp reads, from coefficient arrays in host memory
+// (NULL: all 1; layouts as plcg_system_desc).  jacobi: w_pq = c_pq d_p^{-1/2}
+// d_q^{-1/2} and dd = D^{-1/2}; else w_pq = c_pq and dd = d; d_p is the sum of
+// the edges at p, boundary edges included.  Boundary edges get weight 0
+// (VarOp never reads them).  wx, wy, wz, dd hold (nx+1) ny nz, nx (ny+1) nz,
+// nx ny (nz+1) (3D) and nx ny nz values.
+int32_t plcg::edge_weights(int nx, int ny, int nz, bool d3, const double *cx, const double *cy,
+                           const double *cz, bool jacobi, double *wx, double *wy, double *wz,
+                           double *dd) {
+  const size_t nsx = (size_t)(nx + 1) * ny * nz, nsy = (size_t)nx * (ny + 1) * nz;
+  const size_t nsz = d3 ? (size_t)nx * ny * (nz + 1) : 0;
+  for (size_t k = 0; k < nsx; ++k) wx[k] = cx ? cx[k] : 1.0;
+  for (size_t k = 0; k < nsy; ++k) wy[k] = cy ? cy[k] : 1.0;
+  for (size_t k = 0; k < nsz; ++k) wz[k] = cz ? cz[k] : 1.0;
+  for (size_t k = 0; k < nsx; ++k)
+    if (!(std::isfinite(wx[k]) && wx[k] > 0.0))
+      return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
+  for (size_t k = 0; k < nsy; ++k)
+    if (!(std::isfinite(wy[k]) && wy[k] > 0.0))
+      return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
+  for (size_t k = 0; k < nsz; ++k)
+    if (!(std::isfinite(wz[k]) && wz[k] > 0.0))
+      return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
+  double *cxv = wx, *cyv = wy, *czv = wz;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+        const int64_t row = y + (int64_t)ny * z;
+        double d = cxv[row * (nx + 1) + x] + cxv[row * (nx + 1) + x + 1] +
+                   cyv[((int64_t)z * (ny + 1) + y) * nx + x] +
+                   cyv[((int64_t)z * (ny + 1) + y + 1) * nx + x];
+        if (d3) d += czv[p] + czv[p + (int64_t)nx * ny];
+        if (!(d > 0.0) || !std::isfinite(d))
+          return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
+        dd[p] = jacobi ? 1.0 / std::sqrt(d) : d;
+      }
+  // scaling factor of unknown p: D^{-1/2} (jacobi) or 1
+  auto f = [&](int64_t p) { return jacobi ? dd[p] : 1.0; };
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x <= nx; ++x) {
+        const int64_t row = y + (int64_t)ny * z;
+        const int64_t p = x + (int64_t)nx * row;
+        double &c = cxv[row * (nx + 1) + x];
+        c = (x > 0 && x < nx) ? (jacobi ? c * f(p - 1) * f(p) : c) : 0.0;
+      }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y <= ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        double &c = cyv[((int64_t)z * (ny + 1) + y) * nx + x];
+        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+        c = (y > 0 && y < ny) ? (jacobi ? c * f(p - nx) * f(p) : c) : 0.0;
+      }
+  if (d3)
+    for (int z = 0; z <= nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          double &c = czv[((int64_t)z * ny + y) * nx + x];
+          const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
+          const int64_t plane = (int64_t)nx * ny;
+          c = (z > 0 && z < nz) ? (jacobi ? c * f(p - plane) * f(p) : c) : 0.0;
+        }
+  return PLCG_OK;
+}
+
+namespace {
+
 // Scale the edge coefficients of `sys` (Jacobi: s_pq = c_pq / sqrt(d_p d_q), d_p = sum
 // of the edges at p) and copy sx, sy, sz, D^{-1/2} to `dst` (device, L.op_bytes).
 int32_t upload_operator(const plcg_system_desc *sys, const Layout &L, char *dst, hipStream_t st,
@@ -168,48 +238,11 @@ int32_t upload_operator(const plcg_system_desc *sys, const Layout &L, char *dst,
   const bool d3 = sys->kind == PLCG_OP_STENCIL3D7;
   const int nx = sys->nx, ny = sys->ny, nz = d3 ? sys->nz : 1;
   const int64_t n = L.n;
-  std::vector<double> cx(L.nsx, 1.0), cy(L.nsy, 1.0), cz(L.nsz, 1.0);
-  if (sys->cx) std::memcpy(cx.data(), sys->cx, L.nsx * 8);
-  if (sys->cy) std::memcpy(cy.data(), sys->cy, L.nsy * 8);
-  if (d3 && sys->cz) std::memcpy(cz.data(), sys->cz, L.nsz * 8);
+  std::vector<double> cx(L.nsx), cy(L.nsy), cz(L.nsz);
   std::vector<double> dis(n);
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y < ny; ++y)
-      for (int x = 0; x < nx; ++x) {
-        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
-        const int64_t row = y + (int64_t)ny * z;
-        double d = cx[row * (nx + 1) + x] + cx[row * (nx + 1) + x + 1] +
-                   cy[((int64_t)z * (ny + 1) + y) * nx + x] +
-                   cy[((int64_t)z * (ny + 1) + y + 1) * nx + x];
-        if (d3) d += cz[p] + cz[p + (int64_t)nx * ny];
-        if (!(d > 0.0) || !std::isfinite(d))
-          return set_last_error(PLCG_E_INVALID, "edge coefficients must be positive and finite");
-        dis[p] = 1.0 / std::sqrt(d);
-      }
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y < ny; ++y)
-      for (int x = 0; x <= nx; ++x) {
-        const int64_t row = y + (int64_t)ny * z;
-        const int64_t p = x + (int64_t)nx * row;
-        double &c = cx[row * (nx + 1) + x];
-        c = (x > 0 && x < nx) ? c * dis[p - 1] * dis[p] : 0.0;
-      }
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y <= ny; ++y)
-      for (int x = 0; x < nx; ++x) {
-        double &c = cy[((int64_t)z * (ny + 1) + y) * nx + x];
-        const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
-        c = (y > 0 && y < ny) ? c * dis[p - nx] * dis[p] : 0.0;
-      }
-  if (d3)
-    for (int z = 0; z <= nz; ++z)
-      for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) {
-          double &c = cz[((int64_t)z * ny + y) * nx + x];
-          const int64_t p = x + (int64_t)nx * (y + (int64_t)ny * z);
-          const int64_t plane = (int64_t)nx * ny;
-          c = (z > 0 && z < nz) ? c * dis[p - plane] * dis[p] : 0.0;
-        }
+  const int32_t e = edge_weights(nx, ny, nz, d3, sys->cx, sys->cy, d3 ? sys->cz : nullptr, true,
+                                 cx.data(), cy.data(), cz.data(), dis.data());
+  if (e != PLCG_OK) return e;
   char *q = dst;
   double *sx = reinterpret_cast<double *>(q);
   q += round_up(L.nsx * 8, kAlign);

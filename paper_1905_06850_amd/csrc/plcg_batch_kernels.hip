@@ -25,101 +25,6 @@
 
 namespace plcg {
 
-// A~ at unknown p: u_p - sum of scaled edge weight * neighbour (u stored as T,
-// weights and arithmetic FP64).
-struct VarOp {
-  const double *sx, *sy, *sz;
-  int n, nx, ny, nz, d3;
-  template <typename T>
-  __device__ inline double at(const T *u, int p) const {
-    const int x = p % nx;
-    const int rest = p / nx;
-    const int y = d3 ? rest % ny : rest;
-    double s = 0.0;
-    const int xe = rest * (nx + 1) + x;          // edge left of p in its row
-    if (x > 0) s += sx[xe] * (double)u[p - 1];
-    if (x < nx - 1) s += sx[xe + 1] * (double)u[p + 1];
-    const int z = d3 ? rest / ny : 0;
-    const int ye = p + z * nx;                   // edge below p in its column
-    if (y > 0) s += sy[ye] * (double)u[p - nx];
-    if (y < ny - 1) s += sy[ye + nx] * (double)u[p + nx];
-    if (d3) {
-      const int plane = nx * ny;
-      if (z > 0) s += sz[p] * (double)u[p - plane];
-      if (z < nz - 1) s += sz[p + plane] * (double)u[p + plane];
-    }
-    return (double)u[p] - s;
-  }
-  // FAST (a full chunk, nx a multiple of V): the thread's V unknowns share a
-  // row; x-neighbours come from its own values and the adjacent lanes, the rows
-  // and planes above and below and the y/z edge weights with 16-byte accesses.
-  // Each unknown's terms are added in the order of at().
-  template <int V, bool FAST, typename S>
-  __device__ inline void apply(const S *z, int idx, const Vals<V, S> &zc,
-                               double (&w)[V]) const {
-    if constexpr (FAST && V >= 2) {
-      const int x = idx % nx;
-      const int rest = idx / nx;
-      const int y = d3 ? rest % ny : rest;
-      const int zz = d3 ? rest / ny : 0;
-      const int plane = nx * ny;
-      const int lane = threadIdx.x & 63;
-      double left = lane_prev(zc.v[V - 1]);    // z[idx-1] held by the previous lane
-      double right = lane_next(zc.v[0]);       // z[idx+V] held by the next lane
-      if (lane == 0 && x > 0) left = (double)z[idx - 1];
-      if (lane == 63 && x + V < nx) right = (double)z[idx + V];
-      const int xe = rest * (nx + 1) + x;             // edge left of idx in its row
-      const int ye = idx + zz * nx;                   // edge below idx in its column
-      // one neighbour direction at a time (few values live at once); each
-      // unknown's sum still takes its terms in the order of at()
-      double s[V];
-#pragma unroll
-      for (int k = 0; k < V; ++k) {
-        s[k] = 0.0;
-        if (x + k > 0) s[k] += sx[xe + k] * (k > 0 ? zc.v[k - 1] : left);
-        if (x + k < nx - 1) s[k] += sx[xe + k + 1] * (k < V - 1 ? zc.v[k + 1] : right);
-      }
-      if (y > 0) {
-        Vals<V, S> u;
-        Vals<V, double> c;
-        u.load(z + idx - nx);
-        c.load(sy + ye);
-#pragma unroll
-        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
-      }
-      if (y < ny - 1) {
-        Vals<V, S> u;
-        Vals<V, double> c;
-        u.load(z + idx + nx);
-        c.load(sy + ye + nx);
-#pragma unroll
-        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
-      }
-      if (d3 && zz > 0) {
-        Vals<V, S> u;
-        Vals<V, double> c;
-        u.load(z + idx - plane);
-        c.load(sz + idx);
-#pragma unroll
-        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
-      }
-      if (d3 && zz < nz - 1) {
-        Vals<V, S> u;
-        Vals<V, double> c;
-        u.load(z + idx + plane);
-        c.load(sz + idx + plane);
-#pragma unroll
-        for (int k = 0; k < V; ++k) s[k] += c.v[k] * u.v[k];
-      }
-#pragma unroll
-      for (int k = 0; k < V; ++k) w[k] = zc.v[k] - s[k];
-    } else {
-#pragma unroll
-      for (int v = 0; v < V; ++v) w[v] = at(z, idx + v);
-    }
-  }
-};
-
 __device__ inline void bstate_load(const BatchState *st, BatchState *sh) {
   const double *src = reinterpret_cast<const double *>(st);
   double *dst = reinterpret_cast<double *>(sh);
@@ -166,7 +71,7 @@ __device__ inline void slot_sweep_args(const SlotDesc &S, int i, SweepArgsT<T> &
     a.x = S.x;
   else
     a.x = svec<T>(S, 2 * L + R + 1);
-  a.od = OpData{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  a.od = OpData{nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr};
   a.i = i;
   a.l = L;
   a.n = S.n;
@@ -342,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
   }
   const int phase = in->phase;
   if (phase == kEmpty || phase == kDone || phase == kStart || phase == kReport) return;
-  const VarOp op{S.sx, S.sy, S.sz, S.n, S.nx, S.ny, S.nz, S.d3};
+  const VarOp op{S.sx, S.sy, S.sz, S.n, S.nx, S.ny, S.nz, S.d3, nullptr};
   double acc[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) acc[m] = 0.0;

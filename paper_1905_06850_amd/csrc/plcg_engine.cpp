@@ -119,8 +119,9 @@ struct plcg_handle {
   int hint64 = 0, hint32 = 0;     // streaming cache hints of the FP64 / FP32-stored sweeps
   bool pair64 = false, pair32 = false;   // the same sweeps update x on even t only
   bool ran_resident = false;      // the current solve ran resident launches
-  OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0};   // library copies of d / the CSR arrays
-  bool jacobi = false;            // CSR solved in Jacobi-scaled form D^{-1/2} A D^{-1/2}
+  OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr};   // library copies of the operator data
+  bool var = false;               // variable-coefficient stencil (edge weights in od.sx/sy/sz)
+  bool jacobi = false;            // CSR / variable stencil solved in Jacobi-scaled form D^{-1/2} A D^{-1/2}
   double *dis = nullptr;          // D^{-1/2} (jacobi)
   double *bs = nullptr;           // D^{-1/2} b of the current solve (jacobi)
   int device = 0;
@@ -918,8 +919,17 @@ plcg_status setup_handle(const plcg_operator_desc *op, const plcg_config *cfg, p
   if (op->kind == PLCG_OP_CSR &&
       (op->rowptr == nullptr || op->colind == nullptr || op->vals == nullptr || op->nnz < 0))
     return fail(PLCG_E_INVALID, "CSR operator needs rowptr, colind, vals and nnz >= 0");
-  if (op->jacobi != 0 && op->kind != PLCG_OP_CSR)
-    return fail(PLCG_E_INVALID, "Jacobi scaling is offered for CSR operators");
+  const bool stencil = op->kind == PLCG_OP_STENCIL2D5 || op->kind == PLCG_OP_STENCIL3D7;
+  const bool var = stencil && op->cx != nullptr;
+  if (!stencil && (op->cx != nullptr || op->cy != nullptr || op->cz != nullptr))
+    return fail(PLCG_E_INVALID, "edge coefficients are for the stencil operator kinds");
+  if (stencil && op->cx == nullptr && (op->cy != nullptr || op->cz != nullptr))
+    return fail(PLCG_E_INVALID, "edge coefficients need cx");
+  if (var && (op->cy == nullptr || (op->kind == PLCG_OP_STENCIL3D7 && op->cz == nullptr)))
+    return fail(PLCG_E_INVALID, "a variable-coefficient stencil needs cx, cy (and cz in 3D)");
+  if (op->jacobi != 0 && op->kind != PLCG_OP_CSR && !var)
+    return fail(PLCG_E_INVALID,
+                "Jacobi scaling is offered for CSR operators and variable-coefficient stencils");
   const int nz = op->kind == PLCG_OP_STENCIL2D5 ? 1 : op->nz;
   if (op->nx < 1 || op->ny < 1 || nz < 1) return fail(PLCG_E_INVALID, "grid extents must be >= 1");
   if (op->kind == PLCG_OP_STENCIL2D5 && op->nz > 1)
@@ -945,15 +955,17 @@ plcg_status setup_handle(const plcg_operator_desc *op, const plcg_config *cfg, p
     return fail(PLCG_E_INVALID, "unknown launch_mode");
   if (cfg->x_update < PLCG_X_AUTO || cfg->x_update > PLCG_X_PAIRED)
     return fail(PLCG_E_INVALID, "unknown x_update");
-  *res_ok = cfg->precision == PLCG_PREC_FP64 &&
+  *res_ok = cfg->precision == PLCG_PREC_FP64 && !var &&
             plcg_resident_supported(op->kind, n, cfg->method, cfg->l) == 1;
   if (cfg->launch_mode == PLCG_LAUNCH_RESIDENT && !*res_ok)
     return fail(PLCG_E_INVALID,
-                "PLCG_LAUNCH_RESIDENT needs FP64, n <= PLCG_RESIDENT_MAX and a supported l");
+                "PLCG_LAUNCH_RESIDENT needs FP64, a constant-coefficient operator, "
+                "n <= PLCG_RESIDENT_MAX and a supported l");
 
   h->op = *op;
   h->op.nz = nz;
-  h->jacobi = op->kind == PLCG_OP_CSR && op->jacobi != 0;
+  h->var = var;
+  h->jacobi = (op->kind == PLCG_OP_CSR || var) && op->jacobi != 0;
   h->d3 = op->kind == PLCG_OP_STENCIL3D7;
   h->method = cfg->method;
   h->l = pl ? cfg->l : 1;
@@ -1054,6 +1066,56 @@ void carve_workspace(plcg_handle *h, const Workspace &w, char *base, bool status
   if (status_record) h->hs_dev = reinterpret_cast<HostStatus *>(base + w.hs_at);
 }
 
+// Bytes of operator data a variable-coefficient SpMV reads: the edge weights
+// of every direction, and the diagonal of the unscaled form.
+long long var_op_bytes(const plcg_handle *h) {
+  const long long nx = h->op.nx, ny = h->op.ny, nz = h->op.nz;
+  long long e = (nx + 1) * ny * nz + nx * (ny + 1) * nz + (h->d3 ? nx * ny * (nz + 1) : 0);
+  return 8 * (e + (h->jacobi ? 0 : (long long)h->n));
+}
+
+// Library copy of a variable-coefficient stencil: the caller's edge coefficients
+// (device arrays) checked on the host, turned into the edge weights the kernels
+// read (scaled by D^{-1/2} on both sides for a Jacobi solve) and uploaded with
+// D^{-1/2} (jacobi) or the diagonal d.
+plcg_status copy_var(plcg_handle *h, const plcg_operator_desc *op) {
+  const int nx = h->op.nx, ny = h->op.ny, nz = h->op.nz;
+  const bool d3 = h->d3;
+  const size_t n = (size_t)h->n;
+  const size_t nsx = (size_t)(nx + 1) * ny * nz, nsy = (size_t)nx * (ny + 1) * nz;
+  const size_t nsz = d3 ? (size_t)nx * ny * (nz + 1) : 0;
+  std::vector<double> cx(nsx), cy(nsy), cz(nsz);
+  hipError_t he;
+  if ((he = hipMemcpy(cx.data(), op->cx, 8 * nsx, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (he = hipMemcpy(cy.data(), op->cy, 8 * nsy, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (d3 && (he = hipMemcpy(cz.data(), op->cz, 8 * nsz, hipMemcpyDeviceToHost)) != hipSuccess))
+    return fail(PLCG_E_HIP, std::string("hipMemcpy(edge coefficients): ") + hipGetErrorString(he));
+  std::vector<double> wx(nsx), wy(nsy), wz(nsz), dd(n);
+  plcg_status e = edge_weights(nx, ny, nz, d3, cx.data(), cy.data(), d3 ? cz.data() : nullptr,
+                               h->jacobi, wx.data(), wy.data(), wz.data(), dd.data());
+  if (e != PLCG_OK) return e;
+  double *dsx = nullptr, *dsy = nullptr, *dsz = nullptr, *ddd = nullptr;
+  e = dev_alloc(h, reinterpret_cast<void **>(&dsx), 8 * nsx);
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&dsy), 8 * nsy);
+  if (e == PLCG_OK && d3) e = dev_alloc(h, reinterpret_cast<void **>(&dsz), 8 * nsz);
+  if (e == PLCG_OK) e = dev_alloc(h, reinterpret_cast<void **>(&ddd), 8 * n);
+  if (e == PLCG_OK && h->jacobi) e = dev_alloc(h, reinterpret_cast<void **>(&h->bs), 8 * n);
+  if (e != PLCG_OK) return e;
+  if ((he = hipMemcpy(dsx, wx.data(), 8 * nsx, hipMemcpyHostToDevice)) != hipSuccess ||
+      (he = hipMemcpy(dsy, wy.data(), 8 * nsy, hipMemcpyHostToDevice)) != hipSuccess ||
+      (d3 && (he = hipMemcpy(dsz, wz.data(), 8 * nsz, hipMemcpyHostToDevice)) != hipSuccess) ||
+      (he = hipMemcpy(ddd, dd.data(), 8 * n, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(PLCG_E_HIP, std::string("hipMemcpy(edge weights): ") + hipGetErrorString(he));
+  h->od.sx = dsx;
+  h->od.sy = dsy;
+  h->od.sz = dsz;
+  if (h->jacobi)
+    h->dis = ddd;
+  else
+    h->od.vd = ddd;
+  return PLCG_OK;
+}
+
 // Streaming cache hints, x-update cadence and launch mode, once the operator
 // data is in place.
 plcg_status finish_setup(plcg_handle *h, const plcg_operator_desc *op, const plcg_config *cfg,
@@ -1062,6 +1124,7 @@ plcg_status finish_setup(plcg_handle *h, const plcg_operator_desc *op, const plc
   const bool pl = h->method == PLCG_METHOD_PLCG;
   const long long op_bytes = op->kind == PLCG_OP_CSR  ? 12LL * op->nnz
                              : op->kind == PLCG_OP_DIAG ? 8LL * n
+                             : h->var                   ? var_op_bytes(h)
                                                         : 0;
   h->hint64 = pick_hint(n, h->method, h->l, h->R, 8, op_bytes);
   h->hint32 = pick_hint(n, h->method, h->l, h->R, 4, op_bytes);
@@ -1154,6 +1217,7 @@ plcg_status plcg_create(const plcg_operator_desc *op, const plcg_config *cfg, pl
     h->od.dg = dg;
   }
   if (e == PLCG_OK && op->kind == PLCG_OP_CSR) e = copy_csr(h, op);
+  if (e == PLCG_OK && h->var) e = copy_var(h, op);
   if (e == PLCG_OK) e = finish_setup(h, op, cfg, res_ok);
   if (e != PLCG_OK) {
     release(h);
@@ -1309,9 +1373,11 @@ namespace {
 plcg_status check_workspace_solve(const plcg_operator_desc *op, const plcg_config *cfg,
                                   size_t ws_bytes, plcg_handle *h, bool *res_ok, Workspace *w) {
   if (op == nullptr || cfg == nullptr) return fail(PLCG_E_INVALID, "NULL descriptor or config");
-  if (op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7)
+  if ((op->kind != PLCG_OP_STENCIL2D5 && op->kind != PLCG_OP_STENCIL3D7) || op->cx != nullptr ||
+      op->cy != nullptr || op->cz != nullptr || op->jacobi != 0)
     return fail(PLCG_E_INVALID,
-                "the allocation-free solve takes the 2D and 3D stencil operators only");
+                "the allocation-free solve takes the constant-coefficient 2D and 3D stencils "
+                "only");
   if (cfg->history_cap != 0)
     return fail(PLCG_E_INVALID, "the allocation-free solve keeps no history (history_cap = 0)");
   plcg_status e = setup_handle(op, cfg, h, res_ok);

@@ -39,6 +39,11 @@ struct OpData {
                        // row p at j * ell_ld + p (CSR order within the row; padding is
                        // column p with value 0), j < ell_k
   int32_t ell_ld;      // ELL leading dimension: n rounded up to a multiple of 4
+  // Variable-coefficient stencil (sx != NULL): edge weights of the grid
+  // operator as VarOp reads them, and its diagonal vd (NULL: the unit diagonal
+  // of the Jacobi-scaled form).
+  const double *sx, *sy, *sz;
+  const double *vd;
 };
 
 // Host-visible progress record, written by the block that owns the scalar
@@ -197,6 +202,16 @@ hipError_t launch_x_step(S *x, const S *p, double zeta, int n, hipStream_t s);
 hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
                         const OpData &od, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);
+// The same for the variable-coefficient stencil (od.sx != NULL; plcg_var_kernels.hip);
+// the launchers above hand such operators over to these.
+hipError_t launch_var_sweep(const SweepArgsT<double> &a, hipStream_t s);
+hipError_t launch_var_sweep(const SweepArgsT<float> &a, hipStream_t s);
+hipError_t launch_var_cg_sweep_a(const CgArgs &a, hipStream_t s);
+hipError_t launch_var_residual(const double *b, const double *x, double *r, double *part_out,
+                               int n, int nx, int ny, int nz, bool d3, const OpData &od,
+                               const double *wdiv, int nchunks, int nstream, hipStream_t s);
+hipError_t launch_var_apply(const double *x, double *y, int n, int nx, int ny, int nz, bool d3,
+                            const OpData &od, hipStream_t s);
 
 }  // namespace plcg
 
@@ -278,6 +293,13 @@ hipError_t launch_batch_tick(const BatchArgs &a, int blocks, hipStream_t s);
 
 // Records msg as the calling thread's last error (plcg_last_error) and returns code.
 int32_t set_last_error(int32_t code, const char *msg);
+
+// Host: edge weights and diagonal of the variable-coefficient grid operator
+// (VarOp) from host coefficient arrays (NULL: all 1), Jacobi-scaled or not;
+// PLCG_E_INVALID unless every coefficient is finite and > 0 (plcg_batch.cpp).
+int32_t edge_weights(int nx, int ny, int nz, bool d3, const double *cx, const double *cy,
+                     const double *cz, bool jacobi, double *wx, double *wy, double *wz,
+                     double *dd);
 
 // A whole solve (as plcg_create + plcg_solve) in ws_bytes of device memory at
 // ws, with no device or pinned host allocation; 2D and 3D stencil operators.

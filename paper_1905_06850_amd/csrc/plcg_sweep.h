@@ -1,0 +1,108 @@
+// Kernel bodies shared by the translation units of the single-system path:
+// the p(l)-CG sweep over any operator and the prologue of CG's sweep A.
+#pragma once
+
+#include "plcg_device.h"
+
+namespace plcg {
+
+// Body of the p(l)-CG sweep for every operator.  Each thread takes V =
+// 16 / sizeof(ST) consecutive unknowns of a chunk (one 16-byte access per
+// vector: 2 doubles, or 4 floats for the FP32-stored inner solver).
+// fast_rows: full chunks may take the operator's FAST form; order: the chunk
+// visiting order.
+template <int L, typename ST, int H, bool P, typename Op>
+__device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fast_rows,
+                                  const ChunkOrder &order) {
+  constexpr int V = vec_of<ST>();
+  constexpr int CH = kThreads * V;
+  using S = Sweep<L, ST, Op, H, P>;
+  constexpr int ND = S::ND;
+  __shared__ double lds[4 * ND];
+  __shared__ double red[ND];
+  __shared__ DevState sh;
+
+  // Workgroup 0 owns the scalar state and carries it from launch i-1 to launch
+  // i.  For l = 1 every workgroup finalises column i itself (this launch needs
+  // it); for l >= 2 only workgroup 0 does, and it streams nothing.
+  const bool owner = blockIdx.x == 0;
+  const bool engine = (L == 1) || owner;
+  if (engine) {
+    state_load(a.st_in, &sh);
+    if (a.i >= 1 && sh.status == kRunning && a.nparts_in > 0) {
+      sum_partials<ND>(a.part_in, a.nparts_in, a.pstride, lds, red);
+      if (threadIdx.x == 0) engine_column_l<L>(sh, red, a.i, owner ? a.hist : nullptr);
+      __syncthreads();
+    }
+    if (owner) {
+      state_store(&sh, a.st_out);
+      if (threadIdx.x == 0) publish(sh, a.hs, fabs(sh.zeta[(a.i + kTRing - 1) % kTRing]), a.i);
+    }
+    if (L >= 2) return;
+  }
+  if (!a.work) return;
+
+  const int i = a.i;
+  const int t = i - L;
+  int status, last_t;
+  Coef<L> cf;
+  if (L == 1) {
+    status = sh.status;
+    last_t = sh.last_t;
+    read_coef<L>(sh, i, t, cf);
+  } else {
+    status = a.st_in->status;
+    last_t = a.st_in->last_t;
+    read_coef<L>(*a.st_in, i, t, cf);
+  }
+  // Sweeps past the stop change nothing (the solve's x is x_{last_t}).
+  if (status != kRunning && t > last_t) return;
+
+  double acc[ND];
+#pragma unroll
+  for (int m = 0; m < ND; ++m) acc[m] = 0.0;
+  const int first = L == 1 ? 0 : 1;
+  for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, first, (i & 1) != 0); it.c < it.end;
+       it.c += it.step) {
+    const int base = order.phys(it.at()) * CH;
+    const int idx = base + threadIdx.x * V;
+    if (fast_rows && base + CH <= a.n)
+      S::template chunk<V, true>(a, op, idx, t, cf, acc);
+    else
+      S::template chunk<V, false>(a, op, idx, t, cf, acc);
+  }
+  store_partials<ND>(acc, a.part_out, a.pstride, blockIdx.x - first, lds, red);
+}
+
+// Sweep A of iteration k.  Prologue (every workgroup): rho_k = (r_k, r_k) from
+// sweep B of iteration k-1, beta_{k-1} = rho_k / rho_{k-1}, stopping test
+// ||r_k|| < tol ||r_0||.  Then p_k = r_k + beta_{k-1} p_{k-1} (p_0 = r_0),
+// q = A p_k and the product (p_k, q).
+//
+// Prologue of sweep A, every workgroup; returns false when nothing is streamed.
+__device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds, double *red) {
+  state_load(a.st_in, &sh);
+  if (a.k >= 1 && sh.status == kRunning) {
+    sum_partials<1>(a.part_in, a.nparts_in, a.pstride, lds, red);
+    if (threadIdx.x == 0) {
+      const double rho = red[0];
+      sh.cols = a.k;
+      sh.last_t = a.k;
+      if (!isfinite(rho)) {
+        sh.status = kCgBreak;
+      } else {
+        sh.cg_beta = rho / sh.cg_rho;
+        sh.cg_rho = rho;
+        if (sqrt(rho) < sh.abs_tol) sh.status = kConverged;
+      }
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    state_store(&sh, a.st_out);
+    if (threadIdx.x == 0) publish(sh, a.hs, sqrt(sh.cg_rho), 2 * a.k);
+  }
+  return sh.status == kRunning && a.work;
+}
+
+}  // namespace plcg

@@ -56,7 +56,8 @@ class plcg_operator_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("diag", ctypes.c_void_p), ("nnz", ctypes.c_int64),
                 ("rowptr", ctypes.c_void_p), ("colind", ctypes.c_void_p),
-                ("vals", ctypes.c_void_p), ("jacobi", ctypes.c_int32)]
+                ("vals", ctypes.c_void_p), ("jacobi", ctypes.c_int32),
+                ("cx", ctypes.c_void_p), ("cy", ctypes.c_void_p), ("cz", ctypes.c_void_p)]
 
 
 class plcg_config(ctypes.Structure):
@@ -211,12 +212,15 @@ def check(status, where):
     return status
 
 
-def _dims_desc(kind, dims, diag=None, csr=None, jacobi=False):
+def _dims_desc(kind, dims, diag=None, csr=None, jacobi=False, coef=None):
     dims = tuple(int(d) for d in dims)
+    cx, cy, cz = coef if coef is not None else (None, None, None)
     if kind in ("2d5", PLCG_OP_STENCIL2D5):
-        return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1)
+        return plcg_operator_desc(PLCG_OP_STENCIL2D5, dims[0], dims[1], 1, None, 0, None, None,
+                                  None, 1 if jacobi else 0, cx, cy, cz)
     if kind in ("3d7", PLCG_OP_STENCIL3D7):
-        return plcg_operator_desc(PLCG_OP_STENCIL3D7, dims[0], dims[1], dims[2])
+        return plcg_operator_desc(PLCG_OP_STENCIL3D7, dims[0], dims[1], dims[2], None, 0, None,
+                                  None, None, 1 if jacobi else 0, cx, cy, cz)
     dims = dims + (1,) * (3 - len(dims))
     if kind in ("diag", PLCG_OP_DIAG):
         return plcg_operator_desc(PLCG_OP_DIAG, dims[0], dims[1], dims[2], diag)
@@ -268,14 +272,17 @@ class Solver:
     def __init__(self, kind, dims, method="plcg", l=1, lmin=0.0, lmax=8.0, shifts=None,
                  check_every=0, max_restarts=-1, history_cap=0, precision="fp64",
                  inner_tol=0.0, diag=None, csr=None, jacobi=False, launch="auto",
-                 x_update="auto"):
+                 x_update="auto", coef=None):
         """kind "2d5", "3d7", "diag" or "csr"; for "diag", `diag` is the device
         address of the n FP64 diagonal entries; for "csr", `csr` is (rowptr,
         colind, vals, nnz) with device addresses of int64 / int32 / FP64 arrays
-        (copied by plcg_create); jacobi=True solves a CSR matrix Jacobi-preconditioned.
+        (copied by plcg_create); for "2d5" / "3d7", `coef` = (cx, cy, cz) device
+        addresses of edge coefficients (cz None in 2D) makes the operator the
+        variable-coefficient one; jacobi=True solves a CSR matrix or a
+        variable-coefficient stencil Jacobi-preconditioned.
         launch: "auto", "streaming" or "resident" (PLCG_LAUNCH_*); x_update: "auto",
         "every" or "paired" (PLCG_X_*)."""
-        self.desc = _dims_desc(kind, dims, diag, csr, jacobi)
+        self.desc = _dims_desc(kind, dims, diag, csr, jacobi, coef)
         self._shifts = None
         sp = None
         if shifts is not None:

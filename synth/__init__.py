@@ -61,6 +61,10 @@ WORKLOADS = {
                      interval=(0.0, 8.0), tol=1e-8),
     "diag64": dict(kind="diag", dims=(64, 64), rhs="uniform",
                    interval=(0.0, 8.0), tol=1e-8),
+    # 2D variable-coefficient 5-point operator (lognormal(0, 1) edge coefficients
+    # from seed 7), solved Jacobi-scaled with shifts on [0, 2]; b uniform, seed 0
+    "varcoef2048": dict(kind="2d5var", dims=(2048, 2048), rhs="uniform",
+                        interval=(0.0, 2.0), tol=1e-8, coef_seed=7),
 }
 
 
@@ -139,6 +143,29 @@ def sample_indices(n: int, count: int = 512, seed: int = 12345) -> np.ndarray:
     tail = np.arange(max(0, n - edge), n, dtype=np.int64)
     draws = (splitmix64(seed, 0, count) % np.uint64(max(n, 1))).astype(np.int64)
     return np.unique(np.concatenate([head, tail, draws]))
+
+
+def dense_sample_indices(dims) -> np.ndarray:
+    """Whole grid rows for dense spot checks of full-size results, where a
+    parallel split of the grid into eighths puts its seams.  2D (nx, ny): the
+    first and last row and rows k*ny/8 - 1 and k*ny/8 for k = 1..7.  3D
+    (nx, ny, nz): in planes 0, nz/8 - 1, nz/8, nz/2 - 1, nz/2 and nz - 1, rows 0,
+    15, 16, 31, 32, ny/2 - 1, ny/2 and ny - 1.  Sorted, distinct, in range."""
+    dims = tuple(int(d) for d in dims)
+    nx, ny = dims[0], dims[1]
+    if len(dims) == 2:
+        rows = {0, ny - 1}
+        for k in range(1, 8):
+            rows |= {k * ny // 8 - 1, k * ny // 8}
+        cells = [(0, y) for y in rows]
+    else:
+        nz = dims[2]
+        planes = {0, nz // 8 - 1, nz // 8, nz // 2 - 1, nz // 2, nz - 1}
+        rows = {0, 15, 16, 31, 32, ny // 2 - 1, ny // 2, ny - 1}
+        cells = [(z, y) for z in planes for y in rows]
+    ny_, nz_ = ny, dims[2] if len(dims) == 3 else 1
+    starts = sorted({(z * ny_ + y) * nx for z, y in cells if 0 <= y < ny_ and 0 <= z < nz_})
+    return np.concatenate([np.arange(s0, s0 + nx, dtype=np.int64) for s0 in starts])
 
 
 def lognormal(n: int, seed: int, start: int = 0) -> np.ndarray:

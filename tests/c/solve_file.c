@@ -21,10 +21,12 @@ static int check_hip(hipError_t e, const char *what) {
 }
 
 int main(int argc, char **argv) {
-  if (argc != 8) {
-    fprintf(stderr, "usage: %s nx ny cg|plcg l tol b.bin x.bin\n", argv[0]);
+  if (argc != 8 && argc != 10) {
+    fprintf(stderr, "usage: %s nx ny cg|plcg l tol b.bin x.bin [cx.bin cy.bin]\n", argv[0]);
     return 2;
   }
+  /* with cx.bin, cy.bin: the variable-coefficient operator, Jacobi-scaled, shifts on [0, 2] */
+  const int var = argc == 10;
   const int nx = atoi(argv[1]), ny = atoi(argv[2]), l = atoi(argv[4]);
   const int method = strcmp(argv[3], "cg") == 0 ? PLCG_METHOD_CG : PLCG_METHOD_PLCG;
   const double tol = atof(argv[5]);
@@ -65,6 +67,31 @@ int main(int argc, char **argv) {
 
   cfg.method = method;
   cfg.l = l;
+  double *dcx = NULL, *dcy = NULL;
+  if (var) {
+    const size_t ncx = (size_t)(nx + 1) * ny, ncy = (size_t)nx * (ny + 1);
+    double *hcx = (double *)malloc(ncx * sizeof(double));
+    double *hcy = (double *)malloc(ncy * sizeof(double));
+    FILE *fx = fopen(argv[8], "rb"), *fy = fopen(argv[9], "rb");
+    if (!fx || !fy || fread(hcx, sizeof(double), ncx, fx) != ncx ||
+        fread(hcy, sizeof(double), ncy, fy) != ncy) {
+      fprintf(stderr, "cannot read the coefficient files\n");
+      return 2;
+    }
+    fclose(fx);
+    fclose(fy);
+    if (check_hip(hipMalloc((void **)&dcx, ncx * sizeof(double)), "hipMalloc") ||
+        check_hip(hipMalloc((void **)&dcy, ncy * sizeof(double)), "hipMalloc") ||
+        check_hip(hipMemcpy(dcx, hcx, ncx * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy") ||
+        check_hip(hipMemcpy(dcy, hcy, ncy * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy"))
+      return 1;
+    free(hcx);
+    free(hcy);
+    op.cx = dcx;
+    op.cy = dcy;
+    op.jacobi = 1;
+    cfg.lambda_max = 2.0;
+  }
   if (plcg_create(&op, &cfg, &h) != PLCG_OK) {
     fprintf(stderr, "plcg_create: %s\n", plcg_last_error());
     return 1;
@@ -93,6 +120,11 @@ int main(int argc, char **argv) {
   printf("iters %d reason %d restarts %d true_relres %.6e rec_relres %.6e\n", res.iters,
          res.reason, res.restarts, res.true_relres, res.rec_relres);
   plcg_destroy(h);
+  /* the library copied the coefficients at plcg_create */
+  if (var) {
+    (void)hipFree(dcx);
+    (void)hipFree(dcy);
+  }
   (void)hipFree(db);
   (void)hipFree(dx);
   (void)hipStreamDestroy(s);

@@ -2,7 +2,9 @@
 
 For each (workload, method) the oracle solves the seeded system once and the
 script stores: iteration count, stop reason, restarts, recursive and true
-relative residuals, ||x||_2, and x at the indices of synth.sample_indices.
+relative residuals, ||x||_2, and x at the indices of synth.sample_indices; and,
+in <name>_dense.npy (float64, no pickle), x at synth.dense_sample_indices (whole
+grid rows at the seams of a split into eighths).
 GPU tests compare the library against these at the same sizes.  "mixed" is
 FP32-stored p(l)-CG in FP64 refinement (oracle.refine, inner tol 1e-4);
 "batch" is system k of the batch512 recipe, solved alone on its Jacobi-scaled
@@ -33,6 +35,7 @@ JOBS = {
     "diag2048_cg": ("diag2048", "cg", 0),
     "diag2048_p1": ("diag2048", "plcg", 1),
     "diag2048_p2": ("diag2048", "plcg", 2),
+    "varcoef2048_p2": ("varcoef2048", "plcg", 2),
 }
 # batch512 systems: the smallest and the largest side of the recipe and two more
 BATCH_SYSTEMS = (0, 1, 2, 3)
@@ -94,15 +97,26 @@ def run(name):
         return name, out["iters"], out["oracle_seconds"]
     wl_name, method, l = JOBS[name]
     wl = synth.WORKLOADS[wl_name]
+    dis = None
     if wl["kind"] == "diag":
         A = operators.diagonal(synth.spectrum_diagonal(wl["dims"]))
+    elif wl["kind"] == "2d5var":
+        # Jacobi-scaled: solve D^-1/2 A D^-1/2 y = D^-1/2 b, x = D^-1/2 y
+        cx, cy, cz = synth.edge_coefficients(wl["dims"], wl["coef_seed"])
+        A0, A, dis = operators.variable_laplacian(wl["dims"], cx, cy, cz)
     else:
         A = operators.laplacian(wl["dims"])
     b = synth.uniform(A.n, 0)
     x0 = np.zeros(A.n)
     lo, hi = wl["interval"]
     t0 = time.time()
-    if method == "cg":
+    extra = {}
+    if dis is not None:
+        r = oplcg.plcg(A, dis * b, x0, l, shifts.chebyshev_shifts(l, lo, hi), wl["tol"], 100000)
+        r.x = dis * r.x
+        extra = {"restarts": r.restarts, "coef_seed": wl["coef_seed"], "jacobi": 1,
+                 "orig_relres": float(np.linalg.norm(b - A0(r.x)) / np.linalg.norm(b))}
+    elif method == "cg":
         r = ocg.cg(A, b, x0, wl["tol"], 100000)
         extra = {}
     elif method == "mixed":
@@ -115,6 +129,8 @@ def run(name):
         r = oplcg.plcg(A, b, x0, l, shifts.chebyshev_shifts(l, lo, hi), wl["tol"], 100000)
         extra = {"restarts": r.restarts}
     idx = synth.sample_indices(A.n)
+    dense = synth.dense_sample_indices(wl["dims"])
+    np.save(os.path.join(HERE, name + "_dense.npy"), r.x[dense], allow_pickle=False)
     out = {
         "workload": wl_name, "method": method, "l": l, "dims": list(wl["dims"]),
         "seed": 0, "tol": wl["tol"], "interval": list(wl["interval"]),
@@ -122,6 +138,7 @@ def run(name):
         "true_relres": float(r.true_relres), "xnorm": float(np.linalg.norm(r.x)),
         "sample_idx": [int(i) for i in idx], "sample_x": [float(v) for v in r.x[idx]],
         "oracle_seconds": time.time() - t0, **extra,
+        "dense_file": name + "_dense.npy", "dense_count": int(dense.size),
         "writer": "tests/golden/make_golden.py (oracle only)",
     }
     with open(os.path.join(HERE, name + ".json"), "w") as f:
@@ -132,6 +149,6 @@ def run(name):
 if __name__ == "__main__":
     names = sys.argv[1:] or list(JOBS) + [f"batch512_{k}" for k in BATCH_SYSTEMS]
     os.environ.setdefault("OMP_NUM_THREADS", "1")
-    with Pool(min(len(names), 4)) as pool:
+    with Pool(min(len(names), int(os.environ.get("GOLDEN_JOBS", "4")))) as pool:
         for name, iters, dt in pool.imap_unordered(run, names):
             print(f"{name}: {iters} iterations, {dt:.0f} s", flush=True)

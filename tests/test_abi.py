@@ -147,3 +147,24 @@ def test_noalloc_rejects_before_device_work(kind, nx, ny, nz, l, hist):
     if nx == 2048 or nz == 256:
         assert b"bytes" in msg and str(plcg.PLCG_NOALLOC_BYTES).encode() in msg
     assert plcg.plcg_solve_noalloc(None, None, 0, 0, 1e-8, 10, None, None) == plcg.PLCG_E_INVALID
+
+
+@pytest.mark.parametrize("kind,nz,coef,jacobi", [
+    (1, 1, (16, None, None), 0),        # cy missing
+    (2, 4, (16, 32, None), 0),          # cz missing in 3D
+    (1, 1, (None, 32, None), 0),        # cy without cx
+    (3, 1, (16, 32, None), 0),          # coefficients on a diagonal operator
+    (1, 1, (None, None, None), 1),      # Jacobi scaling of the constant stencil
+])
+def test_create_rejects_bad_edge_coefficients(kind, nz, coef, jacobi):
+    """Descriptor checks of the variable-coefficient stencil made before any
+    device access (the addresses are never read)."""
+    from paper_1905_06850_amd import plcg
+    desc = plcg.plcg_operator_desc(kind, 8, 8, nz, 64 if kind == 3 else None, 0, None, None,
+                                   None, jacobi, *coef)
+    cfg = plcg.plcg_config(1, 2, 0.0, 2.0, None, 0, -1, 0)
+    h = ctypes.c_void_p()
+    assert plcg.plcg_create(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(h)) == \
+        plcg.PLCG_E_INVALID
+    assert not h.value
+    assert plcg.plcg_last_error()

@@ -1,0 +1,275 @@
+"""Variable-coefficient 2D / 3D stencils on the single-solve path (plcg_create
+with edge coefficients cx, cy, cz) through the C ABI against the oracle's
+operators.variable_laplacian: the operator itself, Jacobi-scaled solves (Alg. 1
+with M = diag(A) in its symmetric form, reading 15), unscaled CG, early iterates,
+the preconditioned Alg. 1 with u != z, FP32-stored inner solves, the full-size
+2048^2 workload against the stored oracle result, and rejected inputs."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cg as ocg
+from oracle import operators, refine, shifts
+from oracle import plcg as oplcg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _plcg():
+    from paper_1905_06850_amd import plcg
+    return plcg
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+class Coef:
+    """Edge coefficients of `dims` from `seed`, on the device (kept alive while a
+    solver is created), and the oracle's operators for them."""
+
+    def __init__(self, dev, dims, seed):
+        self.dims = tuple(dims)
+        self.n = int(np.prod(dims))
+        self.c = synth.edge_coefficients(dims, seed)
+        self.t = [torch.from_numpy(np.ascontiguousarray(c)).to(dev) if c is not None else None
+                  for c in self.c]
+        self.A, self.As, self.dis = operators.variable_laplacian(dims, *self.c)
+
+    def arg(self):
+        return tuple(t.data_ptr() if t is not None else None for t in self.t)
+
+
+def _kind(dims):
+    return "2d5" if len(dims) == 2 else "3d7"
+
+
+def gpu_solve(dev, co, method, l, b, x0, tol, maxit, jacobi=True, lo=0.0, hi=2.0, **kw):
+    plcg = _plcg()
+    print(f"[gpu] varcoef {method} l={l} dims={co.dims} jacobi={jacobi} tol={tol} "
+          f"maxit={maxit} {kw}", flush=True)
+    s = plcg.Solver(_kind(co.dims), co.dims, method=method, l=l, lmin=lo, lmax=hi,
+                    coef=co.arg(), jacobi=jacobi, **kw)
+    bt = torch.from_numpy(np.ascontiguousarray(b)).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x0).copy()).to(dev)
+    res = s.solve(bt.data_ptr(), xt.data_ptr(), tol, maxit,
+                  torch.cuda.current_stream(dev).cuda_stream)
+    x = xt.cpu().numpy()
+    s.close()
+    return x, res
+
+
+def oracle_solve(A, method, l, b, x0, tol, maxit, lo=0.0, hi=2.0):
+    if method == "cg":
+        return ocg.cg(A, b, x0, tol, maxit)
+    return oplcg.plcg(A, b, x0, l, shifts.chebyshev_shifts(l, lo, hi), tol, maxit)
+
+
+DIMS = [(64, 64), (100, 37), (37, 100), (102, 30), (1, 300), (300, 1), (20, 13, 7),
+        (32, 48, 5), (9, 7, 5), (1, 1, 200)]
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_var_apply_matches_oracle(dev, dims, jacobi):
+    """plcg_apply: the operator (unscaled), or D^{-1/2} A D^{-1/2} (jacobi), to
+    rounding of the terms it adds."""
+    plcg = _plcg()
+    co = Coef(dev, dims, 41)
+    x = synth.uniform(co.n, 42)
+    s = plcg.Solver(_kind(dims), dims, method="cg", coef=co.arg(), jacobi=jacobi)
+    xt = torch.from_numpy(x).to(dev)
+    yt = torch.empty_like(xt)
+    s.apply(xt.data_ptr(), yt.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
+    y = yt.cpu().numpy()
+    s.close()
+    ref = co.As(x) if jacobi else co.A(x)
+    # bound: a few roundings of the largest term (diagonal times |x|)
+    scale = (np.ones(co.n) if jacobi else 1.0 / co.dis ** 2) * np.abs(x)
+    assert np.all(np.abs(y - ref) <= 32 * np.finfo(float).eps * (scale + np.abs(ref) + 1e-300))
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3)])
+def test_var_jacobi_solve_parity(dev, dims, method, l):
+    """Jacobi-scaled solve against the oracle on the scaled system from the
+    scaled x0: iterations within 1, x within 1e-8, both residual norms."""
+    co = Coef(dev, dims, 43)
+    b = synth.uniform(co.n, 44)
+    x0 = 0.1 * synth.uniform(co.n, 45)
+    ref = oracle_solve(co.As, method, l, co.dis * b, x0 / co.dis, 1e-8, 20000)
+    x, res = gpu_solve(dev, co, method, l, b, x0, 1e-8, 20000)
+    assert res.reason == 1 and ref.reason == "converged", res.as_dict()
+    assert abs(res.iters - ref.iters) <= 1
+    assert _rel(x, co.dis * ref.x) < 1e-8
+    assert res.rec_relres <= 10 * ref.true_relres
+    r0 = np.linalg.norm(b - co.A(x0))
+    assert abs(res.rnorm0 - r0) <= 1e-12 * r0
+    true = np.linalg.norm(b - co.A(x)) / r0
+    assert abs(res.true_relres - true) <= 1e-3 * true + 1e-15
+
+
+@pytest.mark.parametrize("dims", [(64, 64), (102, 30), (20, 13, 7), (32, 48, 5)])
+def test_var_unscaled_cg_parity(dev, dims):
+    """CG on the operator as given (diagonal array, raw edge weights)."""
+    co = Coef(dev, dims, 46)
+    b = synth.uniform(co.n, 47)
+    x0 = np.zeros(co.n)
+    ref = ocg.cg(co.A, b, x0, 1e-8, 20000)
+    x, res = gpu_solve(dev, co, "cg", 1, b, x0, 1e-8, 20000, jacobi=False)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.iters - ref.iters) <= 1
+    assert _rel(x, ref.x) < 1e-8
+    assert res.true_relres <= 10 * ref.true_relres and ref.true_relres <= 10 * res.true_relres
+
+
+@pytest.mark.parametrize("dims", [(64, 40), (20, 13, 7)])
+@pytest.mark.parametrize("l", [1, 2])
+def test_var_unscaled_plcg_early_iterates(dev, dims, l):
+    """p(l)-CG on the unscaled operator with an interval that holds its spectrum
+    (Gershgorin: [0, 2 max d]): the first iterates against the oracle's."""
+    co = Coef(dev, dims, 48)
+    b = synth.uniform(co.n, 49)
+    x0 = np.zeros(co.n)
+    hi = 2.0 * float(np.max(1.0 / co.dis ** 2))
+    for m in (1, 2, 3, 7):
+        ref = oracle_solve(co.A, "plcg", l, b, x0, 1e-30, m, 0.0, hi)
+        x, res = gpu_solve(dev, co, "plcg", l, b, x0, 1e-30, m, jacobi=False, hi=hi,
+                           launch="streaming")
+        assert res.iters == m == ref.iters
+        assert _rel(x, ref.x) < 1e-12
+
+
+@pytest.mark.parametrize("x_update", ["every", "paired"])
+@pytest.mark.parametrize("method,l", [("cg", 1), ("plcg", 1), ("plcg", 2), ("plcg", 3),
+                                      ("plcg", 5)])
+def test_var_early_iterates(dev, method, l, x_update):
+    """x after exactly m steps (Jacobi-scaled) against the oracle's x_m."""
+    co = Coef(dev, (48, 40), 50)
+    b = synth.uniform(co.n, 51)
+    x0 = np.zeros(co.n)
+    for m in (1, 2, 3, 7, 20):
+        ref = oracle_solve(co.As, method, l, co.dis * b, x0, 1e-30, m)
+        x, res = gpu_solve(dev, co, method, l, b, x0, 1e-30, m, x_update=x_update)
+        assert res.iters == m == ref.iters and res.reason == 2
+        assert _rel(x, co.dis * ref.x) < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(40, 30), (12, 10, 8)])
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_var_jacobi_is_preconditioned_alg1(dev, dims, l):
+    """The first iterates equal those of Alg. 1 with M = diag(A) (u != z,
+    M-inner products) run by the oracle on the unscaled operator."""
+    co = Coef(dev, dims, 52)
+    b = synth.uniform(co.n, 53)
+    x0 = np.zeros(co.n)
+    dinv = co.dis * co.dis
+    sig = shifts.chebyshev_shifts(l, 0.0, 2.0)
+    for m in (1, 5, 20):
+        ref = oplcg.alg1(co.A, b, x0, l, sig, 0.0, m, Minv=lambda u: dinv * u)
+        x, res = gpu_solve(dev, co, "plcg", l, b, x0, 1e-30, m)
+        assert res.iters == m == ref.t_done
+        assert _rel(x, ref.x) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(60, 50), (16, 12, 10)])
+def test_var_jacobi_mixed_precision(dev, dims):
+    """FP32-stored inner p(2)-CG in FP64 refinement on the scaled operator
+    against oracle.refine."""
+    co = Coef(dev, dims, 54)
+    b = synth.uniform(co.n, 55)
+    tol, inner = 1e-10, 1e-4
+    ref = refine.refine(co.As, co.dis * b, np.zeros(co.n), 2, shifts.chebyshev_shifts(2, 0.0, 2.0),
+                        tol, inner, 20000)
+    x, res = gpu_solve(dev, co, "plcg", 2, b, np.zeros(co.n), tol, 20000, precision="fp32",
+                       inner_tol=inner)
+    assert res.reason == 1 and ref.reason == "converged"
+    assert abs(res.outer - ref.outer) <= 1
+    assert abs(res.iters - ref.inner_iters) <= 0.1 * ref.inner_iters + 2
+    lam_min = np.linalg.eigvalsh(operators.assemble(co.As))[0]
+    y, yref = x / co.dis, ref.x
+    assert np.linalg.norm(y - yref) <= 2 * (res.rec_relres + ref.true_relres) * ref.rnorm0 / lam_min
+
+
+def test_var_rejects_invalid_coefficients(dev):
+    plcg = _plcg()
+    co = Coef(dev, (6, 5), 56)
+    for which, value in ((0, 0.0), (1, -1.0), (0, float("nan")), (1, float("inf"))):
+        bad = [c.clone() for c in co.t[:2]]
+        bad[which][3] = value
+        with pytest.raises(plcg.PlcgError) as ei:
+            plcg.Solver("2d5", (6, 5), method="plcg", l=2,
+                        coef=(bad[0].data_ptr(), bad[1].data_ptr(), None), jacobi=True)
+        assert ei.value.status == plcg.PLCG_E_INVALID
+    cx, cy = co.t[0].data_ptr(), co.t[1].data_ptr()
+    for kw in (dict(kind="2d5", dims=(6, 5), coef=(cx, None, None)),          # cy missing
+               dict(kind="3d7", dims=(6, 5, 1), coef=(cx, cy, None)),         # cz missing
+               dict(kind="2d5", dims=(6, 5), coef=(cx, cy, None), launch="resident"),
+               dict(kind="2d5", dims=(6, 5), coef=(None, cy, None)),
+               dict(kind="2d5", dims=(6, 5), jacobi=True)):                  # constant stencil
+        with pytest.raises(plcg.PlcgError) as ei:
+            plcg.Solver(method="plcg", l=2, **kw)
+        assert ei.value.status == plcg.PLCG_E_INVALID
+
+
+def test_var_auto_streams_small_systems(dev):
+    """No resident kernel for these operators: a small system streams under AUTO."""
+    co = Coef(dev, (30, 30), 57)
+    b = synth.uniform(co.n, 58)
+    x, res = gpu_solve(dev, co, "plcg", 2, b, np.zeros(co.n), 1e-8, 5000)
+    assert res.reason == 1 and res.launch_mode == _plcg().PLCG_LAUNCH_STREAMING
+
+
+def _golden(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle result {name}")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_var_full_size_against_stored_oracle(dev):
+    """The 2048^2 variable-coefficient workload (lognormal(0, 1) edges from seed
+    7, Jacobi-scaled p(2)-CG on [0, 2], tol 1e-8) in the configuration the
+    benchmark runs, against the oracle's stored result: iterations within 1, x
+    at the stored sample and on the dense sample of whole rows (relative error
+    < 1e-8), ||x||, and both residual norms."""
+    g = _golden("varcoef2048_p2")
+    dims = tuple(g["dims"])
+    n = int(np.prod(dims))
+    plcg = _plcg()
+    c = synth.edge_coefficients(dims, g["coef_seed"])
+    ct = [torch.from_numpy(a).to(dev) for a in c[:2]]
+    s = plcg.Solver("2d5", dims, method="plcg", l=2, lmin=0.0, lmax=2.0,
+                    coef=(ct[0].data_ptr(), ct[1].data_ptr(), None), jacobi=True)
+    bt = torch.from_numpy(synth.uniform(n, g["seed"])).to(dev)
+    xt = torch.zeros(n, dtype=torch.float64, device=dev)
+    res = s.solve(bt.data_ptr(), xt.data_ptr(), g["tol"], 100000,
+                  torch.cuda.current_stream(dev).cuda_stream)
+    s.close()
+    x = xt.cpu().numpy()
+    assert res.reason == 1 and abs(res.iters - g["iters"]) <= 1
+    assert res.true_relres <= 10 * g["orig_relres"] and g["orig_relres"] <= 10 * res.true_relres
+    assert res.rec_relres <= 10 * g["true_relres"]
+    idx = np.array(g["sample_idx"])
+    ref = np.array(g["sample_x"])
+    assert np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"] < 1e-8
+    dense = synth.dense_sample_indices(dims)
+    dref = np.load(os.path.join(os.path.dirname(__file__), "golden", g["dense_file"]),
+                   allow_pickle=False)
+    assert dref.shape == dense.shape
+    assert np.linalg.norm(x[dense] - dref) / np.linalg.norm(dref) < 1e-8
+    assert abs(np.linalg.norm(x) - g["xnorm"]) <= 1e-8 * g["xnorm"]
