@@ -420,6 +420,11 @@ typedef struct {
   int32_t system;         /* index into the op_ids / d_b arrays */
   int32_t maxit;
   double tol;
+  double *x;              /* device, n doubles of the request's system (16-byte aligned), or
+                             NULL: receives the solution.  Set to 0 (x0) when the request is
+                             admitted, written by the solve, and final when out[k].finish_s
+                             is set; the caller keeps ownership.  NULL: the solution stays
+                             inside the batch and is released with the slot. */
 } plcg_request;
 
 typedef struct {
@@ -433,11 +438,12 @@ typedef struct {
  * footprint), enqueues ticks_per_round launches, retires finished solves, and
  * repeats until every request is done or time_limit_s has passed.  Request k
  * solves with operator op_ids[system] and right-hand side d_b[system] (device,
- * shared, read only), x0 = 0; the solution stays inside the batch (this loop
- * measures service, it does not hand solutions back).  Timings and results go
- * to out[k].  Solves still running when the time limit passes keep their slots
- * until the batch is destroyed.  PLCG_E_INVALID for unsorted arrivals, an
- * unknown system or a request that does not fit an empty batch. */
+ * shared, read only), x0 = 0; its solution goes to reqs[k].x (or stays inside
+ * the batch when that is NULL, which also takes n more doubles of arena per
+ * request).  Timings and results go to out[k].  Solves still running when the
+ * time limit passes keep their slots (and keep writing reqs[k].x) until the
+ * batch is destroyed.  PLCG_E_INVALID for unsorted arrivals, an unknown system,
+ * a misaligned x or a request that does not fit an empty batch. */
 plcg_status plcg_serve(plcg_batch *b, const int32_t *op_ids, const double *const *d_b,
                        int32_t nops, const plcg_request *reqs, int32_t nreq,
                        int32_t ticks_per_round, double time_limit_s, void *stream,

@@ -560,6 +560,11 @@ int32_t flush_admissions(plcg_batch *b, hipStream_t st) {
 
 }  // namespace
 
+int64_t plcg::batch_op_unknowns(const plcg_batch *b, int32_t op_id) {
+  if (b == nullptr || op_id < 0 || op_id >= (int32_t)b->ops.size()) return -1;
+  return b->ops[op_id].n;
+}
+
 extern "C" {
 
 plcg_status plcg_batch_add(plcg_batch *b, const plcg_system_desc *sys, const double *d_b,

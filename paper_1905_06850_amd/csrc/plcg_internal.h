@@ -294,6 +294,9 @@ hipError_t launch_batch_tick(const BatchArgs &a, int blocks, hipStream_t s);
 // Records msg as the calling thread's last error (plcg_last_error) and returns code.
 int32_t set_last_error(int32_t code, const char *msg);
 
+// Unknowns of registered operator op_id of a batch (-1: no such operator).
+int64_t batch_op_unknowns(const plcg_batch *b, int32_t op_id);
+
 // Host: edge weights and diagonal of the variable-coefficient grid operator
 // (VarOp) from host coefficient arrays (NULL: all 1), Jacobi-scaled or not;
 // PLCG_E_INVALID unless every coefficient is finite and > 0 (plcg_batch.cpp).

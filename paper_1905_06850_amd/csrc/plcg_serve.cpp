@@ -50,7 +50,14 @@ extern "C" plcg_status plcg_serve(plcg_batch *b, const int32_t *op_ids, const do
       const int32_t r = queue.front();
       const plcg_request &q = reqs[r];
       uint64_t ticket = 0;
-      const plcg_status s = plcg_batch_add_op(b, op_ids[q.system], d_b[q.system], nullptr, q.tol,
+      // x0 = 0 in the caller's buffer, ordered before the launches that read it
+      if (q.x != nullptr) {
+        const int64_t n = batch_op_unknowns(b, op_ids[q.system]);
+        if (n < 0) return set_last_error(PLCG_E_INVALID, "unknown operator");
+        if (hipMemsetAsync(q.x, 0, (size_t)n * sizeof(double), st) != hipSuccess)
+          return set_last_error(PLCG_E_HIP, "hipMemsetAsync(x0)");
+      }
+      const plcg_status s = plcg_batch_add_op(b, op_ids[q.system], d_b[q.system], q.x, q.tol,
                                               q.maxit, stream, &ticket);
       if (s == PLCG_E_BUSY) break;
       if (s != PLCG_OK) return s;

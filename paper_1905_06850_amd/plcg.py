@@ -101,7 +101,7 @@ class plcg_system_desc(ctypes.Structure):
 
 class plcg_request(ctypes.Structure):
     _fields_ = [("arrival_s", ctypes.c_double), ("system", ctypes.c_int32),
-                ("maxit", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("maxit", ctypes.c_int32), ("tol", ctypes.c_double), ("x", ctypes.c_void_p)]
 
 
 class plcg_request_outcome(ctypes.Structure):
@@ -417,13 +417,17 @@ class Batch:
         return t.value
 
     def serve(self, op_ids, b_ptrs, requests, ticks_per_round=16, time_limit_s=60.0, stream=0):
-        """requests: list of (arrival_s, system, maxit, tol), sorted by arrival.
-        Returns the list of plcg_request_outcome."""
+        """requests: list of (arrival_s, system, maxit, tol) or (arrival_s, system,
+        maxit, tol, x_ptr) with x_ptr the device address receiving the solution
+        (None: kept inside the batch), sorted by arrival.  Returns the list of
+        plcg_request_outcome."""
         n = len(op_ids)
         ops = (ctypes.c_int32 * n)(*op_ids)
         bp = (ctypes.c_void_p * n)(*b_ptrs)
-        rq = (plcg_request * len(requests))(*[plcg_request(float(a), int(s), int(m), float(t))
-                                              for a, s, m, t in requests])
+        rq = (plcg_request * len(requests))(*[plcg_request(float(r[0]), int(r[1]), int(r[2]),
+                                                           float(r[3]),
+                                                           r[4] if len(r) > 4 else None)
+                                              for r in requests])
         out = (plcg_request_outcome * len(requests))()
         check(plcg_serve(self.handle, ops, bp, n, rq, len(requests), int(ticks_per_round),
                          float(time_limit_s), stream, out), "plcg_serve")

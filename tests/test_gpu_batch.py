@@ -214,8 +214,9 @@ def test_registered_operator_equals_private_copy(dev):
 
 def test_served_stream_equals_alone(dev):
     """Requests arriving while others are in flight join the running batch
-    (continuous batching, admission by footprint); each request's iteration
-    count and residual norms are bit for bit those of the same solve alone."""
+    (continuous batching, admission by footprint); each request's solution x,
+    iteration count and residual norms are bit for bit those of the same solve
+    alone, and the served solutions match the oracle's."""
     plcg = _plcg()
     stream = torch.cuda.current_stream(dev).cuda_stream
     pool = [_system(*s) for s in SYSTEMS[:6]]
@@ -230,36 +231,55 @@ def test_served_stream_equals_alone(dev):
     reqs = []
     for k in range(18):
         reqs.append((0.002 * k, k % len(pool), 20000, tols[k % 3]))
-    # alone: one request at a time
+    # alone: one request at a time, its solution in its own buffer
     alone = {}
     for k, (a, sidx, m, tol) in enumerate(reqs):
         if (sidx, tol) in alone:
             continue
         batch, ops = make_batch(1, 1 << 28)
-        out = batch.serve(ops, [bt.data_ptr() for bt in bts], [(0.0, sidx, m, tol)], 16, 60.0, stream)
-        alone[(sidx, tol)] = out[0].result
+        xa = torch.full((pool[sidx]["n"],), float("nan"), dtype=torch.float64, device=dev)
+        out = batch.serve(ops, [bt.data_ptr() for bt in bts],
+                          [(0.0, sidx, m, tol, xa.data_ptr())], 16, 60.0, stream)
+        torch.cuda.synchronize()
+        alone[(sidx, tol)] = (out[0].result, xa.cpu().numpy())
         batch.close()
+    # served requests write their solutions into buffers that start as NaN (x0 = 0
+    # is set at admission)
+    xs = [torch.full((pool[sidx]["n"],), float("nan"), dtype=torch.float64, device=dev)
+          for (_, sidx, _, _) in reqs]
+    sreqs = [r + (xs[k].data_ptr(),) for k, r in enumerate(reqs)]
     # served: an arena for about three requests, so admission waits for space
     probe, pops = make_batch(1, 1 << 20)
-    fps = [probe.request_footprint(o) for o in pops]
+    fps = [probe.request_footprint(o, internal_x=False) for o in pops]   # x in the caller's buffer
     probe.close()
     arena = 3 * max(fps)
     batch, ops = make_batch(8, arena)
-    out = batch.serve(ops, [bt.data_ptr() for bt in bts], reqs, 8, 120.0, stream)
+    out = batch.serve(ops, [bt.data_ptr() for bt in bts], sreqs, 8, 120.0, stream)
+    torch.cuda.synchronize()
     # footprint in flight at each admission: never more than the arena, and more
     # than one solve at a time (new requests join solves in flight)
     spans = [(o.admit_s, o.finish_s, fps[reqs[k][1]]) for k, o in enumerate(out)]
     load = [sum(fp for a2, f2, fp in spans if a2 <= a < f2) for a, f, _ in spans]
     count = [sum(1 for a2, f2, _ in spans if a2 <= a < f2) for a, f, _ in spans]
     batch.close()
+    checked = set()
     for k, (a, sidx, m, tol) in enumerate(reqs):
         o = out[k]
         assert o.finish_s >= o.admit_s >= a - 1e-9, (k, o.admit_s, o.finish_s)
         r = o.result
-        ref = alone[(sidx, tol)]
+        ref, xref = alone[(sidx, tol)]
         assert r.reason == ref.reason == 1
         assert r.iters == ref.iters and r.true_relres == ref.true_relres
         assert r.rec_relres == ref.rec_relres < tol
+        x = xs[k].cpu().numpy()
+        assert np.array_equal(x.view(np.uint64), xref.view(np.uint64)), k
+        if sidx not in checked:
+            # the served solution against the oracle (same scaled system, p(2))
+            orc, xo, _ = _oracle(pool[sidx], 2, tol)
+            assert abs(r.iters - orc.iters) <= 2
+            assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+            checked.add(sidx)
+    assert len(checked) == len(pool)
     assert max(load) <= arena and max(count) >= 2
 
 
