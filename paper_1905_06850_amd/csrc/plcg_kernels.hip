@@ -83,11 +83,47 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
     // of the planes below, at and above the current one in registers, so every
     // r and p_{k-1} value is loaded once per plane it is the centre of (the
     // rows above and below come from the tile's own or its neighbours' loads in
-    // L2).  Same neighbour-sum order as the chunk path below.
+    // L2).  The raw r and p_{k-1} values a plane needs (its own, the rows above
+    // and below, the x-neighbours at the wave's edges) are loaded one plane
+    // ahead, so their latency overlaps the current plane's work; p_k is formed
+    // where it is used.  Same neighbour-sum order as the chunk path below.
     const int plane = g.nx * g.ny;
     const int ntiles = plane / kChunk;
     const int nitems = ntiles * ((g.nz + a.zseg - 1) / a.zseg);
     const int lane = threadIdx.x & 63;
+    // raw loads of one plane: own pair, rows above and below, wave-edge neighbours
+    struct Raw {
+      Vals<2> r, p, ur, up, dr, dp;
+      double er, ep;
+    };
+    auto fetch = [&](int idx, int x, int y, bool halo, Raw &w) {
+      w.r.load(a.r + idx);
+      if (!first) w.p.load(a.p_old + idx);
+      if (!halo) return;   // the plane above a segment: only its own values
+      if (y > 0) {
+        w.ur.load(a.r + idx - g.nx);
+        if (!first) w.up.load(a.p_old + idx - g.nx);
+      }
+      if (y < g.ny - 1) {
+        w.dr.load(a.r + idx + g.nx);
+        if (!first) w.dp.load(a.p_old + idx + g.nx);
+      }
+      // lane 0 needs x-1, lane 63 x+2
+      const int e = lane == 0 ? idx - 1 : idx + 2;
+      if ((lane == 0 && x > 0) || (lane == 63 && x + 2 < g.nx)) {
+        w.er = a.r[e];
+        if (!first) w.ep = a.p_old[e];
+      }
+    };
+    // p_k from raw r and p_{k-1} (as pk1 / pk2)
+    auto form = [&](const Vals<2> &r, const Vals<2> &po, double &v0, double &v1) {
+      v0 = r.v[0];
+      v1 = r.v[1];
+      if (!first) {
+        v0 += beta * po.v[0];
+        v1 += beta * po.v[1];
+      }
+    };
     for (ChunkIter it = xcd_chunks(nitems, a.nstream, 0); it.c < it.end; it.c += it.step) {
       const int seg = it.c / ntiles;
       const int off = (it.c - seg * ntiles) * kChunk + threadIdx.x * kVec;   // in the plane
@@ -95,31 +131,30 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       const int y = off / g.nx;
       const int z0 = seg * a.zseg;
       const int z1 = min(g.nz, z0 + a.zseg);
-      double m0 = 0.0, m1 = 0.0, c0, c1, n0 = 0.0, n1 = 0.0;
+      double m0 = 0.0, m1 = 0.0;
       if (z0 > 0) pk2(off + (z0 - 1) * plane, m0, m1);
-      pk2(off + z0 * plane, c0, c1);
+      Raw cur, nxt;
+      fetch(off + z0 * plane, x, y, true, cur);
       for (int zz = z0; zz < z1; ++zz) {
         const int idx0 = off + zz * plane;
-        if (zz + 1 < g.nz) {
-          pk2(idx0 + plane, n0, n1);
-        } else {
-          n0 = 0.0;
-          n1 = 0.0;
-        }
+        if (zz + 1 < g.nz) fetch(idx0 + plane, x, y, zz + 1 < z1, nxt);
+        double c0, c1, n0 = 0.0, n1 = 0.0;
+        form(cur.r, cur.p, c0, c1);
+        if (zz + 1 < g.nz) form(nxt.r, nxt.p, n0, n1);
         double left = lane_prev(c1);
         double right = lane_next(c0);
-        if (lane == 0 && x > 0) left = pk1(idx0 - 1);
-        if (lane == 63 && x + 2 < g.nx) right = pk1(idx0 + 2);
+        if (lane == 0 && x > 0) left = first ? cur.er : cur.er + beta * cur.ep;
+        if (lane == 63 && x + 2 < g.nx) right = first ? cur.er : cur.er + beta * cur.ep;
         double s0 = (x > 0 ? left : 0.0) + c1;
         double s1 = c0 + (x + 2 < g.nx ? right : 0.0);
         double u0, u1;
         if (y > 0) {
-          pk2(idx0 - g.nx, u0, u1);
+          form(cur.ur, cur.up, u0, u1);
           s0 += u0;
           s1 += u1;
         }
         if (y < g.ny - 1) {
-          pk2(idx0 + g.nx, u0, u1);
+          form(cur.dr, cur.dp, u0, u1);
           s0 += u0;
           s1 += u1;
         }
@@ -141,8 +176,7 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
         acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
         m0 = c0;
         m1 = c1;
-        c0 = n0;
-        c1 = n1;
+        cur = nxt;
       }
     }
     store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);

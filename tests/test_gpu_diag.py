@@ -120,6 +120,22 @@ def test_diag_rejects_nonpositive_entries(dev):
         assert ei.value.status == plcg.PLCG_E_INVALID
 
 
+def _dense_error(x, g, dims):
+    """Relative error of x on the stored dense sample (whole grid rows at the
+    seams of a split into eighths, synth.dense_sample_indices), or None when the
+    stored result has none."""
+    import os
+    if "dense_file" not in g:
+        return None
+    path = os.path.join(os.path.dirname(__file__), "golden", g["dense_file"])
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path, allow_pickle=False)
+    idx = synth.dense_sample_indices(dims)
+    assert ref.shape == idx.shape
+    return np.linalg.norm(x[idx] - ref) / np.linalg.norm(ref)
+
+
 def _golden(name):
     import json
     import os
@@ -148,3 +164,5 @@ def test_diag_full_size_against_stored_oracle(dev, name):
     ref = np.array(g["sample_x"])
     est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
     assert est < 1e-8
+    dense = _dense_error(x, g, tuple(g["dims"]))
+    assert dense is None or dense < 1e-8, dense

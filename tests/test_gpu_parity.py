@@ -487,6 +487,22 @@ def test_tiny_systems_krylov_exhaustion(dev, dims, l, launch):
 
 # ------------------------------------------------------------ full-size cases --
 
+def _dense_error(x, g, dims):
+    """Relative error of x on the stored dense sample (whole grid rows at the
+    seams of a split into eighths, synth.dense_sample_indices), or None when the
+    stored result has none."""
+    import os
+    if "dense_file" not in g:
+        return None
+    path = os.path.join(os.path.dirname(__file__), "golden", g["dense_file"])
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path, allow_pickle=False)
+    idx = synth.dense_sample_indices(dims)
+    assert ref.shape == idx.shape
+    return np.linalg.norm(x[idx] - ref) / np.linalg.norm(ref)
+
+
 def _golden(name):
     import json
     import os
@@ -505,7 +521,8 @@ def test_full_size_against_stored_oracle(dev, name):
     benchmark times, against the oracle's stored result (tests/golden,
     written by make_golden.py from the oracle only): same iteration count within
     1, true residual within 10x, and ||x - x_oracle|| / ||x_oracle|| < 1e-8
-    estimated from the stored sample of x (plus ||x|| itself)."""
+    estimated from the stored sample of x and measured on the stored dense sample
+    of whole rows at the seams of a split into eighths (plus ||x|| itself)."""
     g = _golden(name)
     dims = tuple(g["dims"])
     n = int(np.prod(dims))
@@ -524,6 +541,8 @@ def test_full_size_against_stored_oracle(dev, name):
     ref = np.array(g["sample_x"])
     est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
     assert est < 1e-8
+    dense = _dense_error(x, g, dims)
+    assert dense is None or dense < 1e-8, dense
     assert abs(np.linalg.norm(x) - g["xnorm"]) <= 1e-8 * g["xnorm"]
     s.close()
 
@@ -605,6 +624,8 @@ def test_full_size_mixed_against_stored_oracle(dev):
     ref = np.array(g["sample_x"])
     est = np.sqrt(n / idx.size * np.sum((x[idx] - ref) ** 2)) / g["xnorm"]
     assert est <= (lmax / lmin) * 2 * g["tol"]
+    dense = _dense_error(x, g, dims)
+    assert dense is None or dense <= (lmax / lmin) * 2 * g["tol"], dense
     s.close()
 
 
