@@ -266,13 +266,14 @@ def batch_bench(args, plcg, torch, dev, sp):
     l = args.batch_l
     prec = args.batch_precision
 
-    def run(cpb, autotune, timed):
+    def run(sched, autotune, timed, l=l):
         probe = plcg.Batch(l=l, max_slots=1, arena_bytes=1 << 20, precision=prec)
         need = sum(probe.footprint(s["dims"], s["cx"], s["cy"]) for s in systems)
         probe.close()
         batch = plcg.Batch(l=l, max_slots=len(systems), arena_bytes=need + (64 << 20),
-                           chunks_per_block=cpb, use_graph=True, precision=prec,
-                           inner_tol=args.inner_tol)
+                           use_graph=True, precision=prec, inner_tol=args.inner_tol)
+        if sched is not None:
+            batch.set_schedule(sched)
         for x in xs:
             x.zero_()
         tickets = {}
@@ -296,12 +297,17 @@ def batch_bench(args, plcg, torch, dev, sp):
                 if r is not None:
                     done[tickets.pop(t)] = (r, now)
         dt = time.perf_counter() - t0
-        chosen = batch.chunks_per_block()
+        chosen = batch.schedule()
         batch.close()
         return dt, done, ticks, chosen
 
-    _, _, _, cpb = run(0, True, False)           # untimed: autotune the workgroup size
-    dt, done, ticks, _ = run(cpb, False, True)
+    # untimed: autotune the block-to-system schedule on the live batch; then time
+    # a fresh batch with the default schedule (4 chunks per workgroup for every
+    # size class) and one with the tuned schedule, and the tuned one at l + 1
+    _, _, _, sched = run(None, True, False)
+    dt_def, done_def, _, _ = run(None, False, True)
+    dt, done, ticks, _ = run(sched, False, True)
+    dt_l1, done_l1, _, _ = run(sched, False, True, l=l + 1) if l + 1 <= 5 else (None, {}, 0, 0)
     lat = np.array([v[1] for v in done.values()]) * 1e3
     iters = {k: v[0].iters for k, v in done.items()}
     outer = [v[0].outer for v in done.values()]
@@ -326,7 +332,11 @@ def batch_bench(args, plcg, torch, dev, sp):
                               f"FP32-stored p({l})-CG in FP64 refinement (inner tol "
                               f"{args.inner_tol:g}), shifts on [0, 2]"),
                    "converged": ok, "outer_max": max(outer),
-                   "chunks_per_block": cpb, "ticks": ticks,
+                   "schedule_chunks_per_workgroup": {"le8_chunks": sched[0], "le64_chunks": sched[1],
+                                                     "larger": sched[2]},
+                   "default_schedule_solves_per_s": len(done_def) / dt_def,
+                   f"l{l + 1}_solves_per_s": (len(done_l1) / dt_l1) if dt_l1 else None,
+                   "ticks": ticks,
                    "iters_min": min(iters.values()), "iters_max": max(iters.values()),
                    "latency_ms_p50": float(np.percentile(lat, 50)),
                    "latency_ms_p99": float(np.percentile(lat, 99)),

@@ -389,12 +389,24 @@ int32_t plcg_batch_active(const plcg_batch *b);
 /* Workgroups per launch in the current schedule (0 when nothing is admitted). */
 int32_t plcg_batch_grid(const plcg_batch *b);
 
-/* Chunks (512 unknowns) per workgroup in use (after autotuning: the choice made). */
+/* Chunks (512 unknowns) per workgroup in use for the largest systems (more than
+ * 64 chunks); after autotuning, the choice made. */
 int32_t plcg_batch_chunks_per_block(const plcg_batch *b);
 
-/* Autotuner: time `ticks` launches for each candidate workgroup size on the
- * systems currently admitted (the launches advance the solves) and keep the
- * fastest per unknown.  Blocks the host. */
+/* The block-to-system schedule in use: chunks (512 unknowns) per streaming
+ * workgroup for systems of at most 8 chunks (cpb[0]), at most 64 chunks (cpb[1])
+ * and more (cpb[2]); each system also has one owner workgroup. */
+plcg_status plcg_batch_get_schedule(const plcg_batch *b, int32_t *cpb);
+
+/* Set that schedule (each value in 1..1024) for the systems admitted from now
+ * on, e.g. one plcg_batch_autotune chose on an earlier batch of similar systems. */
+plcg_status plcg_batch_set_schedule(plcg_batch *b, const int32_t *cpb);
+
+/* Autotuner of the block-to-system schedule: times `ticks` launches of the
+ * systems currently admitted (the launches advance the solves) for each
+ * candidate (1, 2, 4, 8, 16 chunks per workgroup), first one size for every
+ * size class, then each class in turn from the largest, and keeps the fastest
+ * per active unknown.  Applies to systems admitted later too.  Blocks the host. */
 plcg_status plcg_batch_autotune(plcg_batch *b, int32_t ticks, void *stream);
 
 plcg_status plcg_batch_destroy(plcg_batch *b);

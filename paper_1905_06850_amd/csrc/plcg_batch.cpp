@@ -47,7 +47,9 @@ struct plcg_batch {
   bool mixed = false;                   // FP32-refined: work vectors stored in FP32
   double inner_tol = 1e-3;
   double sigma[kLMax] = {0};
-  int cpb = 4;                          // chunks per streaming workgroup
+  // chunks per streaming workgroup, by the size class of a system (chunks of 512
+  // unknowns: <= kSmallChunks, <= kMediumChunks, more)
+  int cpb[3] = {4, 4, 4};
   // device
   char *arena = nullptr;
   size_t arena_size = 0;
@@ -264,8 +266,12 @@ int32_t upload_operator(const plcg_system_desc *sys, const Layout &L, char *dst,
   return PLCG_OK;
 }
 
+constexpr int kSmallChunks = 8, kMediumChunks = 64;
+int size_class(int nchunks) { return nchunks <= kSmallChunks ? 0 : nchunks <= kMediumChunks ? 1 : 2; }
+
 int blocks_for(const plcg_batch *b, int nchunks) {
-  int nb = (nchunks + b->cpb - 1) / b->cpb;
+  const int c = b->cpb[size_class(nchunks)];
+  int nb = (nchunks + c - 1) / c;
   return std::max(1, std::min(nb, kMaxStream));
 }
 
@@ -403,7 +409,7 @@ plcg_status plcg_batch_create(const plcg_batch_config *cfg, plcg_batch **out) {
   if (b->cfg.max_restarts < 0) b->cfg.max_restarts = 100;
   b->l = cfg->l;
   b->R = b->l - 1 > 2 ? b->l - 1 : 2;
-  b->cpb = cfg->chunks_per_block > 0 ? cfg->chunks_per_block : 4;
+  for (int &c : b->cpb) c = cfg->chunks_per_block > 0 ? cfg->chunks_per_block : 4;
   // Eq. (chebyshev)
   for (int i = 0; i < b->l; ++i)
     b->sigma[i] = 0.5 * (hi + lo) + 0.5 * (hi - lo) * std::cos((2 * i + 1) * M_PI / (2 * b->l));
@@ -682,7 +688,24 @@ int32_t plcg_batch_grid(const plcg_batch *b) {
   return (int32_t)b->sched.size();
 }
 
-int32_t plcg_batch_chunks_per_block(const plcg_batch *b) { return b ? b->cpb : -1; }
+int32_t plcg_batch_chunks_per_block(const plcg_batch *b) { return b ? b->cpb[2] : -1; }
+
+plcg_status plcg_batch_set_schedule(plcg_batch *b, const int32_t *cpb) {
+  if (b == nullptr || cpb == nullptr) return set_last_error(PLCG_E_INVALID, "NULL argument");
+  for (int k = 0; k < 3; ++k)
+    if (cpb[k] < 1 || cpb[k] > kMaxStream)
+      return set_last_error(PLCG_E_INVALID, "chunks per workgroup must be in 1..1024");
+  for (int k = 0; k < 3; ++k) b->cpb[k] = cpb[k];
+  // systems already admitted keep their workgroups until the next autotune;
+  // the choice applies to systems admitted from now on
+  return PLCG_OK;
+}
+
+plcg_status plcg_batch_get_schedule(const plcg_batch *b, int32_t *cpb) {
+  if (b == nullptr || cpb == nullptr) return set_last_error(PLCG_E_INVALID, "NULL argument");
+  for (int k = 0; k < 3; ++k) cpb[k] = b->cpb[k];
+  return PLCG_OK;
+}
 
 plcg_status plcg_batch_autotune(plcg_batch *b, int32_t ticks, void *stream) {
   if (b == nullptr || ticks < 1) return set_last_error(PLCG_E_INVALID, "bad argument");
@@ -692,43 +715,72 @@ plcg_status plcg_batch_autotune(plcg_batch *b, int32_t ticks, void *stream) {
     int32_t e = flush_admissions(b, st);
     if (e != PLCG_OK) return e;
   }
-  const int cands[] = {1, 2, 4, 8, 16};
-  double best = 1e300;
-  int best_c = b->cpb;
   hipEvent_t e0, e1;
   BHIP(hipEventCreate(&e0));
   BHIP(hipEventCreate(&e1));
-  for (int c : cands) {
-    b->cpb = c;
+  // New workgroup counts for every admitted system, in the table and on the device.
+  auto apply = [&]() -> int32_t {
     for (size_t s = 0; s < b->slots.size(); ++s)
       if (b->in_use[s]) {
         b->slots[s].nblocks = blocks_for(b, b->slots[s].nchunks);
-        BHIP(hipMemcpyAsync(b->d_slots + s, &b->slots[s], sizeof(SlotDesc), hipMemcpyHostToDevice, st));
+        BHIP(hipMemcpyAsync(b->d_slots + s, &b->slots[s], sizeof(SlotDesc), hipMemcpyHostToDevice,
+                            st));
       }
     b->dirty = true;
-    int32_t e = run_ticks(b, 2, st);  // settle: the new partial count reaches the owners
+    return PLCG_OK;
+  };
+  // Time `ticks` launches of the live batch under the current choice, per active
+  // unknown (systems that finish between trials shrink the work of later ones).
+  auto trial = [&](double *cost) -> int32_t {
+    int32_t e = apply();
+    if (e == PLCG_OK) e = run_ticks(b, 2, st);   // settle: the new partial count reaches the owners
     if (e != PLCG_OK) return e;
+    int64_t active = 0;
+    for (size_t s = 0; s < b->slots.size(); ++s)
+      if (b->in_use[s] && b->reports[s].phase != kDone) active += b->slots[s].n;
     BHIP(hipEventRecord(e0, st));
     if ((e = run_ticks(b, ticks, st)) != PLCG_OK) return e;
     BHIP(hipEventRecord(e1, st));
     BHIP(hipEventSynchronize(e1));
     float ms = 0.f;
     BHIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      best_c = c;
+    *cost = (double)ms / (double)std::max<int64_t>(active, 1);
+    return PLCG_OK;
+  };
+  const int cands[] = {1, 2, 4, 8, 16};
+  // 1) one size for every class; 2) each class in turn (largest first), the
+  // others held at their best so far.
+  int best_all = b->cpb[2];
+  double best = 1e300;
+  for (int c : cands) {
+    for (int &k : b->cpb) k = c;
+    double cost;
+    int32_t e = trial(&cost);
+    if (e != PLCG_OK) return e;
+    if (cost < best) {
+      best = cost;
+      best_all = c;
     }
+  }
+  for (int &k : b->cpb) k = best_all;
+  for (int cls = 2; cls >= 0; --cls) {
+    int best_c = b->cpb[cls];
+    double best_cls = 1e300;
+    for (int c : cands) {
+      b->cpb[cls] = c;
+      double cost;
+      int32_t e = trial(&cost);
+      if (e != PLCG_OK) return e;
+      if (cost < best_cls) {
+        best_cls = cost;
+        best_c = c;
+      }
+    }
+    b->cpb[cls] = best_c;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->cpb = best_c;
-  for (size_t s = 0; s < b->slots.size(); ++s)
-    if (b->in_use[s]) {
-      b->slots[s].nblocks = blocks_for(b, b->slots[s].nchunks);
-      BHIP(hipMemcpyAsync(b->d_slots + s, &b->slots[s], sizeof(SlotDesc), hipMemcpyHostToDevice, st));
-    }
-  b->dirty = true;
-  return PLCG_OK;
+  return apply();
 }
 
 plcg_status plcg_batch_destroy(plcg_batch *b) {

@@ -149,6 +149,8 @@ SYMBOLS = {
     "plcg_batch_active": (ctypes.c_int32, [_h]),
     "plcg_batch_grid": (ctypes.c_int32, [_h]),
     "plcg_batch_chunks_per_block": (ctypes.c_int32, [_h]),
+    "plcg_batch_get_schedule": (_st, [_h, ctypes.POINTER(ctypes.c_int32)]),
+    "plcg_batch_set_schedule": (_st, [_h, ctypes.POINTER(ctypes.c_int32)]),
     "plcg_batch_autotune": (_st, [_h, ctypes.c_int32, ctypes.c_void_p]),
     "plcg_batch_destroy": (_st, [_h]),
     "plcg_batch_register": (_st, [_h, ctypes.POINTER(plcg_system_desc), ctypes.c_void_p,
@@ -190,6 +192,8 @@ plcg_batch_poll = _lib.plcg_batch_poll
 plcg_batch_active = _lib.plcg_batch_active
 plcg_batch_grid = _lib.plcg_batch_grid
 plcg_batch_chunks_per_block = _lib.plcg_batch_chunks_per_block
+plcg_batch_get_schedule = _lib.plcg_batch_get_schedule
+plcg_batch_set_schedule = _lib.plcg_batch_set_schedule
 plcg_batch_autotune = _lib.plcg_batch_autotune
 plcg_batch_destroy = _lib.plcg_batch_destroy
 plcg_batch_register = _lib.plcg_batch_register
@@ -452,6 +456,17 @@ class Batch:
 
     def chunks_per_block(self):
         return plcg_batch_chunks_per_block(self.handle)
+
+    def schedule(self):
+        """Chunks per streaming workgroup for systems of <= 8, <= 64 and more chunks."""
+        out = (ctypes.c_int32 * 3)()
+        check(plcg_batch_get_schedule(self.handle, out), "plcg_batch_get_schedule")
+        return list(out)
+
+    def set_schedule(self, cpb):
+        """Chunks per workgroup by size class for systems admitted from now on."""
+        check(plcg_batch_set_schedule(self.handle, (ctypes.c_int32 * 3)(*cpb)),
+              "plcg_batch_set_schedule")
 
     def autotune(self, ticks, stream=0):
         check(plcg_batch_autotune(self.handle, int(ticks), stream), "plcg_batch_autotune")

@@ -473,3 +473,63 @@ def test_batch_edge_cases(dev, precision):
     # the original-space residual reported is that of the returned x
     true = np.linalg.norm(s["b"] - A(x["x0"])) / np.linalg.norm(s["b"] - A(x0))
     assert abs(r.true_relres - true) <= 1e-3 * true + 1e-15
+
+
+def test_schedule_by_size_class(dev):
+    """Chunks per workgroup by size class (<= 8 chunks, <= 64, more): the grid of
+    a launch is one owner plus ceil(chunks / cpb) streaming workgroups per
+    system; results under any schedule agree with the default one's and the
+    oracle's; the autotuner picks each class from its candidates."""
+    plcg = _plcg()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    systems = [_system(*s) for s in [((40, 40), 1, 2), ((96, 96), 5, 6), ((300, 200), 21, 22),
+                                     ((12, 10, 9), 7, 8)]]
+    chunks = [-(-s["n"] // 512) for s in systems]
+    oracle = [_oracle(s, 2, 1e-8) for s in systems]
+    for sched in ([1, 4, 16], [2, 1, 8], [16, 16, 1]):
+        batch = plcg.Batch(l=2, max_slots=8, arena_bytes=1 << 30)
+        batch.set_schedule(sched)
+        assert batch.schedule() == sched
+        xs, tickets = [], []
+        for s in systems:
+            bt = torch.from_numpy(s["b"]).to(dev)
+            xt = torch.zeros(s["n"], dtype=torch.float64, device=dev)
+            xs.append((bt, xt))
+            tickets.append(batch.add(s["dims"], bt.data_ptr(), xt.data_ptr(), 1e-8, 20000, stream,
+                                     s["cx"], s["cy"], s["cz"]))
+        batch.step(1, stream)
+        cls = [0 if c <= 8 else 1 if c <= 64 else 2 for c in chunks]
+        assert batch.grid() == sum(1 + -(-c // sched[k]) for c, k in zip(chunks, cls))
+        done = {}
+        for _ in range(2000):
+            batch.step(32, stream)
+            torch.cuda.synchronize()
+            for k, t in enumerate(tickets):
+                if k not in done:
+                    r = batch.poll(t)
+                    if r is not None:
+                        done[k] = r
+            if len(done) == len(tickets):
+                break
+        assert len(done) == len(tickets)
+        for k, s in enumerate(systems):
+            orc, xo, _ = oracle[k]
+            assert done[k].reason == 1 and abs(done[k].iters - orc.iters) <= 2
+            x = xs[k][1].cpu().numpy()
+            assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+        batch.close()
+    with pytest.raises(plcg.PlcgError):
+        plcg.Batch(l=2, max_slots=1, arena_bytes=1 << 20).set_schedule([0, 4, 4])
+    # the autotuner's choice, class by class, from its candidates
+    batch = plcg.Batch(l=2, max_slots=8, arena_bytes=1 << 30)
+    keep = []
+    for s in systems:
+        bt = torch.from_numpy(s["b"]).to(dev)
+        xt = torch.zeros(s["n"], dtype=torch.float64, device=dev)
+        keep.append((bt, xt))
+        batch.add(s["dims"], bt.data_ptr(), xt.data_ptr(), 1e-8, 20000, stream, s["cx"], s["cy"],
+                  s["cz"])
+    batch.autotune(4, stream)
+    assert all(c in (1, 2, 4, 8, 16) for c in batch.schedule())
+    assert batch.chunks_per_block() == batch.schedule()[2]
+    batch.close()
