@@ -201,8 +201,9 @@ def hr_launch(rows, head_method):
     return rows.get(head + (str(head_method[1]) if head != "cg" else ""), {}).get("launch")
 
 
-def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None, csr=None):
+def profile_run(plcg, ctx, methods):
     import torch
+    b, x, sp = ctx["b"], ctx["x"], ctx["sp"]
     n = b.numel()
     y = torch.empty_like(b)
     for _ in range(10):
@@ -210,8 +211,7 @@ def profile_run(plcg, dims, kind, lo, hi, b, x, sp, methods, diag=None, csr=None
     torch.cuda.synchronize()
     for m in methods.split(","):
         method, l = ("cg", 1) if m == "cg" else ("plcg", int(m.lstrip("m")))
-        s = plcg.Solver(kind, dims, method=method, l=l, lmin=lo, lmax=hi,
-                        precision="fp32" if m.startswith("m") else "fp64", diag=diag, csr=csr)
+        s = make_solver(plcg, ctx, method, l, precision="fp32" if m.startswith("m") else "fp64")
         x.zero_()
         s.solve(b.data_ptr(), x.data_ptr(), 1e-30, 100, sp)
         torch.cuda.synchronize()
@@ -496,8 +496,7 @@ def main():
         return
     if args.profile_run:
         ctx = setup_workload(plcg, torch, dev, args.workload)
-        profile_run(plcg, ctx["dims"], ctx["kind"], *ctx["interval"], ctx["b"], ctx["x"],
-                    ctx["sp"], args.methods, ctx["dptr"], ctx["csr_arg"])
+        profile_run(plcg, ctx, args.methods)
         return
 
     methods = [parse_method(m) for m in args.methods.split(",")]
@@ -513,7 +512,9 @@ def main():
     torch.cuda.empty_cache()
     opname = {"2d5": "2D 5-point Dirichlet Poisson", "3d7": "3D 7-point Dirichlet Poisson",
               "diag": "diagonal one-point-stencil toy with the 2D Laplacian's spectrum on",
-              "csr": "2D 5-point Dirichlet Poisson assembled in CSR,"}[kind]
+              "csr": "2D 5-point Dirichlet Poisson assembled in CSR,",
+              "2d5var": "2D variable-coefficient 5-point operator (lognormal(0,1) edges, "
+                        "Jacobi-scaled)"}[kind]
     head = {"plcg": "p", "mixed": "m"}[head_method[0]] + str(head_method[1])
     hl = head_method[1]
     hr = rows[head]
@@ -574,6 +575,14 @@ def setup_workload(plcg, torch, dev, workload):
     dptr = dg.data_ptr() if dg is not None else None
     # a general sparse matrix: the grid operator assembled in CSR
     csr_t, csr_arg, op_bytes = None, None, 0
+    # variable-coefficient stencil: edge coefficients on the device, Jacobi-scaled solve
+    coef_t, coef_arg = None, None
+    if kind == "2d5var":
+        cx, cy, _ = synth.edge_coefficients(dims, wl["coef_seed"])
+        coef_t = [torch.from_numpy(cx).to(dev), torch.from_numpy(cy).to(dev)]
+        coef_arg = (coef_t[0].data_ptr(), coef_t[1].data_ptr(), None)
+        op_bytes = 8 * (len(cx) + len(cy))        # the scaled edge weights, read once per SpMV
+        del cx, cy
     if kind == "csr":
         rp, ci, va = synth.csr_variable_laplacian(dims)
         csr_t = [torch.from_numpy(a).to(dev) for a in (rp, ci, va)]
@@ -590,7 +599,18 @@ def setup_workload(plcg, torch, dev, workload):
         torch.cuda.synchronize()
         op.close()
     return dict(dims=dims, kind=kind, n=n, interval=wl["interval"], tol=wl["tol"], b=b, x=x,
-                sp=sp, dg=dg, dptr=dptr, csr_t=csr_t, csr_arg=csr_arg, op_bytes=op_bytes)
+                sp=sp, dg=dg, dptr=dptr, csr_t=csr_t, csr_arg=csr_arg, op_bytes=op_bytes,
+                coef_t=coef_t, coef_arg=coef_arg)
+
+
+def make_solver(plcg, ctx, method, l, launch="auto", precision="fp64", inner_tol=0.0):
+    """A solver for the workload of ctx (the variable-coefficient stencil Jacobi-scaled)."""
+    lo, hi = ctx["interval"]
+    var = ctx["kind"] == "2d5var"
+    return plcg.Solver("2d5" if var else ctx["kind"], ctx["dims"], method=method, l=max(l, 1),
+                       lmin=lo, lmax=hi, precision=precision, inner_tol=inner_tol,
+                       diag=ctx["dptr"], csr=ctx["csr_arg"], coef=ctx["coef_arg"], jacobi=var,
+                       launch=launch)
 
 
 CACHE_BYTES = 256 << 20     # MI355X memory-side (Infinity) cache
@@ -622,13 +642,12 @@ def run_methods(args, plcg, torch, ctx, methods, steps, warmup, tol=None, inner_
     for method, l in methods:
         name = {"cg": "cg", "plcg": f"p{l}", "mixed": f"m{l}"}[method]
         launch = args.launch
-        if launch == "resident" and (method == "mixed" or not plcg.resident_supported(
-                kind, n, "cg" if method == "cg" else "plcg", max(l, 1))):
+        if launch == "resident" and (method == "mixed" or kind == "2d5var" or
+                                     not plcg.resident_supported(
+                                         kind, n, "cg" if method == "cg" else "plcg", max(l, 1))):
             launch = "auto"
-        s = plcg.Solver(kind, dims, method="cg" if method == "cg" else "plcg", l=max(l, 1),
-                        lmin=lo, lmax=hi, precision="fp32" if method == "mixed" else "fp64",
-                        inner_tol=inner_tol, diag=ctx["dptr"], csr=ctx["csr_arg"],
-                        launch=launch)
+        s = make_solver(plcg, ctx, "cg" if method == "cg" else "plcg", l, launch,
+                        "fp32" if method == "mixed" else "fp64", inner_tol)
         for _ in range(warmup):
             x.zero_()
             s.solve(b.data_ptr(), x.data_ptr(), tol, 100000, sp)
@@ -718,6 +737,8 @@ def roofline(workload, kind, head_method, hr):
         kname = f"plcg_diag_sweep_kernel<{head_method[1]},"
     elif kind == "csr":
         kname = f"plcg_csr_sweep_kernel<{head_method[1]},"
+    elif kind == "2d5var":
+        kname = f"plcg_var_sweep_kernel<{head_method[1]},"
     else:
         kname = f"plcg_sweep_kernel<{head_method[1]},{d3},"
     word = 4 if head_method[0] == "mixed" else 8

@@ -51,6 +51,12 @@ WORKLOADS = {
                         interval=(0.0, 8.0), tol=1e-8),
     "poisson3d256": dict(kind="3d7", dims=(256, 256, 256), rhs="uniform",
                          interval=(0.0, 12.0), tol=1e-10),
+    # the latency- to bandwidth-bound transition: 2D Poisson from 128^2 to 1024^2
+    "poisson128": dict(kind="2d5", dims=(128, 128), rhs="uniform", interval=(0.0, 8.0), tol=1e-8),
+    "poisson256": dict(kind="2d5", dims=(256, 256), rhs="uniform", interval=(0.0, 8.0), tol=1e-8),
+    "poisson512": dict(kind="2d5", dims=(512, 512), rhs="uniform", interval=(0.0, 8.0), tol=1e-8),
+    "poisson1024": dict(kind="2d5", dims=(1024, 1024), rhs="uniform", interval=(0.0, 8.0),
+                        tol=1e-8),
     # the 2048^2 Poisson problem assembled in CSR (a general sparse matrix, as
     # the paper's PETSc runs store it)
     "csr2048": dict(kind="csr", dims=(2048, 2048), rhs="uniform",
