@@ -40,9 +40,93 @@ __global__ __launch_bounds__(kThreads) void cg_var_sweep_a_kernel(CgArgs a) {
   const Grid g{a.n, a.nx, a.ny, a.nz};
   const ChunkOrder order = chunk_order(g, a.d3 != 0, kChunk);
   auto pk1 = [&](int q) { return first ? a.r[q] : a.r[q] + beta * a.p_old[q]; };
+  // p_k at the pair q, q+1 (16-byte loads)
+  auto pk2 = [&](int q, double &v0, double &v1) {
+    Vals<2> rr;
+    rr.load(a.r + q);
+    v0 = rr.v[0];
+    v1 = rr.v[1];
+    if (!first) {
+      Vals<2> po;
+      po.load(a.p_old + q);
+      v0 += beta * po.v[0];
+      v1 += beta * po.v[1];
+    }
+  };
+  const bool fast_rows = (a.nx & 1) == 0;
+  const int plane = a.nx * a.ny;
+  const int lane = threadIdx.x & 63;
   double acc[1] = {0.0};
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
-    const int idx0 = order.phys(it.c) * kChunk + threadIdx.x * kVec;
+    const int base = order.phys(it.c) * kChunk;
+    const int idx0 = base + threadIdx.x * kVec;
+    if (fast_rows && base + kChunk <= a.n) {
+      // A full chunk whose pairs share a row: x-neighbours from the adjacent
+      // lanes, rows, planes and the y / z edge weights with 16-byte loads; each
+      // unknown's terms in the order of VarOp::at.
+      double c0, c1;
+      pk2(idx0, c0, c1);
+      const int x = idx0 % a.nx;
+      const int rest = idx0 / a.nx;
+      const int y = a.d3 ? rest % a.ny : rest;
+      const int zz = a.d3 ? rest / a.ny : 0;
+      double left = lane_prev(c1);
+      double right = lane_next(c0);
+      if (lane == 0 && x > 0) left = pk1(idx0 - 1);
+      if (lane == 63 && x + 2 < a.nx) right = pk1(idx0 + 2);
+      const int xe = rest * (a.nx + 1) + x;
+      const int ye = idx0 + zz * a.nx;
+      double s0 = 0.0, s1 = 0.0;
+      if (x > 0) s0 += op.sx[xe] * left;
+      s0 += op.sx[xe + 1] * c1;                      // x + 1 < nx: nx is even
+      s1 += op.sx[xe + 1] * c0;
+      if (x + 2 < a.nx) s1 += op.sx[xe + 2] * right;
+      double u0, u1;
+      if (y > 0) {
+        Vals<2> w;
+        w.load(op.sy + ye);
+        pk2(idx0 - a.nx, u0, u1);
+        s0 += w.v[0] * u0;
+        s1 += w.v[1] * u1;
+      }
+      if (y < a.ny - 1) {
+        Vals<2> w;
+        w.load(op.sy + ye + a.nx);
+        pk2(idx0 + a.nx, u0, u1);
+        s0 += w.v[0] * u0;
+        s1 += w.v[1] * u1;
+      }
+      if (a.d3 && zz > 0) {
+        Vals<2> w;
+        w.load(op.sz + idx0);
+        pk2(idx0 - plane, u0, u1);
+        s0 += w.v[0] * u0;
+        s1 += w.v[1] * u1;
+      }
+      if (a.d3 && zz < a.nz - 1) {
+        Vals<2> w;
+        w.load(op.sz + idx0 + plane);
+        pk2(idx0 + plane, u0, u1);
+        s0 += w.v[0] * u0;
+        s1 += w.v[1] * u1;
+      }
+      Vals<2> pn, qv;
+      pn.v[0] = c0;
+      pn.v[1] = c1;
+      if (op.dg != nullptr) {
+        Vals<2> dv;
+        dv.load(op.dg + idx0);
+        qv.v[0] = dv.v[0] * c0 - s0;
+        qv.v[1] = dv.v[1] * c1 - s1;
+      } else {
+        qv.v[0] = c0 - s0;
+        qv.v[1] = c1 - s1;
+      }
+      pn.template st<NTS>(a.p_new + idx0);
+      qv.template st<NTS>(a.q + idx0);
+      acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
+      continue;
+    }
     if (idx0 + 1 < a.n) {
       Vals<2> pn, qv;
 #pragma unroll
