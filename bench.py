@@ -382,7 +382,12 @@ def serve_bench(args, plcg, torch, dev, sp):
         arrivals = np.cumsum(gaps) - gaps[0]
         pick = ((synth.uniform(n, 902 + int(rate)) + 1) / 2 * len(pool)).astype(int) % len(pool)
         ptol = ((synth.uniform(n, 903 + int(rate)) + 1) / 2 * 3).astype(int) % 3
-        reqs = [(float(arrivals[k]), int(pick[k]), 200000, tols[ptol[k]]) for k in range(n)]
+        # each request's solution goes to its own device buffer (allocated before the run)
+        outs = [torch.empty(int(np.prod(pool[int(pick[k])])), dtype=torch.float64, device=dev)
+                for k in range(n)]
+        reqs = [(float(arrivals[k]), int(pick[k]), 200000, tols[ptol[k]], outs[k].data_ptr())
+                for k in range(n)]
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = batch.serve(ops, [b.data_ptr() for b in bs], reqs, args.serve_ticks,
                           args.serve_time_limit, sp)
@@ -391,6 +396,7 @@ def serve_bench(args, plcg, torch, dev, sp):
         lat = np.array([out[k].finish_s - reqs[k][0] for k in done]) * 1e3
         wait = np.array([out[k].admit_s - reqs[k][0] for k in done]) * 1e3
         ok = sum(1 for k in done if out[k].result.reason == 1)
+        del outs
         last = max(out[k].finish_s for k in done) if done else wall
         results[f"{rate:g}/s"] = {
             "requests": n, "completed": len(done), "converged": ok,
@@ -419,7 +425,8 @@ def serve_bench(args, plcg, torch, dev, sp):
                    "method": (f"p({args.batch_l})-CG" if args.batch_precision == "fp64" else
                               f"FP32-stored p({args.batch_l})-CG in FP64 refinement (inner tol "
                               f"{args.inner_tol:g})")
-                             + ", continuous batching, admission by HBM footprint",
+                             + ", continuous batching, admission by HBM footprint, "
+                               "solutions into per-request buffers",
                    "pool": [list(d) for d in pool], "slots": args.serve_slots,
                    "arena_gb": args.serve_arena_gb, "runs": results},
     }

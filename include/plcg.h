@@ -435,7 +435,8 @@ typedef struct {
   double *x;              /* device, n doubles of the request's system (16-byte aligned), or
                              NULL: receives the solution.  Set to 0 (x0) when the request is
                              admitted, written by the solve, and final when out[k].finish_s
-                             is set; the caller keeps ownership.  NULL: the solution stays
+                             is set; the caller keeps ownership.  Requests in flight at the
+                             same time need distinct buffers.  NULL: the solution stays
                              inside the batch and is released with the slot. */
 } plcg_request;
 
