@@ -168,3 +168,31 @@ def test_create_rejects_bad_edge_coefficients(kind, nz, coef, jacobi):
         plcg.PLCG_E_INVALID
     assert not h.value
     assert plcg.plcg_last_error()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every structure of include/plcg.h has the size and field offsets of its
+    ctypes mirror in the binding (a plain C program built with the host
+    compiler prints them)."""
+    import shutil
+    import subprocess
+    from paper_1905_06850_amd import plcg
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    exe = tmp_path / "abi_layout"
+    src = os.path.join(ROOT, "tests", "c", "abi_layout.c")
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    seen = set()
+    for line in out.splitlines():
+        parts = line.split()
+        cls = getattr(plcg, parts[0])
+        seen.add(parts[0])
+        if parts[1] == "size":
+            assert ctypes.sizeof(cls) == int(parts[2]), line
+        else:
+            assert getattr(cls, parts[1]).offset == int(parts[2]), line
+    assert seen == {"plcg_operator_desc", "plcg_config", "plcg_result", "plcg_batch_config",
+                    "plcg_system_desc", "plcg_request", "plcg_request_outcome"}
