@@ -781,15 +781,52 @@ struct Sweep {
   static constexpr bool NTL = (H & kHintLoads) != 0;
   static constexpr bool NTS = (H & kHintStores) != 0;
 
+  // The vectors a steady-state step reads at its own unknowns (the operator
+  // reads its neighbours itself), loaded ahead of the step: the sweeps of
+  // l = 2, 3 request their first chunk's before they read the scalar state.
+  // For l <= 3 (no older z^{(l)} vectors are read).
+  template <int V>
+  struct Loads {
+    Vals<V, S> zc, zp, ck[L], pk[L], pv, xv, qv;
+  };
+  template <int V>
+  __device__ static inline void steady_load(const Args &a, int idx, int t, Loads<V> &d) {
+    static_assert(L <= 3, "older z^(l) vectors are not preloaded");
+    d.zc.load(a.zl[0] + idx);
+    d.zp.template ld<NTL>(a.zl[1] + idx);
+#pragma unroll
+    for (int k = L - 1; k >= 0; --k) {
+      d.ck[k].template ld<NTL>(a.zk_cur[k] + idx);
+      if (t >= 1) d.pk[k].template ld<NTL>(a.zk_prev[k] + idx); else d.pk[k].zero();
+    }
+    if (t >= 1) {
+      d.pv.template ld<NTL>(a.p + idx);
+      if constexpr (!PAIR) {
+        d.xv.template ld<NTL>(a.x + idx);
+      } else if (a.xmode != kXSkip) {
+        d.xv.template ld<NTL>(a.x + idx);
+        if (a.xmode == kXPair) d.qv.template ld<NTL>(a.p_out + idx);
+      }
+    }
+  }
+
   // Steady state, i >= l: K1 (SpMV of z^{(l)}_i), K4 (all basis recurrences,
   // Eqs. all_z_rec2 and specific_z_rec), K6 (p_t, x_t; Eqs. pdir, x_a2) and
-  // K5 (the l+1 products that start column i+1 of G).
-  template <int V, bool FAST>
+  // K5 (the l+1 products that start column i+1 of G).  PRE: the vectors read at
+  // the step's own unknowns come from *pre (steady_load) instead of memory;
+  // the arithmetic is the same.
+  template <int V, bool FAST, bool PRE = false>
   __device__ static inline void steady(const Args &a, const Op &op, int idx, int t,
-                                       const Coef<L> &cf, double (&acc)[ND]) {
+                                       const Coef<L> &cf, double (&acc)[ND],
+                                       const Loads<V> *pre = nullptr) {
     Vals<V, S> zc, zp;
-    zc.load(a.zl[0] + idx);
-    zp.template ld<NTL>(a.zl[1] + idx);
+    if constexpr (PRE) {
+      zc = pre->zc;
+      zp = pre->zp;
+    } else {
+      zc.load(a.zl[0] + idx);
+      zp.template ld<NTL>(a.zl[1] + idx);
+    }
     double w[V];
     op.template apply<V, FAST>(a.zl[0], idx, zc, w);
     double zn[V];
@@ -810,8 +847,13 @@ struct Sweep {
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
       Vals<V, S> ck, pk;
-      ck.template ld<NTL>(a.zk_cur[k] + idx);
-      if (t >= 1) pk.template ld<NTL>(a.zk_prev[k] + idx); else pk.zero();
+      if constexpr (PRE) {
+        ck = pre->ck[k];
+        pk = pre->pk[k];
+      } else {
+        ck.template ld<NTL>(a.zk_cur[k] + idx);
+        if (t >= 1) pk.template ld<NTL>(a.zk_prev[k] + idx); else pk.zero();
+      }
       Vals<V, S> nk;
       const double sk = cf.sig[k] - cf.gam;
 #pragma unroll
@@ -833,8 +875,13 @@ struct Sweep {
       for (int v = 0; v < V; ++v) pv.v[v] = vt[v] * cf.inv_eta;
     } else if constexpr (!PAIR) {
       Vals<V, S> xv;
-      pv.template ld<NTL>(a.p + idx);
-      xv.template ld<NTL>(a.x + idx);
+      if constexpr (PRE) {
+        pv = pre->pv;
+        xv = pre->xv;
+      } else {
+        pv.template ld<NTL>(a.p + idx);
+        xv.template ld<NTL>(a.x + idx);
+      }
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         xv.v[v] = fma(cf.zm1, pv.v[v], xv.v[v]);
@@ -842,15 +889,15 @@ struct Sweep {
       }
       xv.template st<NTS>(a.x + idx);
     } else {
-      pv.template ld<NTL>(a.p + idx);
+      if constexpr (PRE) pv = pre->pv; else pv.template ld<NTL>(a.p + idx);
       if (a.xmode != kXSkip) {
         Vals<V, S> xv;
-        xv.template ld<NTL>(a.x + idx);
+        if constexpr (PRE) xv = pre->xv; else xv.template ld<NTL>(a.x + idx);
         if (a.xmode == kXPair) {
           // x_{t-1} = x_{t-2} + zeta_{t-2} p_{t-2}, rounded to S as if stored;
           // p_{t-2} sits in the buffer that receives p_t below
           Vals<V, S> qv;
-          qv.template ld<NTL>(a.p_out + idx);
+          if constexpr (PRE) qv = pre->qv; else qv.template ld<NTL>(a.p_out + idx);
 #pragma unroll
           for (int v = 0; v < V; ++v) xv.v[v] = (double)(S)fma(cf.zm2, qv.v[v], xv.v[v]);
         }
