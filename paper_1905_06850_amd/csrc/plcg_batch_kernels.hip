@@ -26,10 +26,9 @@
 namespace plcg {
 
 __device__ inline void bstate_load(const BatchState *st, BatchState *sh) {
-  const double *src = reinterpret_cast<const double *>(st);
-  double *dst = reinterpret_cast<double *>(sh);
-  for (int k = threadIdx.x; k < (int)(sizeof(BatchState) / 8); k += kThreads) dst[k] = src[k];
-  __syncthreads();
+  WordRegs<BatchState> r;
+  words_fetch(st, r);
+  words_put(r, sh);
 }
 __device__ inline void bstate_store(const BatchState *sh, BatchState *st) {
   __syncthreads();

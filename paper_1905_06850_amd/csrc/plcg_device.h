@@ -312,18 +312,55 @@ __device__ inline void block_sum(const double (&acc)[ND], double *lds /* [4][ND]
   __syncthreads();
 }
 
-// Grid-wide sums of the previous launch's partials, in a fixed order.
+// Grid-wide sums of the previous launch's partials, in a fixed order: thread j
+// adds partials j, j + kThreads, ... of each product from zero, then the
+// workgroup sums the threads' results.  The loads are split from the sums so a
+// caller can request the partials together with its other loads (all of a
+// thread's loads in flight at once: one memory round trip, not one per load).
+constexpr int kPartPer = kMaxStream / kThreads;   // partials per product and thread
+static_assert(kMaxStream % kThreads == 0, "partials split evenly over the threads");
+
 template <int ND>
-__device__ inline void sum_partials(const double *part, int nparts, int pstride, double *lds,
-                                    double *out) {
+struct PartRegs {
+  double v[ND][kPartPer];
+};
+
+template <int ND>
+__device__ inline void partials_fetch(const double *part, int nparts, int pstride,
+                                      PartRegs<ND> &r) {
+#pragma unroll
+  for (int m = 0; m < ND; ++m)
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j) {
+      const int b = threadIdx.x + j * kThreads;
+      r.v[m][j] = b < nparts ? part[m * pstride + b] : 0.0;
+    }
+}
+
+template <int ND>
+__device__ inline void partials_sum(const PartRegs<ND> &r, const double *part, int nparts,
+                                    int pstride, double *lds, double *out) {
   double s[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kThreads) acc += part[m * pstride + b];
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j)
+      if ((int)threadIdx.x + j * kThreads < nparts) acc += r.v[m][j];
+    // More partials than kMaxStream never occur; kept so any count sums right.
+    for (int b = threadIdx.x + kPartPer * kThreads; b < nparts; b += kThreads)
+      acc += part[m * pstride + b];
     s[m] = acc;
   }
   block_sum<ND>(s, lds, out);
+}
+
+template <int ND>
+__device__ inline void sum_partials(const double *part, int nparts, int pstride, double *lds,
+                                    double *out) {
+  PartRegs<ND> r;
+  partials_fetch<ND>(part, nparts, pstride, r);
+  partials_sum<ND>(r, part, nparts, pstride, lds, out);
 }
 
 // This workgroup's partials (index = streaming workgroup number).
@@ -334,12 +371,41 @@ __device__ inline void store_partials(const double (&acc)[ND], double *part, int
   if (threadIdx.x < ND) part[threadIdx.x * pstride + slot] = blk[threadIdx.x];
 }
 
-// Copy the scalar state between global memory and LDS (all threads).
-__device__ inline void state_load(const DevState *st, DevState *sh) {
-  const double *src = reinterpret_cast<const double *>(st);
-  double *dst = reinterpret_cast<double *>(sh);
-  for (int k = threadIdx.x; k < (int)(sizeof(DevState) / 8); k += kThreads) dst[k] = src[k];
+// Copy a scalar state (DevState, BatchState) between global memory and LDS (all
+// threads).  Each thread requests its words before it writes any of them.
+template <typename T>
+struct WordRegs {
+  static_assert(sizeof(T) % 8 == 0, "a state is copied in 8-byte words");
+  static constexpr int kWords = (int)(sizeof(T) / 8);
+  static constexpr int kPer = (kWords + kThreads - 1) / kThreads;
+  double v[kPer];
+};
+
+template <typename T>
+__device__ inline void words_fetch(const T *src, WordRegs<T> &r) {
+  const double *s = reinterpret_cast<const double *>(src);
+#pragma unroll
+  for (int j = 0; j < WordRegs<T>::kPer; ++j) {
+    const int k = threadIdx.x + j * kThreads;
+    if (k < WordRegs<T>::kWords) r.v[j] = s[k];
+  }
+}
+
+template <typename T>
+__device__ inline void words_put(const WordRegs<T> &r, T *dst) {
+  double *d = reinterpret_cast<double *>(dst);
+#pragma unroll
+  for (int j = 0; j < WordRegs<T>::kPer; ++j) {
+    const int k = threadIdx.x + j * kThreads;
+    if (k < WordRegs<T>::kWords) d[k] = r.v[j];
+  }
   __syncthreads();
+}
+
+__device__ inline void state_load(const DevState *st, DevState *sh) {
+  WordRegs<DevState> r;
+  words_fetch(st, r);
+  words_put(r, sh);
 }
 __device__ inline void state_store(const DevState *sh, DevState *st) {
   __syncthreads();

@@ -392,9 +392,13 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
-  state_load(a.st_in, &sh);
+  WordRegs<DevState> sw;
+  PartRegs<1> pr;
+  words_fetch(a.st_in, sw);
+  partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, pr);
+  words_put(sw, &sh);
   if (sh.status == kRunning) {
-    sum_partials<1>(a.part_in, a.nparts_in, a.pstride, lds, red);
+    partials_sum<1>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
     if (threadIdx.x == 0) {
       const double pq = red[0];
       if (!(isfinite(pq) && pq > 0.0)) {

@@ -28,9 +28,16 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   const bool owner = blockIdx.x == 0;
   const bool engine = (L == 1) || owner;
   if (engine) {
-    state_load(a.st_in, &sh);
-    if (a.i >= 1 && sh.status == kRunning && a.nparts_in > 0) {
-      sum_partials<ND>(a.part_in, a.nparts_in, a.pstride, lds, red);
+    // The state and the previous sweep's partials are requested together (the
+    // partials are read before the status says whether they are needed).
+    const bool sums = a.i >= 1 && a.nparts_in > 0;
+    WordRegs<DevState> sw;
+    PartRegs<ND> pr;
+    words_fetch(a.st_in, sw);
+    if (sums) partials_fetch<ND>(a.part_in, a.nparts_in, a.pstride, pr);
+    words_put(sw, &sh);
+    if (sums && sh.status == kRunning) {
+      partials_sum<ND>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
       if (threadIdx.x == 0) engine_column_l<L>(sh, red, a.i, owner ? a.hist : nullptr);
       __syncthreads();
     }
@@ -110,9 +117,14 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
 //
 // Prologue of sweep A, every workgroup; returns false when nothing is streamed.
 __device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds, double *red) {
-  state_load(a.st_in, &sh);
-  if (a.k >= 1 && sh.status == kRunning) {
-    sum_partials<1>(a.part_in, a.nparts_in, a.pstride, lds, red);
+  const bool sums = a.k >= 1;
+  WordRegs<DevState> sw;
+  PartRegs<1> pr;
+  words_fetch(a.st_in, sw);
+  if (sums) partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, pr);
+  words_put(sw, &sh);
+  if (sums && sh.status == kRunning) {
+    partials_sum<1>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
     if (threadIdx.x == 0) {
       const double rho = red[0];
       sh.cols = a.k;
