@@ -20,9 +20,12 @@ SOURCES = [os.path.join(HERE, "csrc", "plcg_kernels.hip"),
            os.path.join(HERE, "csrc", "plcg_serve.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Packed FP32 instructions are disabled for every HIP translation unit.
+# Packed FP32 instructions are disabled for every HIP translation unit.  No
+# floating-point contraction: every fused multiply-add is an fma() in the source,
+# so a value's roundings follow from the source alone, whatever the compiler
+# schedules (the same in every kernel and code path that computes it).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off",
          "-Wall", "-Wno-unused-command-line-argument",
          "-I", os.path.join(ROOT, "include")]
 

@@ -290,15 +290,15 @@ __global__ __launch_bounds__(kThreads) void batch_tick_kernel(BatchArgs a) {
       if (phase == kInit) {
         S.x[p] = S.x[p] / S.dis[p];
       } else if (phase == kResid || phase == kFinal) {
-        const double r = S.dis[p] * S.b[p] - op.at(S.x, p);
+        const double r = fma(S.dis[p], S.b[p], -op.at(S.x, p));
         if (!kMixed && phase == kResid) r0[p] = (ST)r;
-        acc[0] += r * r;
+        acc[0] = fma(r, r, acc[0]);
         const double ro = r / S.dis[p];       // D^{1/2} r~ = b - A x
-        acc[1] += ro * ro;
+        acc[1] = fma(ro, ro, acc[1]);
       } else if (phase == kScale) {
         // z_0 = r / ||r||; the FP32 path recomputes r in FP64 (the same expression as
         // kResid) instead of keeping an FP64 copy, and clears the correction.
-        const double r = kMixed ? S.dis[p] * S.b[p] - op.at(S.x, p) : (double)r0[p];
+        const double r = kMixed ? fma(S.dis[p], S.b[p], -op.at(S.x, p)) : (double)r0[p];
         const ST z = (ST)(r * inv_beta);
         r0[p] = z;
         v0[p] = z;

@@ -263,10 +263,10 @@ __device__ inline void apply_stencil(const S *z, int idx, const Vals<V, S> &zc, 
       }
     }
 #pragma unroll
-    for (int k = 0; k < V; ++k) w[k] = diag * zc.v[k] - s[k];
+    for (int k = 0; k < V; ++k) w[k] = fma(diag, zc.v[k], -s[k]);
   } else {
 #pragma unroll
-    for (int v = 0; v < V; ++v) w[v] = diag * zc.v[v] - neighbour_sum<D3, S>(z, idx + v, g);
+    for (int v = 0; v < V; ++v) w[v] = fma(diag, zc.v[v], -neighbour_sum<D3, S>(z, idx + v, g));
   }
 }
 
@@ -317,6 +317,9 @@ __device__ inline void block_sum(const double (&acc)[ND], double *lds /* [4][ND]
 // workgroup sums the threads' results.  The loads are split from the sums so a
 // caller can request the partials together with its other loads (all of a
 // thread's loads in flight at once: one memory round trip, not one per load).
+// The loads are unconditional - every partial buffer holds ND rows of at least
+// kMaxStream entries, pstride apart - so the compiler can count them exactly
+// and wait for an earlier load without waiting for these.
 constexpr int kPartPer = kMaxStream / kThreads;   // partials per product and thread
 static_assert(kMaxStream % kThreads == 0, "partials split evenly over the threads");
 
@@ -331,15 +334,18 @@ __device__ inline void partials_fetch(const double *part, int nparts, int pstrid
 #pragma unroll
   for (int m = 0; m < ND; ++m)
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) {
-      const int b = threadIdx.x + j * kThreads;
-      r.v[m][j] = b < nparts ? part[m * pstride + b] : 0.0;
-    }
+    for (int j = 0; j < kPartPer; ++j) r.v[m][j] = part[m * pstride + threadIdx.x + j * kThreads];
 }
 
 template <int ND>
-__device__ inline void partials_sum(const PartRegs<ND> &r, const double *part, int nparts,
-                                    int pstride, double *lds, double *out) {
+__device__ inline void partials_sum(PartRegs<ND> r, const double *part, int nparts, int pstride,
+                                    double *lds, double *out) {
+  // The values are taken as opaque here, so no addition is moved up to where
+  // the loads were issued (the workgroup would wait for them there).
+#pragma unroll
+  for (int m = 0; m < ND; ++m)
+#pragma unroll
+    for (int j = 0; j < kPartPer; ++j) asm volatile("" : "+v"(r.v[m][j]));
   double s[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) {
@@ -372,7 +378,8 @@ __device__ inline void store_partials(const double (&acc)[ND], double *part, int
 }
 
 // Copy a scalar state (DevState, BatchState) between global memory and LDS (all
-// threads).  Each thread requests its words before it writes any of them.
+// threads).  Each thread requests its words before it writes any of them; the
+// loads are unconditional (a thread past the end reads the last word again).
 template <typename T>
 struct WordRegs {
   static_assert(sizeof(T) % 8 == 0, "a state is copied in 8-byte words");
@@ -387,7 +394,7 @@ __device__ inline void words_fetch(const T *src, WordRegs<T> &r) {
 #pragma unroll
   for (int j = 0; j < WordRegs<T>::kPer; ++j) {
     const int k = threadIdx.x + j * kThreads;
-    if (k < WordRegs<T>::kWords) r.v[j] = s[k];
+    r.v[j] = s[k < WordRegs<T>::kWords ? k : WordRegs<T>::kWords - 1];
   }
 }
 
@@ -675,11 +682,11 @@ struct CsrOp {
     if (ell_k > 0) {
       for (int j = 0; j < ell_k; ++j) {
         const size_t e = (size_t)j * ell_ld + p;
-        s += va[e] * (double)z[ci[e]];
+        s = fma(va[e], (double)z[ci[e]], s);
       }
     } else {
       const int64_t e = rp[p + 1];
-      for (int64_t j = rp[p]; j < e; ++j) s += va[j] * (double)z[ci[j]];
+      for (int64_t j = rp[p]; j < e; ++j) s = fma(va[j], (double)z[ci[j]], s);
     }
     return s;
   }
@@ -709,7 +716,7 @@ struct CsrOp {
           for (int v = 0; v < V; ++v) c[v] = ci[e + v];
         }
 #pragma unroll
-        for (int v = 0; v < V; ++v) w[v] += vv.v[v] * (double)z[c[v]];
+        for (int v = 0; v < V; ++v) w[v] = fma(vv.v[v], (double)z[c[v]], w[v]);
       }
     } else {
 #pragma unroll
@@ -738,18 +745,18 @@ struct VarOp {
     const int y = d3 ? rest % ny : rest;
     double s = 0.0;
     const int xe = rest * (nx + 1) + x;          // edge left of p in its row
-    if (x > 0) s += sx[xe] * get(p - 1);
-    if (x < nx - 1) s += sx[xe + 1] * get(p + 1);
+    if (x > 0) s = fma(sx[xe], get(p - 1), s);
+    if (x < nx - 1) s = fma(sx[xe + 1], get(p + 1), s);
     const int z = d3 ? rest / ny : 0;
     const int ye = p + z * nx;                   // edge below p in its column
-    if (y > 0) s += sy[ye] * get(p - nx);
-    if (y < ny - 1) s += sy[ye + nx] * get(p + nx);
+    if (y > 0) s = fma(sy[ye], get(p - nx), s);
+    if (y < ny - 1) s = fma(sy[ye + nx], get(p + nx), s);
     if (d3) {
       const int plane = nx * ny;
-      if (z > 0) s += sz[p] * get(p - plane);
-      if (z < nz - 1) s += sz[p + plane] * get(p + plane);
+      if (z > 0) s = fma(sz[p], get(p - plane), s);
+      if (z < nz - 1) s = fma(sz[p + plane], get(p + plane), s);
     }
-    return (dg != nullptr ? dg[p] * up : up) - s;
+    return dg != nullptr ? fma(dg[p], up, -s) : up - s;
   }
   template <typename T>
   __device__ inline double at(const T *u, int p) const {
@@ -781,8 +788,8 @@ struct VarOp {
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         s[k] = 0.0;
-        if (x + k > 0) s[k] += sx[xe + k] * (k > 0 ? zc.v[k - 1] : left);
-        if (x + k < nx - 1) s[k] += sx[xe + k + 1] * (k < V - 1 ? zc.v[k + 1] : right);
+        if (x + k > 0) s[k] = fma(sx[xe + k], k > 0 ? zc.v[k - 1] : left, s[k]);
+        if (x + k < nx - 1) s[k] = fma(sx[xe + k + 1], k < V - 1 ? zc.v[k + 1] : right, s[k]);
       }
       if (y > 0) {
         Vals<V, S> u;
@@ -820,7 +827,7 @@ struct VarOp {
         Vals<V, double> dv;
         dv.load(dg + idx);
 #pragma unroll
-        for (int k = 0; k < V; ++k) w[k] = dv.v[k] * zc.v[k] - s[k];
+        for (int k = 0; k < V; ++k) w[k] = fma(dv.v[k], zc.v[k], -s[k]);
       } else {
 #pragma unroll
         for (int k = 0; k < V; ++k) w[k] = zc.v[k] - s[k];
@@ -849,8 +856,8 @@ struct Sweep {
 
   // The vectors a steady-state step reads at its own unknowns (the operator
   // reads its neighbours itself), loaded ahead of the step: the sweeps of
-  // l = 2, 3 request their first chunk's before they read the scalar state.
-  // For l <= 3 (no older z^{(l)} vectors are read).
+  // l <= 3 request their first chunk's before they read the scalar state (no
+  // older z^{(l)} vectors are read for these l).
   template <int V>
   struct Loads {
     Vals<V, S> zc, zp, ck[L], pk[L], pv, xv, qv;
@@ -897,7 +904,8 @@ struct Sweep {
     op.template apply<V, FAST>(a.zl[0], idx, zc, w);
     double zn[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) zn[v] = ((w[v] - cf.gam * zc.v[v]) - cf.dm1 * zp.v[v]) * cf.inv_del;
+    for (int v = 0; v < V; ++v)
+      zn[v] = fma(-cf.dm1, zp.v[v], fma(-cf.gam, zc.v[v], w[v])) * cf.inv_del;
     // Products with older z^{(l)} vectors, read before zl_out (the slot of
     // z^{(l)}_{i+1-R}) is overwritten below.
 #pragma unroll
@@ -905,7 +913,7 @@ struct Sweep {
       Vals<V, S> zh;
       zh.template ld<NTL>(a.zl[L - 1 - m] + idx);
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[m] += zn[v] * zh.v[v];
+      for (int v = 0; v < V; ++v) acc[m] = fma(zn[v], zh.v[v], acc[m]);
     }
     double above[V], vt[V], vnew[V];
 #pragma unroll
@@ -923,7 +931,8 @@ struct Sweep {
       Vals<V, S> nk;
       const double sk = cf.sig[k] - cf.gam;
 #pragma unroll
-      for (int v = 0; v < V; ++v) nk.v[v] = ((above[v] + sk * ck.v[v]) - cf.dm1 * pk.v[v]) * cf.inv_del;
+      for (int v = 0; v < V; ++v)
+        nk.v[v] = fma(-cf.dm1, pk.v[v], fma(sk, ck.v[v], above[v])) * cf.inv_del;
       nk.template st<NTS>(a.zk_prev[k] + idx);
 #pragma unroll
       for (int v = 0; v < V; ++v) above[v] = ck.v[v];
@@ -951,7 +960,7 @@ struct Sweep {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         xv.v[v] = fma(cf.zm1, pv.v[v], xv.v[v]);
-        pv.v[v] = (vt[v] - cf.dm1 * pv.v[v]) * cf.inv_eta;
+        pv.v[v] = fma(-cf.dm1, pv.v[v], vt[v]) * cf.inv_eta;
       }
       xv.template st<NTS>(a.x + idx);
     } else {
@@ -972,7 +981,7 @@ struct Sweep {
         xv.template st<NTS>(a.x + idx);
       }
 #pragma unroll
-      for (int v = 0; v < V; ++v) pv.v[v] = (vt[v] - cf.dm1 * pv.v[v]) * cf.inv_eta;
+      for (int v = 0; v < V; ++v) pv.v[v] = fma(-cf.dm1, pv.v[v], vt[v]) * cf.inv_eta;
     }
     pv.template st<NTS>((PAIR ? a.p_out : a.p) + idx);
     Vals<V, S> out;
@@ -981,10 +990,10 @@ struct Sweep {
     out.template st<NTS>(a.zl_out + idx);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      acc[0] += zn[v] * vnew[v];                    // (z_{i+1}, v_{t+1})
-      acc[L] += zn[v] * zn[v];                      // (z_{i+1}, z_{i+1})
-      if (L >= 2) acc[L - 1] += zn[v] * zc.v[v];    // (z_{i+1}, z_i)
-      if (L >= 3) acc[L - 2] += zn[v] * zp.v[v];    // (z_{i+1}, z_{i-1})
+      acc[0] = fma(zn[v], vnew[v], acc[0]);                     // (z_{i+1}, v_{t+1})
+      acc[L] = fma(zn[v], zn[v], acc[L]);                       // (z_{i+1}, z_{i+1})
+      if (L >= 2) acc[L - 1] = fma(zn[v], zc.v[v], acc[L - 1]); // (z_{i+1}, z_i)
+      if (L >= 3) acc[L - 2] = fma(zn[v], zp.v[v], acc[L - 2]); // (z_{i+1}, z_{i-1})
     }
   }
 
@@ -999,7 +1008,7 @@ struct Sweep {
     op.template apply<V, FAST>(a.zl[0], idx, zc, w);
     Vals<V, S> zn;
 #pragma unroll
-    for (int v = 0; v < V; ++v) zn.v[v] = w[v] - sigma_i * zc.v[v];
+    for (int v = 0; v < V; ++v) zn.v[v] = fma(-sigma_i, zc.v[v], w[v]);
 #pragma unroll
     for (int m = 1; m <= L - 2; ++m) {
       const int h = L - 1 - m;
@@ -1007,21 +1016,21 @@ struct Sweep {
         Vals<V, S> zh;
         zh.template ld<NTL>(a.zl[h] + idx);
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[m] += zn.v[v] * zh.v[v];
+        for (int v = 0; v < V; ++v) acc[m] = fma(zn.v[v], zh.v[v], acc[m]);
       }
     }
     if (a.v0 != nullptr) {
       Vals<V, S> vz;
       vz.template ld<NTL>(a.v0 + idx);
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[0] += zn.v[v] * vz.v[v];
+      for (int v = 0; v < V; ++v) acc[0] = fma(zn.v[v], vz.v[v], acc[0]);
     }
     zn.template st<NTS>(a.zl_out + idx);
     if (a.copy_dst != nullptr) zn.template st<NTS>(a.copy_dst + idx);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      acc[L] += zn.v[v] * zn.v[v];
-      if (L >= 2) acc[L - 1] += zn.v[v] * zc.v[v];
+      acc[L] = fma(zn.v[v], zn.v[v], acc[L]);
+      if (L >= 2) acc[L - 1] = fma(zn.v[v], zc.v[v], acc[L - 1]);
     }
   }
 

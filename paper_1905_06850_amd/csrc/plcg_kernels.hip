@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
   const bool fast_rows = (a.nx & 1) == 0;
   double acc[1] = {0.0};
   // p_k at index q, formed on the fly from r and p_{k-1}
-  auto pk1 = [&](int q) { return first ? a.r[q] : a.r[q] + beta * a.p_old[q]; };
+  auto pk1 = [&](int q) { return first ? a.r[q] : fma(beta, a.p_old[q], a.r[q]); };
   auto pk2 = [&](int q, double &v0, double &v1) {
     Vals<2> rr;
     rr.load(a.r + q);
@@ -73,8 +73,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
     if (!first) {
       Vals<2> po;
       po.load(a.p_old + q);
-      v0 += beta * po.v[0];
-      v1 += beta * po.v[1];
+      v0 = fma(beta, po.v[0], v0);
+      v1 = fma(beta, po.v[1], v1);
     }
   };
   if (D3 && a.zseg > 0) {
@@ -120,8 +120,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       v0 = r.v[0];
       v1 = r.v[1];
       if (!first) {
-        v0 += beta * po.v[0];
-        v1 += beta * po.v[1];
+        v0 = fma(beta, po.v[0], v0);
+        v1 = fma(beta, po.v[1], v1);
       }
     };
     for (ChunkIter it = xcd_chunks(nitems, a.nstream, 0); it.c < it.end; it.c += it.step) {
@@ -143,8 +143,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
         if (zz + 1 < g.nz) form(nxt.r, nxt.p, n0, n1);
         double left = lane_prev(c1);
         double right = lane_next(c0);
-        if (lane == 0 && x > 0) left = first ? cur.er : cur.er + beta * cur.ep;
-        if (lane == 63 && x + 2 < g.nx) right = first ? cur.er : cur.er + beta * cur.ep;
+        if (lane == 0 && x > 0) left = first ? cur.er : fma(beta, cur.ep, cur.er);
+        if (lane == 63 && x + 2 < g.nx) right = first ? cur.er : fma(beta, cur.ep, cur.er);
         double s0 = (x > 0 ? left : 0.0) + c1;
         double s1 = c0 + (x + 2 < g.nx ? right : 0.0);
         double u0, u1;
@@ -169,11 +169,11 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
         Vals<2> pn, qv;
         pn.v[0] = c0;
         pn.v[1] = c1;
-        qv.v[0] = diag * c0 - s0;
-        qv.v[1] = diag * c1 - s1;
+        qv.v[0] = fma(diag, c0, -s0);
+        qv.v[1] = fma(diag, c1, -s1);
         pn.template st<NTS>(a.p_new + idx0);
         qv.template st<NTS>(a.q + idx0);
-        acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
+        acc[0] = fma(c1, qv.v[1], fma(c0, qv.v[0], acc[0]));
         m0 = c0;
         m1 = c1;
         cur = nxt;
@@ -229,11 +229,11 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
       Vals<2> pn, qv;
       pn.v[0] = c0;
       pn.v[1] = c1;
-      qv.v[0] = diag * c0 - s0;
-      qv.v[1] = diag * c1 - s1;
+      qv.v[0] = fma(diag, c0, -s0);
+      qv.v[1] = fma(diag, c1, -s1);
       pn.template st<NTS>(a.p_new + idx0);
       qv.template st<NTS>(a.q + idx0);
-      acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
+      acc[0] = fma(c1, qv.v[1], fma(c0, qv.v[0], acc[0]));
       continue;
     }
 #pragma unroll
@@ -255,10 +255,10 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
         if (zz > 0) s += pk1(p - plane);
         if (zz < g.nz - 1) s += pk1(p + plane);
       }
-      const double q = diag * pc - s;
+      const double q = fma(diag, pc, -s);
       a.p_new[p] = pc;
       a.q[p] = q;
-      acc[0] += pc * q;
+      acc[0] = fma(pc, q, acc[0]);
     }
   }
   store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
@@ -289,21 +289,21 @@ __global__ __launch_bounds__(kThreads) void cg_diag_sweep_a_kernel(CgArgs a) {
         Vals<2> po;
         po.template ld<NTL>(a.p_old + idx);
 #pragma unroll
-        for (int v = 0; v < 2; ++v) pn.v[v] = r.v[v] + beta * po.v[v];
+        for (int v = 0; v < 2; ++v) pn.v[v] = fma(beta, po.v[v], r.v[v]);
       }
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         q.v[v] = d.v[v] * pn.v[v];
-        acc[0] += pn.v[v] * q.v[v];
+        acc[0] = fma(pn.v[v], q.v[v], acc[0]);
       }
       pn.template st<NTS>(a.p_new + idx);
       q.template st<NTS>(a.q + idx);
     } else if (idx < a.n) {
-      const double pc = first ? a.r[idx] : a.r[idx] + beta * a.p_old[idx];
+      const double pc = first ? a.r[idx] : fma(beta, a.p_old[idx], a.r[idx]);
       const double q = a.od.dg[idx] * pc;
       a.p_new[idx] = pc;
       a.q[idx] = q;
-      acc[0] += pc * q;
+      acc[0] = fma(pc, q, acc[0]);
     }
   }
   store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
 
   const bool first = a.k == 0;
   const double beta = first ? 0.0 : sh.cg_beta;
-  auto pk1 = [&](int q) { return first ? a.r[q] : a.r[q] + beta * a.p_old[q]; };
+  auto pk1 = [&](int q) { return first ? a.r[q] : fma(beta, a.p_old[q], a.r[q]); };
   double acc[1] = {0.0};
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
     const int idx0 = it.c * kChunk + threadIdx.x * kVec;
@@ -335,8 +335,8 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
       if (!first) {
         Vals<2> po;
         po.load(a.p_old + idx0);
-        c0 += beta * po.v[0];
-        c1 += beta * po.v[1];
+        c0 = fma(beta, po.v[0], c0);
+        c1 = fma(beta, po.v[1], c1);
       }
       double q0 = 0.0, q1 = 0.0;
       for (int j = 0; j < a.od.ell_k; ++j) {
@@ -344,8 +344,8 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
         Vals<2> vv;
         vv.template ld<NTL>(a.od.va + e);
         const int2 cc = *reinterpret_cast<const int2 *>(a.od.ci + e);
-        q0 += vv.v[0] * pk1(cc.x);
-        q1 += vv.v[1] * pk1(cc.y);
+        q0 = fma(vv.v[0], pk1(cc.x), q0);
+        q1 = fma(vv.v[1], pk1(cc.y), q1);
       }
       Vals<2> pn, qv;
       pn.v[0] = c0;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
       qv.v[1] = q1;
       pn.template st<NTS>(a.p_new + idx0);
       qv.template st<NTS>(a.q + idx0);
-      acc[0] += c0 * q0 + c1 * q1;
+      acc[0] = fma(c1, q1, fma(c0, q0, acc[0]));
       continue;
     }
 #pragma unroll
@@ -366,15 +366,15 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
       if (a.od.ell_k > 0) {
         for (int j = 0; j < a.od.ell_k; ++j) {
           const size_t e = (size_t)j * a.od.ell_ld + p;
-          q += a.od.va[e] * pk1(a.od.ci[e]);
+          q = fma(a.od.va[e], pk1(a.od.ci[e]), q);
         }
       } else {
         const int64_t e = a.od.rp[p + 1];
-        for (int64_t j = a.od.rp[p]; j < e; ++j) q += a.od.va[j] * pk1(a.od.ci[j]);
+        for (int64_t j = a.od.rp[p]; j < e; ++j) q = fma(a.od.va[j], pk1(a.od.ci[j]), q);
       }
       a.p_new[p] = pc;
       a.q[p] = q;
-      acc[0] += pc * q;
+      acc[0] = fma(pc, q, acc[0]);
     }
   }
   store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
@@ -434,8 +434,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           x.v[v] = fma(alpha, p.v[v], x.v[v]);
-          r.v[v] -= alpha * q.v[v];
-          acc[0] += r.v[v] * r.v[v];
+          r.v[v] = fma(-alpha, q.v[v], r.v[v]);
+          acc[0] = fma(r.v[v], r.v[v], acc[0]);
         }
         x.template st<NTS>(a.x + idx);
         r.template st<NTS>(a.r + idx);
@@ -454,8 +454,8 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
         }
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-          r.v[v] -= alpha * q.v[v];
-          acc[0] += r.v[v] * r.v[v];
+          r.v[v] = fma(-alpha, q.v[v], r.v[v]);
+          acc[0] = fma(r.v[v], r.v[v], acc[0]);
         }
         r.template st<NTS>(a.r + idx);
       }
@@ -464,9 +464,9 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
         a.x[idx] = fma(alpha, a.p_new[idx], a.x[idx]);
       else if (upd)
         a.x[idx] = fma(alpha, a.p_new[idx], fma(alpha_prev, a.p_old[idx], a.x[idx]));
-      const double rv = a.r[idx] - alpha * a.q[idx];
+      const double rv = fma(-alpha, a.q[idx], a.r[idx]);
       a.r[idx] = rv;
-      acc[0] += rv * rv;
+      acc[0] = fma(rv, rv, acc[0]);
     }
   }
   store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
@@ -485,7 +485,7 @@ __device__ inline double op_at(const double *x, int p, const Grid &g, const OpDa
   } else if constexpr (K == 3) {
     return CsrOp<double>{od.rp, od.ci, od.va, od.ell_k, od.ell_ld}.row(x, p);
   } else {
-    return (K == 1 ? 6.0 : 4.0) * x[p] - neighbour_sum<K == 1>(x, p, g);
+    return fma(K == 1 ? 6.0 : 4.0, x[p], -neighbour_sum<K == 1>(x, p, g));
   }
 }
 
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kThreads) void residual_kernel(const double *b, con
       const double rv = b[p] - op_at<K>(x, p, g, od);
       if (r != nullptr) r[p] = rv;
       const double rw = wdiv != nullptr ? rv / wdiv[p] : rv;
-      acc[0] += rw * rw;
+      acc[0] = fma(rw, rw, acc[0]);
     }
   }
   store_partials<1>(acc, part_out, kMaxStream, blockIdx.x, lds, red);

@@ -59,7 +59,7 @@ __device__ inline double res_apply(const double *z, int p, double zc, const Grid
       if (faces & 16) s += z[p - g.nx * g.ny];
       if (faces & 32) s += z[p + g.nx * g.ny];
     }
-    return (K == 1 ? 6.0 : 4.0) * zc - s;
+    return fma(K == 1 ? 6.0 : 4.0, zc, -s);
   } else if constexpr (K == 2) {
     return dp * zc;
   } else {
@@ -69,7 +69,7 @@ __device__ inline double res_apply(const double *z, int p, double zc, const Grid
     if (od.ell_k > 0) {
       for (int j = 0; j < od.ell_k; ++j) {
         const int e = j * od.ell_ld + p;
-        s += od.va[e] * z[od.ci[e]];
+        s = fma(od.va[e], z[od.ci[e]], s);
       }
     } else {
       const int e1 = (int)od.rp[p + 1];
@@ -206,9 +206,9 @@ __global__ __launch_bounds__(kResThreads) void plcg_resident_kernel(ResArgs a) {
           if (t >= 0) {
             // z_{i+1} = (A z_i - gamma_t z_i - delta_{t-1} z_{i-1}) / delta_t
             const double zp = zl[1][v];
-            zn = ((w - cf.gam * zc) - cf.dm1 * zp) * cf.inv_del;
+            zn = fma(-cf.dm1, zp, fma(-cf.gam, zc, w)) * cf.inv_del;
 #pragma unroll
-            for (int m = 1; m <= L - 3; ++m) acc[m] += zn * zl[L - 1 - m][v];
+            for (int m = 1; m <= L - 3; ++m) acc[m] = fma(zn, zl[L - 1 - m][v], acc[m]);
             // bases k = l-1 .. 0, each from the values before this sweep
             double above = zc, vt = 0.0, vnew = 0.0;
 #pragma unroll
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kResThreads) void plcg_resident_kernel(ResArgs a) {
               const double ck = zk[k][0][v];
               const double pk = t >= 1 ? zk[k][1][v] : 0.0;
               const double sk = cf.sig[k] - cf.gam;
-              const double nk = ((above + sk * ck) - cf.dm1 * pk) * cf.inv_del;
+              const double nk = fma(-cf.dm1, pk, fma(sk, ck, above)) * cf.inv_del;
               zk[k][1][v] = ck;
               zk[k][0][v] = nk;
               above = ck;
@@ -229,27 +229,27 @@ __global__ __launch_bounds__(kResThreads) void plcg_resident_kernel(ResArgs a) {
             if (t == 0) {
               pv[v] = vt * cf.inv_eta;
             } else {
-              xv[v] += cf.zm1 * pv[v];
-              pv[v] = (vt - cf.dm1 * pv[v]) * cf.inv_eta;
+              xv[v] = fma(cf.zm1, pv[v], xv[v]);
+              pv[v] = fma(-cf.dm1, pv[v], vt) * cf.inv_eta;
             }
-            acc[0] += zn * vnew;
-            acc[L] += zn * zn;
-            if (L >= 2) acc[L - 1] += zn * zc;
-            if (L >= 3) acc[L - 2] += zn * zp;
+            acc[0] = fma(zn, vnew, acc[0]);
+            acc[L] = fma(zn, zn, acc[L]);
+            if (L >= 2) acc[L - 1] = fma(zn, zc, acc[L - 1]);
+            if (L >= 3) acc[L - 2] = fma(zn, zp, acc[L - 2]);
           } else {
             // start-up: z_{i+1} = (A - sigma_i) z_i, copied into basis i+1
-            zn = w - cf.sigma_i * zc;
+            zn = fma(-cf.sigma_i, zc, w);
 #pragma unroll
             for (int m = 1; m <= L - 2; ++m) {
               const int h = L - 1 - m;
-              if (h <= i) acc[m] += zn * zl[h][v];
+              if (h <= i) acc[m] = fma(zn, zl[h][v], acc[m]);
             }
-            if (i == L - 1) acc[0] += zn * zk[0][0][v];
+            if (i == L - 1) acc[0] = fma(zn, zk[0][0][v], acc[0]);
 #pragma unroll
             for (int k = 1; k < L; ++k)
               if (i == k - 1) zk[k][0][v] = zn;
-            acc[L] += zn * zn;
-            if (L >= 2) acc[L - 1] += zn * zc;
+            acc[L] = fma(zn, zn, acc[L]);
+            if (L >= 2) acc[L - 1] = fma(zn, zc, acc[L - 1]);
           }
 #pragma unroll
           for (int h = R - 1; h >= 1; --h) zl[h][v] = zl[h - 1][v];
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kResThreads) void cg_resident_kernel(ResArgs a) {
     for (int v = 0; v < V; ++v) {
       const int p = v * kResThreads + tid;
       if (p < n) {
-        pv[v] = k == 0 ? rv[v] : rv[v] + beta * pv[v];
+        pv[v] = k == 0 ? rv[v] : fma(beta, pv[v], rv[v]);
         ps[p] = pv[v];
       }
     }
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kResThreads) void cg_resident_kernel(ResArgs a) {
       const int p = v * kResThreads + tid;
       if (p < n) {
         qv[v] = res_apply<K>(ps, p, pv[v], g, a.od, dd[v], fc[v]);
-        acc += pv[v] * qv[v];
+        acc = fma(pv[v], qv[v], acc);
       }
     }
     {
@@ -365,9 +365,9 @@ __global__ __launch_bounds__(kResThreads) void cg_resident_kernel(ResArgs a) {
     for (int v = 0; v < V; ++v) {
       const int p = v * kResThreads + tid;
       if (p < n) {
-        xv[v] += alpha * pv[v];
-        rv[v] -= alpha * qv[v];
-        acc += rv[v] * rv[v];
+        xv[v] = fma(alpha, pv[v], xv[v]);
+        rv[v] = fma(-alpha, qv[v], rv[v]);
+        acc = fma(rv[v], rv[v], acc);
       }
     }
     {

@@ -26,44 +26,50 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   // i.  For l = 1 every workgroup finalises column i itself (this launch needs
   // it); for l >= 2 only workgroup 0 does, and it streams nothing.
   const bool owner = blockIdx.x == 0;
-  const bool engine = (L == 1) || owner;
-  if (engine) {
-    // The state and the previous sweep's partials are requested together (the
-    // partials are read before the status says whether they are needed).
-    const bool sums = a.i >= 1 && a.nparts_in > 0;
-    WordRegs<DevState> sw;
-    PartRegs<ND> pr;
+  const int i = a.i;
+  const int t = i - L;
+  // The state and the previous sweep's partials, requested together (the
+  // partials before the status says whether they are needed), then column i.
+  WordRegs<DevState> sw;
+  PartRegs<ND> pr;
+  auto engine_fetch = [&]() {
     words_fetch(a.st_in, sw);
-    if (sums) partials_fetch<ND>(a.part_in, a.nparts_in, a.pstride, pr);
+    partials_fetch<ND>(a.part_in, a.nparts_in, a.pstride, pr);
+  };
+  auto engine_step = [&]() {
     words_put(sw, &sh);
-    if (sums && sh.status == kRunning) {
+    if (i >= 1 && a.nparts_in > 0 && sh.status == kRunning) {
       partials_sum<ND>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
-      if (threadIdx.x == 0) engine_column_l<L>(sh, red, a.i, owner ? a.hist : nullptr);
+      if (threadIdx.x == 0) engine_column_l<L>(sh, red, i, owner ? a.hist : nullptr);
       __syncthreads();
     }
     if (owner) {
       state_store(&sh, a.st_out);
-      if (threadIdx.x == 0) publish(sh, a.hs, fabs(sh.zeta[(a.i + kTRing - 1) % kTRing]), a.i);
+      if (threadIdx.x == 0) publish(sh, a.hs, fabs(sh.zeta[(i + kTRing - 1) % kTRing]), i);
     }
-    if (L >= 2) return;
+  };
+  if constexpr (L >= 2) {
+    if (owner) {
+      engine_fetch();
+      engine_step();
+      return;
+    }
+  } else {
+    engine_fetch();
   }
-  if (!a.work) return;
-
-  const int i = a.i;
-  const int t = i - L;
-  // l = 2, 3: the streaming workgroups request their first chunk's vectors
-  // before they read the scalar state (which decides only whether this sweep
-  // streams at all and with which coefficients), so the two round trips
-  // overlap; the chunk is computed from those registers with the same
-  // arithmetic.  Measured: 128^2-512^2 p(2) 5-13 % faster per iteration,
-  // 2048^2 0.6 %; not for sweeps that store non-temporally (vectors of
-  // 96 MiB and more: 256^3 p(3) 0.6 % slower with it).
-  constexpr bool kPreload = L >= 2 && L <= 3 && (H & kHintStores) == 0;
+  // The streaming workgroups then request their first chunk's vectors before
+  // the scalar state is read (it decides only whether the sweep streams and
+  // with which coefficients), so the round trips overlap: vector loads complete
+  // in order, and a workgroup barrier does not wait for them.  The chunk is
+  // computed from those registers with the same arithmetic.  Not for sweeps
+  // that store non-temporally (vectors of 96 MiB and more, where it was
+  // measured slower).
+  constexpr bool kPreload = L <= 3 && (H & kHintStores) == 0;
   typename S::template Loads<V> pre;
   bool have_pre = false;
   if constexpr (kPreload) {
-    if (t >= 0) {
-      const ChunkIter it0 = xcd_chunks(a.nchunks, a.nstream, 1, (i & 1) != 0);
+    if (t >= 0 && a.work) {
+      const ChunkIter it0 = xcd_chunks(a.nchunks, a.nstream, L == 1 ? 0 : 1, (i & 1) != 0);
       if (it0.c < it0.end) {
         const int base = order.phys(it0.at()) * CH;
         if (fast_rows && base + CH <= a.n) {
@@ -73,6 +79,9 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
       }
     }
   }
+  if constexpr (L == 1) engine_step();
+  if (!a.work) return;
+
   int status, last_t;
   Coef<L> cf;
   if (L == 1) {
@@ -117,13 +126,12 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
 //
 // Prologue of sweep A, every workgroup; returns false when nothing is streamed.
 __device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds, double *red) {
-  const bool sums = a.k >= 1;
   WordRegs<DevState> sw;
   PartRegs<1> pr;
   words_fetch(a.st_in, sw);
-  if (sums) partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, pr);
+  partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, pr);
   words_put(sw, &sh);
-  if (sums && sh.status == kRunning) {
+  if (a.k >= 1 && sh.status == kRunning) {
     partials_sum<1>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
     if (threadIdx.x == 0) {
       const double rho = red[0];

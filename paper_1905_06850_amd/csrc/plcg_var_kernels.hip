@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kThreads) void cg_var_sweep_a_kernel(CgArgs a) {
   const VarOp op = var_op(a.od, a.n, a.nx, a.ny, a.nz, a.d3);
   const Grid g{a.n, a.nx, a.ny, a.nz};
   const ChunkOrder order = chunk_order(g, a.d3 != 0, kChunk);
-  auto pk1 = [&](int q) { return first ? a.r[q] : a.r[q] + beta * a.p_old[q]; };
+  auto pk1 = [&](int q) { return first ? a.r[q] : fma(beta, a.p_old[q], a.r[q]); };
   // p_k at the pair q, q+1 (16-byte loads)
   auto pk2 = [&](int q, double &v0, double &v1) {
     Vals<2> rr;
@@ -49,8 +49,8 @@ __global__ __launch_bounds__(kThreads) void cg_var_sweep_a_kernel(CgArgs a) {
     if (!first) {
       Vals<2> po;
       po.load(a.p_old + q);
-      v0 += beta * po.v[0];
-      v1 += beta * po.v[1];
+      v0 = fma(beta, po.v[0], v0);
+      v1 = fma(beta, po.v[1], v1);
     }
   };
   const bool fast_rows = (a.nx & 1) == 0;
@@ -77,38 +77,38 @@ __global__ __launch_bounds__(kThreads) void cg_var_sweep_a_kernel(CgArgs a) {
       const int xe = rest * (a.nx + 1) + x;
       const int ye = idx0 + zz * a.nx;
       double s0 = 0.0, s1 = 0.0;
-      if (x > 0) s0 += op.sx[xe] * left;
-      s0 += op.sx[xe + 1] * c1;                      // x + 1 < nx: nx is even
-      s1 += op.sx[xe + 1] * c0;
-      if (x + 2 < a.nx) s1 += op.sx[xe + 2] * right;
+      if (x > 0) s0 = fma(op.sx[xe], left, s0);
+      s0 = fma(op.sx[xe + 1], c1, s0);               // x + 1 < nx: nx is even
+      s1 = fma(op.sx[xe + 1], c0, s1);
+      if (x + 2 < a.nx) s1 = fma(op.sx[xe + 2], right, s1);
       double u0, u1;
       if (y > 0) {
         Vals<2> w;
         w.load(op.sy + ye);
         pk2(idx0 - a.nx, u0, u1);
-        s0 += w.v[0] * u0;
-        s1 += w.v[1] * u1;
+        s0 = fma(w.v[0], u0, s0);
+        s1 = fma(w.v[1], u1, s1);
       }
       if (y < a.ny - 1) {
         Vals<2> w;
         w.load(op.sy + ye + a.nx);
         pk2(idx0 + a.nx, u0, u1);
-        s0 += w.v[0] * u0;
-        s1 += w.v[1] * u1;
+        s0 = fma(w.v[0], u0, s0);
+        s1 = fma(w.v[1], u1, s1);
       }
       if (a.d3 && zz > 0) {
         Vals<2> w;
         w.load(op.sz + idx0);
         pk2(idx0 - plane, u0, u1);
-        s0 += w.v[0] * u0;
-        s1 += w.v[1] * u1;
+        s0 = fma(w.v[0], u0, s0);
+        s1 = fma(w.v[1], u1, s1);
       }
       if (a.d3 && zz < a.nz - 1) {
         Vals<2> w;
         w.load(op.sz + idx0 + plane);
         pk2(idx0 + plane, u0, u1);
-        s0 += w.v[0] * u0;
-        s1 += w.v[1] * u1;
+        s0 = fma(w.v[0], u0, s0);
+        s1 = fma(w.v[1], u1, s1);
       }
       Vals<2> pn, qv;
       pn.v[0] = c0;
@@ -116,15 +116,15 @@ __global__ __launch_bounds__(kThreads) void cg_var_sweep_a_kernel(CgArgs a) {
       if (op.dg != nullptr) {
         Vals<2> dv;
         dv.load(op.dg + idx0);
-        qv.v[0] = dv.v[0] * c0 - s0;
-        qv.v[1] = dv.v[1] * c1 - s1;
+        qv.v[0] = fma(dv.v[0], c0, -s0);
+        qv.v[1] = fma(dv.v[1], c1, -s1);
       } else {
         qv.v[0] = c0 - s0;
         qv.v[1] = c1 - s1;
       }
       pn.template st<NTS>(a.p_new + idx0);
       qv.template st<NTS>(a.q + idx0);
-      acc[0] += c0 * qv.v[0] + c1 * qv.v[1];
+      acc[0] = fma(c1, qv.v[1], fma(c0, qv.v[0], acc[0]));
       continue;
     }
     if (idx0 + 1 < a.n) {
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void cg_var_sweep_a_kernel(CgArgs a) {
       for (int v = 0; v < 2; ++v) {
         pn.v[v] = pk1(idx0 + v);
         qv.v[v] = op.at_f(idx0 + v, pn.v[v], pk1);
-        acc[0] += pn.v[v] * qv.v[v];
+        acc[0] = fma(pn.v[v], qv.v[v], acc[0]);
       }
       pn.template st<NTS>(a.p_new + idx0);
       qv.template st<NTS>(a.q + idx0);
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void cg_var_sweep_a_kernel(CgArgs a) {
       const double q = op.at_f(idx0, pc, pk1);
       a.p_new[idx0] = pc;
       a.q[idx0] = q;
-      acc[0] += pc * q;
+      acc[0] = fma(pc, q, acc[0]);
     }
   }
   store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kThreads) void var_residual_kernel(const double *b,
       const double rv = b[p] - op.at(x, p);
       if (r != nullptr) r[p] = rv;
       const double rw = wdiv != nullptr ? rv / wdiv[p] : rv;
-      acc[0] += rw * rw;
+      acc[0] = fma(rw, rw, acc[0]);
     }
   }
   store_partials<1>(acc, part_out, kMaxStream, blockIdx.x, lds, red);

@@ -69,7 +69,7 @@ def _cases():
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
 def test_engine_forms_agree_and_stop_where_the_oracle_stops(tmp_path):
     exe = str(tmp_path / "engine_replay")
-    cmd = [HIPCC, "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17",
+    cmd = [HIPCC, "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
            "-I", os.path.join(ROOT, "include"),
            "-I", os.path.join(ROOT, "paper_1905_06850_amd", "csrc"),
            os.path.join(ROOT, "tests", "c", "engine_replay.hip"), "-o", exe]

@@ -124,14 +124,19 @@ def test_var_jacobi_solve_parity(dev, dims, method, l):
 
 @pytest.mark.parametrize("dims", [(64, 64), (102, 30), (20, 13, 7), (32, 48, 5)])
 def test_var_unscaled_cg_parity(dev, dims):
-    """CG on the operator as given (diagonal array, raw edge weights)."""
+    """CG on the operator as given (diagonal array, raw edge weights).  These
+    unscaled systems need 110-600 iterations, and their iteration count depends
+    on the rounding sequence: the oracle's own count moves by up to 3 (0.5 %)
+    when b is scaled by 1 + k 2^-52, k = 1..5, or its dot products are rounded
+    exactly (math.fsum), with x staying within 4e-9.  Bound: 1 % (at least 1)."""
     co = Coef(dev, dims, 46)
     b = synth.uniform(co.n, 47)
     x0 = np.zeros(co.n)
     ref = ocg.cg(co.A, b, x0, 1e-8, 20000)
     x, res = gpu_solve(dev, co, "cg", 1, b, x0, 1e-8, 20000, jacobi=False)
     assert res.reason == 1 and ref.reason == "converged"
-    assert abs(res.iters - ref.iters) <= 1
+    assert abs(res.iters - ref.iters) <= max(1, int(np.ceil(0.01 * ref.iters))), \
+        (res.iters, ref.iters)
     assert _rel(x, ref.x) < 1e-8
     assert res.true_relres <= 10 * ref.true_relres and ref.true_relres <= 10 * res.true_relres
 
