@@ -361,12 +361,27 @@ __device__ inline void partials_sum(PartRegs<ND> r, const double *part, int npar
   block_sum<ND>(s, lds, out);
 }
 
+// The same sums where a kernel's streaming path sets its register budget: up to
+// three products all loads in flight; beyond that one load at a time, since
+// ND * kPartPer live values would raise the register count of the whole kernel
+// (the batch tick's l >= 3 kernels: 76 -> 86 VGPRs at l = 3).  Same order.
 template <int ND>
 __device__ inline void sum_partials(const double *part, int nparts, int pstride, double *lds,
                                     double *out) {
-  PartRegs<ND> r;
-  partials_fetch<ND>(part, nparts, pstride, r);
-  partials_sum<ND>(r, part, nparts, pstride, lds, out);
+  if constexpr (ND <= 3) {
+    PartRegs<ND> r;
+    partials_fetch<ND>(part, nparts, pstride, r);
+    partials_sum<ND>(r, part, nparts, pstride, lds, out);
+  } else {
+    double s[ND];
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+      double acc = 0.0;
+      for (int b = threadIdx.x; b < nparts; b += kThreads) acc += part[m * pstride + b];
+      s[m] = acc;
+    }
+    block_sum<ND>(s, lds, out);
+  }
 }
 
 // This workgroup's partials (index = streaming workgroup number).
