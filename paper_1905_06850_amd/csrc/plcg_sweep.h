@@ -63,8 +63,10 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   // in order, and a workgroup barrier does not wait for them.  The chunk is
   // computed from those registers with the same arithmetic.  Not for sweeps
   // that store non-temporally (vectors of 96 MiB and more, where it was
-  // measured slower).
-  constexpr bool kPreload = L <= 3 && (H & kHintStores) == 0;
+  // measured slower), and not for FP32 storage, whose four values per thread
+  // and vector, held as doubles, would double the sweep's registers (the 3D
+  // p(3) sweep: 91 -> 171 VGPRs, two waves per SIMD instead of four).
+  constexpr bool kPreload = L <= 3 && (H & kHintStores) == 0 && sizeof(ST) == 8;
   typename S::template Loads<V> pre;
   bool have_pre = false;
   if constexpr (kPreload) {
