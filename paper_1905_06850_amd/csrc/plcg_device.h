@@ -1,6 +1,8 @@
 // Device helpers shared by the single-system and the batched kernels of libplcg.
 #pragma once
 
+#include <type_traits>
+
 #include "plcg_internal.h"
 
 #include <math.h>
@@ -211,60 +213,128 @@ __device__ inline double neighbour_sum(const S *z, int p, const Grid &g) {
   return s;
 }
 
-// w = A z at the V unknowns starting at idx, given their values zc.
-// FAST (a full chunk, nx a multiple of V): the V unknowns of a thread share a
-// row, x-neighbours come from the thread's own values and the adjacent lanes
-// (consecutive groups of V), the rows and planes above and below are 16-byte
-// loads.  Called by all 64 lanes together.
+// The values the stencil's FAST form reads beyond a thread's own V unknowns:
+// the x-neighbours at the wave's edges (z[idx-1] for lane 0, z[idx+V] for lane
+// 63) and the rows (and planes) above and below, with 16-byte loads.  Loaded
+// apart from the arithmetic, so that a sweep can request them with its first
+// chunk's own vectors, ahead of the scalar state.
+template <int V, bool D3, typename S>
+struct StencilHalo {
+  double left, right;
+  Vals<V, S> u, d;      // rows y-1, y+1
+  Vals<V, S> f, b;      // planes z-1, z+1 (3D)
+};
+
+template <int V, bool D3, typename S>
+__device__ inline void stencil_halo_load(const S *z, int idx, const Grid &g,
+                                         StencilHalo<V, D3, S> &h) {
+  const int x = idx % g.nx;
+  const int rest = idx / g.nx;
+  const int y = D3 ? rest % g.ny : rest;
+  const int lane = threadIdx.x & 63;
+  h.left = 0.0;
+  h.right = 0.0;
+  if (lane == 0 && x > 0) h.left = (double)z[idx - 1];
+  if (lane == 63 && x + V < g.nx) h.right = (double)z[idx + V];
+  if (y > 0) h.u.load(z + idx - g.nx);
+  if (y < g.ny - 1) h.d.load(z + idx + g.nx);
+  if constexpr (D3) {
+    const int zz = rest / g.ny;
+    const int plane = g.nx * g.ny;
+    if (zz > 0) h.f.load(z + idx - plane);
+    if (zz < g.nz - 1) h.b.load(z + idx + plane);
+  }
+}
+
+// Where stencil_fast gets the values beyond a thread's own unknowns: loaded
+// from the vector where they are used (the loop's chunks), or taken from a
+// halo loaded ahead (a sweep's first chunk).  The same arithmetic either way.
+template <int V, typename S>
+struct RowsFromMemory {
+  const S *z;
+  __device__ inline double left(int idx) const { return (double)z[idx - 1]; }
+  __device__ inline double right(int idx) const { return (double)z[idx + V]; }
+  template <int W>   // 0: row above, 1: row below, 2: plane below, 3: plane above
+  __device__ inline Vals<V, S> row(int q) const {
+    Vals<V, S> r;
+    r.load(z + q);
+    return r;
+  }
+};
+
+template <int V, bool D3, typename S>
+struct RowsFromHalo {
+  const StencilHalo<V, D3, S> &h;
+  __device__ inline double left(int) const { return h.left; }
+  __device__ inline double right(int) const { return h.right; }
+  template <int W>
+  __device__ inline const Vals<V, S> &row(int) const {
+    if constexpr (W == 0) return h.u;
+    else if constexpr (W == 1) return h.d;
+    else if constexpr (W == 2) return h.f;
+    else return h.b;
+  }
+};
+
+// w = A z at a thread's V unknowns (a full chunk, nx a multiple of V: they
+// share a row) from their values zc: x-neighbours from the thread's own values
+// and the adjacent lanes (consecutive groups of V), the wave's edges, rows and
+// planes from src.  Called by all 64 lanes together.
+template <int V, bool D3, typename S, typename Src>
+__device__ inline void stencil_fast(const Vals<V, S> &zc, int idx, const Grid &g, const Src &src,
+                                    double (&w)[V]) {
+  const double diag = D3 ? 6.0 : 4.0;
+  const int x = idx % g.nx;
+  const int rest = idx / g.nx;
+  const int y = D3 ? rest % g.ny : rest;
+  const int lane = threadIdx.x & 63;
+  double left = lane_prev(zc.v[V - 1]);   // z[idx-1] held by the previous lane
+  double right = lane_next(zc.v[0]);      // z[idx+V] held by the next lane
+  if (lane == 0 && x > 0) left = src.left(idx);
+  if (lane == 63 && x + V < g.nx) right = src.right(idx);
+  double s[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k)
+    s[k] = (k > 0 ? zc.v[k - 1] : (x > 0 ? left : 0.0)) +
+           (k < V - 1 ? zc.v[k + 1] : (x + V < g.nx ? right : 0.0));
+  if (y > 0) {
+    const Vals<V, S> u = src.template row<0>(idx - g.nx);
+#pragma unroll
+    for (int k = 0; k < V; ++k) s[k] += u.v[k];
+  }
+  if (y < g.ny - 1) {
+    const Vals<V, S> d = src.template row<1>(idx + g.nx);
+#pragma unroll
+    for (int k = 0; k < V; ++k) s[k] += d.v[k];
+  }
+  if constexpr (D3) {
+    const int zz = rest / g.ny;
+    const int plane = g.nx * g.ny;
+    if (zz > 0) {
+      const Vals<V, S> f = src.template row<2>(idx - plane);
+#pragma unroll
+      for (int k = 0; k < V; ++k) s[k] += f.v[k];
+    }
+    if (zz < g.nz - 1) {
+      const Vals<V, S> b = src.template row<3>(idx + plane);
+#pragma unroll
+      for (int k = 0; k < V; ++k) s[k] += b.v[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k) w[k] = fma(diag, zc.v[k], -s[k]);
+}
+
+// w = A z at the V unknowns starting at idx, given their values zc.  FAST: a
+// full chunk with nx a multiple of V; otherwise one unknown at a time, one load
+// per neighbour.
 template <int V, bool D3, bool FAST, typename S>
 __device__ inline void apply_stencil(const S *z, int idx, const Vals<V, S> &zc, const Grid &g,
                                      double (&w)[V]) {
-  const double diag = D3 ? 6.0 : 4.0;
   if constexpr (FAST && V >= 2) {
-    const int x = idx % g.nx;
-    const int rest = idx / g.nx;
-    const int y = D3 ? rest % g.ny : rest;
-    const int lane = threadIdx.x & 63;
-    double left = lane_prev(zc.v[V - 1]);   // z[idx-1] held by the previous lane
-    double right = lane_next(zc.v[0]);      // z[idx+V] held by the next lane
-    if (lane == 0 && x > 0) left = (double)z[idx - 1];
-    if (lane == 63 && x + V < g.nx) right = (double)z[idx + V];
-    double s[V];
-#pragma unroll
-    for (int k = 0; k < V; ++k)
-      s[k] = (k > 0 ? zc.v[k - 1] : (x > 0 ? left : 0.0)) +
-             (k < V - 1 ? zc.v[k + 1] : (x + V < g.nx ? right : 0.0));
-    if (y > 0) {
-      Vals<V, S> u;
-      u.load(z + idx - g.nx);
-#pragma unroll
-      for (int k = 0; k < V; ++k) s[k] += u.v[k];
-    }
-    if (y < g.ny - 1) {
-      Vals<V, S> d;
-      d.load(z + idx + g.nx);
-#pragma unroll
-      for (int k = 0; k < V; ++k) s[k] += d.v[k];
-    }
-    if (D3) {
-      const int zz = rest / g.ny;
-      const int plane = g.nx * g.ny;
-      if (zz > 0) {
-        Vals<V, S> f;
-        f.load(z + idx - plane);
-#pragma unroll
-        for (int k = 0; k < V; ++k) s[k] += f.v[k];
-      }
-      if (zz < g.nz - 1) {
-        Vals<V, S> b;
-        b.load(z + idx + plane);
-#pragma unroll
-        for (int k = 0; k < V; ++k) s[k] += b.v[k];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < V; ++k) w[k] = fma(diag, zc.v[k], -s[k]);
+    stencil_fast<V, D3, S>(zc, idx, g, RowsFromMemory<V, S>{z}, w);
   } else {
+    const double diag = D3 ? 6.0 : 4.0;
 #pragma unroll
     for (int v = 0; v < V; ++v) w[v] = fma(diag, zc.v[v], -neighbour_sum<D3, S>(z, idx + v, g));
   }
@@ -655,12 +725,36 @@ __device__ inline void read_coef(const DevState &s, int i, int t, Coef<L> &cf) {
 }
 
 // The unscaled integer Dirichlet Laplacian (5-point in 2D, 7-point in 3D).
+// Every operator also offers its FAST form split in two: halo_load requests
+// what the operator reads beyond a thread's own unknowns (Halo<V>), apply_halo
+// forms w from it, with the arithmetic of apply<V, true>.  A sweep uses the
+// split to request its first chunk's operator data ahead of the scalar state.
+// Operators whose FAST form is not split have an empty halo, and apply_halo
+// is apply<V, true>.
+struct NoHalo {};
+
+// The 3D stencil's halo is not split: its four rows and planes held ahead
+// took the p(3) sweep to 135 registers (three waves per SIMD).
 template <bool D3, typename S>
 struct ConstOp {
   Grid g;
+  template <int V>
+  using Halo = std::conditional_t<D3, NoHalo, StencilHalo<V, false, S>>;
   template <int V, bool FAST>
   __device__ inline void apply(const S *z, int idx, const Vals<V, S> &zc, double (&w)[V]) const {
     apply_stencil<V, D3, FAST, S>(z, idx, zc, g, w);
+  }
+  template <int V>
+  __device__ inline void halo_load(const S *z, int idx, Halo<V> &h) const {
+    if constexpr (!D3) stencil_halo_load<V, false, S>(z, idx, g, h);
+  }
+  template <int V>
+  __device__ inline void apply_halo(const S *z, int idx, const Vals<V, S> &zc, const Halo<V> &h,
+                                    double (&w)[V]) const {
+    if constexpr (D3)
+      apply_stencil<V, true, true, S>(z, idx, zc, g, w);
+    else
+      stencil_fast<V, false, S>(zc, idx, g, RowsFromHalo<V, false, S>{h}, w);
   }
 };
 
@@ -670,12 +764,24 @@ struct ConstOp {
 template <typename S>
 struct DiagOp {
   const double *d;
+  template <int V>
+  using Halo = Vals<V, double>;   // the diagonal entries
   template <int V, bool FAST>
   __device__ inline void apply(const S *, int idx, const Vals<V, S> &zc, double (&w)[V]) const {
     Vals<V, double> dv;
     dv.load(d + idx);
 #pragma unroll
     for (int v = 0; v < V; ++v) w[v] = dv.v[v] * zc.v[v];
+  }
+  template <int V>
+  __device__ inline void halo_load(const S *, int idx, Halo<V> &h) const {
+    h.load(d + idx);
+  }
+  template <int V>
+  __device__ inline void apply_halo(const S *, int, const Vals<V, S> &zc, const Halo<V> &h,
+                                    double (&w)[V]) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v) w[v] = h.v[v] * zc.v[v];
   }
 };
 
@@ -692,6 +798,15 @@ struct CsrOp {
   const int32_t *ci;
   const double *va;
   int ell_k, ell_ld;
+  template <int V>
+  using Halo = NoHalo;
+  template <int V>
+  __device__ inline void halo_load(const S *, int, Halo<V> &) const {}
+  template <int V>
+  __device__ inline void apply_halo(const S *z, int idx, const Vals<V, S> &zc, const Halo<V> &,
+                                    double (&w)[V]) const {
+    apply<V, true>(z, idx, zc, w);
+  }
   __device__ inline double row(const S *z, int p) const {
     double s = 0.0;
     if (ell_k > 0) {
@@ -751,6 +866,15 @@ struct VarOp {
   const double *sx, *sy, *sz;
   int n, nx, ny, nz, d3;
   const double *dg;
+  template <int V>
+  using Halo = NoHalo;
+  template <int V, typename S>
+  __device__ inline void halo_load(const S *, int, Halo<V> &) const {}
+  template <int V, typename S>
+  __device__ inline void apply_halo(const S *z, int idx, const Vals<V, S> &zc, const Halo<V> &,
+                                    double (&w)[V]) const {
+    apply<V, true, S>(z, idx, zc, w);
+  }
   // The operator at p with the value at p given and the others read through
   // get(q) (a vector, or values formed on the fly).
   template <typename F>
@@ -876,11 +1000,14 @@ struct Sweep {
   template <int V>
   struct Loads {
     Vals<V, S> zc, zp, ck[L], pk[L], pv, xv, qv;
+    typename Op::template Halo<V> halo;   // the operator's data beyond the own unknowns
   };
   template <int V>
-  __device__ static inline void steady_load(const Args &a, int idx, int t, Loads<V> &d) {
+  __device__ static inline void steady_load(const Args &a, const Op &op, int idx, int t,
+                                            Loads<V> &d) {
     static_assert(L <= 3, "older z^(l) vectors are not preloaded");
     d.zc.load(a.zl[0] + idx);
+    op.template halo_load<V>(a.zl[0], idx, d.halo);
     d.zp.template ld<NTL>(a.zl[1] + idx);
 #pragma unroll
     for (int k = L - 1; k >= 0; --k) {
@@ -916,7 +1043,10 @@ struct Sweep {
       zp.template ld<NTL>(a.zl[1] + idx);
     }
     double w[V];
-    op.template apply<V, FAST>(a.zl[0], idx, zc, w);
+    if constexpr (PRE)
+      op.template apply_halo<V>(a.zl[0], idx, zc, pre->halo, w);
+    else
+      op.template apply<V, FAST>(a.zl[0], idx, zc, w);
     double zn[V];
 #pragma unroll
     for (int v = 0; v < V; ++v)

@@ -57,8 +57,9 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   } else {
     engine_fetch();
   }
-  // The streaming workgroups then request their first chunk's vectors before
-  // the scalar state is read (it decides only whether the sweep streams and
+  // The streaming workgroups then request their first chunk's vectors and the
+  // operator's data beyond them (rows and planes of a stencil) before the
+  // scalar state is read (it decides only whether the sweep streams and
   // with which coefficients), so the round trips overlap: vector loads complete
   // in order, and a workgroup barrier does not wait for them.  The chunk is
   // computed from those registers with the same arithmetic.  Not for sweeps
@@ -75,7 +76,7 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
       if (it0.c < it0.end) {
         const int base = order.phys(it0.at()) * CH;
         if (fast_rows && base + CH <= a.n) {
-          S::template steady_load<V>(a, base + threadIdx.x * V, t, pre);
+          S::template steady_load<V>(a, op, base + threadIdx.x * V, t, pre);
           have_pre = true;
         }
       }
