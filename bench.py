@@ -153,14 +153,41 @@ def cpu_baseline(workload: str, l: int, iters: int, reps: int = 5) -> dict:
             "cpu_model": model, "nproc": ncpu, "usable_cpus": usable, "runs": runs}
 
 
+def code_only(text: str) -> str:
+    """C++ source with its comments removed and every run of whitespace made one
+    space: what the compiler sees, so that an edit of a comment or of the layout
+    leaves the kernel source hash alone."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":                      # string or character literal, kept whole
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources of the iteration kernels (device code of the single-system path)."""
+    """Hash of the code (comments and layout aside) of the iteration kernels: the
+    device code of the single-system path."""
     import hashlib
     h = hashlib.sha256()
     for name in ("plcg_kernels.hip", "plcg_var_kernels.hip", "plcg_sweep.h", "plcg_device.h",
                  "plcg_internal.h"):
-        with open(os.path.join(ROOT, "paper_1905_06850_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1905_06850_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

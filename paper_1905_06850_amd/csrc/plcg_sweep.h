@@ -58,11 +58,13 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
     engine_fetch();
   }
   // The streaming workgroups then request their first chunk's vectors and the
-  // operator's data beyond them (rows and planes of a stencil) before the
-  // scalar state is read (it decides only whether the sweep streams and
-  // with which coefficients), so the round trips overlap: vector loads complete
-  // in order, and a workgroup barrier does not wait for them.  The chunk is
-  // computed from those registers with the same arithmetic.  Not for sweeps
+  // operator's data beyond them (Op::Halo: the wave-edge neighbours and rows of
+  // a 2D stencil, a diagonal's entries) before the scalar state is read (it
+  // decides only whether the sweep streams and with which coefficients), so
+  // the round trips overlap: vector loads complete in order, and a workgroup
+  // barrier does not wait for them (for l = 1 they follow the state and partial
+  // loads, which are waited for first).  The chunk is computed from those
+  // registers with the same arithmetic.  Not for sweeps
   // that store non-temporally (vectors of 96 MiB and more, where it was
   // measured slower), and not for FP32 storage, whose four values per thread
   // and vector, held as doubles, would double the sweep's registers (the 3D

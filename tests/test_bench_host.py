@@ -53,3 +53,18 @@ def test_working_set_and_cache_residency():
     n3 = 256 ** 3
     assert bench.working_set("plcg", 3, 2, n3, 8, 0) == 11 * 8 * n3 > bench.CACHE_BYTES
     assert bench.working_set("plcg", 5, 1, n3, 4, 0) == (10 + 4 + 1 + 1) * 4 * n3
+
+
+def test_kernel_source_hash_ignores_comments_and_layout():
+    """The hash that ties the committed traffic counters to the kernels it was
+    taken with covers the code only: comments and layout may change, code not."""
+    import bench
+    src = ('int a = 1; // one\n/* two\n lines */ double b = "x//y /* z */";\n'
+           "char q = '/';   // end\n  int   c = a*2;")
+    assert bench.code_only(src) == 'int a = 1; double b = "x//y /* z */"; char q = \'/\'; int c = a*2;'
+    commented = "// header\nint f(int x) {  /* doubled */\n  return 2 * x;   // here\n}\n"
+    plain = "int f(int x) { return 2 * x; }"
+    assert bench.code_only(commented) == bench.code_only(plain)
+    assert bench.code_only(plain) != bench.code_only(plain.replace("2", "3"))
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and h == bench.kernel_source_hash()
