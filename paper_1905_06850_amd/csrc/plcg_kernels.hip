@@ -49,19 +49,171 @@ __global__ __launch_bounds__(kThreads) void plcg_csr_sweep_kernel(SweepArgsT<ST>
 // Classic CG: two sweeps per iteration
 // ---------------------------------------------------------------------------
 
+// p_k = r_k + beta_{k-1} p_{k-1} for a pair (p_0 = r_0), one rounding each.
+__device__ inline void cg_form(bool first, double beta, const Vals<2> &r, const Vals<2> &po,
+                               double &v0, double &v1) {
+  v0 = r.v[0];
+  v1 = r.v[1];
+  if (!first) {
+    v0 = fma(beta, po.v[0], v0);
+    v1 = fma(beta, po.v[1], v1);
+  }
+}
+
+// The raw r and p_{k-1} values the fast path of sweep A reads for the pair
+// idx, idx+1 (x even): its own, the rows above and below (halo), and the
+// x-neighbour at the wave's edge (lane 0: x-1, lane 63: x+2).  p_{k-1} is not
+// read at k = 0.
+struct CgRaw {
+  Vals<2> r, p, ur, up, dr, dp;
+  double er, ep;
+};
+
+__device__ inline void cg_raw_fetch(const CgArgs &a, bool first, const Grid &g, int idx, int x,
+                                    int y, bool halo, CgRaw &w) {
+  const int lane = threadIdx.x & 63;
+  w.r.load(a.r + idx);
+  if (!first) w.p.load(a.p_old + idx);
+  if (!halo) return;
+  if (y > 0) {
+    w.ur.load(a.r + idx - g.nx);
+    if (!first) w.up.load(a.p_old + idx - g.nx);
+  }
+  if (y < g.ny - 1) {
+    w.dr.load(a.r + idx + g.nx);
+    if (!first) w.dp.load(a.p_old + idx + g.nx);
+  }
+  const int e = lane == 0 ? idx - 1 : idx + 2;
+  if ((lane == 0 && x > 0) || (lane == 63 && x + 2 < g.nx)) {
+    w.er = a.r[e];
+    if (!first) w.ep = a.p_old[e];
+  }
+}
+
+// Where the fast path gets p_k around its pair idx0, idx0+1: formed from r and
+// p_{k-1} loaded where used (the loop's chunks) ...
+struct CgFromMemory {
+  const double *r, *po;
+  double beta;
+  bool first;
+  int idx0, nx, plane;
+  __device__ inline void pair(int q, double &v0, double &v1) const {
+    Vals<2> rr, pp;
+    rr.load(r + q);
+    if (!first) pp.load(po + q);
+    cg_form(first, beta, rr, pp, v0, v1);
+  }
+  __device__ inline double one(int q) const { return first ? r[q] : fma(beta, po[q], r[q]); }
+  __device__ inline void own(double &v0, double &v1) const { pair(idx0, v0, v1); }
+  __device__ inline double left() const { return one(idx0 - 1); }
+  __device__ inline double right() const { return one(idx0 + 2); }
+  __device__ inline void up(double &v0, double &v1) const { pair(idx0 - nx, v0, v1); }
+  __device__ inline void down(double &v0, double &v1) const { pair(idx0 + nx, v0, v1); }
+  __device__ inline void front(double &v0, double &v1) const { pair(idx0 - plane, v0, v1); }
+  __device__ inline void back(double &v0, double &v1) const { pair(idx0 + plane, v0, v1); }
+};
+
+// ... or from raw values loaded ahead (a 2D sweep's first chunk).  The same
+// roundings either way.
+struct CgFromRaw {
+  const CgRaw &w;
+  double beta;
+  bool first;
+  __device__ inline void own(double &v0, double &v1) const { cg_form(first, beta, w.r, w.p, v0, v1); }
+  __device__ inline double left() const { return first ? w.er : fma(beta, w.ep, w.er); }
+  __device__ inline double right() const { return left(); }
+  __device__ inline void up(double &v0, double &v1) const { cg_form(first, beta, w.ur, w.up, v0, v1); }
+  __device__ inline void down(double &v0, double &v1) const { cg_form(first, beta, w.dr, w.dp, v0, v1); }
+};
+
+// Fast path of sweep A for one pair of a full chunk (nx even: the pair shares a
+// row): p_k, q = A p_k and (p_k, q), x-neighbours from the adjacent lanes, the
+// wave's edges, rows and planes from src.
+template <bool D3, bool NTS, typename Src>
+__device__ inline void cg_a_fast(const CgArgs &a, const Grid &g, int idx0, const Src &src,
+                                 double (&acc)[1]) {
+  const double diag = D3 ? 6.0 : 4.0;
+  double c0, c1;
+  src.own(c0, c1);
+  const int x = idx0 % g.nx;
+  const int rest = idx0 / g.nx;
+  const int y = D3 ? rest % g.ny : rest;
+  const int lane = threadIdx.x & 63;
+  double left = lane_prev(c1);
+  double right = lane_next(c0);
+  if (lane == 0 && x > 0) left = src.left();
+  if (lane == 63 && x + 2 < g.nx) right = src.right();
+  double s0 = (x > 0 ? left : 0.0) + c1;
+  double s1 = c0 + (x + 2 < g.nx ? right : 0.0);
+  double u0, u1;
+  if (y > 0) {
+    src.up(u0, u1);
+    s0 += u0;
+    s1 += u1;
+  }
+  if (y < g.ny - 1) {
+    src.down(u0, u1);
+    s0 += u0;
+    s1 += u1;
+  }
+  if constexpr (D3) {
+    const int zz = rest / g.ny;
+    if (zz > 0) {
+      src.front(u0, u1);
+      s0 += u0;
+      s1 += u1;
+    }
+    if (zz < g.nz - 1) {
+      src.back(u0, u1);
+      s0 += u0;
+      s1 += u1;
+    }
+  }
+  Vals<2> pn, qv;
+  pn.v[0] = c0;
+  pn.v[1] = c1;
+  qv.v[0] = fma(diag, c0, -s0);
+  qv.v[1] = fma(diag, c1, -s1);
+  pn.template st<NTS>(a.p_new + idx0);
+  qv.template st<NTS>(a.q + idx0);
+  acc[0] = fma(c1, qv.v[1], fma(c0, qv.v[0], acc[0]));
+}
+
 template <bool D3, int H>
 __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
   constexpr bool NTS = (H & kHintStores) != 0;
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
-  if (!cg_a_prologue(a, sh, lds, red)) return;
-
   const bool first = a.k == 0;
-  const double beta = first ? 0.0 : sh.cg_beta;
   const Grid g{a.n, a.nx, a.ny, a.nz};
-  const double diag = D3 ? 6.0 : 4.0;
   const bool fast_rows = (a.nx & 1) == 0;
+  const ChunkOrder order = chunk_order(g, D3, kChunk);
+  CgPrologue pro;
+  cg_a_fetch(a, pro);
+  // A 2D sweep then requests its first chunk's r and p_{k-1} (the pair, the
+  // rows above and below, the wave-edge neighbour) before it waits for the
+  // state, as the p(l)-CG sweeps do; not where vectors are stored
+  // non-temporally (vectors of 96 MiB and more).
+  CgRaw pre;
+  bool have_pre = false;
+  if constexpr (!D3 && (H & kHintStores) == 0) {
+    if (a.work) {
+      const ChunkIter it0 = xcd_chunks(a.nchunks, a.nstream, 0);
+      if (it0.c < it0.end) {
+        const int base = order.phys(it0.c) * kChunk;
+        if (fast_rows && base + kChunk <= a.n) {
+          const int idx0 = base + threadIdx.x * kVec;
+          cg_raw_fetch(a, first, g, idx0, idx0 % g.nx, idx0 / g.nx, true, pre);
+          have_pre = true;
+        }
+      }
+    }
+  }
+  if (!cg_a_finish(a, pro, sh, lds, red)) return;
+
+  const double beta = first ? 0.0 : sh.cg_beta;
+  const double diag = D3 ? 6.0 : 4.0;
   double acc[1] = {0.0};
   // p_k at index q, formed on the fly from r and p_{k-1}
   auto pk1 = [&](int q) { return first ? a.r[q] : fma(beta, a.p_old[q], a.r[q]); };
@@ -91,38 +243,13 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
     const int ntiles = plane / kChunk;
     const int nitems = ntiles * ((g.nz + a.zseg - 1) / a.zseg);
     const int lane = threadIdx.x & 63;
-    // raw loads of one plane: own pair, rows above and below, wave-edge neighbours
-    struct Raw {
-      Vals<2> r, p, ur, up, dr, dp;
-      double er, ep;
-    };
+    // raw loads of one plane (the plane above a segment: only its own values)
+    using Raw = CgRaw;
     auto fetch = [&](int idx, int x, int y, bool halo, Raw &w) {
-      w.r.load(a.r + idx);
-      if (!first) w.p.load(a.p_old + idx);
-      if (!halo) return;   // the plane above a segment: only its own values
-      if (y > 0) {
-        w.ur.load(a.r + idx - g.nx);
-        if (!first) w.up.load(a.p_old + idx - g.nx);
-      }
-      if (y < g.ny - 1) {
-        w.dr.load(a.r + idx + g.nx);
-        if (!first) w.dp.load(a.p_old + idx + g.nx);
-      }
-      // lane 0 needs x-1, lane 63 x+2
-      const int e = lane == 0 ? idx - 1 : idx + 2;
-      if ((lane == 0 && x > 0) || (lane == 63 && x + 2 < g.nx)) {
-        w.er = a.r[e];
-        if (!first) w.ep = a.p_old[e];
-      }
+      cg_raw_fetch(a, first, g, idx, x, y, halo, w);
     };
-    // p_k from raw r and p_{k-1} (as pk1 / pk2)
     auto form = [&](const Vals<2> &r, const Vals<2> &po, double &v0, double &v1) {
-      v0 = r.v[0];
-      v1 = r.v[1];
-      if (!first) {
-        v0 = fma(beta, po.v[0], v0);
-        v1 = fma(beta, po.v[1], v1);
-      }
+      cg_form(first, beta, r, po, v0, v1);
     };
     for (ChunkIter it = xcd_chunks(nitems, a.nstream, 0); it.c < it.end; it.c += it.step) {
       const int seg = it.c / ntiles;
@@ -182,58 +309,21 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_a_kernel(CgArgs a) {
     store_partials<1>(acc, a.part_out, a.pstride, blockIdx.x, lds, red);
     return;
   }
-  const ChunkOrder order = chunk_order(g, D3, kChunk);
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0); it.c < it.end; it.c += it.step) {
     const int base = order.phys(it.c) * kChunk;
     const int idx0 = base + threadIdx.x * kVec;
     if (fast_rows && base + kChunk <= a.n) {
       // Same layout as the p(l)-CG fast path: pairs in one row, x-neighbours
       // from the adjacent lanes, 16-byte loads for the other rows and planes.
-      double c0, c1;
-      pk2(idx0, c0, c1);
-      const int x = idx0 % g.nx;
-      const int rest = idx0 / g.nx;
-      const int y = D3 ? rest % g.ny : rest;
-      const int lane = threadIdx.x & 63;
-      double left = lane_prev(c1);
-      double right = lane_next(c0);
-      if (lane == 0 && x > 0) left = pk1(idx0 - 1);
-      if (lane == 63 && x + 2 < g.nx) right = pk1(idx0 + 2);
-      double s0 = (x > 0 ? left : 0.0) + c1;
-      double s1 = c0 + (x + 2 < g.nx ? right : 0.0);
-      double u0, u1;
-      if (y > 0) {
-        pk2(idx0 - g.nx, u0, u1);
-        s0 += u0;
-        s1 += u1;
-      }
-      if (y < g.ny - 1) {
-        pk2(idx0 + g.nx, u0, u1);
-        s0 += u0;
-        s1 += u1;
-      }
-      if (D3) {
-        const int zz = rest / g.ny;
-        const int plane = g.nx * g.ny;
-        if (zz > 0) {
-          pk2(idx0 - plane, u0, u1);
-          s0 += u0;
-          s1 += u1;
-        }
-        if (zz < g.nz - 1) {
-          pk2(idx0 + plane, u0, u1);
-          s0 += u0;
-          s1 += u1;
+      if constexpr (!D3) {
+        if (have_pre) {   // the first chunk, preloaded
+          have_pre = false;
+          cg_a_fast<false, NTS>(a, g, idx0, CgFromRaw{pre, beta, first}, acc);
+          continue;
         }
       }
-      Vals<2> pn, qv;
-      pn.v[0] = c0;
-      pn.v[1] = c1;
-      qv.v[0] = fma(diag, c0, -s0);
-      qv.v[1] = fma(diag, c1, -s1);
-      pn.template st<NTS>(a.p_new + idx0);
-      qv.template st<NTS>(a.q + idx0);
-      acc[0] = fma(c1, qv.v[1], fma(c0, qv.v[0], acc[0]));
+      cg_a_fast<D3, NTS>(a, g, idx0,
+                         CgFromMemory{a.r, a.p_old, beta, first, idx0, g.nx, g.nx * g.ny}, acc);
       continue;
     }
 #pragma unroll
@@ -385,10 +475,62 @@ __global__ __launch_bounds__(kThreads) void cg_csr_sweep_a_kernel(CgArgs a) {
 // product (r_{k+1}, r_{k+1}).  P: paired x updates - for even k (a.xmode kXSkip)
 // x is left alone; for odd k (kXPair) x += alpha_{k-1} p_{k-1}, then alpha_k p_k,
 // with p_{k-1} still in the other p buffer (the same two roundings).
+// The vectors one pair of sweep B reads (x, p_k, r, q; paired updates: r, q,
+// and on odd k x, p_k and p_{k-1}), loaded by cg_b_load and used by cg_b_pair.
+struct CgBVals {
+  Vals<2> x, p, r, q, po;
+};
+
+template <int H, bool P>
+__device__ inline void cg_b_load(const CgArgs &a, int idx, bool upd, CgBVals &v) {
+  constexpr bool NTL = (H & kHintLoads) != 0;
+  if (!P || upd) {
+    v.x.template ld<NTL>(a.x + idx);
+    v.p.template ld<NTL>(a.p_new + idx);
+  }
+  v.r.template ld<NTL>(a.r + idx);
+  v.q.template ld<NTL>(a.q + idx);
+  if (P && upd) v.po.template ld<NTL>(a.p_old + idx);
+}
+
+template <int H, bool P>
+__device__ inline void cg_b_pair(const CgArgs &a, int idx, double alpha, double alpha_prev,
+                                 bool upd, CgBVals v, double (&acc)[1]) {
+  constexpr bool NTS = (H & kHintStores) != 0;
+  if constexpr (!P) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      v.x.v[k] = fma(alpha, v.p.v[k], v.x.v[k]);
+      v.r.v[k] = fma(-alpha, v.q.v[k], v.r.v[k]);
+      acc[0] = fma(v.r.v[k], v.r.v[k], acc[0]);
+    }
+    v.x.template st<NTS>(a.x + idx);
+    v.r.template st<NTS>(a.r + idx);
+  } else {
+    if (upd) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        v.x.v[k] = fma(alpha, v.p.v[k], fma(alpha_prev, v.po.v[k], v.x.v[k]));
+      v.x.template st<NTS>(a.x + idx);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      v.r.v[k] = fma(-alpha, v.q.v[k], v.r.v[k]);
+      acc[0] = fma(v.r.v[k], v.r.v[k], acc[0]);
+    }
+    v.r.template st<NTS>(a.r + idx);
+  }
+}
+
+// Sweep B of iteration k.  Prologue: alpha_k = rho_k / (p_k, q) from sweep A
+// (breakdown if (p_k, A p_k) <= 0).  Then x += alpha p_k, r -= alpha q and the
+// product (r_{k+1}, r_{k+1}).  P: paired x updates - for even k (a.xmode kXSkip)
+// x is left alone; for odd k (kXPair) x += alpha_{k-1} p_{k-1}, then alpha_k p_k,
+// with p_{k-1} still in the other p buffer (the same two roundings).  The first
+// pair's vectors are requested with the state and the partials, before the
+// workgroup waits for them (not where vectors are stored non-temporally).
 template <int H, bool P>
 __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
-  constexpr bool NTL = (H & kHintLoads) != 0;
-  constexpr bool NTS = (H & kHintStores) != 0;
   __shared__ double lds[4];
   __shared__ double red[1];
   __shared__ DevState sh;
@@ -396,6 +538,21 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
   PartRegs<1> pr;
   words_fetch(a.st_in, sw);
   partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, pr);
+  const bool upd = a.xmode == kXPair;   // P: this sweep writes x
+  CgBVals pre;
+  bool have_pre = false;
+  if constexpr ((H & kHintStores) == 0) {
+    if (a.work) {
+      const ChunkIter it0 = xcd_chunks(a.nchunks, a.nstream, 0, true);
+      if (it0.c < it0.end) {
+        const int idx = it0.at() * kChunk + threadIdx.x * kVec;
+        if (idx + 1 < a.n) {
+          cg_b_load<H, P>(a, idx, upd, pre);
+          have_pre = true;
+        }
+      }
+    }
+  }
   words_put(sw, &sh);
   if (sh.status == kRunning) {
     partials_sum<1>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
@@ -419,46 +576,19 @@ __global__ __launch_bounds__(kThreads) void cg_sweep_b_kernel(CgArgs a) {
 
   const double alpha = sh.cg_alpha;
   const double alpha_prev = sh.cg_alpha_prev;
-  const bool upd = a.xmode == kXPair;   // P: this sweep writes x
   double acc[1] = {0.0};
   // Sweep A walks the bands front to back, sweep B back to front.
   for (ChunkIter it = xcd_chunks(a.nchunks, a.nstream, 0, true); it.c < it.end; it.c += it.step) {
     const int idx = it.at() * kChunk + threadIdx.x * kVec;
     if (idx + 1 < a.n) {
-      if constexpr (!P) {
-        Vals<2> x, p, r, q;
-        x.template ld<NTL>(a.x + idx);
-        p.template ld<NTL>(a.p_new + idx);
-        r.template ld<NTL>(a.r + idx);
-        q.template ld<NTL>(a.q + idx);
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          x.v[v] = fma(alpha, p.v[v], x.v[v]);
-          r.v[v] = fma(-alpha, q.v[v], r.v[v]);
-          acc[0] = fma(r.v[v], r.v[v], acc[0]);
-        }
-        x.template st<NTS>(a.x + idx);
-        r.template st<NTS>(a.r + idx);
-      } else {
-        Vals<2> r, q;
-        r.template ld<NTL>(a.r + idx);
-        q.template ld<NTL>(a.q + idx);
-        if (upd) {
-          Vals<2> x, p, po;
-          x.template ld<NTL>(a.x + idx);
-          p.template ld<NTL>(a.p_new + idx);
-          po.template ld<NTL>(a.p_old + idx);
-#pragma unroll
-          for (int v = 0; v < 2; ++v) x.v[v] = fma(alpha, p.v[v], fma(alpha_prev, po.v[v], x.v[v]));
-          x.template st<NTS>(a.x + idx);
-        }
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          r.v[v] = fma(-alpha, q.v[v], r.v[v]);
-          acc[0] = fma(r.v[v], r.v[v], acc[0]);
-        }
-        r.template st<NTS>(a.r + idx);
+      if ((H & kHintStores) == 0 && have_pre) {   // the first pair, preloaded
+        have_pre = false;
+        cg_b_pair<H, P>(a, idx, alpha, alpha_prev, upd, pre, acc);
+        continue;
       }
+      CgBVals v;
+      cg_b_load<H, P>(a, idx, upd, v);
+      cg_b_pair<H, P>(a, idx, alpha, alpha_prev, upd, v, acc);
     } else if (idx < a.n) {
       if (!P)
         a.x[idx] = fma(alpha, a.p_new[idx], a.x[idx]);

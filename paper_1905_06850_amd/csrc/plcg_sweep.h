@@ -129,15 +129,25 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
 // ||r_k|| < tol ||r_0||.  Then p_k = r_k + beta_{k-1} p_{k-1} (p_0 = r_0),
 // q = A p_k and the product (p_k, q).
 //
-// Prologue of sweep A, every workgroup; returns false when nothing is streamed.
-__device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds, double *red) {
+// The prologue in two parts, so that a sweep can request its first chunk's
+// vectors in between: cg_a_fetch requests the state and sweep B's partials
+// (before the status says whether they are needed), cg_a_finish waits for them
+// and returns false when nothing is streamed.
+struct CgPrologue {
   WordRegs<DevState> sw;
   PartRegs<1> pr;
-  words_fetch(a.st_in, sw);
-  partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, pr);
-  words_put(sw, &sh);
+};
+
+__device__ inline void cg_a_fetch(const CgArgs &a, CgPrologue &f) {
+  words_fetch(a.st_in, f.sw);
+  partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, f.pr);
+}
+
+__device__ inline bool cg_a_finish(const CgArgs &a, CgPrologue &f, DevState &sh, double *lds,
+                                   double *red) {
+  words_put(f.sw, &sh);
   if (a.k >= 1 && sh.status == kRunning) {
-    partials_sum<1>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
+    partials_sum<1>(f.pr, a.part_in, a.nparts_in, a.pstride, lds, red);
     if (threadIdx.x == 0) {
       const double rho = red[0];
       sh.cols = a.k;
@@ -157,6 +167,12 @@ __device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds,
     if (threadIdx.x == 0) publish(sh, a.hs, sqrt(sh.cg_rho), 2 * a.k);
   }
   return sh.status == kRunning && a.work;
+}
+
+__device__ inline bool cg_a_prologue(const CgArgs &a, DevState &sh, double *lds, double *red) {
+  CgPrologue f;
+  cg_a_fetch(a, f);
+  return cg_a_finish(a, f, sh, lds, red);
 }
 
 }  // namespace plcg
