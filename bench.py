@@ -798,13 +798,14 @@ def roofline(workload, kind, head_method, hr):
 def block_3d(args, plcg, torch, dev):
     """The 256^3 3D 7-point Poisson workload at relative residual 1e-10 (b
     uniform, seed 0): CG, p(1)-CG and p(3)-CG in FP64 and FP32-stored p(3)-CG
-    in FP64 refinement, each solved to the same final accuracy; its working set
-    (1.3-1.6 GB in FP64) is far beyond the memory-side cache, so its roofline is
-    HBM-true.  Fewer steps than the headline (each solve takes 0.2-0.4 s)."""
+    and p(1)-CG in FP64 refinement, each solved to the same final accuracy; its
+    working set (1.3-1.6 GB in FP64) is far beyond the memory-side cache, so its
+    roofline is HBM-true.  Fewer steps than the headline (each solve takes
+    0.15-0.4 s)."""
     ctx = setup_workload(plcg, torch, dev, "poisson3d256")
     steps = max(1, min(args.steps, args.steps_3d))
     rows = run_methods(args, plcg, torch, ctx, [("cg", 0), ("plcg", 1), ("plcg", 3),
-                                                 ("mixed", 3)], steps, 1,
+                                                 ("mixed", 3), ("mixed", 1)], steps, 1,
                        inner_tol=args.inner_tol_3d)
     del ctx
     torch.cuda.empty_cache()
@@ -819,6 +820,7 @@ def block_3d(args, plcg, torch, dev):
         "iters_per_s": {k: v["iters_per_s"] for k, v in rows.items()},
         "mixed_inner_tol": args.inner_tol_3d,
         "mixed_vs_fp64_p3": p3["ms_per_solve"] / rows["m3"]["ms_per_solve"],
+        "fastest": min(rows, key=lambda k: rows[k]["ms_per_solve"]),
         "roofline": roofline("poisson3d256", "3d7", ("plcg", 3), p3),
         "roofline_cg": roofline("poisson3d256", "3d7", ("cg", 0), rows["cg"]),
         "methods": rows,
