@@ -706,22 +706,30 @@ struct Coef {
   double sig[L];
 };
 
+// Every entry is read whatever t is (ring indices clamped into range, entries a
+// sweep does not use replaced by zero afterwards), so that a workgroup reading
+// s from global memory issues all its loads at once: one round trip, where
+// loads under conditions on t took up to three dependent ones.
 template <int L>
 __device__ inline void read_coef(const DevState &s, int i, int t, Coef<L> &cf) {
-  if (t >= 0) {
-    cf.gam = s.gam[t % kTRing];
-    cf.inv_del = 1.0 / s.dlt[t % kTRing];
-    cf.dm1 = t >= 1 ? s.dlt[(t - 1) % kTRing] : 0.0;
-    cf.inv_eta = 1.0 / s.eta[t % kTRing];
-    cf.zm1 = t >= 1 ? s.zeta[(t - 1) % kTRing] : 0.0;
-    cf.zm2 = t >= 2 ? s.zeta[(t - 2) % kTRing] : 0.0;
-    cf.sigma_i = 0.0;
-  } else {
-    cf.gam = cf.inv_del = cf.dm1 = cf.inv_eta = cf.zm1 = cf.zm2 = 0.0;
-    cf.sigma_i = s.sigma[i];
-  }
+  const int t0 = (t >= 0 ? t : 0) % kTRing;
+  const int t1 = (t >= 1 ? t - 1 : 0) % kTRing;
+  const int t2 = (t >= 2 ? t - 2 : 0) % kTRing;
+  const double gam = s.gam[t0], dlt = s.dlt[t0], dlt1 = s.dlt[t1], eta = s.eta[t0];
+  const double zeta1 = s.zeta[t1], zeta2 = s.zeta[t2];
+  const double sigma_i = s.sigma[i >= 0 && i < kLMax ? i : 0];
+  double sig[L];
 #pragma unroll
-  for (int k = 0; k < L; ++k) cf.sig[k] = s.sigma[k];
+  for (int k = 0; k < L; ++k) sig[k] = s.sigma[k];
+  cf.gam = t >= 0 ? gam : 0.0;
+  cf.inv_del = t >= 0 ? 1.0 / dlt : 0.0;
+  cf.dm1 = t >= 1 ? dlt1 : 0.0;
+  cf.inv_eta = t >= 0 ? 1.0 / eta : 0.0;
+  cf.zm1 = t >= 1 ? zeta1 : 0.0;
+  cf.zm2 = t >= 2 ? zeta2 : 0.0;
+  cf.sigma_i = t >= 0 ? 0.0 : sigma_i;
+#pragma unroll
+  for (int k = 0; k < L; ++k) cf.sig[k] = sig[k];
 }
 
 // The unscaled integer Dirichlet Laplacian (5-point in 2D, 7-point in 3D).

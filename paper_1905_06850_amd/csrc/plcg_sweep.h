@@ -97,6 +97,13 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
     status = a.st_in->status;
     last_t = a.st_in->last_t;
     read_coef<L>(*a.st_in, i, t, cf);
+    // The coefficients are taken as used here, before the status test: kept
+    // after it, their loads were issued only once the status had arrived (a
+    // second round trip).
+    asm volatile("" ::"v"(cf.gam), "v"(cf.dm1), "v"(cf.inv_del), "v"(cf.inv_eta), "v"(cf.zm1),
+                 "v"(cf.zm2), "v"(cf.sigma_i));
+#pragma unroll
+    for (int k = 0; k < L; ++k) asm volatile("" ::"v"(cf.sig[k]));
   }
   // Sweeps past the stop change nothing (the solve's x is x_{last_t}).
   if (status != kRunning && t > last_t) return;
