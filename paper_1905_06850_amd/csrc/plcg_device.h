@@ -609,11 +609,105 @@ __host__ __device__ inline void engine_column(DevState &s, const double *raw, in
 // being written and re-read through the state's G ring, and stored once at the
 // end.  Finalised columns are only read, so their loads need not wait for the
 // new column's updates.
+// The column step for l = 1, the step every p(1)-CG workgroup runs before it
+// streams, in two parts: engine_gather_1 reads every entry of the state the
+// column may use (indices clamped into range; what a branch does not take goes
+// unused), engine_column_1 computes with the same expressions as the general
+// form below.  A kernel can so issue all reads of its LDS copy together (and
+// make sure of it between the two calls) instead of one per branch.
+struct EngineIn1 {
+  double g_tt;     // g_{c-1,c-1}: the symmetric entry g_{c-1,c-1} of column c and g_{t,t}
+  double g_pt;     // g_{t-1,t}
+  double dlt1, gam1, eta1, zeta1;   // entries t-1 of the rings
+  double sigma0, beta, abs_tol;
+  int hist_cap;
+};
+
+__host__ __device__ inline EngineIn1 engine_gather_1(const DevState &s, int c) {
+  const int t = c - 1;
+  const int tp = t >= 1 ? t - 1 : 0;
+  EngineIn1 in;
+  in.g_tt = s.g[((c - 1) % kGRing + kGRing) % kGRing][2 * kLMax];
+  in.g_pt = s.g[(t % kGRing + kGRing) % kGRing][tp - t + 2 * kLMax];
+  in.dlt1 = s.dlt[tp % kTRing];
+  in.gam1 = s.gam[tp % kTRing];
+  in.eta1 = s.eta[tp % kTRing];
+  in.zeta1 = s.zeta[tp % kTRing];
+  in.sigma0 = s.sigma[0];
+  in.beta = s.beta;
+  in.abs_tol = s.abs_tol;
+  in.hist_cap = s.hist_cap;
+  return in;
+}
+
+__host__ __device__ inline void engine_column_1(DevState &s, const EngineIn1 &in,
+                                                const double *raw, int c, double *hist) {
+  const int t = c - 1;
+  double gc[3];
+  gc[0] = c - 2 >= 0 ? in.g_tt : 0.0;
+  gc[1] = c - 1 >= 0 ? raw[0] : 0.0;
+  gc[2] = c >= 0 ? raw[1] : 0.0;
+  double arg = gc[2];
+  if (c - 2 >= 0) arg -= gc[0] * gc[0];
+  if (c - 1 >= 0) arg -= gc[1] * gc[1];
+  bool broken = !(isfinite(arg) && arg > 0.0);
+  double gam = 0.0, dlt = 0.0, eta = 0.0, zeta = 0.0;
+  if (!broken) {
+    gc[2] = sqrt(arg);
+    const double gtt = in.g_tt;
+    const double corr = t >= 1 ? in.g_pt * in.dlt1 : 0.0;
+    if (t < 1) {
+      gam = (gc[1] + in.sigma0 * gtt - corr) / gtt;
+      dlt = gc[2] / gtt;
+    } else {
+      gam = (gtt * in.gam1 + gc[1] * in.dlt1 - corr) / gtt;
+      dlt = (gc[2] * in.dlt1) / gtt;
+    }
+    broken = !(isfinite(gam) && isfinite(dlt) && dlt > 0.0);
+    if (!broken) {
+      if (t == 0) {
+        eta = gam;
+        zeta = in.beta;
+      } else {
+        const double lam = in.dlt1 / in.eta1;
+        eta = gam - lam * in.dlt1;
+        zeta = -lam * in.zeta1;
+      }
+      broken = !(isfinite(eta) && eta > 0.0 && isfinite(zeta));
+    }
+  }
+  for (int q = 0; q < 3; ++q) gref(s, c - 2 + q, c) = gc[q];
+  s.cols = c;
+  if (broken) {
+    s.status = kBroken;
+    s.last_t = t - 1;
+    return;
+  }
+  s.gam[t % kTRing] = gam;
+  s.dlt[t % kTRing] = dlt;
+  s.eta[t % kTRing] = eta;
+  s.zeta[t % kTRing] = zeta;
+  if (hist != nullptr && t < in.hist_cap) {
+    hist[4 * t + 0] = gam;
+    hist[4 * t + 1] = dlt;
+    hist[4 * t + 2] = eta;
+    hist[4 * t + 3] = zeta;
+  }
+  if (t >= 1 && fabs(zeta) < in.abs_tol) {
+    s.status = kConverged;
+    s.last_t = t;
+  }
+}
+
 template <int L>
 __host__ __device__ inline void engine_column_l(DevState &s, const double *raw, int c,
                                                 double *hist) {
   constexpr int W = 2 * L + 1;
   const int t = c - 1;
+  if constexpr (L == 1) {
+    engine_column_1(s, engine_gather_1(s, c), raw, c, hist);
+    return;
+  }
   double gc[W];
 #pragma unroll
   for (int q = 0; q < W; ++q) gc[q] = 0.0;

@@ -39,8 +39,20 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   auto engine_step = [&]() {
     words_put(sw, &sh);
     if (i >= 1 && a.nparts_in > 0 && sh.status == kRunning) {
-      partials_sum<ND>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
-      if (threadIdx.x == 0) engine_column_l<L>(sh, red, i, owner ? a.hist : nullptr);
+      if constexpr (L == 1) {
+        // The state entries of the column step are read from LDS before the
+        // partial sums, taken as used right away, so their reads are done
+        // while the sums run; thread 0 then only computes.
+        const EngineIn1 in = engine_gather_1(sh, i);
+        asm volatile("" ::"v"(in.g_tt), "v"(in.g_pt), "v"(in.dlt1), "v"(in.gam1), "v"(in.eta1),
+                     "v"(in.zeta1), "v"(in.sigma0), "v"(in.beta), "v"(in.abs_tol),
+                     "v"(in.hist_cap));
+        partials_sum<ND>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
+        if (threadIdx.x == 0) engine_column_1(sh, in, red, i, owner ? a.hist : nullptr);
+      } else {
+        partials_sum<ND>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
+        if (threadIdx.x == 0) engine_column_l<L>(sh, red, i, owner ? a.hist : nullptr);
+      }
       __syncthreads();
     }
     if (owner) {
