@@ -145,13 +145,22 @@ __global__ __launch_bounds__(kResThreads) void plcg_resident_kernel(ResArgs a) {
       ctl[1][1] = sh.last_t;
     }
     __syncthreads();
+    // l = 1: thread 0 reads the state entries of column i+1 while the other
+    // waves run sweep i (engine_gather_1), so that after the products arrive
+    // the column step is arithmetic only.
+    EngineIn1 in1{};
     for (int i = 0; i <= a.imax; ++i) {
       // column i of G from the products of sweep i-1
       if (i >= 1 && sh.status == kRunning) {
         double raw[ND];
 #pragma unroll
         for (int m = 0; m < ND; ++m) raw[m] = waves_total<ND>(red[(i - 1) & 1], m, kResWaves - 1);
-        if (tid == 0) engine_column_l<L>(sh, raw, i, a.hist);
+        if (tid == 0) {
+          if constexpr (L == 1)
+            engine_column_1(sh, in1, raw, i, a.hist);
+          else
+            engine_column_l<L>(sh, raw, i, a.hist);
+        }
       }
       if (tid == 0) {
         ctl[i & 1][0] = sh.status;
@@ -159,6 +168,14 @@ __global__ __launch_bounds__(kResThreads) void plcg_resident_kernel(ResArgs a) {
       }
       if (L == 1) __syncthreads();   // sweep i needs column i at once
       if (stop(i)) break;
+      if constexpr (L == 1) {
+        if (tid == 0) {
+          in1 = engine_gather_1(sh, i + 1);
+          asm volatile("" ::"v"(in1.g_tt), "v"(in1.g_pt), "v"(in1.dlt1), "v"(in1.gam1),
+                       "v"(in1.eta1), "v"(in1.zeta1), "v"(in1.sigma0), "v"(in1.beta),
+                       "v"(in1.abs_tol), "v"(in1.hist_cap));
+        }
+      }
       __syncthreads();
     }
   } else {
