@@ -53,17 +53,17 @@ enum {
 };
 
 /* Operator kinds: unscaled integer Dirichlet Laplacians (spectrum inside (0, 8)
- * in 2D and (0, 12) in 3D), and a diagonal matrix - the "one-point stencil" of
- * the paper's communication-bound toy problem (Sec. 4.2), whose diagonal holds
- * the 2D Laplacian's eigenvalues so that CG sees the same spectrum with an SpMV
- * that costs no more than a vector update. */
+ * in 2D and (0, 12) in 3D), a general sparse matrix, and a diagonal matrix - the
+ * "one-point stencil" of the paper's communication-bound toy problem (Sec. 4.2),
+ * whose diagonal holds the 2D Laplacian's eigenvalues so that CG sees the same
+ * spectrum with an SpMV that costs no more than a vector update. */
 enum {
   PLCG_OP_STENCIL2D5 = 1,  /* (Au) = 4u - u(x-1) - u(x+1) - u(y-1) - u(y+1) */
   PLCG_OP_STENCIL3D7 = 2,  /* (Au) = 6u - sum of the six face neighbours    */
-  PLCG_OP_DIAG = 3,        /* (Au)_p = d_p u_p, d given in plcg_operator_desc.diag */
-  PLCG_OP_CSR = 4          /* a general sparse matrix in compressed sparse rows (the
+  PLCG_OP_CSR = 3,         /* a general sparse matrix in compressed sparse rows (the
                               assembled matrices the paper's PETSc runs use); it must be
                               symmetric positive definite */
+  PLCG_OP_DIAG = 4         /* (Au)_p = d_p u_p, d given in plcg_operator_desc.diag */
 };
 
 enum { PLCG_METHOD_CG = 0, PLCG_METHOD_PLCG = 1 };

@@ -1167,7 +1167,10 @@ const char *plcg_last_error(void) { return g_last_error.c_str(); }
 int32_t plcg_version(void) { return 100; }
 
 int32_t plcg_resident_supported(int32_t kind, int64_t n, int32_t method, int32_t l) {
-  if (kind < PLCG_OP_STENCIL2D5 || kind > PLCG_OP_CSR || n < 1 || n > PLCG_RESIDENT_MAX) return 0;
+  if (kind != PLCG_OP_STENCIL2D5 && kind != PLCG_OP_STENCIL3D7 && kind != PLCG_OP_CSR &&
+      kind != PLCG_OP_DIAG)
+    return 0;
+  if (n < 1 || n > PLCG_RESIDENT_MAX) return 0;
   if (method != PLCG_METHOD_CG && method != PLCG_METHOD_PLCG) return 0;
   return resident_width(method == PLCG_METHOD_PLCG ? 1 : 0, l, op_kind_index(kind), (int)n) > 0
              ? 1

@@ -25,8 +25,8 @@ PLCG_E_NONFINITE = -5
 
 PLCG_OP_STENCIL2D5 = 1
 PLCG_OP_STENCIL3D7 = 2
-PLCG_OP_DIAG = 3
-PLCG_OP_CSR = 4
+PLCG_OP_CSR = 3
+PLCG_OP_DIAG = 4
 PLCG_METHOD_CG = 0
 PLCG_METHOD_PLCG = 1
 PLCG_PREC_FP64 = 0

@@ -153,14 +153,15 @@ def test_noalloc_rejects_before_device_work(kind, nx, ny, nz, l, hist):
     (1, 1, (16, None, None), 0),        # cy missing
     (2, 4, (16, 32, None), 0),          # cz missing in 3D
     (1, 1, (None, 32, None), 0),        # cy without cx
-    (3, 1, (16, 32, None), 0),          # coefficients on a diagonal operator
+    (4, 1, (16, 32, None), 0),          # coefficients on a diagonal operator
     (1, 1, (None, None, None), 1),      # Jacobi scaling of the constant stencil
 ])
 def test_create_rejects_bad_edge_coefficients(kind, nz, coef, jacobi):
     """Descriptor checks of the variable-coefficient stencil made before any
     device access (the addresses are never read)."""
     from paper_1905_06850_amd import plcg
-    desc = plcg.plcg_operator_desc(kind, 8, 8, nz, 64 if kind == 3 else None, 0, None, None,
+    desc = plcg.plcg_operator_desc(kind, 8, 8, nz, 64 if kind == plcg.PLCG_OP_DIAG else None, 0,
+                                   None, None,
                                    None, jacobi, *coef)
     cfg = plcg.plcg_config(1, 2, 0.0, 2.0, None, 0, -1, 0)
     h = ctypes.c_void_p()
