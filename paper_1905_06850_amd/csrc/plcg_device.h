@@ -388,43 +388,46 @@ __device__ inline void block_sum(const double (&acc)[ND], double *lds /* [4][ND]
 // caller can request the partials together with its other loads (all of a
 // thread's loads in flight at once: one memory round trip, not one per load).
 // The loads are unconditional - every partial buffer holds ND rows of at least
-// kMaxStream entries, pstride apart - so the compiler can count them exactly
-// and wait for an earlier load without waiting for these.
+// PER * kThreads entries, pstride apart - so the compiler can count them
+// exactly and wait for an earlier load without waiting for these.  PER is
+// kPartPer for kMaxStream workgroups, kSweepPer for the wider p(l)-CG sweeps.
 constexpr int kPartPer = kMaxStream / kThreads;   // partials per product and thread
-static_assert(kMaxStream % kThreads == 0, "partials split evenly over the threads");
+constexpr int kSweepPer = kSweepStream / kThreads;
+static_assert(kMaxStream % kThreads == 0 && kSweepStream % kThreads == 0,
+              "partials split evenly over the threads");
 
-template <int ND>
+template <int ND, int PER = kPartPer>
 struct PartRegs {
-  double v[ND][kPartPer];
+  double v[ND][PER];
 };
 
-template <int ND>
+template <int ND, int PER>
 __device__ inline void partials_fetch(const double *part, int nparts, int pstride,
-                                      PartRegs<ND> &r) {
+                                      PartRegs<ND, PER> &r) {
 #pragma unroll
   for (int m = 0; m < ND; ++m)
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) r.v[m][j] = part[m * pstride + threadIdx.x + j * kThreads];
+    for (int j = 0; j < PER; ++j) r.v[m][j] = part[m * pstride + threadIdx.x + j * kThreads];
 }
 
-template <int ND>
-__device__ inline void partials_sum(PartRegs<ND> r, const double *part, int nparts, int pstride,
-                                    double *lds, double *out) {
+template <int ND, int PER>
+__device__ inline void partials_sum(PartRegs<ND, PER> r, const double *part, int nparts,
+                                    int pstride, double *lds, double *out) {
   // The values are taken as opaque here, so no addition is moved up to where
   // the loads were issued (the workgroup would wait for them there).
 #pragma unroll
   for (int m = 0; m < ND; ++m)
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j) asm volatile("" : "+v"(r.v[m][j]));
+    for (int j = 0; j < PER; ++j) asm volatile("" : "+v"(r.v[m][j]));
   double s[ND];
 #pragma unroll
   for (int m = 0; m < ND; ++m) {
     double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < kPartPer; ++j)
+    for (int j = 0; j < PER; ++j)
       if ((int)threadIdx.x + j * kThreads < nparts) acc += r.v[m][j];
-    // More partials than kMaxStream never occur; kept so any count sums right.
-    for (int b = threadIdx.x + kPartPer * kThreads; b < nparts; b += kThreads)
+    // More partials than PER * kThreads never occur; kept so any count sums right.
+    for (int b = threadIdx.x + PER * kThreads; b < nparts; b += kThreads)
       acc += part[m * pstride + b];
     s[m] = acc;
   }
@@ -440,8 +443,8 @@ __device__ inline void sum_partials(const double *part, int nparts, int pstride,
                                     double *out) {
   if constexpr (ND <= 3) {
     PartRegs<ND> r;
-    partials_fetch<ND>(part, nparts, pstride, r);
-    partials_sum<ND>(r, part, nparts, pstride, lds, out);
+    partials_fetch<ND, kPartPer>(part, nparts, pstride, r);
+    partials_sum<ND, kPartPer>(r, part, nparts, pstride, lds, out);
   } else {
     double s[ND];
 #pragma unroll

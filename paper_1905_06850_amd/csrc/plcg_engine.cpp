@@ -53,7 +53,6 @@ constexpr long long kLargeVector = 96LL << 20;   // vectors worth storing non-te
 constexpr int kResIterCap = 1 << 20;
 constexpr int kDefaultRestarts = 100;
 
-// Streaming workgroups of a launch: one per chunk up to kMaxStream, a multiple of 8.
 // Streaming cache hints for the sweeps of a solver whose vectors are `word`
 // bytes per unknown (measured on 2048^2 and 256^3 Poisson, the 2048^2 CSR
 // matrix and diagonal toy): non-temporal loads pay once the vectors and
@@ -90,11 +89,37 @@ int op_kind_index(int kind) {
   return kind == PLCG_OP_STENCIL3D7 ? 1 : kind == PLCG_OP_DIAG ? 2 : kind == PLCG_OP_CSR ? 3 : 0;
 }
 
+// Streaming workgroups of a launch: one per chunk up to kMaxStream, a multiple of 8.
 int grid_blocks(int nchunks) {
   int b = ((nchunks + kXcds - 1) / kXcds) * kXcds;
   if (b > kMaxStream) b = kMaxStream;
   if (b < kXcds) b = kXcds;
   return b;
+}
+
+// Streaming workgroups of a p(l)-CG sweep.  Without cache hints (the working
+// set fits the memory-side cache) grid_blocks.  With them, as many as a CU
+// keeps resident of the sweep's kernel, at most kSweepPerCu per CU, when that
+// is more than four; grid_blocks where the occupancy cannot be read.  A
+// multiple of kXcds, at most one per chunk rounded up to kXcds.  Measured per
+// sweep against grid_blocks: 256^3 p(1) 240.8 -> 215.0 us, its FP32-stored form
+// 122.8 -> 109.2, p(3) -4.7 %; 2048^2 p(4), p(5) -2.9 %, the variable stencil
+// -2 to -3 %, CSR -1 %; the diagonal operator 2 % slower, so not for it.
+template <typename S>
+int sweep_blocks(const SweepArgsT<S> &a, int device, int nchunks) {
+  const int base = grid_blocks(nchunks);
+  if (a.hint == 0 || a.od.dg != nullptr) return base;
+  int per_cu = 0, cus = 0;
+  if (plcg_sweep_occupancy(a, &per_cu) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return base;
+  if (per_cu > kSweepPerCu) per_cu = kSweepPerCu;
+  if (per_cu <= 4) return base;
+  int b = (per_cu * cus / kXcds) * kXcds;
+  if (b > kSweepStream) b = kSweepStream;
+  const int cap = ((nchunks + kXcds - 1) / kXcds) * kXcds;
+  if (b > cap) b = cap;
+  return b > base ? b : base;
 }
 
 }  // namespace
@@ -117,6 +142,7 @@ struct plcg_handle {
   bool d3 = false;
   int res_kind = -1;              // operator kind of the resident kernels; -1: streaming
   int hint64 = 0, hint32 = 0;     // streaming cache hints of the FP64 / FP32-stored sweeps
+  int sweep_nb[2] = {0, 0};       // streaming workgroups of the FP32 / FP64-stored sweeps (0: not chosen yet)
   bool pair64 = false, pair32 = false;   // the same sweeps update x on even t only
   bool ran_resident = false;      // the current solve ran resident launches
   OpData od{nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr};   // library copies of the operator data
@@ -337,11 +363,15 @@ void fill_sweep_args(plcg_handle *h, int i, S *const (*basis)[2], S *const *ring
   // chunks of kThreads * (16 / sizeof(S)) unknowns: 512 doubles or 1024 floats
   const int chunk = kThreads * (16 / (int)sizeof(S));
   a.nchunks = (h->n + chunk - 1) / chunk;
-  a.nstream = h->blocks;
-  a.nparts_in = i >= 1 ? h->blocks : 0;
-  a.pstride = kMaxStream;
-  a.work = 1;
   a.hint = sizeof(S) == 8 ? h->hint64 : h->hint32;
+  // chosen at the first sweep of the handle (the kernel is then known), kept
+  // for every later one: a sweep sums the partials of the one before it
+  int &nb = h->sweep_nb[sizeof(S) == 8 ? 1 : 0];
+  if (nb == 0) nb = sweep_blocks(a, h->device, a.nchunks);
+  a.nstream = nb;
+  a.nparts_in = i >= 1 ? nb : 0;
+  a.pstride = kSweepStream;
+  a.work = 1;
 }
 
 // r = b - A x (r may be NULL) and ||r||^2 into state copy `slot`; mode as in
@@ -1005,7 +1035,7 @@ struct Workspace {
   int nvec, nvec32;
   size_t vec32_at, part_at, st_at, hist_at, hs_at, total;   // offsets (bytes) and size
 };
-constexpr size_t kPartBytes = sizeof(double) * (kLMax + 1) * kMaxStream;
+constexpr size_t kPartBytes = sizeof(double) * (kLMax + 1) * kSweepStream;
 
 Workspace workspace_layout(const plcg_handle *h, bool status_record) {
   auto up = [](size_t v, size_t a) { return (v + a - 1) / a * a; };

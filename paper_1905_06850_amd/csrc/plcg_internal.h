@@ -22,6 +22,14 @@ constexpr int kVec = 2;               // consecutive unknowns per thread and chu
 constexpr int kChunk = kThreads * kVec;
 constexpr int kXcds = 8;              // MI355X: workgroups are dealt round-robin to 8 XCDs
 constexpr int kMaxStream = 1024;      // streaming blocks per launch (multiple of kXcds)
+// The p(l)-CG sweeps of a working set beyond the memory-side cache (those with
+// cache hints) stream with as many workgroups as a CU keeps resident, up to six
+// per CU: more waves keep more loads in flight, which is what an HBM-bound
+// stream needs (256^3: p(1) 240 -> 213 us per sweep with six per CU instead of
+// four; seven or eight per CU were slower than four).  Their partials are laid
+// out for up to kSweepStream workgroups.
+constexpr int kSweepPerCu = 6;
+constexpr int kSweepStream = 1536;    // = kSweepPerCu * 256 CUs (multiple of kXcds and kThreads)
 // Largest number of unknowns: indices are int32, and a loop that has reached
 // the last unknown may still add one launch's stride (< 2^22) before its test.
 constexpr long long kMaxUnknowns = (1LL << 31) - (1LL << 23);
@@ -172,6 +180,10 @@ hipError_t launch_cg_resident(const ResArgs &a, int kind, hipStream_t s);
 // Launchers (plcg_kernels.hip).
 hipError_t launch_plcg_sweep(const SweepArgsT<double> &a, hipStream_t s);
 hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s);
+// Workgroups per CU that the kernel launch_plcg_sweep would run for `a` keeps
+// resident (hipOccupancyMaxActiveBlocksPerMultiprocessor); nothing is launched.
+hipError_t plcg_sweep_occupancy(const SweepArgsT<double> &a, int *per_cu);
+hipError_t plcg_sweep_occupancy(const SweepArgsT<float> &a, int *per_cu);
 hipError_t launch_cg_sweep_a(const CgArgs &a, hipStream_t s);
 hipError_t launch_cg_sweep_b(const CgArgs &a, hipStream_t s);
 // r = b - A x (r may be NULL); per-block partial sums of r.r into part_out, or
@@ -204,8 +216,9 @@ hipError_t launch_apply(const double *x, double *y, int n, int nx, int ny, int n
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t s);
 // The same for the variable-coefficient stencil (od.sx != NULL; plcg_var_kernels.hip);
 // the launchers above hand such operators over to these.
-hipError_t launch_var_sweep(const SweepArgsT<double> &a, hipStream_t s);
-hipError_t launch_var_sweep(const SweepArgsT<float> &a, hipStream_t s);
+// With occ not NULL the var launcher reports the kernel's occupancy instead of launching.
+hipError_t launch_var_sweep(const SweepArgsT<double> &a, hipStream_t s, int *occ = nullptr);
+hipError_t launch_var_sweep(const SweepArgsT<float> &a, hipStream_t s, int *occ = nullptr);
 hipError_t launch_var_cg_sweep_a(const CgArgs &a, hipStream_t s);
 hipError_t launch_var_residual(const double *b, const double *x, double *r, double *part_out,
                                int n, int nx, int ny, int nz, bool d3, const OpData &od,

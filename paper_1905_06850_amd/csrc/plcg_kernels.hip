@@ -757,62 +757,79 @@ static int simple_blocks(int64_t n) {
   return (int)b;
 }
 
-template <int L, typename S, int H, bool P>
-static hipError_t launch_sweep_lhp(const SweepArgsT<S> &a, hipStream_t s) {
-  const int grid = a.nstream + (L >= 2 ? 1 : 0);
-  if (a.od.rp != nullptr)
-    hipLaunchKernelGGL((plcg_csr_sweep_kernel<L, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
-  else if (a.od.dg != nullptr)
-    hipLaunchKernelGGL((plcg_diag_sweep_kernel<L, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
-  else if (a.d3)
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, true, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((plcg_sweep_kernel<L, false, S, H, P>), dim3(grid), dim3(kThreads), 0, s, a);
+// Launch the sweep kernel that `a` selects or, with occ not NULL, report how
+// many of its workgroups a CU keeps resident (the same selection, nothing
+// launched).
+template <typename S, typename K>
+static hipError_t launch_or_occupancy(K kernel, int grid, const SweepArgsT<S> &a, hipStream_t s,
+                                      int *occ) {
+  if (occ != nullptr) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kernel, kThreads, 0);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
+template <int L, typename S, int H, bool P>
+static hipError_t launch_sweep_lhp(const SweepArgsT<S> &a, hipStream_t s, int *occ) {
+  const int grid = a.nstream + (L >= 2 ? 1 : 0);
+  if (a.od.rp != nullptr)
+    return launch_or_occupancy(plcg_csr_sweep_kernel<L, S, H, P>, grid, a, s, occ);
+  if (a.od.dg != nullptr)
+    return launch_or_occupancy(plcg_diag_sweep_kernel<L, S, H, P>, grid, a, s, occ);
+  if (a.d3) return launch_or_occupancy(plcg_sweep_kernel<L, true, S, H, P>, grid, a, s, occ);
+  return launch_or_occupancy(plcg_sweep_kernel<L, false, S, H, P>, grid, a, s, occ);
+}
+
 template <int L, typename S, int H>
-static hipError_t launch_sweep_lh(const SweepArgsT<S> &a, hipStream_t s) {
+static hipError_t launch_sweep_lh(const SweepArgsT<S> &a, hipStream_t s, int *occ) {
   switch (a.xmode) {
-    case kXEvery: return launch_sweep_lhp<L, S, H, false>(a, s);
+    case kXEvery: return launch_sweep_lhp<L, S, H, false>(a, s, occ);
     case kXSkip:
-    case kXPair: return launch_sweep_lhp<L, S, H, true>(a, s);
+    case kXPair: return launch_sweep_lhp<L, S, H, true>(a, s, occ);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int L, typename S>
-static hipError_t launch_sweep_l(const SweepArgsT<S> &a, hipStream_t s) {
+static hipError_t launch_sweep_l(const SweepArgsT<S> &a, hipStream_t s, int *occ) {
   switch (a.hint) {
-    case 0: return launch_sweep_lh<L, S, 0>(a, s);
-    case kHintLoads: return launch_sweep_lh<L, S, kHintLoads>(a, s);
-    case kHintLoads | kHintStores: return launch_sweep_lh<L, S, kHintLoads | kHintStores>(a, s);
+    case 0: return launch_sweep_lh<L, S, 0>(a, s, occ);
+    case kHintLoads: return launch_sweep_lh<L, S, kHintLoads>(a, s, occ);
+    case kHintLoads | kHintStores:
+      return launch_sweep_lh<L, S, kHintLoads | kHintStores>(a, s, occ);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename S>
-static hipError_t launch_sweep_any(const SweepArgsT<S> &a, hipStream_t s) {
-  if (a.od.sx != nullptr) return launch_var_sweep(a, s);
+static hipError_t launch_sweep_any(const SweepArgsT<S> &a, hipStream_t s, int *occ) {
+  if (a.od.sx != nullptr) return launch_var_sweep(a, s, occ);
   switch (a.l) {
-    case 1: return launch_sweep_l<1, S>(a, s);
-    case 2: return launch_sweep_l<2, S>(a, s);
-    case 3: return launch_sweep_l<3, S>(a, s);
-    case 4: return launch_sweep_l<4, S>(a, s);
-    case 5: return launch_sweep_l<5, S>(a, s);
-    case 6: return launch_sweep_l<6, S>(a, s);
-    case 7: return launch_sweep_l<7, S>(a, s);
-    case 8: return launch_sweep_l<8, S>(a, s);
+    case 1: return launch_sweep_l<1, S>(a, s, occ);
+    case 2: return launch_sweep_l<2, S>(a, s, occ);
+    case 3: return launch_sweep_l<3, S>(a, s, occ);
+    case 4: return launch_sweep_l<4, S>(a, s, occ);
+    case 5: return launch_sweep_l<5, S>(a, s, occ);
+    case 6: return launch_sweep_l<6, S>(a, s, occ);
+    case 7: return launch_sweep_l<7, S>(a, s, occ);
+    case 8: return launch_sweep_l<8, S>(a, s, occ);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_plcg_sweep(const SweepArgsT<double> &a, hipStream_t s) {
-  return launch_sweep_any<double>(a, s);
+  return launch_sweep_any<double>(a, s, nullptr);
 }
 
 hipError_t launch_plcg_sweep(const SweepArgsT<float> &a, hipStream_t s) {
-  return launch_sweep_any<float>(a, s);
+  return launch_sweep_any<float>(a, s, nullptr);
+}
+
+hipError_t plcg_sweep_occupancy(const SweepArgsT<double> &a, int *per_cu) {
+  return launch_sweep_any<double>(a, nullptr, per_cu);
+}
+
+hipError_t plcg_sweep_occupancy(const SweepArgsT<float> &a, int *per_cu) {
+  return launch_sweep_any<float>(a, nullptr, per_cu);
 }
 
 template <int H>

@@ -30,11 +30,16 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
   const int t = i - L;
   // The state and the previous sweep's partials, requested together (the
   // partials before the status says whether they are needed), then column i.
+  // Sweeps with cache hints may run up to kSweepStream workgroups; up to three
+  // products their partials are all requested at once, beyond that (l >= 3,
+  // where only the owner sums) those past kMaxStream one at a time, in the same
+  // order, so that the owner's registers do not raise the kernel's count.
+  constexpr int PER = H != 0 && ND <= 3 ? kSweepPer : kPartPer;
   WordRegs<DevState> sw;
-  PartRegs<ND> pr;
+  PartRegs<ND, PER> pr;
   auto engine_fetch = [&]() {
     words_fetch(a.st_in, sw);
-    partials_fetch<ND>(a.part_in, a.nparts_in, a.pstride, pr);
+    partials_fetch<ND, PER>(a.part_in, a.nparts_in, a.pstride, pr);
   };
   auto engine_step = [&]() {
     words_put(sw, &sh);
@@ -47,10 +52,10 @@ __device__ inline void plcg_sweep(const SweepArgsT<ST> &a, const Op &op, bool fa
         asm volatile("" ::"v"(in.g_tt), "v"(in.g_pt), "v"(in.dlt1), "v"(in.gam1), "v"(in.eta1),
                      "v"(in.zeta1), "v"(in.sigma0), "v"(in.beta), "v"(in.abs_tol),
                      "v"(in.hist_cap));
-        partials_sum<ND>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
+        partials_sum<ND, PER>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
         if (threadIdx.x == 0) engine_column_1(sh, in, red, i, owner ? a.hist : nullptr);
       } else {
-        partials_sum<ND>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
+        partials_sum<ND, PER>(pr, a.part_in, a.nparts_in, a.pstride, lds, red);
         if (threadIdx.x == 0) engine_column_l<L>(sh, red, i, owner ? a.hist : nullptr);
       }
       __syncthreads();
@@ -159,14 +164,14 @@ struct CgPrologue {
 
 __device__ inline void cg_a_fetch(const CgArgs &a, CgPrologue &f) {
   words_fetch(a.st_in, f.sw);
-  partials_fetch<1>(a.part_in, a.nparts_in, a.pstride, f.pr);
+  partials_fetch<1, kPartPer>(a.part_in, a.nparts_in, a.pstride, f.pr);
 }
 
 __device__ inline bool cg_a_finish(const CgArgs &a, CgPrologue &f, DevState &sh, double *lds,
                                    double *red) {
   words_put(f.sw, &sh);
   if (a.k >= 1 && sh.status == kRunning) {
-    partials_sum<1>(f.pr, a.part_in, a.nparts_in, a.pstride, lds, red);
+    partials_sum<1, kPartPer>(f.pr, a.part_in, a.nparts_in, a.pstride, lds, red);
     if (threadIdx.x == 0) {
       const double rho = red[0];
       sh.cols = a.k;

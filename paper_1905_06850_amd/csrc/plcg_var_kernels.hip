@@ -187,15 +187,21 @@ __global__ __launch_bounds__(kThreads) void var_apply_kernel(const double *x, do
 // ---------------------------------------------------------------------------
 
 template <int L, typename S, int H>
-static hipError_t var_sweep_lh(const SweepArgsT<S> &a, hipStream_t s) {
+static hipError_t var_sweep_lh(const SweepArgsT<S> &a, hipStream_t s, int *occ) {
   const int grid = a.nstream + (L >= 2 ? 1 : 0);
   switch (a.xmode) {
     case kXEvery:
+      if (occ != nullptr)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occ, plcg_var_sweep_kernel<L, S, H, false>, kThreads, 0);
       hipLaunchKernelGGL((plcg_var_sweep_kernel<L, S, H, false>), dim3(grid), dim3(kThreads), 0, s,
                          a);
       break;
     case kXSkip:
     case kXPair:
+      if (occ != nullptr)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            occ, plcg_var_sweep_kernel<L, S, H, true>, kThreads, 0);
       hipLaunchKernelGGL((plcg_var_sweep_kernel<L, S, H, true>), dim3(grid), dim3(kThreads), 0, s,
                          a);
       break;
@@ -205,36 +211,37 @@ static hipError_t var_sweep_lh(const SweepArgsT<S> &a, hipStream_t s) {
 }
 
 template <int L, typename S>
-static hipError_t var_sweep_l(const SweepArgsT<S> &a, hipStream_t s) {
+static hipError_t var_sweep_l(const SweepArgsT<S> &a, hipStream_t s, int *occ) {
   switch (a.hint) {
-    case 0: return var_sweep_lh<L, S, 0>(a, s);
-    case kHintLoads: return var_sweep_lh<L, S, kHintLoads>(a, s);
-    case kHintLoads | kHintStores: return var_sweep_lh<L, S, kHintLoads | kHintStores>(a, s);
+    case 0: return var_sweep_lh<L, S, 0>(a, s, occ);
+    case kHintLoads: return var_sweep_lh<L, S, kHintLoads>(a, s, occ);
+    case kHintLoads | kHintStores:
+      return var_sweep_lh<L, S, kHintLoads | kHintStores>(a, s, occ);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename S>
-static hipError_t var_sweep_any(const SweepArgsT<S> &a, hipStream_t s) {
+static hipError_t var_sweep_any(const SweepArgsT<S> &a, hipStream_t s, int *occ) {
   switch (a.l) {
-    case 1: return var_sweep_l<1, S>(a, s);
-    case 2: return var_sweep_l<2, S>(a, s);
-    case 3: return var_sweep_l<3, S>(a, s);
-    case 4: return var_sweep_l<4, S>(a, s);
-    case 5: return var_sweep_l<5, S>(a, s);
-    case 6: return var_sweep_l<6, S>(a, s);
-    case 7: return var_sweep_l<7, S>(a, s);
-    case 8: return var_sweep_l<8, S>(a, s);
+    case 1: return var_sweep_l<1, S>(a, s, occ);
+    case 2: return var_sweep_l<2, S>(a, s, occ);
+    case 3: return var_sweep_l<3, S>(a, s, occ);
+    case 4: return var_sweep_l<4, S>(a, s, occ);
+    case 5: return var_sweep_l<5, S>(a, s, occ);
+    case 6: return var_sweep_l<6, S>(a, s, occ);
+    case 7: return var_sweep_l<7, S>(a, s, occ);
+    case 8: return var_sweep_l<8, S>(a, s, occ);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_var_sweep(const SweepArgsT<double> &a, hipStream_t s) {
-  return var_sweep_any<double>(a, s);
+hipError_t launch_var_sweep(const SweepArgsT<double> &a, hipStream_t s, int *occ) {
+  return var_sweep_any<double>(a, s, occ);
 }
 
-hipError_t launch_var_sweep(const SweepArgsT<float> &a, hipStream_t s) {
-  return var_sweep_any<float>(a, s);
+hipError_t launch_var_sweep(const SweepArgsT<float> &a, hipStream_t s, int *occ) {
+  return var_sweep_any<float>(a, s, occ);
 }
 
 hipError_t launch_var_cg_sweep_a(const CgArgs &a, hipStream_t s) {
