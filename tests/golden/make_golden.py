@@ -29,6 +29,7 @@ JOBS = {
     "poisson2048_p3": ("poisson2048", "plcg", 3),
     "poisson2048_p4": ("poisson2048", "plcg", 4),
     "poisson2048_p5": ("poisson2048", "plcg", 5),
+    "poisson3d256_p1": ("poisson3d256", "plcg", 1),
     "poisson3d256_p3": ("poisson3d256", "plcg", 3),
     "poisson3d256_cg": ("poisson3d256", "cg", 0),
     "poisson3d256_m3": ("poisson3d256", "mixed", 3),

@@ -515,7 +515,7 @@ def _golden(name):
 
 @pytest.mark.parametrize("name", ["poisson2048_cg", "poisson2048_p1", "poisson2048_p2",
                                   "poisson2048_p3", "poisson2048_p4", "poisson2048_p5",
-                                  "poisson3d256_p3", "poisson3d256_cg"])
+                                  "poisson3d256_p1", "poisson3d256_p3", "poisson3d256_cg"])
 def test_full_size_against_stored_oracle(dev, name):
     """The benchmark workloads at full size, in the launch configuration the
     benchmark times, against the oracle's stored result (tests/golden,
