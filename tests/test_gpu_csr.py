@@ -220,7 +220,8 @@ def test_csr_uneven_rows_parity(dev, method, l, launch):
     assert _rel(x, ref.x) < 1e-8
 
 
-@pytest.mark.parametrize("name", ["poisson2048_cg", "poisson2048_p1", "poisson2048_p2"])
+@pytest.mark.parametrize("name", ["poisson2048_cg", "poisson2048_p1", "poisson2048_p2",
+                                  "poisson2048_p3"])
 def test_csr_full_size_against_stored_oracle(dev, name):
     """The 2048^2 Poisson matrix assembled in CSR (the csr2048 benchmark
     workload) against the oracle's stored result for the same problem

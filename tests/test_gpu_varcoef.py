@@ -246,19 +246,20 @@ def _golden(name):
         return json.load(f)
 
 
-def test_var_full_size_against_stored_oracle(dev):
+@pytest.mark.parametrize("name", ["varcoef2048_p1", "varcoef2048_p2"])
+def test_var_full_size_against_stored_oracle(dev, name):
     """The 2048^2 variable-coefficient workload (lognormal(0, 1) edges from seed
-    7, Jacobi-scaled p(2)-CG on [0, 2], tol 1e-8) in the configuration the
+    7, Jacobi-scaled p(l)-CG on [0, 2], tol 1e-8) in the configuration the
     benchmark runs, against the oracle's stored result: iterations within 1, x
     at the stored sample and on the dense sample of whole rows (relative error
     < 1e-8), ||x||, and both residual norms."""
-    g = _golden("varcoef2048_p2")
+    g = _golden(name)
     dims = tuple(g["dims"])
     n = int(np.prod(dims))
     plcg = _plcg()
     c = synth.edge_coefficients(dims, g["coef_seed"])
     ct = [torch.from_numpy(a).to(dev) for a in c[:2]]
-    s = plcg.Solver("2d5", dims, method="plcg", l=2, lmin=0.0, lmax=2.0,
+    s = plcg.Solver("2d5", dims, method="plcg", l=int(g["l"]), lmin=0.0, lmax=2.0,
                     coef=(ct[0].data_ptr(), ct[1].data_ptr(), None), jacobi=True)
     bt = torch.from_numpy(synth.uniform(n, g["seed"])).to(dev)
     xt = torch.zeros(n, dtype=torch.float64, device=dev)
