@@ -36,6 +36,7 @@ JOBS = {
     "diag2048_cg": ("diag2048", "cg", 0),
     "diag2048_p1": ("diag2048", "plcg", 1),
     "diag2048_p2": ("diag2048", "plcg", 2),
+    "varcoef2048_p1": ("varcoef2048", "plcg", 1),
     "varcoef2048_p2": ("varcoef2048", "plcg", 2),
 }
 # batch512 systems: the smallest and the largest side of the recipe and two more
