@@ -2,7 +2,9 @@
 its gfx950 code objects (no GPU needed).
 
 The streaming kernels run 1024 workgroups of 256 threads across 256 compute
-units, four workgroups per CU, which needs four waves per SIMD; the resident
+units, four workgroups per CU, which needs four waves per SIMD (the p(l)-CG
+sweeps beyond the memory-side cache run up to six per CU where their registers
+allow, chosen at run time from the kernel's occupancy); the resident
 kernels run one workgroup of 1024 threads on one CU, which needs the same.  A
 CDNA SIMD holds 512 registers per lane for its waves, so every kernel must stay
 within 128 vector registers (arch VGPRs + AGPRs), and none may spill vector
